@@ -1,0 +1,233 @@
+#!/usr/bin/env python
+"""Benchmark of the FE-projection projected-CG hot path on one MI355X.
+
+One step = one full effective-stiffness solve of the workload: right-hand
+side, batched projected CG of all load cases to the tolerance, and the
+post-processing to <sigma> and C_eff, with the material already resident in
+HBM.  Default workload: 3D 256^3 voxels, 6 Kuhn tetrahedra per voxel,
+E(x) = exp(g(x)) with g a seeded Gaussian random field (Gaussian spectrum,
+correlation length 16 voxels, unit variance), nu = 0.3, the 6 unit load cases
+(0.01), FP32 fields / FFT / stencils with FP64 CG scalars, tol 1e-5.
+
+Prints ONE JSON line.  value = DOF-CG-iterations/s = D * N * (sum over load
+cases of their CG iterations) / wall time of the steps.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def kernel_bytes(dim, s, n_last, iters, n_voxels):
+    """Algorithmic HBM bytes of every CG kernel over one solve.
+
+    Per voxel and active load case (V = D s for a nodal vector, Vh = D 2 s
+    (n_last/2+1)/n_last for the half spectrum):
+      stencil      read z, p_old, u; write p, q, u: 6V (3V in a load case's
+                   first iteration: no p_old, no pending u update); plus the
+                   (lambda, mu) material once per launch: 2 s per voxel
+      last fwd     read r, q; write r and the half spectrum: 3V + Vh
+      middle       read + write the spectrum: 2 Vh (each direction, 3D)
+      first+solve  read + write the spectrum: 2 Vh
+      last inv     read the spectrum, write z: Vh + V
+    """
+    V = dim * s
+    Vh = dim * 2 * s * (n_last // 2 + 1) / n_last
+    lc_it = float(sum(iters))
+    firsts = float(sum(1 for i in iters if i > 0))
+    launches = float(max(iters)) if iters else 0.0
+    out = {
+        "stencil": ((lc_it - firsts) * 6 * V + firsts * 3 * V) * n_voxels + launches * 2 * s * n_voxels,
+        "fft_last_fwd": lc_it * (3 * V + Vh) * n_voxels,
+        "fft_first_ksolve": lc_it * 2 * Vh * n_voxels,
+        "fft_last_inv": lc_it * (Vh + V) * n_voxels,
+    }
+    if dim == 3:
+        out["fft_middle_fwd"] = lc_it * 2 * Vh * n_voxels
+        out["fft_middle_inv"] = lc_it * 2 * Vh * n_voxels
+    return out
+
+
+def cpu_baseline(n=40, iters=6000):
+    """Oracle timing on the host: the same random-field recipe on an n^3 grid
+    (correlation length scaled to the same fraction of the cell), one load
+    case, sparse assembly then a fixed number of plain CG iterations of the
+    oracle's C CSR solver (OpenMP)."""
+    import microstructures as ms
+    from oracle import cg as ocg
+    from oracle import fe
+    m = ms.grf_modulus((n, n, n), 16.0 * n / 256.0, 1004)
+    lam, mu = fe.lame(m.E, m.nu)
+    t0 = time.perf_counter()
+    K = fe.assemble(lam, mu)
+    f = fe.load_vector(lam, mu, ms.unit_loads(3)[0])
+    t_asm = time.perf_counter() - t0
+    ocg.run_fixed(K, f, 5)  # warm-up (loads the library, touches memory)
+    t0 = time.perf_counter()
+    ocg.run_fixed(K, f, iters)
+    t_cg = time.perf_counter() - t0
+    dof = 3 * n ** 3
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": dof * iters / t_cg,
+        "unit": "DOF-CG-iterations/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"oracle plain CG (C CSR, OpenMP) on the same E=exp(GRF) recipe at {n}^3 "
+                   f"(ell={16.0 * n / 256.0:g}), 1 load case, {iters} iterations in {t_cg:.2f} s; "
+                   f"sparse assembly {t_asm:.2f} s excluded; nnz={K.nnz}"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="grf256")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import microstructures as ms
+    import paper_2105_03297_amd as feh
+
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
+    m, Ebars, tol, precname = ms.workload(args.workload)
+    shape = m.shape
+    dim = len(shape)
+    N = int(np.prod(shape))
+    L = len(Ebars)
+    log(f"workload {args.workload}: {m.recipe}; L={L}, tol={tol}, {precname}")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    hz = feh.Homogenizer(shape, n_load=L, precision=precname, device=dev)
+    dt = torch.float32 if precname == "fp32" else torch.float64
+    if m.phase is not None and args.workload != "grf256" and not args.workload.startswith("grf"):
+        table = np.stack([np.unique(m.E[m.phase == k])[:1] for k in range(m.phase.max() + 1)])
+        nus = np.stack([np.unique(m.nu[m.phase == k])[:1] for k in range(m.phase.max() + 1)])
+        hz.set_material(phases=m.phase, table=np.concatenate([table, nus], axis=1))
+    else:
+        hz.set_material(E=torch.as_tensor(m.E, dtype=dt), nu=float(m.nu.flat[0]))
+    torch.cuda.synchronize()
+
+    max_iter = 5000
+    for i in range(args.warmup):
+        out = hz.solve(Ebars, tol=tol, max_iter=max_iter)
+        log("warmup", i, [r["iterations"] for r in out["report"]])
+    feh.feh_profile_enable(hz.plan, True)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    iters_all = []
+    t0 = time.perf_counter()
+    ev0.record()
+    for k in range(args.steps):
+        out = hz.solve(Ebars, tol=tol, max_iter=max_iter)
+        iters_all.append([r["iterations"] for r in out["report"]])
+    ev1.record()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t0
+    t_ev = ev0.elapsed_time(ev1) / 1e3
+    prof = feh.feh_profile_read(hz.plan)
+    feh.feh_profile_enable(hz.plan, False)
+    log("steps", iters_all, f"wall {t_wall:.3f}s events {t_ev:.3f}s")
+    t = max(t_wall, t_ev)
+    lc_iters = sum(sum(x) for x in iters_all)
+    value = dim * N * lc_iters / t
+    C32 = out.get("C_eff")
+
+    # roofline of the dominant kernel (live HIP events around each launch)
+    s = 4 if precname == "fp32" else 8
+    kb = {k: 0.0 for k in feh.PROFILE_KINDS}
+    for its in iters_all:
+        for k, v in kernel_bytes(dim, s, shape[-1], its, N).items():
+            kb[k] += v
+    dom = max((k for k in kb if kb[k] > 0), key=lambda k: prof[k][0])
+    dom_ms, dom_n = prof[dom]
+    achieved = kb[dom] / (dom_ms / 1e3) / 1e9
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", f"traffic_{dom}_{args.workload}.json")
+    if os.path.exists(tf):
+        try:
+            tj = json.load(open(tf))
+            traffic = tj.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    kernels = {k: {"ms_total": round(v[0], 3), "launches": v[1],
+                   "GBps_algorithmic": (round(kb[k] / (v[0] / 1e3) / 1e9, 1) if v[0] > 0 and kb[k] > 0 else None)}
+               for k, v in prof.items()}
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "avg_launch_ms": round(dom_ms / max(dom_n, 1), 4),
+            "algorithmic_bytes_per_launch": round(kb[dom] / max(dom_n, 1))}
+    cg_ms = sum(v[0] for v in prof.values())
+    all_bytes = sum(kb.values())
+
+    # FP32 vs FP64 on the same input (untimed)
+    fp_err = None
+    if precname == "fp32" and not args.no_fp64_check and C32 is not None:
+        del hz
+        torch.cuda.empty_cache()
+        h64 = feh.Homogenizer(shape, n_load=L, precision="fp64", device=dev)
+        h64.set_material(E=torch.as_tensor(m.E, dtype=torch.float64), nu=float(m.nu.flat[0]))
+        o64 = h64.solve(Ebars, tol=1e-10, max_iter=max_iter)
+        C64 = o64["C_eff"]
+        fp_err = float(np.abs(C32 - C64).max() / np.abs(C64).max())
+        log("fp64 iterations", [r["iterations"] for r in o64["report"]], "C_eff rel err fp32 vs fp64", fp_err)
+        del h64
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline()
+        log("cpu baseline", cpu["value"])
+
+    line = {
+        "metric": "DOF-CG-iterations/s",
+        "value": value,
+        "unit": "DOF-CG-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if precname == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": list(shape), "elements_per_voxel": 6 if dim == 3 else 2,
+                   "load_cases": L, "tol": tol, "recipe": m.recipe,
+                   "precision": "fp32 fields/FFT/stencil, fp64 CG scalars and k-solve" if precname == "fp32" else "fp64"},
+        "s_per_C_eff": t / args.steps,
+        "cg_iterations_per_load_case": iters_all[-1],
+        "ms_per_cg_iteration": 1e3 * t / max(1, sum(max(x) for x in iters_all)),
+        "fp32_vs_fp64_C_eff_rel_err": fp_err,
+        "cg_loop_GBps_algorithmic": round(all_bytes / (cg_ms / 1e3) / 1e9, 1) if cg_ms > 0 else None,
+        "roofline": roof,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+        "C_eff": np.round(C32, 8).tolist() if C32 is not None else None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

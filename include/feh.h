@@ -1,0 +1,190 @@
+/*
+ * feh.h -- finite-element-projection FFT homogenization on MI355X (gfx950).
+ *
+ * A C ABI around hand-written HIP kernels that solve small-strain periodic
+ * homogenization on a fully structured grid of linear finite elements with
+ * the finite-element compatibility projection of Leute et al.,
+ * "Elimination of ringing artifacts by finite-element projection in
+ * FFT-based homogenization" (arXiv 2105.03297).
+ *
+ * The method (paper sections cited by title):
+ *   - Sec. "Compatibility projection": equilibrium in weak form with test
+ *     strains projected by a self-adjoint operator G onto compatible fields;
+ *     the strain is the unknown and the mean strain Ebar is the macroscopic
+ *     boundary condition (carried by k = 0).
+ *   - Sec. "Discrete projection": G built from a discrete derivative symbol,
+ *     block diagonal in Fourier space; the DFT only accelerates a convolution.
+ *   - Sec. "Linear finite elements": 2 linear triangles per pixel (2D); the
+ *     3D generalisation used here is 6 Kuhn tetrahedra per voxel.
+ *   - Small-strain appendix: G = B (B^*B)^-1 B^* per wavevector, with
+ *     e_T = sym(grad_T u) per element T.
+ *   - Discrete Fourier transform appendix: grid, wavevectors, transform pair.
+ *
+ * The solver runs projected conjugate gradients on G K in strain space in
+ * its factored form: every Krylov vector is a nodal displacement field (D
+ * reals per voxel), B and B^T are applied as real-space stencils and only
+ * (B^*B)^-1, a D x D Hermitian matrix per wavevector, is applied in Fourier
+ * space.  This is iterate-for-iterate the same as CG on the strain field,
+ * and its converged strain is the canonical FE strain.
+ *
+ * Conventions
+ *   - Grid: dim = 2 or 3, sizes n[0..dim-1]; arrays are C-ordered with the
+ *     last axis fastest; N = prod n.  Node (i,j[,k]) is the lower-left
+ *     corner of voxel (i,j[,k]); voxel sizes h[a] (Delta_a).
+ *   - Elements per voxel n_e: 2D e=0 nodes 00,10,01, e=1 nodes 11,01,10;
+ *     3D e = axis paths (x,y,z),(x,z,y),(y,x,z),(y,z,x),(z,x,y),(z,y,x),
+ *     tetrahedron with vertices 0, e_a0, e_a0+e_a1, (1,1,1).
+ *   - Material: isotropic, per voxel Lame constants (lambda, mu); 2D is
+ *     plane strain when set from (E, nu).  E = 0 (vacuum) is accepted.
+ *   - Precision: FEH_FP64 runs everything in double.  FEH_FP32 stores and
+ *     streams fields, stencils and FFTs in float and keeps the CG dot
+ *     products, alpha/beta and the per-wavevector (B^*B)^-1 solve in double.
+ *   - Nodal vector fields at the ABI are [n_load][N][D] and element fields
+ *     [n_load][N][n_e][D][D], in the plan's precision (float or double).
+ *   - All device pointers are caller-owned device memory (e.g. torch
+ *     tensors); the library never allocates or frees device memory: the
+ *     caller queries feh_plan_workspace_bytes and hands a buffer to
+ *     feh_plan_set_workspace, which the caller keeps alive.
+ *   - Every call enqueues its device work on the plan's stream.  Calls that
+ *     return host values synchronise that stream before returning.
+ *   - Return value: FEH_OK (0) or a negative error code; feh_last_error()
+ *     gives a message for the last failure on the calling thread.  No C++
+ *     exception crosses the ABI.  A plan is not thread safe.
+ */
+#ifndef FEH_H
+#define FEH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FEH_OK = 0,
+    FEH_EINVAL = -1,      /* invalid argument (null pointer, shape, value)     */
+    FEH_ENOMEM = -2,      /* workspace missing or too small                    */
+    FEH_EHIP = -3,        /* HIP runtime error                                 */
+    FEH_ENOCONV = -4,     /* max_iter reached; outputs hold the last iterate   */
+    FEH_EBREAKDOWN = -5,  /* CG breakdown (p.q <= 0 or not finite)             */
+    FEH_ENOTSUP = -6      /* unsupported size (FFT length with a prime > 13)   */
+};
+
+enum { FEH_FP64 = 0, FEH_FP32 = 1 };
+
+typedef struct feh_plan feh_plan;
+
+typedef struct {
+    int32_t iterations;   /* CG iterations performed for this load case           */
+    int32_t status;       /* FEH_OK, FEH_ENOCONV or FEH_EBREAKDOWN                */
+    double rel_residual;  /* sqrt(r.z / f.M^+f): relative residual in the strain
+                             space norm (Euclidean over all elements)            */
+} feh_report;
+
+/* Create a plan for a dim-dimensional periodic grid n[] with voxel sizes h[]
+ * (NULL = unit), n_load load cases solved together, precision FEH_FP64 or
+ * FEH_FP32, and a HIP stream (hipStream_t; NULL = default stream).
+ * Each n[a] must lie in [2, 4096] and factor into primes <= 13 (else
+ * FEH_ENOTSUP); n_load in [1, 64]; N <= 2^31.  Host-side only: computes the
+ * FFT factorisations, twiddle and phase tables (Discrete Fourier transform
+ * appendix: k_a = 2 pi m / (n_a h_a)). */
+int feh_plan_create(feh_plan **plan, int dim, const int64_t n[], const double h[],
+                    int n_load, int precision, void *hip_stream);
+
+/* Destroy a plan (NULL is a no-op).  Does not free the workspace. */
+int feh_plan_destroy(feh_plan *plan);
+
+/* Bytes of device workspace the plan needs (vectors u, r, z, p (two), q,
+ * the half spectrum, the material, tables, partial sums and CG scalars). */
+int feh_plan_workspace_bytes(const feh_plan *plan, size_t *bytes);
+
+/* Hand the plan a device buffer of at least feh_plan_workspace_bytes bytes,
+ * 256-byte aligned.  Uploads the tables (asynchronously on the stream).
+ * The material must be set again after a new workspace. */
+int feh_plan_set_workspace(feh_plan *plan, void *dev_ptr, size_t bytes);
+
+/* Material from per-voxel Lame constants (device arrays of N values in the
+ * plan precision).  lambda and mu must be finite with mu >= 0 and
+ * lambda + 2 mu / dim >= 0 (checked on the device; FEH_EINVAL otherwise). */
+int feh_set_material_lame(feh_plan *plan, const void *lambda_dev, const void *mu_dev);
+
+/* Material from a phase map (device int32[N], values in [0, n_phase)) and a
+ * host table E_nu[n_phase][2] = (E, nu) with E >= 0 and -1 < nu < 0.5.
+ * Plane strain in 2D: lambda = E nu/((1+nu)(1-2nu)), mu = E/(2(1+nu)). */
+int feh_set_material_phases(feh_plan *plan, const int32_t *phase_dev,
+                            const double *E_nu_host, int n_phase);
+
+/* Material from a per-voxel Young's modulus field (device, N values in the
+ * plan precision, E >= 0) and a uniform Poisson ratio (-1 < nu < 0.5). */
+int feh_set_material_field(feh_plan *plan, const void *E_dev, double nu);
+
+/* Solve all load cases: find the periodic fluctuation u with zero mean such
+ * that the element strains e = Ebar_l + B u satisfy the discrete equilibrium
+ * B^T C e = 0 (equivalently G(C e) = 0 with compatible e - Ebar).
+ *   Ebar_host         [n_load][D][D] symmetric macroscopic strains (host)
+ *   tol               stop a load case when sqrt(r.z / f.M^+f) <= tol
+ *   max_iter          per load case, >= 1
+ *   u0_dev            nullable warm start [n_load][N][D]
+ *   u_dev             nullable output fluctuation [n_load][N][D]
+ *   strain_dev        nullable output [n_load][N][n_e][D][D]  (Ebar + B u)
+ *   stress_dev        nullable output [n_load][N][n_e][D][D]  (C e)
+ *   stress_mean_host  nullable [n_load][D][D]  volume average of the stress
+ *   energy_host       nullable [n_load][n_load] W_lm = < e_l : C : e_m >
+ *   report_host       nullable [n_load]
+ * Returns FEH_OK if every load case converged, FEH_ENOCONV or
+ * FEH_EBREAKDOWN otherwise (outputs still filled from the last iterate). */
+int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
+              const void *u0_dev, void *u_dev, void *strain_dev, void *stress_dev,
+              double *stress_mean_host, double *energy_host, feh_report *report_host);
+
+/* Host helper: effective Voigt stiffness C[nv][nv] (engineering shear,
+ * order 2D (xx,yy,xy), 3D (xx,yy,zz,yz,xz,xy)) from an energy matrix W of
+ * n_load = nv load cases whose Voigt strains are linearly independent:
+ * W = E^T C E with E the engineering Voigt strain columns of Ebar. */
+int feh_effective_stiffness(int dim, int n_load, const double *Ebar_host,
+                            const double *energy_host, double *C_host);
+
+/* Test export: q = K p with K = sum_e |e| B_e^T C_e B_e, p and q
+ * [n_load][N][D] in the plan precision. */
+int feh_apply_operator(feh_plan *plan, const void *p_dev, void *q_dev);
+
+/* Test export: z = M^+ r with M = sum_e |e| B_e^T B_e (K for lambda = 0,
+ * mu = 1/2), applied per wavevector; z has zero mean. [n_load][N][D]. */
+int feh_apply_preconditioner(feh_plan *plan, const void *r_dev, void *z_dev);
+
+/* Test export: the small-strain projection G = B (B^T B)^+ B^T on element
+ * fields e [n_load][N][n_e][D][D] (only the symmetric part of e enters). */
+int feh_apply_projection(feh_plan *plan, const void *e_dev, void *Ge_dev);
+
+/* Test export: unnormalised forward real-to-half-complex DFT over the grid
+ * (sum_r f(r) exp(-i k.r)) of n_load*D real fields [n_load*D][N]; output
+ * [n_load*D][n0]..[n_last/2+1] interleaved complex (numpy.fft.rfftn layout). */
+int feh_fft_forward(feh_plan *plan, const void *x_dev, void *X_dev);
+
+/* Test export: inverse of feh_fft_forward including the 1/N factor. */
+int feh_fft_inverse(feh_plan *plan, const void *X_dev, void *x_dev);
+
+/* Measurement: enable (1) or disable (0) HIP-event timing of every kernel
+ * launch inside the CG iterations of feh_solve on the plan's stream, and
+ * reset the counters.  Kinds: 0 stencil (p update, q = K p, p.q), 1 alpha,
+ * 2 last-axis r2c with r -= alpha q, 3 middle-axis forward (3D), 4 first
+ * axis forward + (B^*B)^-1 + inverse with r.z, 5 middle-axis inverse (3D),
+ * 6 last-axis c2r, 7 beta / stop test. */
+int feh_profile_enable(feh_plan *plan, int enable);
+
+/* Accumulated milliseconds and launch counts per kind (n_kinds entries,
+ * kinds beyond 7 read as zero). */
+int feh_profile_read(const feh_plan *plan, double *ms_total, int64_t *launches, int n_kinds);
+
+/* Message of the last error on this thread ("" if none). */
+const char *feh_last_error(void);
+
+/* Library version, 10000*major + 100*minor + patch. */
+int feh_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEH_H */

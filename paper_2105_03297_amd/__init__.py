@@ -1,0 +1,333 @@
+"""FE-projection FFT homogenization on MI355X (gfx950): Python binding.
+
+A thin ctypes binding of ``libfeh.so`` (declared in ``include/feh.h``).  The
+functions ``feh_*`` below carry the C names and only marshal arguments; every
+step of the computation runs in the library's HIP kernels.  PyTorch provides
+device memory and the stream (``Homogenizer`` is a convenience wrapper that
+allocates the workspace and outputs as torch tensors).
+
+The library refuses to load if it has not been built (``build.py``); there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "FEH_OK", "FEH_EINVAL", "FEH_ENOMEM", "FEH_EHIP", "FEH_ENOCONV", "FEH_EBREAKDOWN", "FEH_ENOTSUP",
+    "FEH_FP64", "FEH_FP32", "FehError", "feh_report", "library_path", "load",
+    "feh_plan_create", "feh_plan_destroy", "feh_plan_workspace_bytes", "feh_plan_set_workspace",
+    "feh_set_material_lame", "feh_set_material_phases", "feh_set_material_field", "feh_solve",
+    "feh_effective_stiffness", "feh_apply_operator", "feh_apply_preconditioner", "feh_apply_projection",
+    "feh_fft_forward", "feh_fft_inverse", "feh_profile_enable", "feh_profile_read", "PROFILE_KINDS",
+    "feh_last_error", "feh_version", "Homogenizer",
+]
+
+FEH_OK, FEH_EINVAL, FEH_ENOMEM, FEH_EHIP, FEH_ENOCONV, FEH_EBREAKDOWN, FEH_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+FEH_FP64, FEH_FP32 = 0, 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libfeh.so")
+
+
+class FehError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"feh error {status}: {message}")
+        self.status = status
+        self.message = message
+
+
+class feh_report(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32), ("rel_residual", ctypes.c_double)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "feh_plan_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                       _dp, ctypes.c_int, ctypes.c_int, _vp]),
+    "feh_plan_destroy": (ctypes.c_int, [_vp]),
+    "feh_plan_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "feh_plan_set_workspace": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+    "feh_set_material_lame": (ctypes.c_int, [_vp, _vp, _vp]),
+    "feh_set_material_phases": (ctypes.c_int, [_vp, _vp, _dp, ctypes.c_int]),
+    "feh_set_material_field": (ctypes.c_int, [_vp, _vp, ctypes.c_double]),
+    "feh_solve": (ctypes.c_int, [_vp, _dp, ctypes.c_double, ctypes.c_int, _vp, _vp, _vp, _vp, _dp, _dp,
+                                 ctypes.POINTER(feh_report)]),
+    "feh_effective_stiffness": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]),
+    "feh_apply_operator": (ctypes.c_int, [_vp, _vp, _vp]),
+    "feh_apply_preconditioner": (ctypes.c_int, [_vp, _vp, _vp]),
+    "feh_apply_projection": (ctypes.c_int, [_vp, _vp, _vp]),
+    "feh_fft_forward": (ctypes.c_int, [_vp, _vp, _vp]),
+    "feh_fft_inverse": (ctypes.c_int, [_vp, _vp, _vp]),
+    "feh_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "feh_profile_read": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
+    "feh_last_error": (ctypes.c_char_p, []),
+    "feh_version": (ctypes.c_int, []),
+}
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def load():
+    """Load libfeh.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                               "`python paper_2105_03297_amd/build.py` (no CPU fallback exists)")
+        lib = ctypes.CDLL(_LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc, allow=()):
+    if rc != FEH_OK and rc not in allow:
+        raise FehError(rc, load().feh_last_error().decode())
+    return rc
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+# --------------------------------------------------------------------------
+# same-name wrappers (argument marshalling only)
+# --------------------------------------------------------------------------
+def feh_last_error():
+    return load().feh_last_error().decode()
+
+
+def feh_version():
+    return load().feh_version()
+
+
+def feh_plan_create(dim, n, h=None, n_load=1, precision=FEH_FP64, stream=0):
+    n_arr = (ctypes.c_int64 * 3)(*(list(n) + [1] * (3 - len(n))))
+    if h is None:
+        h_ptr = None
+    else:
+        h_keep = (ctypes.c_double * 3)(*(list(h) + [1.0] * (3 - len(h))))
+        h_ptr = ctypes.cast(h_keep, _dp)
+    plan = _vp()
+    _check(load().feh_plan_create(ctypes.byref(plan), int(dim), n_arr, h_ptr, int(n_load), int(precision),
+                                  _vp(stream or 0)))
+    return plan
+
+
+def feh_plan_destroy(plan):
+    return _check(load().feh_plan_destroy(plan))
+
+
+def feh_plan_workspace_bytes(plan):
+    b = ctypes.c_size_t(0)
+    _check(load().feh_plan_workspace_bytes(plan, ctypes.byref(b)))
+    return b.value
+
+
+def feh_plan_set_workspace(plan, dev_ptr, nbytes):
+    return _check(load().feh_plan_set_workspace(plan, _vp(dev_ptr), ctypes.c_size_t(nbytes)))
+
+
+def feh_set_material_lame(plan, lam_ptr, mu_ptr):
+    return _check(load().feh_set_material_lame(plan, _vp(lam_ptr), _vp(mu_ptr)))
+
+
+def feh_set_material_phases(plan, phase_ptr, E_nu):
+    t, tp = _f64(E_nu)
+    return _check(load().feh_set_material_phases(plan, _vp(phase_ptr), tp, int(t.shape[0])))
+
+
+def feh_set_material_field(plan, E_ptr, nu):
+    return _check(load().feh_set_material_field(plan, _vp(E_ptr), float(nu)))
+
+
+def feh_solve(plan, Ebar, tol, max_iter, u0_ptr=0, u_ptr=0, strain_ptr=0, stress_ptr=0, allow_noconv=True):
+    """Returns (status, stress_mean[L,D,D], energy[L,L], reports)."""
+    Eb, Ebp = _f64(Ebar)
+    L, D = Eb.shape[0], Eb.shape[1]
+    smean = np.zeros((L, D, D))
+    W = np.zeros((L, L))
+    rep = (feh_report * L)()
+    rc = load().feh_solve(plan, Ebp, float(tol), int(max_iter), _vp(u0_ptr or 0), _vp(u_ptr or 0),
+                          _vp(strain_ptr or 0), _vp(stress_ptr or 0), smean.ctypes.data_as(_dp),
+                          W.ctypes.data_as(_dp), rep)
+    _check(rc, allow=(FEH_ENOCONV,) if allow_noconv else ())
+    return rc, smean, W, [dict(iterations=r.iterations, status=r.status, rel_residual=r.rel_residual) for r in rep]
+
+
+def feh_effective_stiffness(dim, Ebar, W):
+    Eb, Ebp = _f64(Ebar)
+    Wm, Wp = _f64(W)
+    nv = 3 if dim == 2 else 6
+    C = np.zeros((nv, nv))
+    _check(load().feh_effective_stiffness(int(dim), int(Eb.shape[0]), Ebp, Wp, C.ctypes.data_as(_dp)))
+    return C
+
+
+PROFILE_KINDS = ["stencil", "alpha", "fft_last_fwd", "fft_middle_fwd", "fft_first_ksolve", "fft_middle_inv",
+                 "fft_last_inv", "beta"]
+
+
+def feh_profile_enable(plan, enable=True):
+    return _check(load().feh_profile_enable(plan, 1 if enable else 0))
+
+
+def feh_profile_read(plan):
+    """Returns {kind: (total_ms, launches)}."""
+    n = len(PROFILE_KINDS)
+    ms = np.zeros(n)
+    cnt = (ctypes.c_int64 * n)()
+    _check(load().feh_profile_read(plan, ms.ctypes.data_as(_dp), cnt, n))
+    return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PROFILE_KINDS)}
+
+
+def feh_apply_operator(plan, p_ptr, q_ptr):
+    return _check(load().feh_apply_operator(plan, _vp(p_ptr), _vp(q_ptr)))
+
+
+def feh_apply_preconditioner(plan, r_ptr, z_ptr):
+    return _check(load().feh_apply_preconditioner(plan, _vp(r_ptr), _vp(z_ptr)))
+
+
+def feh_apply_projection(plan, e_ptr, Ge_ptr):
+    return _check(load().feh_apply_projection(plan, _vp(e_ptr), _vp(Ge_ptr)))
+
+
+def feh_fft_forward(plan, x_ptr, X_ptr):
+    return _check(load().feh_fft_forward(plan, _vp(x_ptr), _vp(X_ptr)))
+
+
+def feh_fft_inverse(plan, X_ptr, x_ptr):
+    return _check(load().feh_fft_inverse(plan, _vp(X_ptr), _vp(x_ptr)))
+
+
+# --------------------------------------------------------------------------
+# torch convenience wrapper
+# --------------------------------------------------------------------------
+class Homogenizer:
+    """One plan bound to a torch device and stream, with a torch-owned workspace.
+
+    shape: grid (Nx, Ny[, Nz]); n_load: load cases solved together;
+    precision: "fp64" or "fp32" (FP32 fields/FFT/stencils, FP64 CG scalars
+    and per-wavevector solve); h: voxel sizes (default 1).
+    """
+
+    def __init__(self, shape, n_load=1, precision="fp64", h=None, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.shape = tuple(int(s) for s in shape)
+        self.dim = len(self.shape)
+        self.N = int(np.prod(self.shape))
+        self.n_load = int(n_load)
+        self.precision = precision
+        self.prec = FEH_FP64 if precision == "fp64" else FEH_FP32
+        self.dtype = torch.float64 if self.prec == FEH_FP64 else torch.float32
+        self.device = torch.device(device)
+        self.ne = 2 if self.dim == 2 else 6
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self.plan = feh_plan_create(self.dim, self.shape, h, self.n_load, self.prec, stream.cuda_stream)
+        nbytes = feh_plan_workspace_bytes(self.plan)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        feh_plan_set_workspace(self.plan, self.workspace.data_ptr(), self.workspace.numel())
+        self._keep = []
+
+    def _dev(self, x, dtype=None):
+        t = self.torch.as_tensor(x, device=self.device, dtype=dtype or self.dtype)
+        return t.contiguous()
+
+    def set_material(self, E=None, nu=None, phases=None, table=None, lam=None, mu=None):
+        """Either (E field, uniform nu), (phases, table[(E, nu)]), or (lam, mu) fields."""
+        if lam is not None:
+            l, m = self._dev(lam), self._dev(mu)
+            feh_set_material_lame(self.plan, l.data_ptr(), m.data_ptr())
+        elif phases is not None:
+            ph = self._dev(phases, self.torch.int32)
+            feh_set_material_phases(self.plan, ph.data_ptr(), np.asarray(table, dtype=np.float64))
+        else:
+            e = self._dev(E)
+            feh_set_material_field(self.plan, e.data_ptr(), float(nu))
+        self.stream.synchronize()
+
+    def solve(self, Ebar, tol=1e-10, max_iter=1000, u0=None, fields=False, return_u=False):
+        torch = self.torch
+        Ebar = np.asarray(Ebar, dtype=np.float64).reshape(self.n_load, self.dim, self.dim)
+        L, D, N, ne = self.n_load, self.dim, self.N, self.ne
+        u = torch.empty((L, N, D), dtype=self.dtype, device=self.device) if return_u else None
+        strain = stress = None
+        if fields:
+            strain = torch.empty((L, N, ne, D, D), dtype=self.dtype, device=self.device)
+            stress = torch.empty_like(strain)
+        u0t = self._dev(u0).reshape(L, N, D) if u0 is not None else None
+        rc, smean, W, rep = feh_solve(self.plan, Ebar, tol, max_iter,
+                                      u0t.data_ptr() if u0t is not None else 0,
+                                      u.data_ptr() if u is not None else 0,
+                                      strain.data_ptr() if strain is not None else 0,
+                                      stress.data_ptr() if stress is not None else 0)
+        out = dict(status=rc, stress_mean=smean, energy=W, report=rep, u=u, strain=strain, stress=stress)
+        nv = 3 if D == 2 else 6
+        if L == nv:
+            try:
+                out["C_eff"] = feh_effective_stiffness(D, Ebar, W)
+            except FehError:
+                pass
+        return out
+
+    def apply_operator(self, p):
+        p = self._dev(p).reshape(self.n_load, self.N, self.dim)
+        q = self.torch.empty_like(p)
+        feh_apply_operator(self.plan, p.data_ptr(), q.data_ptr())
+        return q
+
+    def apply_preconditioner(self, r):
+        r = self._dev(r).reshape(self.n_load, self.N, self.dim)
+        z = self.torch.empty_like(r)
+        feh_apply_preconditioner(self.plan, r.data_ptr(), z.data_ptr())
+        return z
+
+    def apply_projection(self, e):
+        e = self._dev(e).reshape(self.n_load, self.N, self.ne, self.dim, self.dim)
+        g = self.torch.empty_like(e)
+        feh_apply_projection(self.plan, e.data_ptr(), g.data_ptr())
+        return g
+
+    def fft_forward(self, x):
+        x = self._dev(x).reshape(self.n_load * self.dim, self.N)
+        nh = self.shape[-1] // 2 + 1
+        cd = self.torch.complex128 if self.prec == FEH_FP64 else self.torch.complex64
+        X = self.torch.empty((self.n_load * self.dim,) + self.shape[:-1] + (nh,), dtype=cd, device=self.device)
+        feh_fft_forward(self.plan, x.data_ptr(), X.data_ptr())
+        return X
+
+    def fft_inverse(self, X):
+        cd = self.torch.complex128 if self.prec == FEH_FP64 else self.torch.complex64
+        X = self.torch.as_tensor(X, device=self.device, dtype=cd).contiguous()
+        x = self.torch.empty((self.n_load * self.dim, self.N), dtype=self.dtype, device=self.device)
+        feh_fft_inverse(self.plan, X.data_ptr(), x.data_ptr())
+        return x
+
+    def close(self):
+        if self.plan is not None:
+            feh_plan_destroy(self.plan)
+            self.plan = None
+            self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

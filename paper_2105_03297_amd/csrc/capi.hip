@@ -1,0 +1,696 @@
+// C ABI, plan management and the projected-CG driver.
+//
+// Projected CG on G K in strain space (Sec. "Compatibility projection": the
+// test strains are projected by G, and gradient-based solvers started from a
+// compatible field stay compatible) is run in its factored form: with
+// e~ = B u the strain-space iterates are those of CG on K u = f preconditioned
+// by M = B^T B, since G = B (B^T B)^+ B^T (small-strain appendix).  All Krylov
+// vectors are nodal displacement fields; B, B^T run as real-space stencils
+// (kern_stencil.hip) and only M^+ is applied per wavevector
+// (kern_fft.hip).  Per iteration and load case:
+//   stencil:  p = z + beta p (or z), u += alpha_prev p_prev, q = K p, p.q
+//   scalars:  alpha = rho / p.q
+//   FFT:      r -= alpha q fused into the last-axis r2c, first-axis pass with
+//             z^ = M^-1 r^ and rho_new = r.z by Parseval, inverse passes
+//   scalars:  stop test sqrt(rho_new / f.M^+f) <= tol, beta = rho_new / rho
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "feh_internal.hpp"
+
+namespace feh {
+
+static thread_local std::string g_err;
+
+int set_error(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return FEH_OK;
+    return set_error(FEH_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define CK(x)                        \
+    do {                             \
+        int rc__ = (x);              \
+        if (rc__ != FEH_OK) return rc__; \
+    } while (0)
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static bool factorize(int n, AxisFFT &ax) {
+    ax = AxisFFT{};
+    ax.n = n;
+    int rad[64];
+    int nr = 0;
+    int m = n;
+    const int order[] = {8, 4, 2, 3, 5, 7, 11, 13};
+    for (int r : order) {
+        while (m % r == 0 && m > 1) {
+            if (nr >= kMaxRadixCount) return false;
+            rad[nr++] = r;
+            m /= r;
+        }
+    }
+    if (m != 1) return false;
+    int Lstar = 1;
+    for (int s = 0; s < nr; ++s) {
+        PassInfo ps;
+        ps.R = rad[s];
+        ps.Lstar = Lstar;
+        ps.m = FastDiv::make((uint32_t)(n / (Lstar * rad[s])));
+        ax.pass[s] = ps;
+        Lstar *= rad[s];
+    }
+    ax.npass = nr;
+    return true;
+}
+
+static void layout(feh_plan &p) {
+    const size_t vec = (size_t)p.L * p.dim * p.N * p.rsize;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    p.off_u = take(vec);
+    p.off_r = take(vec);
+    p.off_z = take(vec);
+    p.off_p0 = take(vec);
+    p.off_p1 = take(vec);
+    p.off_q = take(vec);
+    p.off_spec = take((size_t)p.L * p.dim * p.Nspec * 2 * p.rsize);
+    p.off_lam = take(p.N * p.rsize);
+    p.off_mu = take(p.N * p.rsize);
+    for (int a = 0; a < 3; ++a) {
+        const size_t na = (size_t)p.n[a];
+        p.off_tw[a] = take(na * 2 * p.rsize);
+        p.off_om[a] = take(na * 2 * sizeof(double));
+        p.off_aa[a] = take(na * 2 * sizeof(double));
+    }
+    p.off_tab = take(kMaxPhase * 2 * sizeof(double));
+    p.off_ebar = take((size_t)p.L * 9 * sizeof(double));
+    p.off_sums = take((size_t)post_num_slots(p) * sizeof(double));
+    const int sp = stencil_num_parts(p), fp = first_num_parts(p);
+    p.part_stride = (size_t)(sp > fp ? sp : fp);
+    size_t parts = p.part_stride * p.L;
+    const size_t post_parts = (size_t)post_num_slots(p) * post_num_parts(p);
+    if (post_parts > parts) parts = post_parts;
+    p.off_part = take(parts * sizeof(double));
+    p.off_state = take((size_t)p.L * sizeof(LcState));
+    p.off_flag = take(256);
+    p.total = o;
+}
+
+static void tables(feh_plan &p) {
+    for (int a = 0; a < 3; ++a) {
+        const int n = (int)p.n[a];
+        p.tw_host[a].assign(2 * n, 0.0);
+        p.om_host[a].assign(2 * n, 0.0);
+        p.aa_host[a].assign(2 * n, 0.0);
+        for (int j = 0; j < n; ++j) {
+            const double th = 2.0 * M_PI * (double)j / (double)n;
+            // twiddle exp(-i th)
+            p.tw_host[a][2 * j] = std::cos(th);
+            p.tw_host[a][2 * j + 1] = -std::sin(th);
+            // omega = exp(+i th); a = (omega - 1)/h = (-2 sin^2(th/2) + i sin th)/h
+            p.om_host[a][2 * j] = std::cos(th);
+            p.om_host[a][2 * j + 1] = std::sin(th);
+            const double s2 = std::sin(0.5 * th);
+            p.aa_host[a][2 * j] = -2.0 * s2 * s2 / p.h[a];
+            p.aa_host[a][2 * j + 1] = std::sin(th) / p.h[a];
+        }
+    }
+}
+
+static int upload_tables(feh_plan &p) {
+    for (int a = 0; a < 3; ++a) {
+        const int n = (int)p.n[a];
+        if (p.prec == FEH_FP64) {
+            CK(hip_check(hipMemcpyAsync(p.ws + p.off_tw[a], p.tw_host[a].data(), 2 * n * sizeof(double),
+                                        hipMemcpyHostToDevice, p.stream),
+                         "upload twiddles"));
+        } else {
+            std::vector<float> f(2 * n);
+            for (int j = 0; j < 2 * n; ++j) f[j] = (float)p.tw_host[a][j];
+            CK(hip_check(hipMemcpyAsync(p.ws + p.off_tw[a], f.data(), 2 * n * sizeof(float), hipMemcpyHostToDevice,
+                                        p.stream),
+                         "upload twiddles"));
+            CK(hip_check(hipStreamSynchronize(p.stream), "upload twiddles"));
+        }
+        CK(hip_check(hipMemcpyAsync(p.ws + p.off_om[a], p.om_host[a].data(), 2 * n * sizeof(double),
+                                    hipMemcpyHostToDevice, p.stream),
+                     "upload phases"));
+        CK(hip_check(hipMemcpyAsync(p.ws + p.off_aa[a], p.aa_host[a].data(), 2 * n * sizeof(double),
+                                    hipMemcpyHostToDevice, p.stream),
+                     "upload phases"));
+    }
+    return hip_check(hipStreamSynchronize(p.stream), "upload tables");
+}
+
+static int check_plan(const feh_plan *p, bool need_material) {
+    if (!p) return set_error(FEH_EINVAL, "null plan");
+    if (!p->ws) return set_error(FEH_ENOMEM, "workspace not set (feh_plan_set_workspace)");
+    if (need_material && !p->material_set) return set_error(FEH_EINVAL, "material not set");
+    return FEH_OK;
+}
+
+static int read_flag(feh_plan &p, int *flag_dev, const char *what) {
+    int h = 0;
+    CK(hip_check(hipMemcpyAsync(&h, flag_dev, sizeof(int), hipMemcpyDeviceToHost, p.stream), what));
+    CK(hip_check(hipStreamSynchronize(p.stream), what));
+    return h ? set_error(FEH_EINVAL, std::string(what) + ": invalid material value") : FEH_OK;
+}
+
+// z = M^+ r on SoA fields (spectrum buffer as scratch); Parseval r.z partials.
+static int precondition(const feh_plan &p, const void *r, void *z, double *partial, const LcState *st) {
+    FftArgs fa;
+    fa.r = r;
+    fa.spec = p.ws + p.off_spec;
+    fa.z = z;
+    fa.partial = partial;
+    fa.state = st;
+    fa.out_scale = 1.0 / (double)p.N;
+    CK(launch_forward_last(p, fa));
+    if (p.dim == 3) CK(launch_middle(p, fa, false));
+    CK(launch_first_fused(p, fa));
+    if (p.dim == 3) CK(launch_middle(p, fa, true));
+    return launch_inverse_last(p, fa);
+}
+
+// Optional event timing of the CG loop: a (start, end) event pair around
+// every launch, drained after each host synchronisation.
+struct ProfScope {
+    const feh_plan &p;
+    int kind;
+    ProfScope(const feh_plan &pl, int k) : p(pl), kind(k) {
+        if (!p.prof_on) return;
+        if (2 * p.prof_used + 2 > p.prof_ev.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+            p.prof_ev.push_back(a);
+            p.prof_ev.push_back(b);
+            p.prof_kind.push_back(0);
+        }
+        hipEventRecord(p.prof_ev[2 * p.prof_used], p.stream);
+    }
+    ~ProfScope() {
+        if (!p.prof_on || 2 * p.prof_used + 2 > p.prof_ev.size()) return;
+        hipEventRecord(p.prof_ev[2 * p.prof_used + 1], p.stream);
+        p.prof_kind[p.prof_used] = kind;
+        ++p.prof_used;
+    }
+};
+
+static void prof_drain(const feh_plan &p) {
+    for (size_t i = 0; i < p.prof_used; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.prof_ev[2 * i], p.prof_ev[2 * i + 1]) == hipSuccess) {
+            p.prof_ms[p.prof_kind[i]] += ms;
+            p.prof_n[p.prof_kind[i]] += 1;
+        }
+    }
+    p.prof_used = 0;
+}
+
+static int cg_iteration(const feh_plan &p, LcState *st, double tol, int max_iter) {
+    double *part = p.ptr<double>(p.off_part);
+    StencilArgs sa;
+    sa.in0 = p.ws + p.off_z;
+    sa.in1 = p.ws + p.off_p0;
+    sa.in1b = p.ws + p.off_p1;
+    sa.out0 = p.ws + p.off_q;
+    sa.out1 = p.ws + p.off_p0;
+    sa.out1b = p.ws + p.off_p1;
+    sa.u = p.ws + p.off_u;
+    sa.partial = part;
+    sa.state = st;
+    {
+        ProfScope ps(p, 0);
+        CK(launch_stencil(p, ST_CG, sa));
+    }
+    {
+        ProfScope ps(p, 1);
+        CK(launch_finish_pq(p, st, part, stencil_num_parts(p)));
+    }
+    FftArgs fa;
+    fa.r = p.ws + p.off_r;
+    fa.q = p.ws + p.off_q;
+    fa.r_out = p.ws + p.off_r;
+    fa.spec = p.ws + p.off_spec;
+    fa.z = p.ws + p.off_z;
+    fa.partial = part;
+    fa.state = st;
+    fa.out_scale = 1.0 / (double)p.N;
+    {
+        ProfScope ps(p, 2);
+        CK(launch_forward_last(p, fa));
+    }
+    if (p.dim == 3) {
+        ProfScope ps(p, 3);
+        CK(launch_middle(p, fa, false));
+    }
+    {
+        ProfScope ps(p, 4);
+        CK(launch_first_fused(p, fa));
+    }
+    if (p.dim == 3) {
+        ProfScope ps(p, 5);
+        CK(launch_middle(p, fa, true));
+    }
+    {
+        ProfScope ps(p, 6);
+        CK(launch_inverse_last(p, fa));
+    }
+    ProfScope ps(p, 7);
+    return launch_finish_rho(p, st, part, first_num_parts(p), 2, tol, max_iter);
+}
+
+static void invert(int n, std::vector<double> &A, bool &ok) {
+    // Gauss-Jordan with partial pivoting, in place (row-major n x n)
+    std::vector<double> I(n * n, 0.0);
+    for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
+    ok = true;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+        if (std::fabs(A[piv * n + c]) < 1e-300) {
+            ok = false;
+            return;
+        }
+        for (int k = 0; k < n; ++k) {
+            std::swap(A[c * n + k], A[piv * n + k]);
+            std::swap(I[c * n + k], I[piv * n + k]);
+        }
+        const double d = 1.0 / A[c * n + c];
+        for (int k = 0; k < n; ++k) {
+            A[c * n + k] *= d;
+            I[c * n + k] *= d;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const double f = A[r * n + c];
+            if (f == 0.0) continue;
+            for (int k = 0; k < n; ++k) {
+                A[r * n + k] -= f * A[c * n + k];
+                I[r * n + k] -= f * I[c * n + k];
+            }
+        }
+    }
+    A = I;
+}
+
+}  // namespace feh
+
+using namespace feh;
+
+extern "C" {
+
+const char *feh_last_error(void) { return g_err.c_str(); }
+
+int feh_version(void) { return 10000; }
+
+int feh_plan_create(feh_plan **plan, int dim, const int64_t n[], const double h[], int n_load, int precision,
+                    void *hip_stream) {
+    try {
+        if (!plan) return set_error(FEH_EINVAL, "null plan pointer");
+        *plan = nullptr;
+        if (dim != 2 && dim != 3) return set_error(FEH_EINVAL, "dim must be 2 or 3");
+        if (!n) return set_error(FEH_EINVAL, "null size array");
+        if (n_load < 1 || n_load > kMaxLoad) return set_error(FEH_EINVAL, "n_load must be in [1, 64]");
+        if (precision != FEH_FP64 && precision != FEH_FP32) return set_error(FEH_EINVAL, "bad precision");
+        auto p = new feh_plan();
+        p->dim = dim;
+        p->L = n_load;
+        p->prec = precision;
+        p->rsize = precision == FEH_FP64 ? 8 : 4;
+        p->stream = static_cast<hipStream_t>(hip_stream);
+        p->N = 1;
+        for (int a = 0; a < dim; ++a) {
+            if (n[a] < 2 || n[a] > kMaxN) {
+                delete p;
+                return set_error(FEH_EINVAL, "grid sizes must lie in [2, 4096]");
+            }
+            p->n[a] = n[a];
+            p->h[a] = h ? h[a] : 1.0;
+            if (!(p->h[a] > 0.0) || !std::isfinite(p->h[a])) {
+                delete p;
+                return set_error(FEH_EINVAL, "voxel sizes must be positive and finite");
+            }
+            p->N *= n[a];
+        }
+        if (p->N > (int64_t(1) << 31)) {
+            delete p;
+            return set_error(FEH_EINVAL, "grid too large (N > 2^31)");
+        }
+        const int64_t nl = n[dim - 1];
+        p->last_even = (nl % 2) == 0;
+        p->nh = nl / 2 + 1;
+        p->Nspec = p->N / nl * p->nh;
+        p->ne = dim == 3 ? 6 : 2;
+        for (int a = 0; a < dim; ++a) {
+            int len = (int)n[a];
+            if (a == dim - 1 && p->last_even) len /= 2;
+            if (!factorize(len, p->fft[a])) {
+                delete p;
+                return set_error(FEH_ENOTSUP, "grid size has a prime factor above 13");
+            }
+        }
+        // LDS capacity of the transforms (points per workgroup)
+        const int cap = (precision == FEH_FP32 ? 24 : 16) * 256;
+        const int nc = p->fft[dim - 1].n;
+        if (nc * dim > cap || (int)n[0] * dim > cap || (dim == 3 && (int)n[1] > cap)) {
+            delete p;
+            return set_error(FEH_ENOTSUP, "axis too long for the LDS-staged transform");
+        }
+        tables(*p);
+        layout(*p);
+        *plan = p;
+        return FEH_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error(FEH_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return set_error(FEH_EINVAL, "unexpected host exception");
+    }
+}
+
+int feh_plan_destroy(feh_plan *plan) {
+    if (plan)
+        for (hipEvent_t e : plan->prof_ev) hipEventDestroy(e);
+    delete plan;
+    return FEH_OK;
+}
+
+int feh_plan_workspace_bytes(const feh_plan *plan, size_t *bytes) {
+    if (!plan || !bytes) return set_error(FEH_EINVAL, "null argument");
+    *bytes = plan->total;
+    return FEH_OK;
+}
+
+int feh_plan_set_workspace(feh_plan *plan, void *dev_ptr, size_t bytes) {
+    try {
+        if (!plan || !dev_ptr) return set_error(FEH_EINVAL, "null argument");
+        if (bytes < plan->total) return set_error(FEH_ENOMEM, "workspace too small");
+        if (reinterpret_cast<uintptr_t>(dev_ptr) % 256 != 0) return set_error(FEH_EINVAL, "workspace must be 256-byte aligned");
+        plan->ws = static_cast<char *>(dev_ptr);
+        plan->ws_bytes = bytes;
+        plan->material_set = false;
+        return upload_tables(*plan);
+    } catch (...) {
+        return set_error(FEH_EINVAL, "unexpected host exception");
+    }
+}
+
+int feh_set_material_lame(feh_plan *plan, const void *lambda_dev, const void *mu_dev) {
+    CK(check_plan(plan, false));
+    if (!lambda_dev || !mu_dev) return set_error(FEH_EINVAL, "null material pointer");
+    int *flag = plan->ptr<int>(plan->off_flag);
+    CK(hip_check(hipMemsetAsync(flag, 0, sizeof(int), plan->stream), "material"));
+    CK(launch_material_lame(*plan, lambda_dev, mu_dev, flag));
+    CK(read_flag(*plan, flag, "feh_set_material_lame"));
+    plan->material_set = true;
+    return FEH_OK;
+}
+
+int feh_set_material_phases(feh_plan *plan, const int32_t *phase_dev, const double *E_nu_host, int n_phase) {
+    CK(check_plan(plan, false));
+    if (!phase_dev || !E_nu_host) return set_error(FEH_EINVAL, "null material pointer");
+    if (n_phase < 1 || n_phase > kMaxPhase) return set_error(FEH_EINVAL, "n_phase must be in [1, 4096]");
+    std::vector<double> tab(2 * n_phase);
+    for (int k = 0; k < n_phase; ++k) {
+        const double E = E_nu_host[2 * k], nu = E_nu_host[2 * k + 1];
+        if (!std::isfinite(E) || E < 0.0 || !(nu > -1.0 && nu < 0.5))
+            return set_error(FEH_EINVAL, "phase table needs E >= 0 and -1 < nu < 0.5");
+        tab[2 * k] = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+        tab[2 * k + 1] = E / (2.0 * (1.0 + nu));
+    }
+    double *dtab = plan->ptr<double>(plan->off_tab);
+    CK(hip_check(hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, plan->stream),
+                 "phase table"));
+    int *flag = plan->ptr<int>(plan->off_flag);
+    CK(hip_check(hipMemsetAsync(flag, 0, sizeof(int), plan->stream), "material"));
+    CK(launch_material_phases(*plan, phase_dev, dtab, n_phase, flag));
+    CK(read_flag(*plan, flag, "feh_set_material_phases"));
+    plan->material_set = true;
+    return FEH_OK;
+}
+
+int feh_set_material_field(feh_plan *plan, const void *E_dev, double nu) {
+    CK(check_plan(plan, false));
+    if (!E_dev) return set_error(FEH_EINVAL, "null material pointer");
+    if (!(nu > -1.0 && nu < 0.5)) return set_error(FEH_EINVAL, "nu must lie in (-1, 0.5)");
+    int *flag = plan->ptr<int>(plan->off_flag);
+    CK(hip_check(hipMemsetAsync(flag, 0, sizeof(int), plan->stream), "material"));
+    CK(launch_material_field(*plan, E_dev, nu, flag));
+    CK(read_flag(*plan, flag, "feh_set_material_field"));
+    plan->material_set = true;
+    return FEH_OK;
+}
+
+int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter, const void *u0_dev, void *u_dev,
+              void *strain_dev, void *stress_dev, double *stress_mean_host, double *energy_host,
+              feh_report *report_host) {
+    try {
+        CK(check_plan(plan, true));
+        feh_plan &p = *plan;
+        if (!Ebar_host) return set_error(FEH_EINVAL, "null Ebar");
+        if (!(tol >= 0.0) || !std::isfinite(tol)) return set_error(FEH_EINVAL, "tol must be finite and >= 0");
+        if (max_iter < 1) return set_error(FEH_EINVAL, "max_iter must be >= 1");
+        const int D = p.dim;
+        for (int l = 0; l < p.L; ++l)
+            for (int i = 0; i < D; ++i)
+                for (int j = 0; j < D; ++j) {
+                    const double a = Ebar_host[(l * D + i) * D + j], b = Ebar_host[(l * D + j) * D + i];
+                    if (!std::isfinite(a)) return set_error(FEH_EINVAL, "Ebar must be finite");
+                    if (std::fabs(a - b) > 1e-12 * (std::fabs(a) + std::fabs(b)) + 1e-300)
+                        return set_error(FEH_EINVAL, "Ebar must be symmetric");
+                }
+        // Ebar padded to 3x3 stride per load case is not needed: the kernels read D x D
+        std::vector<double> eb(Ebar_host, Ebar_host + (size_t)p.L * D * D);
+        double *ebar_dev = p.ptr<double>(p.off_ebar);
+        CK(hip_check(hipMemcpyAsync(ebar_dev, eb.data(), eb.size() * sizeof(double), hipMemcpyHostToDevice, p.stream),
+                     "upload Ebar"));
+        LcState *st = p.ptr<LcState>(p.off_state);
+        double *part = p.ptr<double>(p.off_part);
+        const size_t nvec = (size_t)p.L * D * p.N;
+        CK(launch_init_state(p, st, p.L));
+        CK(launch_fill(p, p.ws + p.off_p0, nvec, 0.0));
+        CK(launch_fill(p, p.ws + p.off_p1, nvec, 0.0));
+        StencilArgs sa;
+        sa.Ebar = ebar_dev;
+        if (u0_dev) {
+            CK(launch_aos_to_soa(p, u0_dev, p.ws + p.off_u));
+            // the fluctuation is fixed up to a rigid translation: start from zero mean
+            CK(launch_remove_mean(p, p.ws + p.off_u, part, p.ptr<double>(p.off_sums)));
+            // reference f.M^+f from the right-hand side alone
+            sa.in0 = nullptr;
+            sa.out0 = p.ws + p.off_q;
+            CK(launch_stencil(p, ST_RESID, sa));
+            CK(precondition(p, p.ws + p.off_q, p.ws + p.off_z, part, nullptr));
+            CK(launch_finish_rho(p, st, part, first_num_parts(p), 0, tol, max_iter));
+            sa.in0 = p.ws + p.off_u;
+        } else {
+            CK(launch_fill(p, p.ws + p.off_u, nvec, 0.0));
+            sa.in0 = nullptr;
+        }
+        // r = f - K u0
+        sa.out0 = p.ws + p.off_r;
+        CK(launch_stencil(p, ST_RESID, sa));
+        CK(precondition(p, p.ws + p.off_r, p.ws + p.off_z, part, nullptr));
+        CK(launch_finish_rho(p, st, part, first_num_parts(p), u0_dev ? 1 : 11, tol, max_iter));
+
+        std::vector<LcState> hs(p.L);
+        int done = 0, chunk = 4;
+        while (done < max_iter) {
+            CK(hip_check(hipMemcpyAsync(hs.data(), st, p.L * sizeof(LcState), hipMemcpyDeviceToHost, p.stream),
+                         "read CG state"));
+            CK(hip_check(hipStreamSynchronize(p.stream), "CG"));
+            prof_drain(p);
+            bool any = false;
+            for (int l = 0; l < p.L; ++l) any = any || hs[l].active;
+            if (!any) break;
+            const int c = chunk < max_iter - done ? chunk : max_iter - done;
+            for (int i = 0; i < c; ++i) CK(cg_iteration(p, st, tol, max_iter));
+            done += c;
+            if (chunk < 16) chunk *= 2;
+        }
+        CK(launch_finalize_u(p, p.ws + p.off_u, p.ws + p.off_p0, p.ws + p.off_p1, st));
+        double *sums = p.ptr<double>(p.off_sums);
+        CK(launch_post_sums(p, p.ws + p.off_u, ebar_dev, strain_dev, stress_dev, part, sums));
+        if (u_dev) CK(launch_soa_to_aos(p, p.ws + p.off_u, u_dev));
+        const int ns = D == 3 ? 6 : 3;
+        std::vector<double> hsum(post_num_slots(p));
+        CK(hip_check(hipMemcpyAsync(hsum.data(), sums, hsum.size() * sizeof(double), hipMemcpyDeviceToHost, p.stream),
+                     "read sums"));
+        CK(hip_check(hipMemcpyAsync(hs.data(), st, p.L * sizeof(LcState), hipMemcpyDeviceToHost, p.stream),
+                     "read CG state"));
+        CK(hip_check(hipStreamSynchronize(p.stream), "solve"));
+        if (stress_mean_host) {
+            for (int l = 0; l < p.L; ++l) {
+                const double *s = hsum.data() + l * ns;
+                double *o = stress_mean_host + (size_t)l * D * D;
+                if (D == 3) {
+                    const double full[9] = {s[0], s[5], s[4], s[5], s[1], s[3], s[4], s[3], s[2]};
+                    std::memcpy(o, full, sizeof(full));
+                } else {
+                    const double full[4] = {s[0], s[2], s[2], s[1]};
+                    std::memcpy(o, full, sizeof(full));
+                }
+            }
+        }
+        if (energy_host) {
+            int k = 0;
+            for (int l = 0; l < p.L; ++l)
+                for (int m = l; m < p.L; ++m, ++k) {
+                    const double w = hsum[(size_t)p.L * ns + k];
+                    energy_host[l * p.L + m] = w;
+                    energy_host[m * p.L + l] = w;
+                }
+        }
+        int rc = FEH_OK;
+        for (int l = 0; l < p.L; ++l) {
+            if (report_host) {
+                report_host[l].iterations = hs[l].iters;
+                report_host[l].status = hs[l].status;
+                report_host[l].rel_residual = hs[l].relres;
+            }
+            if (hs[l].status == FEH_EBREAKDOWN) rc = FEH_EBREAKDOWN;
+            else if ((hs[l].status == FEH_ENOCONV || hs[l].active) && rc == FEH_OK) rc = FEH_ENOCONV;
+        }
+        if (rc == FEH_ENOCONV) return set_error(rc, "max_iter reached before the tolerance");
+        if (rc == FEH_EBREAKDOWN) return set_error(rc, "CG breakdown (p.q <= 0 or not finite)");
+        return FEH_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error(FEH_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return set_error(FEH_EINVAL, "unexpected host exception");
+    }
+}
+
+int feh_effective_stiffness(int dim, int n_load, const double *Ebar_host, const double *energy_host, double *C_host) {
+    if (dim != 2 && dim != 3) return set_error(FEH_EINVAL, "dim must be 2 or 3");
+    const int nv = dim == 3 ? 6 : 3;
+    if (n_load != nv) return set_error(FEH_EINVAL, "need exactly nv load cases");
+    if (!Ebar_host || !energy_host || !C_host) return set_error(FEH_EINVAL, "null argument");
+    static const int P2[3][2] = {{0, 0}, {1, 1}, {0, 1}};
+    static const int P3[6][2] = {{0, 0}, {1, 1}, {2, 2}, {1, 2}, {0, 2}, {0, 1}};
+    std::vector<double> E(nv * nv);  // E[v][l]: engineering Voigt strain of load l
+    for (int l = 0; l < nv; ++l)
+        for (int v = 0; v < nv; ++v) {
+            const int a = dim == 3 ? P3[v][0] : P2[v][0], b = dim == 3 ? P3[v][1] : P2[v][1];
+            E[v * nv + l] = Ebar_host[(l * dim + a) * dim + b] * (a == b ? 1.0 : 2.0);
+        }
+    bool ok = false;
+    invert(nv, E, ok);
+    if (!ok) return set_error(FEH_EINVAL, "load-case strains are linearly dependent");
+    // C = Einv^T W Einv
+    std::vector<double> T(nv * nv, 0.0);
+    for (int i = 0; i < nv; ++i)
+        for (int j = 0; j < nv; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < nv; ++k) s += energy_host[i * nv + k] * E[k * nv + j];
+            T[i * nv + j] = s;
+        }
+    for (int i = 0; i < nv; ++i)
+        for (int j = 0; j < nv; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < nv; ++k) s += E[k * nv + i] * T[k * nv + j];
+            C_host[i * nv + j] = s;
+        }
+    return FEH_OK;
+}
+
+int feh_profile_enable(feh_plan *plan, int enable) {
+    if (!plan) return set_error(FEH_EINVAL, "null plan");
+    plan->prof_on = enable != 0;
+    plan->prof_used = 0;
+    for (int k = 0; k < feh_plan::kProfKinds; ++k) {
+        plan->prof_ms[k] = 0.0;
+        plan->prof_n[k] = 0;
+    }
+    return FEH_OK;
+}
+
+int feh_profile_read(const feh_plan *plan, double *ms_total, int64_t *launches, int n_kinds) {
+    if (!plan || !ms_total || !launches) return set_error(FEH_EINVAL, "null argument");
+    for (int k = 0; k < n_kinds; ++k) {
+        ms_total[k] = k < feh_plan::kProfKinds ? plan->prof_ms[k] : 0.0;
+        launches[k] = k < feh_plan::kProfKinds ? plan->prof_n[k] : 0;
+    }
+    return FEH_OK;
+}
+
+int feh_apply_operator(feh_plan *plan, const void *p_dev, void *q_dev) {
+    CK(check_plan(plan, true));
+    if (!p_dev || !q_dev) return set_error(FEH_EINVAL, "null argument");
+    feh_plan &p = *plan;
+    CK(launch_aos_to_soa(p, p_dev, p.ws + p.off_p0));
+    StencilArgs sa;
+    sa.in0 = p.ws + p.off_p0;
+    sa.out0 = p.ws + p.off_q;
+    CK(launch_stencil(p, ST_APPLY, sa));
+    CK(launch_soa_to_aos(p, p.ws + p.off_q, q_dev));
+    return hip_check(hipStreamSynchronize(p.stream), "apply operator");
+}
+
+int feh_apply_preconditioner(feh_plan *plan, const void *r_dev, void *z_dev) {
+    CK(check_plan(plan, false));
+    if (!r_dev || !z_dev) return set_error(FEH_EINVAL, "null argument");
+    feh_plan &p = *plan;
+    CK(launch_aos_to_soa(p, r_dev, p.ws + p.off_r));
+    CK(precondition(p, p.ws + p.off_r, p.ws + p.off_z, nullptr, nullptr));
+    CK(launch_soa_to_aos(p, p.ws + p.off_z, z_dev));
+    return hip_check(hipStreamSynchronize(p.stream), "apply preconditioner");
+}
+
+int feh_apply_projection(feh_plan *plan, const void *e_dev, void *Ge_dev) {
+    CK(check_plan(plan, false));
+    if (!e_dev || !Ge_dev) return set_error(FEH_EINVAL, "null argument");
+    feh_plan &p = *plan;
+    StencilArgs sa;
+    sa.in0 = e_dev;
+    sa.out0 = p.ws + p.off_q;
+    sa.identity_material = true;
+    CK(launch_stencil(p, ST_DIV, sa));
+    CK(precondition(p, p.ws + p.off_q, p.ws + p.off_z, nullptr, nullptr));
+    CK(launch_grad(p, p.ws + p.off_z, Ge_dev));
+    return hip_check(hipStreamSynchronize(p.stream), "apply projection");
+}
+
+int feh_fft_forward(feh_plan *plan, const void *x_dev, void *X_dev) {
+    CK(check_plan(plan, false));
+    if (!x_dev || !X_dev) return set_error(FEH_EINVAL, "null argument");
+    feh_plan &p = *plan;
+    FftArgs fa;
+    fa.r = x_dev;
+    fa.spec = p.ws + p.off_spec;
+    CK(launch_forward_last(p, fa));
+    if (p.dim == 3) CK(launch_middle(p, fa, false));
+    CK(launch_first(p, fa, false));
+    CK(launch_spec_to_numpy(p, p.ws + p.off_spec, X_dev, true));
+    return hip_check(hipStreamSynchronize(p.stream), "fft forward");
+}
+
+int feh_fft_inverse(feh_plan *plan, const void *X_dev, void *x_dev) {
+    CK(check_plan(plan, false));
+    if (!x_dev || !X_dev) return set_error(FEH_EINVAL, "null argument");
+    feh_plan &p = *plan;
+    FftArgs fa;
+    fa.spec = p.ws + p.off_spec;
+    fa.z = x_dev;
+    fa.out_scale = 1.0 / (double)p.N;
+    CK(launch_spec_to_numpy(p, X_dev, p.ws + p.off_spec, false));
+    CK(launch_first(p, fa, true));
+    if (p.dim == 3) CK(launch_middle(p, fa, true));
+    CK(launch_inverse_last(p, fa));
+    return hip_check(hipStreamSynchronize(p.stream), "fft inverse");
+}
+
+}  // extern "C"

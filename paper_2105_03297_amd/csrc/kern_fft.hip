@@ -1,0 +1,741 @@
+// Batched Stockham FFTs staged through LDS, and the per-wavevector
+// projection core (B^*B)^-1 fused into the first-axis pass.
+//
+// The transform pair follows the discrete Fourier transform appendix of the
+// paper: forward sum_r f(r) exp(-i k.r) (unnormalised), inverse with 1/N.
+// Real fields are transformed along the last (contiguous) axis to the half
+// spectrum n_last/2 + 1 (two real samples packed into one complex point and
+// untangled with a post-twiddle when n_last is even), then complex-to-complex
+// along the other axes.  The spectrum of load case l is stored as
+// [n0][(n1)][nh][D], components innermost, so the first-axis pass can read
+// all D components of a wavevector in one coalesced segment.
+//
+// Stockham autosort (each pass reads the previous pass's output layout and
+// writes the next, natural order at the end, no bit reversal): pass with
+// radix R after earlier radices of product L*, L = L* R, m = n / L:
+//   y[q + m (p + L* d)] = sum_c exp(-2 pi i c d / R) w_n^{c p m} x[q + c m + m R p]
+// for q < m, p < L*, d < R.
+#include "device_common.hpp"
+
+namespace feh {
+namespace {
+
+constexpr int kFftThreads = 256;
+
+template <typename T>
+__device__ __forceinline__ Cx<T> mul_mi(Cx<T> a) { return {a.y, -a.x}; }  // a * (-i)
+template <typename T>
+__device__ __forceinline__ Cx<T> mul_pi(Cx<T> a) { return {-a.y, a.x}; }  // a * (+i)
+template <typename T>
+__device__ __forceinline__ Cx<T> cscale(Cx<T> a, T s) { return {a.x * s, a.y * s}; }
+
+template <typename T>
+__device__ __forceinline__ Cx<T> twid(const Cx<T> *tw, int tws, int e, bool inv) {
+    Cx<T> w = tw[e * tws];
+    if (inv) w.y = -w.y;
+    return w;
+}
+
+// In-place DFT of length R on registers: x[d] <- sum_c x[c] exp(-+2 pi i c d / R).
+template <typename T, int R>
+struct Dft {
+    // generic radix (7, 11, 13): roots from the table of the full length n
+    static __device__ __forceinline__ void run(Cx<T> (&x)[R], bool inv, const Cx<T> *tw, int tws, int n) {
+        Cx<T> y[R];
+        const int step = n / R;
+        #pragma unroll
+        for (int d = 0; d < R; ++d) {
+            Cx<T> s = x[0];
+            #pragma unroll
+            for (int c = 1; c < R; ++c) s = cadd(s, cmul(x[c], twid(tw, tws, ((c * d) % R) * step, inv)));
+            y[d] = s;
+        }
+        #pragma unroll
+        for (int d = 0; d < R; ++d) x[d] = y[d];
+    }
+};
+
+template <typename T>
+struct Dft<T, 2> {
+    static __device__ __forceinline__ void run(Cx<T> (&x)[2], bool, const Cx<T> *, int, int) {
+        const Cx<T> a = x[0];
+        x[0] = cadd(a, x[1]);
+        x[1] = csub(a, x[1]);
+    }
+};
+
+template <typename T>
+struct Dft<T, 3> {
+    static __device__ __forceinline__ void run(Cx<T> (&x)[3], bool inv, const Cx<T> *, int, int) {
+        const T s3 = T(0.86602540378443864676);
+        const Cx<T> t1 = cadd(x[1], x[2]), t2 = csub(x[1], x[2]);
+        const Cx<T> a = {x[0].x - T(0.5) * t1.x, x[0].y - T(0.5) * t1.y};
+        const Cx<T> b = cscale(t2, s3);
+        x[0] = cadd(x[0], t1);
+        if (!inv) {
+            x[1] = cadd(a, mul_mi(b));
+            x[2] = cadd(a, mul_pi(b));
+        } else {
+            x[1] = cadd(a, mul_pi(b));
+            x[2] = cadd(a, mul_mi(b));
+        }
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ void dft4(Cx<T> &x0, Cx<T> &x1, Cx<T> &x2, Cx<T> &x3, bool inv) {
+    const Cx<T> a = cadd(x0, x2), b = csub(x0, x2), c = cadd(x1, x3), d = csub(x1, x3);
+    x0 = cadd(a, c);
+    x2 = csub(a, c);
+    if (!inv) {
+        x1 = cadd(b, mul_mi(d));
+        x3 = cadd(b, mul_pi(d));
+    } else {
+        x1 = cadd(b, mul_pi(d));
+        x3 = cadd(b, mul_mi(d));
+    }
+}
+
+template <typename T>
+struct Dft<T, 4> {
+    static __device__ __forceinline__ void run(Cx<T> (&x)[4], bool inv, const Cx<T> *, int, int) {
+        dft4(x[0], x[1], x[2], x[3], inv);
+    }
+};
+
+template <typename T>
+struct Dft<T, 5> {
+    static __device__ __forceinline__ void run(Cx<T> (&x)[5], bool inv, const Cx<T> *, int, int) {
+        const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);
+        const T s1 = T(0.95105651629515357212), s2 = T(0.58778525229247312917);
+        const Cx<T> t1 = cadd(x[1], x[4]), t2 = cadd(x[2], x[3]);
+        const Cx<T> t3 = csub(x[1], x[4]), t4 = csub(x[2], x[3]);
+        const Cx<T> a1 = {x[0].x + c1 * t1.x + c2 * t2.x, x[0].y + c1 * t1.y + c2 * t2.y};
+        const Cx<T> a2 = {x[0].x + c2 * t1.x + c1 * t2.x, x[0].y + c2 * t1.y + c1 * t2.y};
+        const Cx<T> b1 = {s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y};
+        const Cx<T> b2 = {s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y};
+        x[0] = cadd(x[0], cadd(t1, t2));
+        if (!inv) {
+            x[1] = cadd(a1, mul_mi(b1));
+            x[4] = cadd(a1, mul_pi(b1));
+            x[2] = cadd(a2, mul_mi(b2));
+            x[3] = cadd(a2, mul_pi(b2));
+        } else {
+            x[1] = cadd(a1, mul_pi(b1));
+            x[4] = cadd(a1, mul_mi(b1));
+            x[2] = cadd(a2, mul_pi(b2));
+            x[3] = cadd(a2, mul_mi(b2));
+        }
+    }
+};
+
+template <typename T>
+struct Dft<T, 8> {
+    static __device__ __forceinline__ void run(Cx<T> (&x)[8], bool inv, const Cx<T> *, int, int) {
+        const T h = T(0.70710678118654752440);
+        Cx<T> e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+        Cx<T> o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+        dft4(e0, e1, e2, e3, inv);
+        dft4(o0, o1, o2, o3, inv);
+        // o_d *= W8^d, W8 = exp(-+ i pi / 4)
+        if (!inv) {
+            o1 = {h * (o1.x + o1.y), h * (o1.y - o1.x)};
+            o2 = mul_mi(o2);
+            o3 = {h * (o3.y - o3.x), -h * (o3.x + o3.y)};
+        } else {
+            o1 = {h * (o1.x - o1.y), h * (o1.x + o1.y)};
+            o2 = mul_pi(o2);
+            o3 = {-h * (o3.x + o3.y), h * (o3.x - o3.y)};
+        }
+        x[0] = cadd(e0, o0);
+        x[4] = csub(e0, o0);
+        x[1] = cadd(e1, o1);
+        x[5] = csub(e1, o1);
+        x[2] = cadd(e2, o2);
+        x[6] = csub(e2, o2);
+        x[3] = cadd(e3, o3);
+        x[7] = csub(e3, o3);
+    }
+};
+
+// One Stockham pass over nb batches stored interleaved: element j of batch b
+// at buf[j * nb + b].  Threads take butterflies batch-fastest so that a
+// wavefront reads and writes consecutive LDS words.
+template <typename T, int R, int PPT>
+__device__ __forceinline__ void stockham_pass(Cx<T> *buf, int nb, const FastDiv &nbd, int n,
+                                              const PassInfo &ps, const Cx<T> *tw, int tws, bool inv) {
+    constexpr int NT = kFftThreads;
+    constexpr int K = (PPT + R - 1) / R;
+    const int nbf = nb * (n / R);
+    const int m = (int)ps.m.d;
+    const int ostride = m * ps.Lstar * nb;
+    Cx<T> y[K][R];
+    int obase[K];
+    #pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int t = threadIdx.x + k * NT;
+        obase[k] = -1;
+        if (t < nbf) {
+            const int w = (int)nbd.div((uint32_t)t);
+            const int b = t - w * nb;
+            const int p = (int)ps.m.div((uint32_t)w);
+            const int q = w - p * m;
+            Cx<T> x[R];
+            const int ib = (q + m * R * p) * nb + b;
+            #pragma unroll
+            for (int c = 0; c < R; ++c) x[c] = buf[ib + c * m * nb];
+            if (p != 0) {
+                #pragma unroll
+                for (int c = 1; c < R; ++c) x[c] = cmul(x[c], twid(tw, tws, c * p * m, inv));
+            }
+            Dft<T, R>::run(x, inv, tw, tws, n);
+            #pragma unroll
+            for (int d = 0; d < R; ++d) y[k][d] = x[d];
+            obase[k] = (q + m * p) * nb + b;
+        }
+    }
+    __syncthreads();
+    #pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (obase[k] >= 0) {
+            #pragma unroll
+            for (int d = 0; d < R; ++d) buf[obase[k] + d * ostride] = y[k][d];
+        }
+    }
+    __syncthreads();
+}
+
+// GEN = false instantiates only the radices of power-of-two lengths (2, 4, 8),
+// which keeps the register footprint of the common case small.
+template <typename T, int PPT, bool GEN>
+__device__ void lds_fft(Cx<T> *buf, int nb, const FastDiv &nbd, const AxisFFT &ax, const Cx<T> *tw, int tws,
+                        bool inv) {
+    for (int s = 0; s < ax.npass; ++s) {
+        const PassInfo &ps = ax.pass[s];
+        switch (ps.R) {
+        case 2: stockham_pass<T, 2, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv); break;
+        case 4: stockham_pass<T, 4, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv); break;
+        case 8: stockham_pass<T, 8, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv); break;
+        default:
+            if constexpr (GEN) {
+                switch (ps.R) {
+                case 3: stockham_pass<T, 3, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv); break;
+                case 5: stockham_pass<T, 5, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv); break;
+                case 7: stockham_pass<T, 7, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv); break;
+                case 11: stockham_pass<T, 11, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv); break;
+                case 13: stockham_pass<T, 13, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv); break;
+                default: break;
+                }
+            }
+            break;
+        }
+    }
+}
+
+template <typename T>
+struct FK {
+    const T *r;
+    const T *q;
+    T *r_out;
+    Cx<T> *spec;
+    T *z;
+    double *partial;
+    const LcState *st;
+    const Cx<T> *tw;          // twiddles of the transformed axis (full length)
+    int tws;                  // table stride (2 for the packed last axis)
+    const Cx<T> *tw_last;     // last-axis table (post-twiddle of the packed transform)
+    const double *om[3];      // e^{2 pi i m / n_a}, interleaved complex
+    const double *aa[3];      // (e^{2 pi i m / n_a} - 1) / h_a
+    AxisFFT ax;
+    FastDiv nbd;              // batches per block
+    FastDiv d_nc;             // packed length / FFT length
+    FastDiv d_D;              // components
+    FastDiv d_nhD;            // nh * D
+    FastDiv d_PB;             // pencils per block
+    FastDiv d_nh;
+    int dim, D, L;
+    int n0, n1, nlast, nh;
+    long long N, rows, inner_total;
+    int RR, PB, nblk, total;
+    int part_stride;
+    int last_even;
+    int use_axpy;
+    double out_scale, invN, chalf;  // chalf = element volume / 2
+};
+
+// ---------------------------------------------------------------------------
+// last axis, real -> half spectrum (optionally fused r -= alpha q)
+// ---------------------------------------------------------------------------
+template <typename T, int PPT, bool GEN>
+__global__ __launch_bounds__(kFftThreads) void k_last_fwd(FK<T> a) {
+    constexpr int NT = kFftThreads;
+    __shared__ Cx<T> buf[PPT * NT];
+    int t = xcd_remap(blockIdx.x, a.total);
+    const int lc = t / a.nblk;
+    const int blk = t - lc * a.nblk;
+    T alpha = T(0);
+    if (a.st) {
+        if (!a.st[lc].active) return;
+        if (a.use_axpy) alpha = T(a.st[lc].alpha);
+    }
+    const int D = a.D;
+    const int nb = D * a.RR;
+    const long long s0 = (long long)blk * a.RR;
+    const int nrows = (int)min((long long)a.RR, a.rows - s0);
+    const int nc = a.ax.n;
+    const long long N = a.N;
+    for (int e = threadIdx.x; e < nb * nc; e += NT) {
+        const int b = (int)a.d_nc.div((uint32_t)e);
+        const int j = e - b * nc;
+        const int sl = (int)a.d_D.div((uint32_t)b);
+        const int c = b - sl * D;
+        Cx<T> v = {T(0), T(0)};
+        if (sl < nrows) {
+            const long long base = ((long long)lc * D + c) * N + (s0 + sl) * a.nlast;
+            if (a.last_even) {
+                Cx<T> x = reinterpret_cast<const Cx<T> *>(a.r + base)[j];
+                if (a.use_axpy) {
+                    const Cx<T> qv = reinterpret_cast<const Cx<T> *>(a.q + base)[j];
+                    x.x -= alpha * qv.x;
+                    x.y -= alpha * qv.y;
+                    reinterpret_cast<Cx<T> *>(a.r_out + base)[j] = x;
+                }
+                v = x;
+            } else {
+                T x = a.r[base + j];
+                if (a.use_axpy) {
+                    x -= alpha * a.q[base + j];
+                    a.r_out[base + j] = x;
+                }
+                v.x = x;
+            }
+        }
+        buf[j * nb + b] = v;
+    }
+    __syncthreads();
+    lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, a.tw, a.tws, false);
+    const int nh = a.nh;
+    for (int e = threadIdx.x; e < nrows * nh * D; e += NT) {
+        const int kk = (int)a.d_D.div((uint32_t)e);
+        const int c = e - kk * D;
+        const int sl = (int)a.d_nh.div((uint32_t)kk);
+        const int k = kk - sl * nh;
+        const int b = sl * D + c;
+        Cx<T> X;
+        if (a.last_even) {
+            const int ka = (k == nc) ? 0 : k;
+            const int kb = (k == 0) ? 0 : nc - k;
+            const Cx<T> Zk = buf[ka * nb + b], Zm = cconj(buf[kb * nb + b]);
+            const Cx<T> A = {T(0.5) * (Zk.x + Zm.x), T(0.5) * (Zk.y + Zm.y)};
+            const Cx<T> dZ = csub(Zk, Zm);
+            const Cx<T> B = {T(0.5) * dZ.y, -T(0.5) * dZ.x};  // -i/2 (Zk - conj Z(nc-k))
+            X = cadd(A, cmul(a.tw_last[k], B));
+        } else {
+            X = buf[k * nb + b];
+        }
+        a.spec[((long long)lc * a.rows + s0 + sl) * (long long)nh * D + (long long)k * D + c] = X;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// last axis, half spectrum -> real (times out_scale)
+// ---------------------------------------------------------------------------
+template <typename T, int PPT, bool GEN>
+__global__ __launch_bounds__(kFftThreads) void k_last_inv(FK<T> a) {
+    constexpr int NT = kFftThreads;
+    __shared__ Cx<T> buf[PPT * NT];
+    int t = xcd_remap(blockIdx.x, a.total);
+    const int lc = t / a.nblk;
+    const int blk = t - lc * a.nblk;
+    if (a.st && !a.st[lc].active) return;
+    const int D = a.D;
+    const int nb = D * a.RR;
+    const long long s0 = (long long)blk * a.RR;
+    const int nrows = (int)min((long long)a.RR, a.rows - s0);
+    const int nc = a.ax.n;
+    const int nh = a.nh;
+    const long long N = a.N;
+    // gather: e -> (sl, k, c), components fastest (coalesced spectrum reads)
+    for (int e = threadIdx.x; e < nb * nc; e += NT) {
+        const int kk = (int)a.d_D.div((uint32_t)e);
+        const int c = e - kk * D;
+        const int sl = (int)a.d_nc.div((uint32_t)kk);
+        const int k = kk - sl * nc;
+        const int b = sl * D + c;
+        Cx<T> Z = {T(0), T(0)};
+        if (sl < nrows) {
+            const Cx<T> *row = a.spec + ((long long)lc * a.rows + s0 + sl) * (long long)nh * D + c;
+            if (a.last_even) {
+                const Cx<T> Xk = row[(long long)k * D];
+                const Cx<T> Xm = cconj(row[(long long)(nc - k) * D]);
+                const Cx<T> A = cadd(Xk, Xm);
+                const Cx<T> B = cmulc(csub(Xk, Xm), a.tw_last[k]);  // exp(+2 pi i k / n) (Xk - conj X(nc-k))
+                Z = cadd(A, mul_pi(B));
+            } else {
+                Z = (k < nh) ? row[(long long)k * D] : cconj(row[(long long)(a.nlast - k) * D]);
+            }
+        }
+        buf[k * nb + b] = Z;
+    }
+    __syncthreads();
+    lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, a.tw, a.tws, true);
+    const T sc = T(a.out_scale);
+    for (int e = threadIdx.x; e < nb * nc; e += NT) {
+        const int b = (int)a.d_nc.div((uint32_t)e);
+        const int j = e - b * nc;
+        const int sl = (int)a.d_D.div((uint32_t)b);
+        const int c = b - sl * D;
+        if (sl < nrows) {
+            const long long base = ((long long)lc * D + c) * N + (s0 + sl) * a.nlast;
+            const Cx<T> v = buf[j * nb + b];
+            if (a.last_even) {
+                reinterpret_cast<Cx<T> *>(a.z + base)[j] = Cx<T>{v.x * sc, v.y * sc};
+            } else {
+                a.z[base + j] = v.x * sc;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// middle axis (3D), complex to complex
+// ---------------------------------------------------------------------------
+template <typename T, int PPT, bool GEN>
+__global__ __launch_bounds__(kFftThreads) void k_middle(FK<T> a, int inv) {
+    constexpr int NT = kFftThreads;
+    __shared__ Cx<T> buf[PPT * NT];
+    int t = xcd_remap(blockIdx.x, a.total);
+    const int ib = t % a.nblk;
+    t /= a.nblk;
+    const int i0 = t % a.n0;
+    const int lc = t / a.n0;
+    if (a.st && !a.st[lc].active) return;
+    const int PB = a.PB;
+    const int n1 = a.n1;
+    const long long inner = a.inner_total;
+    const long long in0 = (long long)ib * PB;
+    Cx<T> *base = a.spec + ((long long)lc * a.n0 + i0) * n1 * inner + in0;
+    const int lim = (int)min((long long)PB, inner - in0);
+    for (int e = threadIdx.x; e < PB * n1; e += NT) {
+        const int j = (int)a.d_PB.div((uint32_t)e);
+        const int b = e - j * PB;
+        buf[e] = (b < lim) ? base[(long long)j * inner + b] : Cx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    lds_fft<T, PPT, GEN>(buf, PB, a.d_PB, a.ax, a.tw, 1, inv != 0);
+    for (int e = threadIdx.x; e < PB * n1; e += NT) {
+        const int j = (int)a.d_PB.div((uint32_t)e);
+        const int b = e - j * PB;
+        if (b < lim) base[(long long)j * inner + b] = buf[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// first axis: forward, per-wavevector (B^*B)^-1 solve with Parseval r.z,
+// inverse (mode 0); forward only (mode 1); inverse only (mode 2)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ Cx<double> ld2(const double *p, int i) { return Cx<double>{p[2 * i], p[2 * i + 1]}; }
+__device__ __forceinline__ double nrm(Cx<double> a) { return a.x * a.x + a.y * a.y; }
+
+// Solve M z = r for Hermitian positive definite M (upper triangle given).
+template <int D>
+__device__ __forceinline__ void herm_solve(const double (&Md)[D], const Cx<double> (&Mo)[3], Cx<double> (&r)[D]) {
+    if constexpr (D == 2) {
+        // M = [[d0, o01], [conj o01, d1]]
+        const double det = Md[0] * Md[1] - nrm(Mo[0]);
+        const double id = 1.0 / det;
+        const Cx<double> r0 = r[0], r1 = r[1];
+        const Cx<double> t0 = csub(cscale(r0, Md[1]), cmul(Mo[0], r1));
+        const Cx<double> t1 = csub(cscale(r1, Md[0]), cmul(cconj(Mo[0]), r0));
+        r[0] = cscale(t0, id);
+        r[1] = cscale(t1, id);
+    } else {
+        // Cholesky M = L L^H; Mo = (M01, M02, M12)
+        const double l00 = sqrt(Md[0]);
+        const double i00 = 1.0 / l00;
+        const Cx<double> l10 = cscale(cconj(Mo[0]), i00);  // M10 / l00
+        const Cx<double> l20 = cscale(cconj(Mo[1]), i00);  // M20 / l00
+        const double l11 = sqrt(Md[1] - nrm(l10));
+        const double i11 = 1.0 / l11;
+        const Cx<double> l21 = cscale(csub(cconj(Mo[2]), cmulc(l20, l10)), i11);  // (M21 - l20 conj(l10)) / l11
+        const double l22 = sqrt(Md[2] - nrm(l20) - nrm(l21));
+        const double i22 = 1.0 / l22;
+        const Cx<double> y0 = cscale(r[0], i00);
+        const Cx<double> y1 = cscale(csub(r[1], cmul(l10, y0)), i11);
+        const Cx<double> y2 = cscale(csub(csub(r[2], cmul(l20, y0)), cmul(l21, y1)), i22);
+        const Cx<double> z2 = cscale(y2, i22);
+        const Cx<double> z1 = cscale(csub(y1, cmul(cconj(l21), z2)), i11);
+        const Cx<double> z0 = cscale(csub(csub(y0, cmul(cconj(l10), z1)), cmul(cconj(l20), z2)), i00);
+        r[0] = z0;
+        r[1] = z1;
+        r[2] = z2;
+    }
+}
+
+template <typename T, int PPT, int DIM, int MODE, bool GEN>
+__global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
+    constexpr int NT = kFftThreads;
+    constexpr int D = DIM;
+    __shared__ Cx<T> buf[PPT * NT];
+    __shared__ double red[NT / 64];
+    int t = xcd_remap(blockIdx.x, a.total);
+    const int lc = t / a.nblk;
+    const int blk = t - lc * a.nblk;
+    if (a.st && !a.st[lc].active) return;
+    const int PB = a.PB;
+    const int nb = PB * D;
+    const int n0 = a.n0;
+    const long long inner = a.inner_total;
+    const long long in0 = (long long)blk * PB;
+    const int lim = (int)min((long long)PB, inner - in0) * D;
+    Cx<T> *base = a.spec + ((long long)lc * n0 * inner + in0) * D;
+    for (int e = threadIdx.x; e < nb * n0; e += NT) {
+        const int j = (int)a.nbd.div((uint32_t)e);
+        const int bc = e - j * nb;
+        buf[e] = (bc < lim) ? base[(long long)j * inner * D + bc] : Cx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    if (MODE != 2) lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, a.tw, 1, false);
+    double acc = 0.0;
+    if (MODE == 0) {
+        const double ch = a.chalf;
+        for (int e = threadIdx.x; e < PB * n0; e += NT) {
+            const int j = (int)a.d_PB.div((uint32_t)e);
+            const int b = e - j * PB;
+            const long long inn = in0 + b;
+            if (b * D >= lim) continue;
+            int m1 = 0, kh;
+            if (DIM == 3) {
+                m1 = (int)a.d_nh.div((uint32_t)inn);
+                kh = (int)(inn - (long long)m1 * a.nh);
+            } else {
+                kh = (int)inn;
+            }
+            Cx<T> *pt = buf + j * nb + b * D;
+            Cx<double> r[D];
+            #pragma unroll
+            for (int c = 0; c < D; ++c) r[c] = Cx<double>{double(pt[c].x), double(pt[c].y)};
+            Cx<double> zz[D];
+            if (j == 0 && inn == 0) {
+                #pragma unroll
+                for (int c = 0; c < D; ++c) zz[c] = Cx<double>{0.0, 0.0};
+            } else {
+                double Md[D];
+                Cx<double> Mo[3];
+                #pragma unroll
+                for (int c = 0; c < D; ++c) zz[c] = r[c];
+                if (DIM == 3) {
+                    const Cx<double> a0 = ld2(a.aa[0], j), a1 = ld2(a.aa[1], m1), a2 = ld2(a.aa[2], kh);
+                    const Cx<double> w0 = ld2(a.om[0], j), w1 = ld2(a.om[1], m1), w2 = ld2(a.om[2], kh);
+                    const double n0s = nrm(a0), n1s = nrm(a1), n2s = nrm(a2);
+                    const double S = 6.0 * (n0s + n1s + n2s);
+                    Md[0] = ch * (S + 6.0 * n0s);
+                    Md[1] = ch * (S + 6.0 * n1s);
+                    Md[2] = ch * (S + 6.0 * n2s);
+                    const Cx<double> two = {2.0, 0.0};
+                    // M_ab = ch a_a conj(a_b) [conj(w_a)(2 + conj(w_c)) + w_b (2 + w_c)]
+                    Mo[0] = cscale(cmul(cmulc(a0, a1), cadd(cmulc(cadd(two, cconj(w2)), w0), cmul(w1, cadd(two, w2)))), ch);
+                    Mo[1] = cscale(cmul(cmulc(a0, a2), cadd(cmulc(cadd(two, cconj(w1)), w0), cmul(w2, cadd(two, w1)))), ch);
+                    Mo[2] = cscale(cmul(cmulc(a1, a2), cadd(cmulc(cadd(two, cconj(w0)), w1), cmul(w2, cadd(two, w0)))), ch);
+                } else {
+                    const Cx<double> a0 = ld2(a.aa[0], j), a1 = ld2(a.aa[1], kh);
+                    const Cx<double> w0 = ld2(a.om[0], j), w1 = ld2(a.om[1], kh);
+                    const double n0s = nrm(a0), n1s = nrm(a1);
+                    const double S = 2.0 * (n0s + n1s);
+                    Md[0] = ch * (S + 2.0 * n0s);
+                    Md[1] = ch * (S + 2.0 * n1s);
+                    // M_01 = ch a0 conj(a1) (1 + w1 conj(w0))
+                    const Cx<double> f = {1.0 + (w1.x * w0.x + w1.y * w0.y), w1.y * w0.x - w1.x * w0.y};
+                    Mo[0] = cscale(cmul(cmulc(a0, a1), f), ch);
+                    Mo[1] = Mo[2] = Cx<double>{0.0, 0.0};
+                }
+                herm_solve<D>(Md, Mo, zz);
+            }
+            const double wk = (kh == 0 || (a.last_even && kh == a.nh - 1)) ? 1.0 : 2.0;
+            double dot = 0.0;
+            #pragma unroll
+            for (int c = 0; c < D; ++c) {
+                dot += r[c].x * zz[c].x + r[c].y * zz[c].y;
+                pt[c] = Cx<T>{T(zz[c].x), T(zz[c].y)};
+            }
+            acc += wk * dot;
+        }
+        __syncthreads();
+    }
+    if (MODE != 1) lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, a.tw, 1, true);
+    for (int e = threadIdx.x; e < nb * n0; e += NT) {
+        const int j = (int)a.nbd.div((uint32_t)e);
+        const int bc = e - j * nb;
+        if (bc < lim) base[(long long)j * inner * D + bc] = buf[e];
+    }
+    if (MODE == 0 && a.partial) {
+        const double s = block_sum<NT>(acc, red);
+        if (threadIdx.x == 0) a.partial[(long long)lc * a.part_stride + blk] = s * a.invN;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+bool pow2_len(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+template <typename T>
+FK<T> base_args(const feh_plan &p, const FftArgs &fa) {
+    FK<T> a{};
+    a.r = static_cast<const T *>(fa.r);
+    a.q = static_cast<const T *>(fa.q);
+    a.r_out = static_cast<T *>(fa.r_out);
+    a.spec = static_cast<Cx<T> *>(fa.spec);
+    a.z = static_cast<T *>(fa.z);
+    a.partial = fa.partial;
+    a.st = fa.state;
+    a.dim = p.dim;
+    a.D = p.dim;
+    a.L = p.L;
+    a.n0 = (int)p.n[0];
+    a.n1 = p.dim == 3 ? (int)p.n[1] : 1;
+    a.nlast = (int)p.n[p.dim - 1];
+    a.nh = (int)p.nh;
+    a.N = p.N;
+    a.rows = p.N / a.nlast;
+    a.inner_total = p.dim == 3 ? (long long)p.n[1] * p.nh : p.nh;
+    a.last_even = p.last_even ? 1 : 0;
+    a.part_stride = (int)p.part_stride;
+    a.out_scale = fa.out_scale;
+    a.invN = 1.0 / (double)p.N;
+    const double vol = p.dim == 3 ? p.h[0] * p.h[1] * p.h[2] / 6.0 : p.h[0] * p.h[1] / 2.0;
+    a.chalf = 0.5 * vol;
+    a.tw_last = p.ptr<const Cx<T>>(p.off_tw[p.dim - 1]);
+    for (int ax = 0; ax < 3; ++ax) {
+        a.om[ax] = p.ptr<const double>(p.off_om[ax]);
+        a.aa[ax] = p.ptr<const double>(p.off_aa[ax]);
+    }
+    a.d_D = FastDiv::make((uint32_t)a.D);
+    a.d_nh = FastDiv::make((uint32_t)a.nh);
+    a.d_nhD = FastDiv::make((uint32_t)(a.nh * a.D));
+    return a;
+}
+
+template <typename T>
+constexpr int ppt() { return sizeof(T) == 4 ? 24 : 16; }
+
+template <typename T>
+int last_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
+    constexpr int PPT = ppt<T>();
+    FK<T> a = base_args<T>(p, fa);
+    const int last = p.dim - 1;
+    a.ax = p.fft[last];
+    a.tw = p.ptr<const Cx<T>>(p.off_tw[last]);
+    a.tws = p.last_even ? 2 : 1;
+    const int nc = a.ax.n;
+    int RR = (PPT * kFftThreads) / (nc * a.D);
+    if (RR < 1) return set_error(FEH_ENOTSUP, "last axis too long for the LDS transform");
+    if (RR > 64) RR = 64;
+    if (RR > a.rows) RR = (int)a.rows;
+    a.RR = RR;
+    a.nbd = FastDiv::make((uint32_t)(a.D * RR));
+    a.d_nc = FastDiv::make((uint32_t)nc);
+    a.nblk = (int)((a.rows + RR - 1) / RR);
+    a.total = a.nblk * p.L;
+    a.use_axpy = (!inverse && fa.q != nullptr && fa.state != nullptr) ? 1 : 0;
+    const dim3 g(a.total), b(kFftThreads);
+    const bool gen = !pow2_len(a.ax.n);
+    if (inverse) {
+        if (gen) hipLaunchKernelGGL((k_last_inv<T, PPT, true>), g, b, 0, p.stream, a);
+        else hipLaunchKernelGGL((k_last_inv<T, PPT, false>), g, b, 0, p.stream, a);
+    } else {
+        if (gen) hipLaunchKernelGGL((k_last_fwd<T, PPT, true>), g, b, 0, p.stream, a);
+        else hipLaunchKernelGGL((k_last_fwd<T, PPT, false>), g, b, 0, p.stream, a);
+    }
+    return hip_check(hipGetLastError(), "last-axis fft launch");
+}
+
+template <typename T>
+int middle_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
+    constexpr int PPT = ppt<T>();
+    FK<T> a = base_args<T>(p, fa);
+    a.ax = p.fft[1];
+    a.tw = p.ptr<const Cx<T>>(p.off_tw[1]);
+    a.tws = 1;
+    // pencils along axis 1 are indexed by the contiguous (kh, component) pairs
+    const long long inner = (long long)a.nh * a.D;
+    int PB = (PPT * kFftThreads) / a.n1;
+    if (PB < 1) return set_error(FEH_ENOTSUP, "middle axis too long for the LDS transform");
+    if (PB > 32) PB = 32;
+    if (PB > inner) PB = (int)inner;
+    a.PB = PB;
+    a.d_PB = FastDiv::make((uint32_t)PB);
+    a.inner_total = inner;
+    a.nblk = (int)((inner + PB - 1) / PB);
+    a.total = a.nblk * a.n0 * p.L;
+    if (pow2_len(a.ax.n))
+        hipLaunchKernelGGL((k_middle<T, PPT, false>), dim3(a.total), dim3(kFftThreads), 0, p.stream, a, inverse ? 1 : 0);
+    else
+        hipLaunchKernelGGL((k_middle<T, PPT, true>), dim3(a.total), dim3(kFftThreads), 0, p.stream, a, inverse ? 1 : 0);
+    return hip_check(hipGetLastError(), "middle-axis fft launch");
+}
+
+template <typename T, int DIM>
+int first_t(const feh_plan &p, const FftArgs &fa, int mode) {
+    constexpr int PPT = ppt<T>();
+    FK<T> a = base_args<T>(p, fa);
+    a.ax = p.fft[0];
+    a.tw = p.ptr<const Cx<T>>(p.off_tw[0]);
+    a.tws = 1;
+    int PB = (PPT * kFftThreads) / (a.n0 * DIM);
+    if (PB < 1) return set_error(FEH_ENOTSUP, "first axis too long for the LDS transform");
+    if (PB > 32) PB = 32;
+    if (PB > a.inner_total) PB = (int)a.inner_total;
+    a.PB = PB;
+    a.d_PB = FastDiv::make((uint32_t)PB);
+    a.nbd = FastDiv::make((uint32_t)(PB * DIM));
+    a.nblk = (int)((a.inner_total + PB - 1) / PB);
+    a.total = a.nblk * p.L;
+    dim3 g(a.total), b(kFftThreads);
+    const bool gen = !pow2_len(a.ax.n);
+    switch (mode * 2 + (gen ? 1 : 0)) {
+    case 0: hipLaunchKernelGGL((k_first<T, PPT, DIM, 0, false>), g, b, 0, p.stream, a); break;
+    case 1: hipLaunchKernelGGL((k_first<T, PPT, DIM, 0, true>), g, b, 0, p.stream, a); break;
+    case 2: hipLaunchKernelGGL((k_first<T, PPT, DIM, 1, false>), g, b, 0, p.stream, a); break;
+    case 3: hipLaunchKernelGGL((k_first<T, PPT, DIM, 1, true>), g, b, 0, p.stream, a); break;
+    case 4: hipLaunchKernelGGL((k_first<T, PPT, DIM, 2, false>), g, b, 0, p.stream, a); break;
+    default: hipLaunchKernelGGL((k_first<T, PPT, DIM, 2, true>), g, b, 0, p.stream, a); break;
+    }
+    return hip_check(hipGetLastError(), "first-axis fft launch");
+}
+
+template <typename T>
+int first_dispatch(const feh_plan &p, const FftArgs &fa, int mode) {
+    return p.dim == 3 ? first_t<T, 3>(p, fa, mode) : first_t<T, 2>(p, fa, mode);
+}
+
+}  // namespace
+
+int first_num_parts(const feh_plan &p) {
+    const int PPT = p.prec == FEH_FP32 ? 24 : 16;
+    int PB = (PPT * kFftThreads) / (int)(p.n[0] * p.dim);
+    if (PB < 1) PB = 1;
+    if (PB > 32) PB = 32;
+    const long long inner = p.dim == 3 ? p.n[1] * p.nh : p.nh;
+    if (PB > inner) PB = (int)inner;
+    return (int)((inner + PB - 1) / PB);
+}
+
+int launch_forward_last(const feh_plan &p, const FftArgs &a) {
+    return p.prec == FEH_FP64 ? last_t<double>(p, a, false) : last_t<float>(p, a, false);
+}
+int launch_inverse_last(const feh_plan &p, const FftArgs &a) {
+    return p.prec == FEH_FP64 ? last_t<double>(p, a, true) : last_t<float>(p, a, true);
+}
+int launch_middle(const feh_plan &p, const FftArgs &a, bool inverse) {
+    return p.prec == FEH_FP64 ? middle_t<double>(p, a, inverse) : middle_t<float>(p, a, inverse);
+}
+int launch_first_fused(const feh_plan &p, const FftArgs &a) {
+    return p.prec == FEH_FP64 ? first_dispatch<double>(p, a, 0) : first_dispatch<float>(p, a, 0);
+}
+int launch_first(const feh_plan &p, const FftArgs &a, bool inverse) {
+    const int mode = inverse ? 2 : 1;
+    return p.prec == FEH_FP64 ? first_dispatch<double>(p, a, mode) : first_dispatch<float>(p, a, mode);
+}
+
+}  // namespace feh

@@ -1,0 +1,333 @@
+// Post-processing of converged displacement fluctuations.
+//
+// Per element: e = Ebar + sym(grad u) (small-strain appendix), sigma = C e;
+// volume averages <sigma>_l and the energy matrix W_lm = <e_l : C : e_m>
+// (all elements carry the same volume, so the averages are plain means).
+// W is the Hill energy form of the effective stiffness, second order in the
+// CG error.  One grid axis enumerates the scalar quantities (stress means of
+// each load case, and each load-case pair of W); partial sums per block are
+// combined in a fixed order by k_reduce_slots.
+#include "device_common.hpp"
+
+namespace feh {
+namespace {
+
+constexpr int kThreads = 256;
+
+// symmetric strain of every element of a voxel from its corner
+// displacements; e[t] = (xx, yy, zz, yz, xz, xy) (tensor components)
+template <typename T>
+__device__ __forceinline__ void strains3(const T (&P)[8][3], const T (&ih)[3], double (&e)[6][6]) {
+    constexpr int KP[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    #pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        const int a0 = KP[t][0], a1 = KP[t][1], a2 = KP[t][2];
+        const int v1 = 1 << a0, v2 = v1 | (1 << a1);
+        double G[3][3];
+        #pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            G[i][a0] = double(P[v1][i] - P[0][i]) * double(ih[a0]);
+            G[i][a1] = double(P[v2][i] - P[v1][i]) * double(ih[a1]);
+            G[i][a2] = double(P[7][i] - P[v2][i]) * double(ih[a2]);
+        }
+        e[t][0] = G[0][0];
+        e[t][1] = G[1][1];
+        e[t][2] = G[2][2];
+        e[t][3] = 0.5 * (G[1][2] + G[2][1]);
+        e[t][4] = 0.5 * (G[0][2] + G[2][0]);
+        e[t][5] = 0.5 * (G[0][1] + G[1][0]);
+    }
+}
+
+// 2D: element 0 nodes 00,10,01; element 1 nodes 11,01,10; e[t] = (xx, yy, xy)
+template <typename T>
+__device__ __forceinline__ void strains2(const T (&P)[4][2], const T (&ih)[3], double (&e)[2][3]) {
+    const double hx = ih[0], hy = ih[1];
+    double G[2][2];
+    G[0][0] = double(P[1][0] - P[0][0]) * hx;
+    G[0][1] = double(P[2][0] - P[0][0]) * hy;
+    G[1][0] = double(P[1][1] - P[0][1]) * hx;
+    G[1][1] = double(P[2][1] - P[0][1]) * hy;
+    e[0][0] = G[0][0];
+    e[0][1] = G[1][1];
+    e[0][2] = 0.5 * (G[0][1] + G[1][0]);
+    G[0][0] = double(P[3][0] - P[2][0]) * hx;
+    G[0][1] = double(P[3][0] - P[1][0]) * hy;
+    G[1][0] = double(P[3][1] - P[2][1]) * hx;
+    G[1][1] = double(P[3][1] - P[1][1]) * hy;
+    e[1][0] = G[0][0];
+    e[1][1] = G[1][1];
+    e[1][2] = 0.5 * (G[0][1] + G[1][0]);
+}
+
+template <typename T>
+struct PK {
+    const T *u;         // SoA [L][D][N], may be null (zero fluctuation)
+    const double *Ebar; // [L][D][D]
+    const T *lam;
+    const T *mu;
+    T *strain;          // [L][N][ne][D][D] or null
+    T *stress;
+    double *partial;    // [slot][nblk]
+    int n0, n1, n2;     // 2D: n1 = 1, n2 = n[1]
+    long long N;
+    int L, nblk, nsym;
+    T ih[3];
+    int grad_only;      // projection test: write sym(grad u) only (no Ebar, no sums)
+};
+
+template <typename T, int DIM>
+__device__ __forceinline__ void load_corners(const PK<T> &a, int l, long long v, T (&P)[1 << DIM][DIM]) {
+    const int k2 = (int)(v % a.n2);
+    const long long r = v / a.n2;
+    const int k1 = (int)(r % a.n1);
+    const int k0 = (int)(r / a.n1);
+    const T *ub = a.u + (long long)l * DIM * a.N;
+    #pragma unroll
+    for (int c = 0; c < (1 << DIM); ++c) {
+        int i0, i1, i2;
+        if (DIM == 3) {
+            i0 = wrap(k0 + (c & 1), a.n0);
+            i1 = wrap(k1 + ((c >> 1) & 1), a.n1);
+            i2 = wrap(k2 + ((c >> 2) & 1), a.n2);
+        } else {
+            i0 = wrap(k0 + (c & 1), a.n0);
+            i1 = 0;
+            i2 = wrap(k2 + ((c >> 1) & 1), a.n2);
+        }
+        const long long idx = ((long long)i0 * a.n1 + i1) * a.n2 + i2;
+        #pragma unroll
+        for (int i = 0; i < DIM; ++i) P[c][i] = a.u ? ub[i * a.N + idx] : T(0);
+    }
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ void voxel_strains(const PK<T> &a, int l, long long v, bool add_ebar,
+                                              double (&e)[DIM == 3 ? 6 : 2][DIM == 3 ? 6 : 3]) {
+    T P[1 << DIM][DIM];
+    load_corners<T, DIM>(a, l, v, P);
+    if constexpr (DIM == 3) {
+        strains3<T>(P, a.ih, e);
+        if (add_ebar) {
+            const double *E = a.Ebar + l * 9;
+            const double eb[6] = {E[0], E[4], E[8], E[5], E[2], E[1]};
+            #pragma unroll
+            for (int t = 0; t < 6; ++t)
+                #pragma unroll
+                for (int k = 0; k < 6; ++k) e[t][k] += eb[k];
+        }
+    } else {
+        strains2<T>(P, a.ih, e);
+        if (add_ebar) {
+            const double *E = a.Ebar + l * 4;
+            const double eb[3] = {E[0], E[3], E[1]};
+            #pragma unroll
+            for (int t = 0; t < 2; ++t)
+                #pragma unroll
+                for (int k = 0; k < 3; ++k) e[t][k] += eb[k];
+        }
+    }
+}
+
+// sigma (symmetric components) from a strain in the same storage
+template <int DIM>
+__device__ __forceinline__ void stress_of(const double *e, double lam, double mu, double *s) {
+    if constexpr (DIM == 3) {
+        const double lt = lam * (e[0] + e[1] + e[2]);
+        s[0] = lt + 2 * mu * e[0];
+        s[1] = lt + 2 * mu * e[1];
+        s[2] = lt + 2 * mu * e[2];
+        s[3] = 2 * mu * e[3];
+        s[4] = 2 * mu * e[4];
+        s[5] = 2 * mu * e[5];
+    } else {
+        const double lt = lam * (e[0] + e[1]);
+        s[0] = lt + 2 * mu * e[0];
+        s[1] = lt + 2 * mu * e[1];
+        s[2] = 2 * mu * e[2];
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ double ddot(const double *e, const double *s) {
+    if constexpr (DIM == 3) return e[0] * s[0] + e[1] * s[1] + e[2] * s[2] + 2.0 * (e[3] * s[3] + e[4] * s[4] + e[5] * s[5]);
+    else return e[0] * s[0] + e[1] * s[1] + 2.0 * e[2] * s[2];
+}
+
+// write a symmetric tensor as a full D x D block
+template <typename T, int DIM>
+__device__ __forceinline__ void put_full(T *dst, const double *s) {
+    if constexpr (DIM == 3) {
+        dst[0] = T(s[0]); dst[1] = T(s[5]); dst[2] = T(s[4]);
+        dst[3] = T(s[5]); dst[4] = T(s[1]); dst[5] = T(s[3]);
+        dst[6] = T(s[4]); dst[7] = T(s[3]); dst[8] = T(s[2]);
+    } else {
+        dst[0] = T(s[0]); dst[1] = T(s[2]);
+        dst[2] = T(s[2]); dst[3] = T(s[1]);
+    }
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kThreads) void k_post(PK<T> a) {
+    constexpr int NE = DIM == 3 ? 6 : 2;
+    constexpr int NS = DIM == 3 ? 6 : 3;
+    __shared__ double red[kThreads / 64];
+    const int qslot = blockIdx.y;  // quantity
+    const int blk = blockIdx.x;
+    double acc[NS];
+    #pragma unroll
+    for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+    int l = qslot, m = -1;
+    if (qslot >= a.L) {
+        // pair index -> (l, m), l <= m
+        int rem = qslot - a.L;
+        l = 0;
+        while (rem >= a.L - l) {
+            rem -= a.L - l;
+            ++l;
+        }
+        m = l + rem;
+    }
+    for (long long v = blk * (long long)kThreads + threadIdx.x; v < a.N; v += (long long)a.nblk * kThreads) {
+        const double lam = double(a.lam[v]), mu = double(a.mu[v]);
+        double e[NE][NS];
+        voxel_strains<T, DIM>(a, l, v, true, e);
+        if (m < 0) {
+            #pragma unroll
+            for (int t = 0; t < NE; ++t) {
+                double s[NS];
+                stress_of<DIM>(e[t], lam, mu, s);
+                #pragma unroll
+                for (int k = 0; k < NS; ++k) acc[k] += s[k];
+                const long long off = (((long long)l * a.N + v) * NE + t) * DIM * DIM;
+                if (a.strain) put_full<T, DIM>(a.strain + off, e[t]);
+                if (a.stress) put_full<T, DIM>(a.stress + off, s);
+            }
+        } else {
+            double f[NE][NS];
+            voxel_strains<T, DIM>(a, m, v, true, f);
+            #pragma unroll
+            for (int t = 0; t < NE; ++t) {
+                double s[NS];
+                stress_of<DIM>(f[t], lam, mu, s);
+                acc[0] += ddot<DIM>(e[t], s);
+            }
+        }
+    }
+    const int nout = (m < 0) ? NS : 1;
+    for (int k = 0; k < nout; ++k) {
+        const double s = block_sum<kThreads>(acc[k], red);
+        if (threadIdx.x == 0) {
+            const long long slot = (m < 0) ? (long long)l * NS + k : (long long)a.L * NS + (qslot - a.L);
+            a.partial[slot * a.nblk + blk] = s;
+        }
+    }
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kThreads) void k_grad(PK<T> a) {
+    constexpr int NE = DIM == 3 ? 6 : 2;
+    constexpr int NS = DIM == 3 ? 6 : 3;
+    const int l = blockIdx.y;
+    for (long long v = blockIdx.x * (long long)kThreads + threadIdx.x; v < a.N; v += (long long)gridDim.x * kThreads) {
+        double e[NE][NS];
+        voxel_strains<T, DIM>(a, l, v, false, e);
+        #pragma unroll
+        for (int t = 0; t < NE; ++t) put_full<T, DIM>(a.strain + (((long long)l * a.N + v) * NE + t) * DIM * DIM, e[t]);
+    }
+}
+
+__global__ void k_reduce_slots(const double *part, int nblk, double *out, double scale) {
+    __shared__ double red[kThreads / 64];
+    const int slot = blockIdx.x;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += kThreads) v += part[(long long)slot * nblk + i];
+    const double s = block_sum<kThreads>(v, red);
+    if (threadIdx.x == 0) out[slot] = s * scale;
+}
+
+template <typename T>
+PK<T> post_args(const feh_plan &p) {
+    PK<T> a{};
+    a.lam = p.ptr<const T>(p.off_lam);
+    a.mu = p.ptr<const T>(p.off_mu);
+    if (p.dim == 3) {
+        a.n0 = (int)p.n[0];
+        a.n1 = (int)p.n[1];
+        a.n2 = (int)p.n[2];
+    } else {
+        a.n0 = (int)p.n[0];
+        a.n1 = 1;
+        a.n2 = (int)p.n[1];
+    }
+    a.N = p.N;
+    a.L = p.L;
+    for (int i = 0; i < 3; ++i) a.ih[i] = T(1.0 / p.h[i]);
+    a.nsym = p.dim == 3 ? 6 : 3;
+    return a;
+}
+
+}  // namespace
+
+int post_num_parts(const feh_plan &p) {
+    long long b = (p.N + kThreads - 1) / kThreads;
+    if (b > 512) b = 512;
+    return (int)b;
+}
+
+int post_num_slots(const feh_plan &p) {
+    const int ns = p.dim == 3 ? 6 : 3;
+    return p.L * ns + p.L * (p.L + 1) / 2;
+}
+
+template <typename T>
+static int post_t(const feh_plan &p, const void *u, const double *Ebar, void *strain, void *stress, double *partial,
+                  double *sums) {
+    PK<T> a = post_args<T>(p);
+    a.u = static_cast<const T *>(u);
+    a.Ebar = Ebar;
+    a.strain = static_cast<T *>(strain);
+    a.stress = static_cast<T *>(stress);
+    a.partial = partial;
+    a.nblk = post_num_parts(p);
+    const int nq = p.L + p.L * (p.L + 1) / 2;
+    dim3 g(a.nblk, nq);
+    if (p.dim == 3)
+        hipLaunchKernelGGL((k_post<T, 3>), g, dim3(kThreads), 0, p.stream, a);
+    else
+        hipLaunchKernelGGL((k_post<T, 2>), g, dim3(kThreads), 0, p.stream, a);
+    int rc = hip_check(hipGetLastError(), "post launch");
+    if (rc) return rc;
+    const int ne = p.dim == 3 ? 6 : 2;
+    hipLaunchKernelGGL(k_reduce_slots, dim3(post_num_slots(p)), dim3(kThreads), 0, p.stream, partial, a.nblk, sums,
+                       1.0 / ((double)p.N * ne));
+    return hip_check(hipGetLastError(), "post reduce");
+}
+
+int launch_post_sums(const feh_plan &p, const void *u, const double *Ebar_dev, void *strain, void *stress,
+                     double *partial, double *sums) {
+    return p.prec == FEH_FP64 ? post_t<double>(p, u, Ebar_dev, strain, stress, partial, sums)
+                              : post_t<float>(p, u, Ebar_dev, strain, stress, partial, sums);
+}
+
+template <typename T>
+static int grad_t(const feh_plan &p, const void *u, void *e) {
+    PK<T> a = post_args<T>(p);
+    a.u = static_cast<const T *>(u);
+    a.strain = static_cast<T *>(e);
+    a.grad_only = 1;
+    long long g = (p.N + kThreads - 1) / kThreads;
+    if (g > 65535) g = 65535;
+    dim3 grid((unsigned)g, p.L);
+    if (p.dim == 3)
+        hipLaunchKernelGGL((k_grad<T, 3>), grid, dim3(kThreads), 0, p.stream, a);
+    else
+        hipLaunchKernelGGL((k_grad<T, 2>), grid, dim3(kThreads), 0, p.stream, a);
+    return hip_check(hipGetLastError(), "grad launch");
+}
+
+int launch_grad(const feh_plan &p, const void *u, void *e) {
+    return p.prec == FEH_FP64 ? grad_t<double>(p, u, e) : grad_t<float>(p, u, e);
+}
+
+}  // namespace feh

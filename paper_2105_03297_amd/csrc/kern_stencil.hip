@@ -1,0 +1,512 @@
+// Finite-element stencils on the structured grid: q = B^T C B p and friends.
+//
+// Discretisation (Sec. "Linear finite elements", small-strain appendix): each
+// voxel holds n_e linear simplices (2 triangles in 2D, 6 Kuhn tetrahedra in
+// 3D) with a constant strain e = sym(grad u) per element, stress
+// sigma = lambda tr(e) I + 2 mu e and nodal force |e| B_e^T sigma.
+//
+// Both B and B^T are written in edge-difference form.  Every element
+// gradient is built from differences of nodal values along voxel edges
+// (G[:, a] = (u(end) - u(start)) / h_a), so constants map to exactly zero.
+// Transposed, every element pushes the column sigma[:, a] |e| / h_a onto the
+// voxel edge it used along axis a ("edge flux").  An edge of type (a, c)
+// (axis a, start corner c inside its voxel) starting at node n belongs to
+// voxel n - c, and the same edge type ending at n to voxel n - e_a - c, so
+//   q(n) = sum_{a, c: c_a = 0} [ E_{a,c}(n - e_a - c) - E_{a,c}(n - c) ].
+// Each bracket is a difference of the same quantity taken from two voxels:
+// in a uniform region every bracket is exactly zero, so a uniform strain in
+// a uniform material produces exactly zero force in any precision.
+//
+// Kernel layout: one workgroup owns a TY x TZ tile of nodes in the (axis 1,
+// axis 2) plane and marches along axis 0 over a chunk of planes.  Per step
+// it stages one node plane (one-node halo) in LDS, evaluates every voxel of
+// the extended voxel plane once (12 edge fluxes into LDS), and each node
+// thread combines the edge fluxes of the voxels around it; the terms whose
+// voxels lie in the previous plane are carried in registers.  The fused CG
+// variant also forms p = z + beta p_old on the fly, writes p, applies the
+// pending u += alpha p_old and accumulates p.q in FP64.
+#include "device_common.hpp"
+
+namespace feh {
+namespace {
+
+// Edge numbering: axis a, start corner c with c_a = 0; k enumerates the
+// bits of the two other axes in increasing order (low bit first).
+template <int A, int C>
+struct EdgeK {
+    static constexpr int b = A == 0 ? 1 : 0;
+    static constexpr int d = A == 2 ? 1 : 2;
+    static constexpr int k = ((C >> b) & 1) | (((C >> d) & 1) << 1);
+};
+
+// Strain (+ Ebar) -> stress -> edge fluxes of one tetrahedron with axis path
+// (A0, A1, A2), from G[i][a] = d u_i / d x_a.  Eb = (xx, yy, zz, yz, xz, xy).
+// E[(a * 4 + k) * 3 + i].
+template <typename T, int A0, int A1, int A2>
+__device__ __forceinline__ void tet_edges(const T (&G)[3][3], T lam, T mu, const T (&ih)[3], const T (&Eb)[6],
+                                          T (&E)[36]) {
+    constexpr int V1 = 1 << A0, V2 = V1 | (1 << A1);
+    constexpr int k0 = EdgeK<A0, 0>::k, k1 = EdgeK<A1, V1>::k, k2 = EdgeK<A2, V2>::k;
+    const T e0 = G[0][0] + Eb[0], e1 = G[1][1] + Eb[1], e2 = G[2][2] + Eb[2];
+    const T lt = lam * (e0 + e1 + e2), m2 = mu + mu;
+    T S[3][3];
+    S[0][0] = lt + m2 * e0;
+    S[1][1] = lt + m2 * e1;
+    S[2][2] = lt + m2 * e2;
+    S[1][2] = S[2][1] = mu * (G[1][2] + G[2][1]) + m2 * Eb[3];
+    S[0][2] = S[2][0] = mu * (G[0][2] + G[2][0]) + m2 * Eb[4];
+    S[0][1] = S[1][0] = mu * (G[0][1] + G[1][0]) + m2 * Eb[5];
+    #pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        E[(A0 * 4 + k0) * 3 + i] += S[i][A0] * ih[A0];
+        E[(A1 * 4 + k1) * 3 + i] += S[i][A1] * ih[A1];
+        E[(A2 * 4 + k2) * 3 + i] += S[i][A2] * ih[A2];
+    }
+}
+
+template <typename T, int A0, int A1, int A2>
+__device__ __forceinline__ void tet_from_nodes(const T (&P)[8][3], T lam, T mu, const T (&ih)[3], const T (&Eb)[6],
+                                               T (&E)[36]) {
+    constexpr int V1 = 1 << A0, V2 = V1 | (1 << A1);
+    T G[3][3];
+    #pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        G[i][A0] = (P[V1][i] - P[0][i]) * ih[A0];
+        G[i][A1] = (P[V2][i] - P[V1][i]) * ih[A1];
+        G[i][A2] = (P[7][i] - P[V2][i]) * ih[A2];
+    }
+    tet_edges<T, A0, A1, A2>(G, lam, mu, ih, Eb, E);
+}
+
+// All six tetrahedra of a voxel; lam, mu already carry the tetrahedron volume.
+template <typename T>
+__device__ __forceinline__ void voxel3(const T (&P)[8][3], T lam, T mu, const T (&ih)[3], const T (&Eb)[6],
+                                       T (&E)[36]) {
+    #pragma unroll
+    for (int j = 0; j < 36; ++j) E[j] = T(0);
+    tet_from_nodes<T, 0, 1, 2>(P, lam, mu, ih, Eb, E);
+    tet_from_nodes<T, 0, 2, 1>(P, lam, mu, ih, Eb, E);
+    tet_from_nodes<T, 1, 0, 2>(P, lam, mu, ih, Eb, E);
+    tet_from_nodes<T, 1, 2, 0>(P, lam, mu, ih, Eb, E);
+    tet_from_nodes<T, 2, 0, 1>(P, lam, mu, ih, Eb, E);
+    tet_from_nodes<T, 2, 1, 0>(P, lam, mu, ih, Eb, E);
+}
+
+// Element field given directly (projection test export): fluxes of |e| sym(e_T).
+template <typename T, int A0, int A1, int A2>
+__device__ __forceinline__ void tet_div(const T *e, T vol, const T (&ih)[3], T (&E)[36]) {
+    constexpr int V1 = 1 << A0, V2 = V1 | (1 << A1);
+    constexpr int k0 = EdgeK<A0, 0>::k, k1 = EdgeK<A1, V1>::k, k2 = EdgeK<A2, V2>::k;
+    #pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        E[(A0 * 4 + k0) * 3 + i] += T(0.5) * vol * (e[i * 3 + A0] + e[A0 * 3 + i]) * ih[A0];
+        E[(A1 * 4 + k1) * 3 + i] += T(0.5) * vol * (e[i * 3 + A1] + e[A1 * 3 + i]) * ih[A1];
+        E[(A2 * 4 + k2) * 3 + i] += T(0.5) * vol * (e[i * 3 + A2] + e[A2 * 3 + i]) * ih[A2];
+    }
+}
+
+// 2D: element 0 nodes 00,10,01 uses edges (x, c=0) and (y, c=0); element 1
+// nodes 11,01,10 uses edges (x, c=e_y) and (y, c=e_x).  Corner index
+// c = cx | c1 << 1.  E[(a * 2 + k) * 2 + i], k = offset along the other axis.
+template <typename T>
+__device__ __forceinline__ void tri_edges(T g00, T g01, T g10, T g11, T lam, T mu, T ihx, T ihy, const T (&Eb)[3],
+                                          int kx, int ky, T (&E)[8]) {
+    // g_ia = d u_i / d x_a
+    const T e0 = g00 + Eb[0], e1 = g11 + Eb[1];
+    const T lt = lam * (e0 + e1), m2 = mu + mu;
+    const T sxy = mu * (g01 + g10) + m2 * Eb[2];
+    E[(0 * 2 + kx) * 2 + 0] = (lt + m2 * e0) * ihx;
+    E[(0 * 2 + kx) * 2 + 1] = sxy * ihx;
+    E[(1 * 2 + ky) * 2 + 0] = sxy * ihy;
+    E[(1 * 2 + ky) * 2 + 1] = (lt + m2 * e1) * ihy;
+}
+
+template <typename T>
+__device__ __forceinline__ void voxel2(const T (&P)[4][2], T lam, T mu, T ihx, T ihy, const T (&Eb)[3], T (&E)[8]) {
+    // element 0: d/dx = (P10 - P00) ihx, d/dy = (P01 - P00) ihy
+    tri_edges<T>((P[1][0] - P[0][0]) * ihx, (P[2][0] - P[0][0]) * ihy, (P[1][1] - P[0][1]) * ihx,
+                 (P[2][1] - P[0][1]) * ihy, lam, mu, ihx, ihy, Eb, 0, 0, E);
+    // element 1: d/dx = (P11 - P01) ihx, d/dy = (P11 - P10) ihy
+    tri_edges<T>((P[3][0] - P[2][0]) * ihx, (P[3][0] - P[1][0]) * ihy, (P[3][1] - P[2][1]) * ihx,
+                 (P[3][1] - P[1][1]) * ihy, lam, mu, ihx, ihy, Eb, 1, 1, E);
+}
+
+template <typename T>
+__device__ __forceinline__ void voxel2_div(const T *e, T vol, T ihx, T ihy, T (&E)[8]) {
+    // e: [2 elements][2][2]
+    #pragma unroll
+    for (int el = 0; el < 2; ++el) {
+        const T *ee = e + el * 4;
+        const T sxy = T(0.5) * vol * (ee[1] + ee[2]);
+        E[(0 * 2 + el) * 2 + 0] = vol * ee[0] * ihx;
+        E[(0 * 2 + el) * 2 + 1] = sxy * ihx;
+        E[(1 * 2 + el) * 2 + 0] = sxy * ihy;
+        E[(1 * 2 + el) * 2 + 1] = vol * ee[3] * ihy;
+    }
+}
+
+template <typename T>
+struct SK {
+    const T *in0;      // p / z / u
+    const T *pold0;    // CG: p buffer 0
+    const T *pold1;    // CG: p buffer 1
+    T *out0;           // q / r
+    T *pnew0;          // CG: p buffer 0
+    T *pnew1;          // CG: p buffer 1
+    T *u;              // CG
+    const T *lam;
+    const T *mu;
+    const double *Ebar;
+    double *partial;
+    const LcState *st;
+    int n0, n1, n2;    // 2D: n1 = 1, n2 = n[1]
+    long long N;
+    int xc, nchunk, nty, ntz, total;
+    int part_stride;
+    T ih[3];
+    T vol;
+    int ident;         // lambda = 0, mu = 1/2 everywhere
+};
+
+template <int DIM>
+struct Tile;
+template <>
+struct Tile<3> {
+    static constexpr int TY = 4, TZ = 64, HY = 1, NC = 3, NEDGE = 12;
+};
+template <>
+struct Tile<2> {
+    static constexpr int TY = 1, TZ = 256, HY = 0, NC = 2, NEDGE = 4;
+};
+
+constexpr int kStencilThreads = 256;
+
+template <typename T, int DIM, int MODE>
+__global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
+    using TL = Tile<DIM>;
+    constexpr int TY = TL::TY, TZ = TL::TZ, HY = TL::HY, NC = TL::NC, NEDGE = TL::NEDGE;
+    constexpr int EY = TY + 2 * HY, EZ = TZ + 2, VY = TY + HY, VZ = TZ + 1;
+    constexpr int NE = EY * EZ, NV = VY * VZ, NT = kStencilThreads;
+    constexpr int NQ = NEDGE * NC;  // edge-flux values per voxel
+    __shared__ T Pl[2][NC][NE];
+    __shared__ T Es[NQ][NV];
+    __shared__ double red[NT / 64];
+
+    const int tid = threadIdx.x;
+    int t = xcd_remap(blockIdx.x, a.total);
+    const int tz_t = t % a.ntz;
+    t /= a.ntz;
+    const int ty_t = t % a.nty;
+    t /= a.nty;
+    const int ch = t % a.nchunk;
+    const int lc = t / a.nchunk;
+    const int blk_in_lc = (ch * a.nty + ty_t) * a.ntz + tz_t;
+
+    // CG scalars of this load case
+    bool first = false;
+    T beta = T(0), alpha_pend = T(0);
+    const T *pold = nullptr;
+    T *pnew = nullptr;
+    if constexpr (MODE == ST_CG) {
+        const LcState &s = a.st[lc];
+        if (!s.active) return;
+        first = s.first != 0;
+        beta = T(s.beta);
+        alpha_pend = T(s.alpha_pend);
+        pold = s.pbuf ? a.pold1 : a.pold0;
+        pnew = s.pbuf ? a.pnew0 : a.pnew1;
+    }
+    T Eb[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    if constexpr (MODE == ST_RESID) {
+        const double *E = a.Ebar + lc * DIM * DIM;
+        if constexpr (DIM == 3) {
+            Eb[0] = T(E[0]); Eb[1] = T(E[4]); Eb[2] = T(E[8]);
+            Eb[3] = T(E[5]); Eb[4] = T(E[2]); Eb[5] = T(E[1]);
+        } else {
+            Eb[0] = T(E[0]); Eb[1] = T(E[3]); Eb[2] = T(E[1]);
+        }
+    }
+
+    const int y0 = ty_t * TY, z0 = tz_t * TZ;
+    const int x0 = ch * a.xc;
+    const int x1 = min(x0 + a.xc, a.n0);
+    const long long N = a.N;
+    const long long lcoff = (long long)lc * NC * N;
+
+    auto load_plane = [&](int X, bool interior_plane) {
+        const int xw = wrap(X, a.n0);
+        const int buf = X & 1;
+        for (int e = tid; e < NE; e += NT) {
+            const int ey = e / EZ, ez = e - ey * EZ;
+            const int yy = y0 - HY + ey, zz = z0 - 1 + ez;
+            const int yw = wrap(yy, a.n1), zw = wrap(zz, a.n2);
+            const long long idx = ((long long)xw * a.n1 + yw) * a.n2 + zw;
+            const bool inter = interior_plane && ey >= HY && ey < HY + TY && ez >= 1 && ez <= TZ &&
+                               yy < a.n1 && zz < a.n2;
+            #pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const long long gi = lcoff + c * N + idx;
+                T v;
+                if constexpr (MODE == ST_APPLY) {
+                    v = a.in0[gi];
+                } else if constexpr (MODE == ST_CG) {
+                    const T zv = a.in0[gi];
+                    if (first) {
+                        v = zv;
+                    } else {
+                        const T po = pold[gi];
+                        v = zv + beta * po;
+                        if (inter) a.u[gi] += alpha_pend * po;
+                    }
+                    if (inter) pnew[gi] = v;
+                } else if constexpr (MODE == ST_RESID) {
+                    v = a.in0 ? a.in0[gi] : T(0);
+                } else {
+                    v = T(0);
+                }
+                Pl[buf][c][e] = v;
+            }
+        }
+    };
+
+    // carried terms: raw axis-0 edge fluxes of the previous voxel plane, and
+    // the differences of the other axes' edges (voxels in the previous plane)
+    constexpr int NXE = DIM == 3 ? 4 : 2;  // axis-0 edges per voxel
+    T cx[NXE * NC];                        // (k, i): the axis-0 edges of the nodes' voxels
+    T cq[NC];
+    #pragma unroll
+    for (int j = 0; j < NXE * NC; ++j) cx[j] = T(0);
+    #pragma unroll
+    for (int c = 0; c < NC; ++c) cq[c] = T(0);
+    double acc = 0.0;
+
+    const int ty = tid / TZ, tz = tid - (tid / TZ) * TZ;
+    const bool node_thread = tid < TY * TZ;
+
+    if constexpr (MODE != ST_DIV) load_plane(x0 - 1, false);
+
+    for (int X = x0 - 1; X < x1; ++X) {
+        if constexpr (MODE != ST_DIV) load_plane(X + 1, X + 1 < x1);
+        __syncthreads();
+        // ---- voxel phase: voxel plane X of the extended tile
+        const int xw = wrap(X, a.n0);
+        for (int v = tid; v < NV; v += NT) {
+            const int vy = v / VZ, vz = v - (v / VZ) * VZ;
+            const int yw = wrap(y0 - HY + vy, a.n1), zw = wrap(z0 - 1 + vz, a.n2);
+            const long long vidx = ((long long)xw * a.n1 + yw) * a.n2 + zw;
+            T lam, mu;
+            if (a.ident) {
+                lam = T(0);
+                mu = T(0.5) * a.vol;
+            } else {
+                lam = a.lam[vidx] * a.vol;
+                mu = a.mu[vidx] * a.vol;
+            }
+            if constexpr (DIM == 3) {
+                T E[36];
+                if constexpr (MODE == ST_DIV) {
+                    const T *e = a.in0 + ((long long)lc * N + vidx) * 54;
+                    #pragma unroll
+                    for (int j = 0; j < 36; ++j) E[j] = T(0);
+                    tet_div<T, 0, 1, 2>(e + 0, a.vol, a.ih, E);
+                    tet_div<T, 0, 2, 1>(e + 9, a.vol, a.ih, E);
+                    tet_div<T, 1, 0, 2>(e + 18, a.vol, a.ih, E);
+                    tet_div<T, 1, 2, 0>(e + 27, a.vol, a.ih, E);
+                    tet_div<T, 2, 0, 1>(e + 36, a.vol, a.ih, E);
+                    tet_div<T, 2, 1, 0>(e + 45, a.vol, a.ih, E);
+                } else {
+                    T P[8][3];
+                    #pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        const int cxb = c & 1, cyb = (c >> 1) & 1, czb = (c >> 2) & 1;
+                        #pragma unroll
+                        for (int i = 0; i < 3; ++i) P[c][i] = Pl[(X + cxb) & 1][i][(vy + cyb) * EZ + vz + czb];
+                    }
+                    voxel3<T>(P, lam, mu, a.ih, Eb, E);
+                }
+                #pragma unroll
+                for (int j = 0; j < 36; ++j) Es[j][v] = E[j];
+            } else {
+                T E[8];
+                if constexpr (MODE == ST_DIV) {
+                    voxel2_div<T>(a.in0 + ((long long)lc * N + vidx) * 8, a.vol, a.ih[0], a.ih[1], E);
+                } else {
+                    T P[4][2];
+                    #pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int cxb = c & 1, c1 = (c >> 1) & 1;
+                        #pragma unroll
+                        for (int i = 0; i < 2; ++i) P[c][i] = Pl[(X + cxb) & 1][i][vz + c1];
+                    }
+                    const T Eb2[3] = {Eb[0], Eb[1], Eb[2]};
+                    voxel2<T>(P, lam, mu, a.ih[0], a.ih[1], Eb2, E);
+                }
+                #pragma unroll
+                for (int j = 0; j < 8; ++j) Es[j][v] = E[j];
+            }
+        }
+        __syncthreads();
+        // ---- node phase
+        if (node_thread) {
+            T q[NC], nq[NC];
+            #pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                q[i] = cq[i];
+                nq[i] = T(0);
+            }
+            // voxel of the node's plane at in-plane offset (-dy, -dz)
+            auto vix = [&](int dy, int dz) { return (ty + HY - dy) * VZ + (tz + 1 - dz); };
+            if constexpr (DIM == 3) {
+                // axis-0 edges: E_{0,k}(n - e_x - c) - E_{0,k}(n - c), c = (0, cy, cz), k = cy + 2 cz
+                #pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int v = vix(k & 1, k >> 1);
+                    #pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const T cur = Es[(0 * 4 + k) * 3 + i][v];
+                        q[i] += cx[k * 3 + i] - cur;
+                        cx[k * 3 + i] = cur;
+                    }
+                }
+                // axis-1 edges: c = (cx, 0, cz), k = cx + 2 cz; voxels n - e_y - c and n - c
+                #pragma unroll
+                for (int cz = 0; cz < 2; ++cz) {
+                    const int vlo = vix(1, cz), vhi = vix(0, cz);
+                    #pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        q[i] += Es[(1 * 4 + 2 * cz) * 3 + i][vlo] - Es[(1 * 4 + 2 * cz) * 3 + i][vhi];
+                        nq[i] += Es[(1 * 4 + 1 + 2 * cz) * 3 + i][vlo] - Es[(1 * 4 + 1 + 2 * cz) * 3 + i][vhi];
+                    }
+                }
+                // axis-2 edges: c = (cx, cy, 0), k = cx + 2 cy; voxels n - e_z - c and n - c
+                #pragma unroll
+                for (int cy = 0; cy < 2; ++cy) {
+                    const int vlo = vix(cy, 1), vhi = vix(cy, 0);
+                    #pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        q[i] += Es[(2 * 4 + 2 * cy) * 3 + i][vlo] - Es[(2 * 4 + 2 * cy) * 3 + i][vhi];
+                        nq[i] += Es[(2 * 4 + 1 + 2 * cy) * 3 + i][vlo] - Es[(2 * 4 + 1 + 2 * cy) * 3 + i][vhi];
+                    }
+                }
+            } else {
+                // axis-0 edges: c = (0, c1), k = c1
+                #pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int v = vix(0, k);
+                    #pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        const T cur = Es[(0 * 2 + k) * 2 + i][v];
+                        q[i] += cx[k * 2 + i] - cur;
+                        cx[k * 2 + i] = cur;
+                    }
+                }
+                // axis-1 edges: c = (cx, 0), k = cx; voxels n - e_1 - c and n - c
+                const int vlo = vix(0, 1), vhi = vix(0, 0);
+                #pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    q[i] += Es[(1 * 2 + 0) * 2 + i][vlo] - Es[(1 * 2 + 0) * 2 + i][vhi];
+                    nq[i] += Es[(1 * 2 + 1) * 2 + i][vlo] - Es[(1 * 2 + 1) * 2 + i][vhi];
+                }
+            }
+            if (X >= x0) {
+                const int yy = y0 + ty, zz = z0 + tz;
+                if (yy < a.n1 && zz < a.n2) {
+                    const long long idx = ((long long)X * a.n1 + yy) * a.n2 + zz;
+                    #pragma unroll
+                    for (int i = 0; i < NC; ++i) {
+                        if constexpr (MODE == ST_RESID) {
+                            a.out0[lcoff + i * N + idx] = -q[i];
+                        } else {
+                            a.out0[lcoff + i * N + idx] = q[i];
+                        }
+                        if constexpr (MODE == ST_CG) {
+                            const T pv = Pl[X & 1][i][(ty + HY) * EZ + tz + 1];
+                            acc += double(pv) * double(q[i]);
+                        }
+                    }
+                }
+            }
+            #pragma unroll
+            for (int i = 0; i < NC; ++i) cq[i] = nq[i];
+        }
+        __syncthreads();
+    }
+    if constexpr (MODE == ST_CG) {
+        const double s = block_sum<NT>(acc, red);
+        if (tid == 0) a.partial[(long long)lc * a.part_stride + blk_in_lc] = s;
+    }
+}
+
+template <typename T, int DIM>
+int launch_t(const feh_plan &p, int mode, const StencilArgs &sa) {
+    using TL = Tile<DIM>;
+    SK<T> a{};
+    a.in0 = static_cast<const T *>(sa.in0);
+    a.pold0 = static_cast<const T *>(sa.in1);
+    a.pold1 = static_cast<const T *>(sa.in1b);
+    a.out0 = static_cast<T *>(sa.out0);
+    a.pnew0 = static_cast<T *>(sa.out1);
+    a.pnew1 = static_cast<T *>(sa.out1b);
+    a.u = static_cast<T *>(sa.u);
+    a.lam = p.ptr<const T>(p.off_lam);
+    a.mu = p.ptr<const T>(p.off_mu);
+    a.Ebar = sa.Ebar;
+    a.partial = sa.partial;
+    a.st = sa.state;
+    a.ident = sa.identity_material ? 1 : 0;
+    if (DIM == 3) {
+        a.n0 = (int)p.n[0];
+        a.n1 = (int)p.n[1];
+        a.n2 = (int)p.n[2];
+        a.ih[0] = T(1.0 / p.h[0]);
+        a.ih[1] = T(1.0 / p.h[1]);
+        a.ih[2] = T(1.0 / p.h[2]);
+        a.vol = T(p.h[0] * p.h[1] * p.h[2] / 6.0);
+    } else {
+        a.n0 = (int)p.n[0];
+        a.n1 = 1;
+        a.n2 = (int)p.n[1];
+        a.ih[0] = T(1.0 / p.h[0]);
+        a.ih[1] = T(1.0 / p.h[1]);
+        a.ih[2] = T(1);
+        a.vol = T(p.h[0] * p.h[1] / 2.0);
+    }
+    a.N = p.N;
+    a.xc = a.n0 < 16 ? a.n0 : 16;
+    a.nchunk = (a.n0 + a.xc - 1) / a.xc;
+    a.nty = (a.n1 + TL::TY - 1) / TL::TY;
+    a.ntz = (a.n2 + TL::TZ - 1) / TL::TZ;
+    a.total = p.L * a.nchunk * a.nty * a.ntz;
+    a.part_stride = (int)p.part_stride;
+    dim3 grid(a.total), block(kStencilThreads);
+    switch (mode) {
+    case ST_APPLY: hipLaunchKernelGGL((k_stencil<T, DIM, ST_APPLY>), grid, block, 0, p.stream, a); break;
+    case ST_CG: hipLaunchKernelGGL((k_stencil<T, DIM, ST_CG>), grid, block, 0, p.stream, a); break;
+    case ST_RESID: hipLaunchKernelGGL((k_stencil<T, DIM, ST_RESID>), grid, block, 0, p.stream, a); break;
+    case ST_DIV: hipLaunchKernelGGL((k_stencil<T, DIM, ST_DIV>), grid, block, 0, p.stream, a); break;
+    default: return set_error(FEH_EINVAL, "bad stencil mode");
+    }
+    return hip_check(hipGetLastError(), "stencil launch");
+}
+
+}  // namespace
+
+int stencil_num_parts(const feh_plan &p) {
+    const int n0 = (int)p.n[0];
+    const int xc = n0 < 16 ? n0 : 16;
+    const int nchunk = (n0 + xc - 1) / xc;
+    if (p.dim == 3) {
+        return nchunk * (int)((p.n[1] + Tile<3>::TY - 1) / Tile<3>::TY) *
+               (int)((p.n[2] + Tile<3>::TZ - 1) / Tile<3>::TZ);
+    }
+    return nchunk * (int)((p.n[1] + Tile<2>::TZ - 1) / Tile<2>::TZ);
+}
+
+int launch_stencil(const feh_plan &p, int mode, const StencilArgs &a) {
+    if (p.prec == FEH_FP64) {
+        return p.dim == 3 ? launch_t<double, 3>(p, mode, a) : launch_t<double, 2>(p, mode, a);
+    }
+    return p.dim == 3 ? launch_t<float, 3>(p, mode, a) : launch_t<float, 2>(p, mode, a);
+}
+
+}  // namespace feh

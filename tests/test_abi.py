@@ -1,0 +1,96 @@
+"""Host-side checks of the C ABI (no GPU work): the library loads, exports
+every entry point the header declares, validates arguments, and its host
+helper for the effective stiffness agrees with the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import microstructures as ms
+import paper_2105_03297_amd as feh
+from oracle import fe
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "feh.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(feh_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_symbols_exported():
+    names = _declared()
+    assert len(names) >= 16
+    lib = ctypes.CDLL(feh.library_path())
+    for n in names:
+        assert hasattr(lib, n), n
+    # the binding wraps every declared entry point under the same name
+    for n in names:
+        assert callable(getattr(feh, n)), n
+
+
+def test_version_and_error_string():
+    assert feh.feh_version() == 10000
+    assert isinstance(feh.feh_last_error(), str)
+
+
+@pytest.mark.parametrize("dim,n,nl,prec,code", [
+    (1, (8,), 1, 0, feh.FEH_EINVAL),
+    (2, (8, 1), 1, 0, feh.FEH_EINVAL),
+    (2, (8, 8), 0, 0, feh.FEH_EINVAL),
+    (2, (8, 8), 65, 0, feh.FEH_EINVAL),
+    (2, (8, 8), 1, 7, feh.FEH_EINVAL),
+    (2, (17 * 2, 8), 1, 0, feh.FEH_ENOTSUP),
+    (3, (8, 8, 8192), 1, 0, feh.FEH_EINVAL),
+])
+def test_plan_validation(dim, n, nl, prec, code):
+    with pytest.raises(feh.FehError) as ei:
+        feh.feh_plan_create(dim, n, None, nl, prec)
+    assert ei.value.status == code
+
+
+def test_bad_voxel_size():
+    with pytest.raises(feh.FehError) as ei:
+        feh.feh_plan_create(2, (8, 8), (1.0, -1.0), 1, 0)
+    assert ei.value.status == feh.FEH_EINVAL
+
+
+def test_plan_sizes_and_workspace_checks():
+    p = feh.feh_plan_create(3, (256, 256, 256), None, 6, feh.FEH_FP32)
+    b = feh.feh_plan_workspace_bytes(p)
+    # 6 vectors + half spectrum + material: about 8.6 GB at 256^3 x 6 load cases in FP32
+    assert 8.0e9 < b < 9.5e9
+    # calls that need a workspace fail before touching the device
+    Eb = ms.unit_loads(3)
+    with pytest.raises(feh.FehError) as ei:
+        feh.feh_solve(p, Eb, 1e-5, 10)
+    assert ei.value.status == feh.FEH_ENOMEM
+    with pytest.raises(feh.FehError) as ei:
+        feh.feh_plan_set_workspace(p, 0, b)
+    assert ei.value.status == feh.FEH_EINVAL
+    with pytest.raises(feh.FehError) as ei:
+        feh.feh_plan_set_workspace(p, 4096, b - 1)
+    assert ei.value.status == feh.FEH_ENOMEM
+    feh.feh_plan_destroy(p)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_effective_stiffness_helper_matches_oracle(dim):
+    rng = np.random.default_rng(3)
+    nv = 3 if dim == 2 else 6
+    A = rng.standard_normal((nv, nv))
+    C = A @ A.T + nv * np.eye(nv)
+    Ebars = []
+    for _ in range(nv):
+        E = rng.standard_normal((dim, dim)) * 0.01
+        Ebars.append(0.5 * (E + E.T))
+    Ebars = np.array(Ebars)
+    Ev = np.stack([fe.voigt_strain(E) for E in Ebars], axis=1)
+    W = Ev.T @ C @ Ev
+    got = feh.feh_effective_stiffness(dim, Ebars, W)
+    np.testing.assert_allclose(got, fe.c_eff_energy(W, Ebars), rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(got, C, rtol=1e-9, atol=1e-10)
+    with pytest.raises(feh.FehError):
+        feh.feh_effective_stiffness(dim, np.zeros((nv, dim, dim)), W)
