@@ -168,11 +168,14 @@ struct SK {
     int ident;         // lambda = 0, mu = 1/2 everywhere
 };
 
+// Tile shapes: TY x TZ nodes per workgroup (one node per thread); the voxel
+// plane of a tile needs one extra row (y0 - 1) and column (z0 - 1), which
+// the first NV - TY*TZ threads evaluate in a second round.
 template <int DIM>
 struct Tile;
 template <>
 struct Tile<3> {
-    static constexpr int TY = 4, TZ = 64, HY = 1, NC = 3, NEDGE = 12;
+    static constexpr int TY = 8, TZ = 32, HY = 1, NC = 3, NEDGE = 12;
 };
 template <>
 struct Tile<2> {
@@ -187,8 +190,11 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
     constexpr int TY = TL::TY, TZ = TL::TZ, HY = TL::HY, NC = TL::NC, NEDGE = TL::NEDGE;
     constexpr int EY = TY + 2 * HY, EZ = TZ + 2, VY = TY + HY, VZ = TZ + 1;
     constexpr int NE = EY * EZ, NV = VY * VZ, NT = kStencilThreads;
-    constexpr int NQ = NEDGE * NC;  // edge-flux values per voxel
-    __shared__ T Pl[2][NC][NE];
+    constexpr int NQ = NEDGE * NC;               // edge-flux values per voxel
+    constexpr int NSE = (NE + NT - 1) / NT;      // node-plane slots per thread
+    constexpr int NSV = (NV + NT - 1) / NT;      // voxel slots per thread
+    static_assert(TY * TZ == NT, "one node per thread");
+    __shared__ T Pl[3][NC][NE];                  // ring of three node planes
     __shared__ T Es[NQ][NV];
     __shared__ double red[NT / 64];
 
@@ -203,14 +209,12 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
     const int blk_in_lc = (ch * a.nty + ty_t) * a.ntz + tz_t;
 
     // CG scalars of this load case
-    bool first = false;
     T beta = T(0), alpha_pend = T(0);
     const T *pold = nullptr;
     T *pnew = nullptr;
     if constexpr (MODE == ST_CG) {
         const LcState &s = a.st[lc];
         if (!s.active) return;
-        first = s.first != 0;
         beta = T(s.beta);
         alpha_pend = T(s.alpha_pend);
         pold = s.pbuf ? a.pold1 : a.pold0;
@@ -231,48 +235,152 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
     const int x0 = ch * a.xc;
     const int x1 = min(x0 + a.xc, a.n0);
     const long long N = a.N;
+    const long long plane = (long long)a.n1 * a.n2;
     const long long lcoff = (long long)lc * NC * N;
+    const int ty = tid / TZ, tz = tid - (tid / TZ) * TZ;
 
-    auto load_plane = [&](int X, bool interior_plane) {
-        const int xw = wrap(X, a.n0);
-        const int buf = X & 1;
-        for (int e = tid; e < NE; e += NT) {
-            const int ey = e / EZ, ez = e - ey * EZ;
+    // ---- per-thread slots, fixed for the whole march.  Node-plane slot 0 is
+    // the thread's own node (extended index (ty + HY, tz + 1)); later slots
+    // cover the halo ring.  Voxel slot 0 is the voxel at the thread's node,
+    // later slots the halo row / column of voxels.
+    int e_lds[NSE];        // extended node index, -1 if unused
+    long long e_off[NSE];  // in-plane global offset
+    bool e_in[NSE];        // node owned (written) by this tile
+    #pragma unroll
+    for (int s = 0; s < NSE; ++s) {
+        int ey = -1, ez = -1;
+        if (s == 0) {
+            ey = ty + HY;
+            ez = tz + 1;
+        } else {
+            const int hh = tid + (s - 1) * NT;  // halo node number
+            constexpr int NH = NE - TY * TZ;
+            if (hh < NH) {
+                if constexpr (HY == 0) {
+                    // single row: the two end nodes
+                    ey = 0;
+                    ez = (hh & 1) ? EZ - 1 : 0;
+                } else if (hh < EZ) {
+                    ey = 0;  // row y0 - 1
+                    ez = hh;
+                } else if (hh < 2 * EZ) {
+                    ey = EY - 1;  // row y0 + TY
+                    ez = hh - EZ;
+                } else {
+                    const int r = hh - 2 * EZ;  // columns z0 - 1 and z0 + TZ
+                    ey = HY + r / 2;
+                    ez = (r & 1) ? EZ - 1 : 0;
+                }
+            }
+        }
+        if (ey >= 0) {
             const int yy = y0 - HY + ey, zz = z0 - 1 + ez;
-            const int yw = wrap(yy, a.n1), zw = wrap(zz, a.n2);
-            const long long idx = ((long long)xw * a.n1 + yw) * a.n2 + zw;
-            const bool inter = interior_plane && ey >= HY && ey < HY + TY && ez >= 1 && ez <= TZ &&
-                               yy < a.n1 && zz < a.n2;
+            e_lds[s] = ey * EZ + ez;
+            e_off[s] = (long long)wrap(yy, a.n1) * a.n2 + wrap(zz, a.n2);
+            e_in[s] = (s == 0) && yy < a.n1 && zz < a.n2;
+        } else {
+            e_lds[s] = -1;
+            e_off[s] = 0;
+            e_in[s] = false;
+        }
+    }
+    int v_lds[NSV];
+    long long v_off[NSV];
+    #pragma unroll
+    for (int s = 0; s < NSV; ++s) {
+        int vy = -1, vz = -1;
+        if (s == 0) {
+            vy = ty + HY;
+            vz = tz + 1;
+        } else {
+            const int hh = tid + (s - 1) * NT;
+            constexpr int NHV = NV - TY * TZ;
+            if (hh < NHV) {
+                if (hh < VZ) {
+                    vy = 0;
+                    vz = hh;
+                } else {
+                    vy = hh - VZ + 1;
+                    vz = 0;
+                }
+            }
+        }
+        if (vy >= 0) {
+            v_lds[s] = vy * VZ + vz;
+            v_off[s] = (long long)wrap(y0 - HY + vy, a.n1) * a.n2 + wrap(z0 - 1 + vz, a.n2);
+        } else {
+            v_lds[s] = -1;
+            v_off[s] = 0;
+        }
+    }
+
+    // ---- prefetch registers: node plane P (values needed to form p) and the
+    // material of one voxel plane
+    T rz[NSE][NC], rp[NSE][NC], ru[NC];  // u only at the thread's own node (slot 0)
+    T mlam[NSV], mmu[NSV], clam[NSV], cmu[NSV];
+    auto fetch_nodes = [&](int P) __attribute__((always_inline)) {
+        const long long base = (long long)wrap(P, a.n0) * plane;
+        #pragma unroll
+        for (int s = 0; s < NSE; ++s) {
+            if (e_lds[s] >= 0) {
             #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                const long long gi = lcoff + c * N + idx;
-                T v;
+                const long long gi = lcoff + c * N + base + e_off[s];
                 if constexpr (MODE == ST_APPLY) {
-                    v = a.in0[gi];
+                    rz[s][c] = a.in0[gi];
                 } else if constexpr (MODE == ST_CG) {
-                    const T zv = a.in0[gi];
-                    if (first) {
-                        v = zv;
-                    } else {
-                        const T po = pold[gi];
-                        v = zv + beta * po;
-                        if (inter) a.u[gi] += alpha_pend * po;
-                    }
-                    if (inter) pnew[gi] = v;
+                    // before the first search direction beta = alpha_pend = 0
+                    // and both p buffers are zero-filled, so no branch is needed
+                    rz[s][c] = a.in0[gi];
+                    rp[s][c] = pold[gi];
+                    if (s == 0) ru[c] = a.u[gi];
                 } else if constexpr (MODE == ST_RESID) {
-                    v = a.in0 ? a.in0[gi] : T(0);
-                } else {
-                    v = T(0);
+                    rz[s][c] = a.in0 ? a.in0[gi] : T(0);
                 }
-                Pl[buf][c][e] = v;
+            }
+            }
+        }
+    };
+    auto commit_nodes = [&](int P) __attribute__((always_inline)) {
+        const long long base = (long long)wrap(P, a.n0) * plane;
+        const bool interior_plane = P >= x0 && P < x1;
+        const int buf = (P + 3) % 3;
+        #pragma unroll
+        for (int s = 0; s < NSE; ++s) {
+            if (e_lds[s] >= 0) {
+            const bool inter = interior_plane && e_in[s];
+            #pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                T v = rz[s][c];
+                if constexpr (MODE == ST_CG) {
+                    const long long gi = lcoff + c * N + base + e_off[s];
+                    v = rz[s][c] + beta * rp[s][c];
+                    if (inter) {
+                        pnew[gi] = v;
+                        if (s == 0) a.u[gi] = ru[c] + alpha_pend * rp[s][c];
+                    }
+                }
+                Pl[buf][c][e_lds[s]] = v;
+            }
+            }
+        }
+    };
+    auto fetch_material = [&](int V) __attribute__((always_inline)) {
+        const long long base = (long long)wrap(V, a.n0) * plane;
+        #pragma unroll
+        for (int s = 0; s < NSV; ++s) {
+            if (v_lds[s] >= 0 && !a.ident) {
+                mlam[s] = a.lam[base + v_off[s]];
+                mmu[s] = a.mu[base + v_off[s]];
             }
         }
     };
 
     // carried terms: raw axis-0 edge fluxes of the previous voxel plane, and
-    // the differences of the other axes' edges (voxels in the previous plane)
+    // the differences of the other axes' edges whose voxels lie in the
+    // previous plane
     constexpr int NXE = DIM == 3 ? 4 : 2;  // axis-0 edges per voxel
-    T cx[NXE * NC];                        // (k, i): the axis-0 edges of the nodes' voxels
+    T cx[NXE * NC];
     T cq[NC];
     #pragma unroll
     for (int j = 0; j < NXE * NC; ++j) cx[j] = T(0);
@@ -280,31 +388,45 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
     for (int c = 0; c < NC; ++c) cq[c] = T(0);
     double acc = 0.0;
 
-    const int ty = tid / TZ, tz = tid - (tid / TZ) * TZ;
-    const bool node_thread = tid < TY * TZ;
-
-    if constexpr (MODE != ST_DIV) load_plane(x0 - 1, false);
+    if constexpr (MODE != ST_DIV) {
+        fetch_nodes(x0 - 1);
+        commit_nodes(x0 - 1);
+        fetch_nodes(x0);
+    }
+    fetch_material(x0 - 1);
 
     for (int X = x0 - 1; X < x1; ++X) {
-        if constexpr (MODE != ST_DIV) load_plane(X + 1, X + 1 < x1);
+        // ---- stage plane X+1, prefetch plane X+2 and the material of voxel plane X+1
+        if constexpr (MODE != ST_DIV) commit_nodes(X + 1);
+        #pragma unroll
+        for (int s = 0; s < NSV; ++s) {
+            clam[s] = mlam[s];
+            cmu[s] = mmu[s];
+        }
+        if (X + 2 <= x1) {
+            if constexpr (MODE != ST_DIV) fetch_nodes(X + 2);
+        }
+        if (X + 1 < x1) fetch_material(X + 1);
         __syncthreads();
         // ---- voxel phase: voxel plane X of the extended tile
-        const int xw = wrap(X, a.n0);
-        for (int v = tid; v < NV; v += NT) {
+        const int b0 = (X + 3) % 3, b1 = (X + 4) % 3;
+        #pragma unroll
+        for (int s = 0; s < NSV; ++s) {
+            const int v = v_lds[s];
+            if (v >= 0) {
             const int vy = v / VZ, vz = v - (v / VZ) * VZ;
-            const int yw = wrap(y0 - HY + vy, a.n1), zw = wrap(z0 - 1 + vz, a.n2);
-            const long long vidx = ((long long)xw * a.n1 + yw) * a.n2 + zw;
             T lam, mu;
             if (a.ident) {
                 lam = T(0);
                 mu = T(0.5) * a.vol;
             } else {
-                lam = a.lam[vidx] * a.vol;
-                mu = a.mu[vidx] * a.vol;
+                lam = clam[s] * a.vol;
+                mu = cmu[s] * a.vol;
             }
             if constexpr (DIM == 3) {
                 T E[36];
                 if constexpr (MODE == ST_DIV) {
+                    const long long vidx = (long long)wrap(X, a.n0) * plane + v_off[s];
                     const T *e = a.in0 + ((long long)lc * N + vidx) * 54;
                     #pragma unroll
                     for (int j = 0; j < 36; ++j) E[j] = T(0);
@@ -318,9 +440,10 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
                     T P[8][3];
                     #pragma unroll
                     for (int c = 0; c < 8; ++c) {
-                        const int cxb = c & 1, cyb = (c >> 1) & 1, czb = (c >> 2) & 1;
+                        const int cyb = (c >> 1) & 1, czb = (c >> 2) & 1;
+                        const int bb = (c & 1) ? b1 : b0;
                         #pragma unroll
-                        for (int i = 0; i < 3; ++i) P[c][i] = Pl[(X + cxb) & 1][i][(vy + cyb) * EZ + vz + czb];
+                        for (int i = 0; i < 3; ++i) P[c][i] = Pl[bb][i][(vy + cyb) * EZ + vz + czb];
                     }
                     voxel3<T>(P, lam, mu, a.ih, Eb, E);
                 }
@@ -329,14 +452,16 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
             } else {
                 T E[8];
                 if constexpr (MODE == ST_DIV) {
+                    const long long vidx = (long long)wrap(X, a.n0) * plane + v_off[s];
                     voxel2_div<T>(a.in0 + ((long long)lc * N + vidx) * 8, a.vol, a.ih[0], a.ih[1], E);
                 } else {
                     T P[4][2];
                     #pragma unroll
                     for (int c = 0; c < 4; ++c) {
-                        const int cxb = c & 1, c1 = (c >> 1) & 1;
+                        const int c1 = (c >> 1) & 1;
+                        const int bb = (c & 1) ? b1 : b0;
                         #pragma unroll
-                        for (int i = 0; i < 2; ++i) P[c][i] = Pl[(X + cxb) & 1][i][vz + c1];
+                        for (int i = 0; i < 2; ++i) P[c][i] = Pl[bb][i][vz + c1];
                     }
                     const T Eb2[3] = {Eb[0], Eb[1], Eb[2]};
                     voxel2<T>(P, lam, mu, a.ih[0], a.ih[1], Eb2, E);
@@ -344,10 +469,11 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
                 #pragma unroll
                 for (int j = 0; j < 8; ++j) Es[j][v] = E[j];
             }
+            }
         }
         __syncthreads();
-        // ---- node phase
-        if (node_thread) {
+        // ---- node phase (one node per thread)
+        {
             T q[NC], nq[NC];
             #pragma unroll
             for (int i = 0; i < NC; ++i) {
@@ -408,34 +534,32 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
                     nq[i] += Es[(1 * 2 + 1) * 2 + i][vlo] - Es[(1 * 2 + 1) * 2 + i][vhi];
                 }
             }
-            if (X >= x0) {
-                const int yy = y0 + ty, zz = z0 + tz;
-                if (yy < a.n1 && zz < a.n2) {
-                    const long long idx = ((long long)X * a.n1 + yy) * a.n2 + zz;
-                    #pragma unroll
-                    for (int i = 0; i < NC; ++i) {
-                        if constexpr (MODE == ST_RESID) {
-                            a.out0[lcoff + i * N + idx] = -q[i];
-                        } else {
-                            a.out0[lcoff + i * N + idx] = q[i];
-                        }
-                        if constexpr (MODE == ST_CG) {
-                            const T pv = Pl[X & 1][i][(ty + HY) * EZ + tz + 1];
-                            acc += double(pv) * double(q[i]);
-                        }
+            if (X >= x0 && e_in[0]) {
+                const long long idx = (long long)X * plane + e_off[0];
+                #pragma unroll
+                for (int i = 0; i < NC; ++i) {
+                    if constexpr (MODE == ST_RESID) {
+                        a.out0[lcoff + i * N + idx] = -q[i];
+                    } else {
+                        a.out0[lcoff + i * N + idx] = q[i];
+                    }
+                    if constexpr (MODE == ST_CG) {
+                        const T pv = Pl[b0][i][e_lds[0]];
+                        acc += double(pv) * double(q[i]);
                     }
                 }
             }
             #pragma unroll
             for (int i = 0; i < NC; ++i) cq[i] = nq[i];
         }
-        __syncthreads();
     }
     if constexpr (MODE == ST_CG) {
         const double s = block_sum<NT>(acc, red);
         if (tid == 0) a.partial[(long long)lc * a.part_stride + blk_in_lc] = s;
     }
 }
+
+int xchunk(int n0) { return n0 < 32 ? n0 : 32; }
 
 template <typename T, int DIM>
 int launch_t(const feh_plan &p, int mode, const StencilArgs &sa) {
@@ -472,7 +596,7 @@ int launch_t(const feh_plan &p, int mode, const StencilArgs &sa) {
         a.vol = T(p.h[0] * p.h[1] / 2.0);
     }
     a.N = p.N;
-    a.xc = a.n0 < 16 ? a.n0 : 16;
+    a.xc = xchunk(a.n0);
     a.nchunk = (a.n0 + a.xc - 1) / a.xc;
     a.nty = (a.n1 + TL::TY - 1) / TL::TY;
     a.ntz = (a.n2 + TL::TZ - 1) / TL::TZ;
@@ -493,7 +617,7 @@ int launch_t(const feh_plan &p, int mode, const StencilArgs &sa) {
 
 int stencil_num_parts(const feh_plan &p) {
     const int n0 = (int)p.n[0];
-    const int xc = n0 < 16 ? n0 : 16;
+    const int xc = xchunk(n0);
     const int nchunk = (n0 + xc - 1) / xc;
     if (p.dim == 3) {
         return nchunk * (int)((p.n[1] + Tile<3>::TY - 1) / Tile<3>::TY) *
