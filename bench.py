@@ -58,6 +58,32 @@ def kernel_bytes(dim, s, n_last, iters, n_voxels):
     return out
 
 
+KERNEL_SOURCE = {"stencil": "kern_stencil.hip"}
+
+
+def source_sha1(name):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2105_03297_amd", "csrc", KERNEL_SOURCE.get(name, "kern_fft.hip"))
+    return hashlib.sha1(open(path, "rb").read()).hexdigest()
+
+
+def traffic_from_profiles(kernel, workload):
+    """HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
+    (scaled by the counters of a plain copy of known size), as committed
+    under profiles/; None when absent or when the kernel source has changed
+    since the counters were taken."""
+    tf = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(tf):
+        return None
+    try:
+        tj = json.load(open(tf))
+    except ValueError:
+        return None
+    if tj.get("source_sha1") != source_sha1(kernel):
+        return None
+    return tj.get("bytes_per_launch")
+
+
 def cpu_baseline(n=40, iters=6000):
     """Oracle timing on the host: the same random-field recipe on an n^3 grid
     (correlation length scaled to the same fraction of the cell), one load
@@ -97,6 +123,8 @@ def main():
     ap.add_argument("--workload", default="grf256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-check", action="store_true")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="after the steps, copy a 1 GiB buffer once (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU runs are not part of it",
@@ -162,14 +190,14 @@ def main():
     dom = max((k for k in kb if kb[k] > 0), key=lambda k: prof[k][0])
     dom_ms, dom_n = prof[dom]
     achieved = kb[dom] / (dom_ms / 1e3) / 1e9
-    traffic = None
-    tf = os.path.join(ROOT, "profiles", f"traffic_{dom}_{args.workload}.json")
-    if os.path.exists(tf):
-        try:
-            tj = json.load(open(tf))
-            traffic = tj.get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    if args.copy_ref:
+        xs = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        ys = torch.empty_like(xs)
+        torch.cuda.synchronize()
+        ys.copy_(xs)
+        torch.cuda.synchronize()
+        del xs, ys
+    traffic = traffic_from_profiles(dom, args.workload)
     kernels = {k: {"ms_total": round(v[0], 3), "launches": v[1],
                    "GBps_algorithmic": (round(kb[k] / (v[0] / 1e3) / 1e9, 1) if v[0] > 0 and kb[k] > 0 else None)}
                for k, v in prof.items()}

@@ -36,6 +36,16 @@ __device__ __forceinline__ Cx<T> twid(const Cx<T> *tw, int tws, int e, bool inv)
     return w;
 }
 
+// Dynamic LDS holds the twiddle table of the transformed axis (and, in the
+// first-axis pass, the per-wavevector phase tables): staged once per
+// workgroup so the butterflies never wait on global memory.
+extern __shared__ double feh_dyn_lds[];
+
+template <typename T>
+__device__ __forceinline__ void stage(T *dst, const T *src, int count) {
+    for (int i = threadIdx.x; i < count; i += kFftThreads) dst[i] = src[i];
+}
+
 // In-place DFT of length R on registers: x[d] <- sum_c x[c] exp(-+2 pi i c d / R).
 template <typename T, int R>
 struct Dft {
@@ -208,8 +218,8 @@ __device__ __forceinline__ void stockham_pass(Cx<T> *buf, int nb, const FastDiv 
 // GEN = false instantiates only the radices of power-of-two lengths (2, 4, 8),
 // which keeps the register footprint of the common case small.
 template <typename T, int PPT, bool GEN>
-__device__ void lds_fft(Cx<T> *buf, int nb, const FastDiv &nbd, const AxisFFT &ax, const Cx<T> *tw, int tws,
-                        bool inv) {
+__device__ __forceinline__ void lds_fft(Cx<T> *buf, int nb, const FastDiv &nbd, const AxisFFT &ax,
+                                        const Cx<T> *tw, int tws, bool inv) {
     for (int s = 0; s < ax.npass; ++s) {
         const PassInfo &ps = ax.pass[s];
         switch (ps.R) {
@@ -284,6 +294,8 @@ __global__ __launch_bounds__(kFftThreads) void k_last_fwd(FK<T> a) {
     const int nrows = (int)min((long long)a.RR, a.rows - s0);
     const int nc = a.ax.n;
     const long long N = a.N;
+    Cx<T> *twl = reinterpret_cast<Cx<T> *>(feh_dyn_lds);
+    stage(twl, a.tw_last, a.nlast);
     for (int e = threadIdx.x; e < nb * nc; e += NT) {
         const int b = (int)a.d_nc.div((uint32_t)e);
         const int j = e - b * nc;
@@ -313,7 +325,7 @@ __global__ __launch_bounds__(kFftThreads) void k_last_fwd(FK<T> a) {
         buf[j * nb + b] = v;
     }
     __syncthreads();
-    lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, a.tw, a.tws, false);
+    lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, twl, a.tws, false);
     const int nh = a.nh;
     for (int e = threadIdx.x; e < nrows * nh * D; e += NT) {
         const int kk = (int)a.d_D.div((uint32_t)e);
@@ -329,7 +341,7 @@ __global__ __launch_bounds__(kFftThreads) void k_last_fwd(FK<T> a) {
             const Cx<T> A = {T(0.5) * (Zk.x + Zm.x), T(0.5) * (Zk.y + Zm.y)};
             const Cx<T> dZ = csub(Zk, Zm);
             const Cx<T> B = {T(0.5) * dZ.y, -T(0.5) * dZ.x};  // -i/2 (Zk - conj Z(nc-k))
-            X = cadd(A, cmul(a.tw_last[k], B));
+            X = cadd(A, cmul(twl[k], B));
         } else {
             X = buf[k * nb + b];
         }
@@ -355,6 +367,8 @@ __global__ __launch_bounds__(kFftThreads) void k_last_inv(FK<T> a) {
     const int nc = a.ax.n;
     const int nh = a.nh;
     const long long N = a.N;
+    Cx<T> *twl = reinterpret_cast<Cx<T> *>(feh_dyn_lds);
+    stage(twl, a.tw_last, a.nlast);
     // gather: e -> (sl, k, c), components fastest (coalesced spectrum reads)
     for (int e = threadIdx.x; e < nb * nc; e += NT) {
         const int kk = (int)a.d_D.div((uint32_t)e);
@@ -378,7 +392,7 @@ __global__ __launch_bounds__(kFftThreads) void k_last_inv(FK<T> a) {
         buf[k * nb + b] = Z;
     }
     __syncthreads();
-    lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, a.tw, a.tws, true);
+    lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, twl, a.tws, true);
     const T sc = T(a.out_scale);
     for (int e = threadIdx.x; e < nb * nc; e += NT) {
         const int b = (int)a.d_nc.div((uint32_t)e);
@@ -416,13 +430,15 @@ __global__ __launch_bounds__(kFftThreads) void k_middle(FK<T> a, int inv) {
     const long long in0 = (long long)ib * PB;
     Cx<T> *base = a.spec + ((long long)lc * a.n0 + i0) * n1 * inner + in0;
     const int lim = (int)min((long long)PB, inner - in0);
+    Cx<T> *twl = reinterpret_cast<Cx<T> *>(feh_dyn_lds);
+    stage(twl, a.tw, n1);
     for (int e = threadIdx.x; e < PB * n1; e += NT) {
         const int j = (int)a.d_PB.div((uint32_t)e);
         const int b = e - j * PB;
         buf[e] = (b < lim) ? base[(long long)j * inner + b] : Cx<T>{T(0), T(0)};
     }
     __syncthreads();
-    lds_fft<T, PPT, GEN>(buf, PB, a.d_PB, a.ax, a.tw, 1, inv != 0);
+    lds_fft<T, PPT, GEN>(buf, PB, a.d_PB, a.ax, twl, 1, inv != 0);
     for (int e = threadIdx.x; e < PB * n1; e += NT) {
         const int j = (int)a.d_PB.div((uint32_t)e);
         const int b = e - j * PB;
@@ -489,13 +505,41 @@ __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
     const long long in0 = (long long)blk * PB;
     const int lim = (int)min((long long)PB, inner - in0) * D;
     Cx<T> *base = a.spec + ((long long)lc * n0 * inner + in0) * D;
+    // dynamic LDS: twiddles of axis 0, then (FP64) the axis-0 phase tables and
+    // the phase factors of this block's PB inner wavevector indices
+    Cx<T> *twl = reinterpret_cast<Cx<T> *>(feh_dyn_lds);
+    const int tw_bytes = ((n0 * (int)sizeof(Cx<T>) + 15) / 16) * 16;
+    Cx<double> *aa0 = reinterpret_cast<Cx<double> *>(reinterpret_cast<char *>(feh_dyn_lds) + tw_bytes);
+    Cx<double> *om0 = aa0 + n0;
+    Cx<double> *pin = om0 + n0;  // [PB][4]: aa1, om1, aa2, om2 (2D: aa1, om1)
+    stage(twl, a.tw, n0);
+    if (MODE == 0) {
+        stage(aa0, reinterpret_cast<const Cx<double> *>(a.aa[0]), n0);
+        stage(om0, reinterpret_cast<const Cx<double> *>(a.om[0]), n0);
+        for (int b = threadIdx.x; b < PB; b += NT) {
+            const long long inn = in0 + b;
+            if (inn < inner) {
+                if (DIM == 3) {
+                    const int m1 = (int)a.d_nh.div((uint32_t)inn);
+                    const int kh = (int)(inn - (long long)m1 * a.nh);
+                    pin[4 * b + 0] = ld2(a.aa[1], m1);
+                    pin[4 * b + 1] = ld2(a.om[1], m1);
+                    pin[4 * b + 2] = ld2(a.aa[2], kh);
+                    pin[4 * b + 3] = ld2(a.om[2], kh);
+                } else {
+                    pin[4 * b + 0] = ld2(a.aa[1], (int)inn);
+                    pin[4 * b + 1] = ld2(a.om[1], (int)inn);
+                }
+            }
+        }
+    }
     for (int e = threadIdx.x; e < nb * n0; e += NT) {
         const int j = (int)a.nbd.div((uint32_t)e);
         const int bc = e - j * nb;
         buf[e] = (bc < lim) ? base[(long long)j * inner * D + bc] : Cx<T>{T(0), T(0)};
     }
     __syncthreads();
-    if (MODE != 2) lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, a.tw, 1, false);
+    if (MODE != 2) lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, twl, 1, false);
     double acc = 0.0;
     if (MODE == 0) {
         const double ch = a.chalf;
@@ -525,8 +569,8 @@ __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
                 #pragma unroll
                 for (int c = 0; c < D; ++c) zz[c] = r[c];
                 if (DIM == 3) {
-                    const Cx<double> a0 = ld2(a.aa[0], j), a1 = ld2(a.aa[1], m1), a2 = ld2(a.aa[2], kh);
-                    const Cx<double> w0 = ld2(a.om[0], j), w1 = ld2(a.om[1], m1), w2 = ld2(a.om[2], kh);
+                    const Cx<double> a0 = aa0[j], a1 = pin[4 * b + 0], a2 = pin[4 * b + 2];
+                    const Cx<double> w0 = om0[j], w1 = pin[4 * b + 1], w2 = pin[4 * b + 3];
                     const double n0s = nrm(a0), n1s = nrm(a1), n2s = nrm(a2);
                     const double S = 6.0 * (n0s + n1s + n2s);
                     Md[0] = ch * (S + 6.0 * n0s);
@@ -538,8 +582,8 @@ __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
                     Mo[1] = cscale(cmul(cmulc(a0, a2), cadd(cmulc(cadd(two, cconj(w1)), w0), cmul(w2, cadd(two, w1)))), ch);
                     Mo[2] = cscale(cmul(cmulc(a1, a2), cadd(cmulc(cadd(two, cconj(w0)), w1), cmul(w2, cadd(two, w0)))), ch);
                 } else {
-                    const Cx<double> a0 = ld2(a.aa[0], j), a1 = ld2(a.aa[1], kh);
-                    const Cx<double> w0 = ld2(a.om[0], j), w1 = ld2(a.om[1], kh);
+                    const Cx<double> a0 = aa0[j], a1 = pin[4 * b + 0];
+                    const Cx<double> w0 = om0[j], w1 = pin[4 * b + 1];
                     const double n0s = nrm(a0), n1s = nrm(a1);
                     const double S = 2.0 * (n0s + n1s);
                     Md[0] = ch * (S + 2.0 * n0s);
@@ -562,7 +606,7 @@ __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
         }
         __syncthreads();
     }
-    if (MODE != 1) lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, a.tw, 1, true);
+    if (MODE != 1) lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, twl, 1, true);
     for (int e = threadIdx.x; e < nb * n0; e += NT) {
         const int j = (int)a.nbd.div((uint32_t)e);
         const int bc = e - j * nb;
@@ -640,12 +684,13 @@ int last_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     a.use_axpy = (!inverse && fa.q != nullptr && fa.state != nullptr) ? 1 : 0;
     const dim3 g(a.total), b(kFftThreads);
     const bool gen = !pow2_len(a.ax.n);
+    const size_t dyn = (size_t)a.nlast * sizeof(Cx<T>);
     if (inverse) {
-        if (gen) hipLaunchKernelGGL((k_last_inv<T, PPT, true>), g, b, 0, p.stream, a);
-        else hipLaunchKernelGGL((k_last_inv<T, PPT, false>), g, b, 0, p.stream, a);
+        if (gen) hipLaunchKernelGGL((k_last_inv<T, PPT, true>), g, b, dyn, p.stream, a);
+        else hipLaunchKernelGGL((k_last_inv<T, PPT, false>), g, b, dyn, p.stream, a);
     } else {
-        if (gen) hipLaunchKernelGGL((k_last_fwd<T, PPT, true>), g, b, 0, p.stream, a);
-        else hipLaunchKernelGGL((k_last_fwd<T, PPT, false>), g, b, 0, p.stream, a);
+        if (gen) hipLaunchKernelGGL((k_last_fwd<T, PPT, true>), g, b, dyn, p.stream, a);
+        else hipLaunchKernelGGL((k_last_fwd<T, PPT, false>), g, b, dyn, p.stream, a);
     }
     return hip_check(hipGetLastError(), "last-axis fft launch");
 }
@@ -669,9 +714,11 @@ int middle_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     a.nblk = (int)((inner + PB - 1) / PB);
     a.total = a.nblk * a.n0 * p.L;
     if (pow2_len(a.ax.n))
-        hipLaunchKernelGGL((k_middle<T, PPT, false>), dim3(a.total), dim3(kFftThreads), 0, p.stream, a, inverse ? 1 : 0);
+        hipLaunchKernelGGL((k_middle<T, PPT, false>), dim3(a.total), dim3(kFftThreads), (size_t)a.n1 * sizeof(Cx<T>),
+                           p.stream, a, inverse ? 1 : 0);
     else
-        hipLaunchKernelGGL((k_middle<T, PPT, true>), dim3(a.total), dim3(kFftThreads), 0, p.stream, a, inverse ? 1 : 0);
+        hipLaunchKernelGGL((k_middle<T, PPT, true>), dim3(a.total), dim3(kFftThreads), (size_t)a.n1 * sizeof(Cx<T>),
+                           p.stream, a, inverse ? 1 : 0);
     return hip_check(hipGetLastError(), "middle-axis fft launch");
 }
 
@@ -693,13 +740,14 @@ int first_t(const feh_plan &p, const FftArgs &fa, int mode) {
     a.total = a.nblk * p.L;
     dim3 g(a.total), b(kFftThreads);
     const bool gen = !pow2_len(a.ax.n);
+    const size_t dyn = ((a.n0 * sizeof(Cx<T>) + 15) / 16) * 16 + (2 * (size_t)a.n0 + 4 * (size_t)PB) * sizeof(Cx<double>);
     switch (mode * 2 + (gen ? 1 : 0)) {
-    case 0: hipLaunchKernelGGL((k_first<T, PPT, DIM, 0, false>), g, b, 0, p.stream, a); break;
-    case 1: hipLaunchKernelGGL((k_first<T, PPT, DIM, 0, true>), g, b, 0, p.stream, a); break;
-    case 2: hipLaunchKernelGGL((k_first<T, PPT, DIM, 1, false>), g, b, 0, p.stream, a); break;
-    case 3: hipLaunchKernelGGL((k_first<T, PPT, DIM, 1, true>), g, b, 0, p.stream, a); break;
-    case 4: hipLaunchKernelGGL((k_first<T, PPT, DIM, 2, false>), g, b, 0, p.stream, a); break;
-    default: hipLaunchKernelGGL((k_first<T, PPT, DIM, 2, true>), g, b, 0, p.stream, a); break;
+    case 0: hipLaunchKernelGGL((k_first<T, PPT, DIM, 0, false>), g, b, dyn, p.stream, a); break;
+    case 1: hipLaunchKernelGGL((k_first<T, PPT, DIM, 0, true>), g, b, dyn, p.stream, a); break;
+    case 2: hipLaunchKernelGGL((k_first<T, PPT, DIM, 1, false>), g, b, dyn, p.stream, a); break;
+    case 3: hipLaunchKernelGGL((k_first<T, PPT, DIM, 1, true>), g, b, dyn, p.stream, a); break;
+    case 4: hipLaunchKernelGGL((k_first<T, PPT, DIM, 2, false>), g, b, dyn, p.stream, a); break;
+    default: hipLaunchKernelGGL((k_first<T, PPT, DIM, 2, true>), g, b, dyn, p.stream, a); break;
     }
     return hip_check(hipGetLastError(), "first-axis fft launch");
 }
