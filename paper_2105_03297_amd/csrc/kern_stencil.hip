@@ -41,55 +41,77 @@ struct EdgeK {
 
 // Strain (+ Ebar) -> stress -> edge fluxes of one tetrahedron with axis path
 // (A0, A1, A2), from G[i][a] = d u_i / d x_a.  Eb = (xx, yy, zz, yz, xz, xy).
-// E[(a * 4 + k) * 3 + i].
-template <typename T, int A0, int A1, int A2>
+// E[(a * 4 + k) * 3 + i].  UNIT: all voxel sizes are 1 (no 1/h factors);
+// EB: the macroscopic strain enters (right-hand side / residual only).
+template <typename T, int A0, int A1, int A2, bool UNIT, bool EB>
 __device__ __forceinline__ void tet_edges(const T (&G)[3][3], T lam, T mu, const T (&ih)[3], const T (&Eb)[6],
                                           T (&E)[36]) {
     constexpr int V1 = 1 << A0, V2 = V1 | (1 << A1);
     constexpr int k0 = EdgeK<A0, 0>::k, k1 = EdgeK<A1, V1>::k, k2 = EdgeK<A2, V2>::k;
-    const T e0 = G[0][0] + Eb[0], e1 = G[1][1] + Eb[1], e2 = G[2][2] + Eb[2];
+    T e0 = G[0][0], e1 = G[1][1], e2 = G[2][2];
+    if constexpr (EB) {
+        e0 += Eb[0];
+        e1 += Eb[1];
+        e2 += Eb[2];
+    }
     const T lt = lam * (e0 + e1 + e2), m2 = mu + mu;
     T S[3][3];
     S[0][0] = lt + m2 * e0;
     S[1][1] = lt + m2 * e1;
     S[2][2] = lt + m2 * e2;
-    S[1][2] = S[2][1] = mu * (G[1][2] + G[2][1]) + m2 * Eb[3];
-    S[0][2] = S[2][0] = mu * (G[0][2] + G[2][0]) + m2 * Eb[4];
-    S[0][1] = S[1][0] = mu * (G[0][1] + G[1][0]) + m2 * Eb[5];
+    S[1][2] = S[2][1] = mu * (G[1][2] + G[2][1]);
+    S[0][2] = S[2][0] = mu * (G[0][2] + G[2][0]);
+    S[0][1] = S[1][0] = mu * (G[0][1] + G[1][0]);
+    if constexpr (EB) {
+        S[1][2] = S[2][1] = S[1][2] + m2 * Eb[3];
+        S[0][2] = S[2][0] = S[0][2] + m2 * Eb[4];
+        S[0][1] = S[1][0] = S[0][1] + m2 * Eb[5];
+    }
     #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        E[(A0 * 4 + k0) * 3 + i] += S[i][A0] * ih[A0];
-        E[(A1 * 4 + k1) * 3 + i] += S[i][A1] * ih[A1];
-        E[(A2 * 4 + k2) * 3 + i] += S[i][A2] * ih[A2];
+        if constexpr (UNIT) {
+            E[(A0 * 4 + k0) * 3 + i] += S[i][A0];
+            E[(A1 * 4 + k1) * 3 + i] += S[i][A1];
+            E[(A2 * 4 + k2) * 3 + i] += S[i][A2];
+        } else {
+            E[(A0 * 4 + k0) * 3 + i] += S[i][A0] * ih[A0];
+            E[(A1 * 4 + k1) * 3 + i] += S[i][A1] * ih[A1];
+            E[(A2 * 4 + k2) * 3 + i] += S[i][A2] * ih[A2];
+        }
     }
 }
 
-template <typename T, int A0, int A1, int A2>
+template <typename T, int A0, int A1, int A2, bool UNIT, bool EB>
 __device__ __forceinline__ void tet_from_nodes(const T (&P)[8][3], T lam, T mu, const T (&ih)[3], const T (&Eb)[6],
                                                T (&E)[36]) {
     constexpr int V1 = 1 << A0, V2 = V1 | (1 << A1);
     T G[3][3];
     #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        G[i][A0] = (P[V1][i] - P[0][i]) * ih[A0];
-        G[i][A1] = (P[V2][i] - P[V1][i]) * ih[A1];
-        G[i][A2] = (P[7][i] - P[V2][i]) * ih[A2];
+        G[i][A0] = P[V1][i] - P[0][i];
+        G[i][A1] = P[V2][i] - P[V1][i];
+        G[i][A2] = P[7][i] - P[V2][i];
+        if constexpr (!UNIT) {
+            G[i][A0] *= ih[A0];
+            G[i][A1] *= ih[A1];
+            G[i][A2] *= ih[A2];
+        }
     }
-    tet_edges<T, A0, A1, A2>(G, lam, mu, ih, Eb, E);
+    tet_edges<T, A0, A1, A2, UNIT, EB>(G, lam, mu, ih, Eb, E);
 }
 
 // All six tetrahedra of a voxel; lam, mu already carry the tetrahedron volume.
-template <typename T>
+template <typename T, bool UNIT, bool EB>
 __device__ __forceinline__ void voxel3(const T (&P)[8][3], T lam, T mu, const T (&ih)[3], const T (&Eb)[6],
                                        T (&E)[36]) {
     #pragma unroll
     for (int j = 0; j < 36; ++j) E[j] = T(0);
-    tet_from_nodes<T, 0, 1, 2>(P, lam, mu, ih, Eb, E);
-    tet_from_nodes<T, 0, 2, 1>(P, lam, mu, ih, Eb, E);
-    tet_from_nodes<T, 1, 0, 2>(P, lam, mu, ih, Eb, E);
-    tet_from_nodes<T, 1, 2, 0>(P, lam, mu, ih, Eb, E);
-    tet_from_nodes<T, 2, 0, 1>(P, lam, mu, ih, Eb, E);
-    tet_from_nodes<T, 2, 1, 0>(P, lam, mu, ih, Eb, E);
+    tet_from_nodes<T, 0, 1, 2, UNIT, EB>(P, lam, mu, ih, Eb, E);
+    tet_from_nodes<T, 0, 2, 1, UNIT, EB>(P, lam, mu, ih, Eb, E);
+    tet_from_nodes<T, 1, 0, 2, UNIT, EB>(P, lam, mu, ih, Eb, E);
+    tet_from_nodes<T, 1, 2, 0, UNIT, EB>(P, lam, mu, ih, Eb, E);
+    tet_from_nodes<T, 2, 0, 1, UNIT, EB>(P, lam, mu, ih, Eb, E);
+    tet_from_nodes<T, 2, 1, 0, UNIT, EB>(P, lam, mu, ih, Eb, E);
 }
 
 // Element field given directly (projection test export): fluxes of |e| sym(e_T).
@@ -184,7 +206,7 @@ struct Tile<2> {
 
 constexpr int kStencilThreads = 256;
 
-template <typename T, int DIM, int MODE>
+template <typename T, int DIM, int MODE, bool UNIT>
 __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
     using TL = Tile<DIM>;
     constexpr int TY = TL::TY, TZ = TL::TZ, HY = TL::HY, NC = TL::NC, NEDGE = TL::NEDGE;
@@ -445,7 +467,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
                         #pragma unroll
                         for (int i = 0; i < 3; ++i) P[c][i] = Pl[bb][i][(vy + cyb) * EZ + vz + czb];
                     }
-                    voxel3<T>(P, lam, mu, a.ih, Eb, E);
+                    voxel3<T, UNIT, MODE == ST_RESID>(P, lam, mu, a.ih, Eb, E);
                 }
                 #pragma unroll
                 for (int j = 0; j < 36; ++j) Es[j][v] = E[j];
@@ -603,13 +625,20 @@ int launch_t(const feh_plan &p, int mode, const StencilArgs &sa) {
     a.total = p.L * a.nchunk * a.nty * a.ntz;
     a.part_stride = (int)p.part_stride;
     dim3 grid(a.total), block(kStencilThreads);
+    const bool unit = p.h[0] == 1.0 && p.h[1] == 1.0 && (DIM == 2 || p.h[2] == 1.0);
+#define FEH_STENCIL_CASE(M)                                                                                   \
+    case M:                                                                                                   \
+        if (unit) hipLaunchKernelGGL((k_stencil<T, DIM, M, true>), grid, block, 0, p.stream, a);             \
+        else hipLaunchKernelGGL((k_stencil<T, DIM, M, false>), grid, block, 0, p.stream, a);                 \
+        break;
     switch (mode) {
-    case ST_APPLY: hipLaunchKernelGGL((k_stencil<T, DIM, ST_APPLY>), grid, block, 0, p.stream, a); break;
-    case ST_CG: hipLaunchKernelGGL((k_stencil<T, DIM, ST_CG>), grid, block, 0, p.stream, a); break;
-    case ST_RESID: hipLaunchKernelGGL((k_stencil<T, DIM, ST_RESID>), grid, block, 0, p.stream, a); break;
-    case ST_DIV: hipLaunchKernelGGL((k_stencil<T, DIM, ST_DIV>), grid, block, 0, p.stream, a); break;
+        FEH_STENCIL_CASE(ST_APPLY)
+        FEH_STENCIL_CASE(ST_CG)
+        FEH_STENCIL_CASE(ST_RESID)
+        FEH_STENCIL_CASE(ST_DIV)
     default: return set_error(FEH_EINVAL, "bad stencil mode");
     }
+#undef FEH_STENCIL_CASE
     return hip_check(hipGetLastError(), "stencil launch");
 }
 
