@@ -269,14 +269,19 @@ struct FK {
     int RR, PB, nblk, total;
     int part_stride;
     int last_even;
-    int use_axpy;
+    int use_axpy;             // selects the AXPY instantiation on the host
     double out_scale, invN, chalf;  // chalf = element volume / 2
 };
 
 // ---------------------------------------------------------------------------
-// last axis, real -> half spectrum (optionally fused r -= alpha q)
+// last axis, real -> half spectrum (AXPY: fused r -= alpha q, r written back)
+//
+// Global memory is touched in two phases per kernel: every load of a thread
+// is issued before the first use (indices of slots past the end are clamped
+// into the block so the loads stay in bounds; their values are discarded),
+// then every store; r and r_out may be the same buffer.
 // ---------------------------------------------------------------------------
-template <typename T, int PPT, bool GEN>
+template <typename T, int PPT, bool GEN, bool AXPY>
 __global__ __launch_bounds__(kFftThreads) void k_last_fwd(FK<T> a) {
     constexpr int NT = kFftThreads;
     __shared__ Cx<T> buf[PPT * NT];
@@ -286,66 +291,99 @@ __global__ __launch_bounds__(kFftThreads) void k_last_fwd(FK<T> a) {
     T alpha = T(0);
     if (a.st) {
         if (!a.st[lc].active) return;
-        if (a.use_axpy) alpha = T(a.st[lc].alpha);
+        if (AXPY) alpha = T(a.st[lc].alpha);
     }
     const int D = a.D;
     const int nb = D * a.RR;
     const long long s0 = (long long)blk * a.RR;
     const int nrows = (int)min((long long)a.RR, a.rows - s0);
     const int nc = a.ax.n;
+    const int cnt = nb * nc;
     const long long N = a.N;
+    const int even = a.last_even;
     Cx<T> *twl = reinterpret_cast<Cx<T> *>(feh_dyn_lds);
     stage(twl, a.tw_last, a.nlast);
-    for (int e = threadIdx.x; e < nb * nc; e += NT) {
-        const int b = (int)a.d_nc.div((uint32_t)e);
-        const int j = e - b * nc;
-        const int sl = (int)a.d_D.div((uint32_t)b);
-        const int c = b - sl * D;
-        Cx<T> v = {T(0), T(0)};
-        if (sl < nrows) {
-            const long long base = ((long long)lc * D + c) * N + (s0 + sl) * a.nlast;
-            if (a.last_even) {
-                Cx<T> x = reinterpret_cast<const Cx<T> *>(a.r + base)[j];
-                if (a.use_axpy) {
-                    const Cx<T> qv = reinterpret_cast<const Cx<T> *>(a.q + base)[j];
-                    x.x -= alpha * qv.x;
-                    x.y -= alpha * qv.y;
-                    reinterpret_cast<Cx<T> *>(a.r_out + base)[j] = x;
-                }
-                v = x;
+    const long long lbase = (long long)lc * D * N + s0 * a.nlast;
+    // AXPY keeps two loads per slot in flight: 8 slots per round
+    constexpr int CH = AXPY ? 8 : PPT;
+    #pragma unroll
+    for (int h = 0; h < PPT; h += CH) {
+        Cx<T> v[CH];
+        Cx<T> w[AXPY ? CH : 1];
+        #pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int e0 = threadIdx.x + (h + k) * NT;
+            const int e = e0 < cnt ? e0 : 0;
+            const int b = (int)a.d_nc.div((uint32_t)e);
+            const int j = e - b * nc;
+            const int sl0 = (int)a.d_D.div((uint32_t)b);
+            const int c = b - sl0 * D;
+            const int sl = sl0 < nrows ? sl0 : nrows - 1;
+            // element offset of the packed pair (even) or of the sample (odd)
+            const long long off = lbase + (long long)c * N + (long long)sl * a.nlast + (even ? 2 * j : j);
+            if (even) {
+                v[k] = *reinterpret_cast<const Cx<T> *>(a.r + off);
+                if (AXPY) w[k] = *reinterpret_cast<const Cx<T> *>(a.q + off);
             } else {
-                T x = a.r[base + j];
-                if (a.use_axpy) {
-                    x -= alpha * a.q[base + j];
-                    a.r_out[base + j] = x;
-                }
-                v.x = x;
+                v[k] = Cx<T>{a.r[off], T(0)};
+                if (AXPY) w[k] = Cx<T>{a.q[off], T(0)};
             }
         }
-        buf[j * nb + b] = v;
+        #pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int e0 = threadIdx.x + (h + k) * NT;
+            const int e = e0 < cnt ? e0 : 0;
+            const int b = (int)a.d_nc.div((uint32_t)e);
+            const int j = e - b * nc;
+            const int sl = (int)a.d_D.div((uint32_t)b);
+            const int c = b - sl * D;
+            const bool ok = e0 < cnt && sl < nrows;
+            if (AXPY) {
+                v[k].x -= alpha * w[k].x;
+                v[k].y -= alpha * w[k].y;
+                if (ok) {
+                    const long long off = lbase + (long long)c * N + (long long)sl * a.nlast + (even ? 2 * j : j);
+                    if (even) *reinterpret_cast<Cx<T> *>(a.r_out + off) = v[k];
+                    else a.r_out[off] = v[k].x;
+                }
+            }
+            if (!ok) v[k] = Cx<T>{T(0), T(0)};
+            if (e0 < cnt) buf[j * nb + b] = v[k];
+        }
     }
     __syncthreads();
     lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, twl, a.tws, false);
+    // untangle the packed transform and store the half spectrum, components
+    // fastest; the count nrows * nh * D exceeds PPT * NT by at most nb
     const int nh = a.nh;
-    for (int e = threadIdx.x; e < nrows * nh * D; e += NT) {
+    const int ocnt = nrows * nh * D;
+    Cx<T> X[PPT + 1];
+    #pragma unroll
+    for (int k = 0; k < PPT + 1; ++k) {
+        const int e0 = threadIdx.x + k * NT;
+        const int e = e0 < ocnt ? e0 : 0;
         const int kk = (int)a.d_D.div((uint32_t)e);
         const int c = e - kk * D;
         const int sl = (int)a.d_nh.div((uint32_t)kk);
-        const int k = kk - sl * nh;
+        const int kx = kk - sl * nh;
         const int b = sl * D + c;
-        Cx<T> X;
-        if (a.last_even) {
-            const int ka = (k == nc) ? 0 : k;
-            const int kb = (k == 0) ? 0 : nc - k;
+        if (even) {
+            const int ka = (kx == nc) ? 0 : kx;
+            const int kb = (kx == 0) ? 0 : nc - kx;
             const Cx<T> Zk = buf[ka * nb + b], Zm = cconj(buf[kb * nb + b]);
             const Cx<T> A = {T(0.5) * (Zk.x + Zm.x), T(0.5) * (Zk.y + Zm.y)};
             const Cx<T> dZ = csub(Zk, Zm);
             const Cx<T> B = {T(0.5) * dZ.y, -T(0.5) * dZ.x};  // -i/2 (Zk - conj Z(nc-k))
-            X = cadd(A, cmul(twl[k], B));
+            X[k] = cadd(A, cmul(twl[kx], B));
         } else {
-            X = buf[k * nb + b];
+            X[k] = buf[kx * nb + b];
         }
-        a.spec[((long long)lc * a.rows + s0 + sl) * (long long)nh * D + (long long)k * D + c] = X;
+    }
+    Cx<T> *dst = a.spec + ((long long)lc * a.rows + s0) * (long long)nh * D;
+    #pragma unroll
+    for (int k = 0; k < PPT + 1; ++k) {
+        const int e0 = threadIdx.x + k * NT;
+        if (e0 < ocnt) dst[e0] = X[k];
     }
 }
 
@@ -366,47 +404,81 @@ __global__ __launch_bounds__(kFftThreads) void k_last_inv(FK<T> a) {
     const int nrows = (int)min((long long)a.RR, a.rows - s0);
     const int nc = a.ax.n;
     const int nh = a.nh;
+    const int cnt = nb * nc;
     const long long N = a.N;
+    const int even = a.last_even;
     Cx<T> *twl = reinterpret_cast<Cx<T> *>(feh_dyn_lds);
     stage(twl, a.tw_last, a.nlast);
-    // gather: e -> (sl, k, c), components fastest (coalesced spectrum reads)
-    for (int e = threadIdx.x; e < nb * nc; e += NT) {
-        const int kk = (int)a.d_D.div((uint32_t)e);
-        const int c = e - kk * D;
-        const int sl = (int)a.d_nc.div((uint32_t)kk);
-        const int k = kk - sl * nc;
-        const int b = sl * D + c;
-        Cx<T> Z = {T(0), T(0)};
-        if (sl < nrows) {
-            const Cx<T> *row = a.spec + ((long long)lc * a.rows + s0 + sl) * (long long)nh * D + c;
-            if (a.last_even) {
-                const Cx<T> Xk = row[(long long)k * D];
-                const Cx<T> Xm = cconj(row[(long long)(nc - k) * D]);
-                const Cx<T> A = cadd(Xk, Xm);
-                const Cx<T> B = cmulc(csub(Xk, Xm), a.tw_last[k]);  // exp(+2 pi i k / n) (Xk - conj X(nc-k))
-                Z = cadd(A, mul_pi(B));
+    __syncthreads();
+    // gather e -> (sl, k, c), components fastest (coalesced spectrum reads);
+    // the packed input Z(k) needs X(k) and X(nc - k)
+    const Cx<T> *src = a.spec + ((long long)lc * a.rows + s0) * (long long)nh * D;
+    constexpr int CH = PPT / 2;
+    #pragma unroll
+    for (int h = 0; h < PPT; h += CH) {
+        Cx<T> Xa[CH], Xb[CH];
+        #pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int e0 = threadIdx.x + (h + k) * NT;
+            const int e = e0 < cnt ? e0 : 0;
+            const int kk = (int)a.d_D.div((uint32_t)e);
+            const int c = e - kk * D;
+            const int sl0 = (int)a.d_nc.div((uint32_t)kk);
+            const int kx = kk - sl0 * nc;
+            const int sl = sl0 < nrows ? sl0 : nrows - 1;
+            const Cx<T> *row = src + (long long)sl * nh * D + c;
+            if (even) {
+                Xa[k] = row[(long long)kx * D];
+                Xb[k] = row[(long long)(nc - kx) * D];
             } else {
-                Z = (k < nh) ? row[(long long)k * D] : cconj(row[(long long)(a.nlast - k) * D]);
+                Xa[k] = row[(long long)(kx < nh ? kx : a.nlast - kx) * D];
             }
         }
-        buf[k * nb + b] = Z;
+        #pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int e0 = threadIdx.x + (h + k) * NT;
+            const int e = e0 < cnt ? e0 : 0;
+            const int kk = (int)a.d_D.div((uint32_t)e);
+            const int c = e - kk * D;
+            const int sl = (int)a.d_nc.div((uint32_t)kk);
+            const int kx = kk - sl * nc;
+            Cx<T> Z;
+            if (even) {
+                const Cx<T> Xm = cconj(Xb[k]);
+                const Cx<T> A = cadd(Xa[k], Xm);
+                const Cx<T> B = cmulc(csub(Xa[k], Xm), twl[kx]);  // exp(+2 pi i k / n) (Xk - conj X(nc-k))
+                Z = cadd(A, mul_pi(B));
+            } else {
+                Z = kx < nh ? Xa[k] : cconj(Xa[k]);
+            }
+            if (sl >= nrows) Z = Cx<T>{T(0), T(0)};
+            if (e0 < cnt) buf[kx * nb + sl * D + c] = Z;
+        }
     }
     __syncthreads();
     lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, twl, a.tws, true);
     const T sc = T(a.out_scale);
-    for (int e = threadIdx.x; e < nb * nc; e += NT) {
+    Cx<T> y[PPT];
+    #pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int e0 = threadIdx.x + k * NT;
+        const int e = e0 < cnt ? e0 : 0;
         const int b = (int)a.d_nc.div((uint32_t)e);
         const int j = e - b * nc;
+        y[k] = buf[j * nb + b];
+    }
+    const long long lbase = (long long)lc * D * N + s0 * a.nlast;
+    #pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int e0 = threadIdx.x + k * NT;
+        const int b = (int)a.d_nc.div((uint32_t)e0);
+        const int j = e0 - b * nc;
         const int sl = (int)a.d_D.div((uint32_t)b);
         const int c = b - sl * D;
-        if (sl < nrows) {
-            const long long base = ((long long)lc * D + c) * N + (s0 + sl) * a.nlast;
-            const Cx<T> v = buf[j * nb + b];
-            if (a.last_even) {
-                reinterpret_cast<Cx<T> *>(a.z + base)[j] = Cx<T>{v.x * sc, v.y * sc};
-            } else {
-                a.z[base + j] = v.x * sc;
-            }
+        if (e0 < cnt && sl < nrows) {
+            const long long o = lbase + (long long)c * N + (long long)sl * a.nlast;
+            if (even) reinterpret_cast<Cx<T> *>(a.z + o)[j] = Cx<T>{y[k].x * sc, y[k].y * sc};
+            else a.z[o + j] = y[k].x * sc;
         }
     }
 }
@@ -426,23 +498,42 @@ __global__ __launch_bounds__(kFftThreads) void k_middle(FK<T> a, int inv) {
     if (a.st && !a.st[lc].active) return;
     const int PB = a.PB;
     const int n1 = a.n1;
+    const int cnt = PB * n1;
     const long long inner = a.inner_total;
     const long long in0 = (long long)ib * PB;
     Cx<T> *base = a.spec + ((long long)lc * a.n0 + i0) * n1 * inner + in0;
     const int lim = (int)min((long long)PB, inner - in0);
     Cx<T> *twl = reinterpret_cast<Cx<T> *>(feh_dyn_lds);
     stage(twl, a.tw, n1);
-    for (int e = threadIdx.x; e < PB * n1; e += NT) {
+    Cx<T> v[PPT];
+    #pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int e0 = threadIdx.x + k * NT;
+        const int e = e0 < cnt ? e0 : 0;
         const int j = (int)a.d_PB.div((uint32_t)e);
         const int b = e - j * PB;
-        buf[e] = (b < lim) ? base[(long long)j * inner + b] : Cx<T>{T(0), T(0)};
+        v[k] = base[(long long)j * inner + (b < lim ? b : lim - 1)];
+    }
+    #pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int e0 = threadIdx.x + k * NT;
+        const int j = (int)a.d_PB.div((uint32_t)e0);
+        const int b = e0 - j * PB;
+        if (e0 < cnt) buf[e0] = (b < lim) ? v[k] : Cx<T>{T(0), T(0)};
     }
     __syncthreads();
     lds_fft<T, PPT, GEN>(buf, PB, a.d_PB, a.ax, twl, 1, inv != 0);
-    for (int e = threadIdx.x; e < PB * n1; e += NT) {
-        const int j = (int)a.d_PB.div((uint32_t)e);
-        const int b = e - j * PB;
-        if (b < lim) base[(long long)j * inner + b] = buf[e];
+    #pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int e0 = threadIdx.x + k * NT;
+        v[k] = buf[e0 < cnt ? e0 : 0];
+    }
+    #pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int e0 = threadIdx.x + k * NT;
+        const int j = (int)a.d_PB.div((uint32_t)e0);
+        const int b = e0 - j * PB;
+        if (e0 < cnt && b < lim) base[(long long)j * inner + b] = v[k];
     }
 }
 
@@ -533,10 +624,24 @@ __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
             }
         }
     }
-    for (int e = threadIdx.x; e < nb * n0; e += NT) {
-        const int j = (int)a.nbd.div((uint32_t)e);
-        const int bc = e - j * nb;
-        buf[e] = (bc < lim) ? base[(long long)j * inner * D + bc] : Cx<T>{T(0), T(0)};
+    const int cnt = nb * n0;
+    {
+        Cx<T> v[PPT];
+        #pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int e0 = threadIdx.x + k * NT;
+            const int e = e0 < cnt ? e0 : 0;
+            const int j = (int)a.nbd.div((uint32_t)e);
+            const int bc = e - j * nb;
+            v[k] = base[(long long)j * inner * D + (bc < lim ? bc : lim - 1)];
+        }
+        #pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int e0 = threadIdx.x + k * NT;
+            const int j = (int)a.nbd.div((uint32_t)e0);
+            const int bc = e0 - j * nb;
+            if (e0 < cnt) buf[e0] = (bc < lim) ? v[k] : Cx<T>{T(0), T(0)};
+        }
     }
     __syncthreads();
     if (MODE != 2) lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, twl, 1, false);
@@ -607,10 +712,20 @@ __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
         __syncthreads();
     }
     if (MODE != 1) lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, twl, 1, true);
-    for (int e = threadIdx.x; e < nb * n0; e += NT) {
-        const int j = (int)a.nbd.div((uint32_t)e);
-        const int bc = e - j * nb;
-        if (bc < lim) base[(long long)j * inner * D + bc] = buf[e];
+    {
+        Cx<T> v[PPT];
+        #pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int e0 = threadIdx.x + k * NT;
+            v[k] = buf[e0 < cnt ? e0 : 0];
+        }
+        #pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int e0 = threadIdx.x + k * NT;
+            const int j = (int)a.nbd.div((uint32_t)e0);
+            const int bc = e0 - j * nb;
+            if (e0 < cnt && bc < lim) base[(long long)j * inner * D + bc] = v[k];
+        }
     }
     if (MODE == 0 && a.partial) {
         const double s = block_sum<NT>(acc, red);
@@ -689,8 +804,13 @@ int last_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
         if (gen) hipLaunchKernelGGL((k_last_inv<T, PPT, true>), g, b, dyn, p.stream, a);
         else hipLaunchKernelGGL((k_last_inv<T, PPT, false>), g, b, dyn, p.stream, a);
     } else {
-        if (gen) hipLaunchKernelGGL((k_last_fwd<T, PPT, true>), g, b, dyn, p.stream, a);
-        else hipLaunchKernelGGL((k_last_fwd<T, PPT, false>), g, b, dyn, p.stream, a);
+        if (a.use_axpy) {
+            if (gen) hipLaunchKernelGGL((k_last_fwd<T, PPT, true, true>), g, b, dyn, p.stream, a);
+            else hipLaunchKernelGGL((k_last_fwd<T, PPT, false, true>), g, b, dyn, p.stream, a);
+        } else {
+            if (gen) hipLaunchKernelGGL((k_last_fwd<T, PPT, true, false>), g, b, dyn, p.stream, a);
+            else hipLaunchKernelGGL((k_last_fwd<T, PPT, false, false>), g, b, dyn, p.stream, a);
+        }
     }
     return hip_check(hipGetLastError(), "last-axis fft launch");
 }
