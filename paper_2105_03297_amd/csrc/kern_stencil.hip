@@ -17,13 +17,17 @@
 // in a uniform region every bracket is exactly zero, so a uniform strain in
 // a uniform material produces exactly zero force in any precision.
 //
-// Kernel layout: one workgroup owns a TY x TZ tile of nodes in the (axis 1,
-// axis 2) plane and marches along axis 0 over a chunk of planes.  Per step
-// it stages one node plane (one-node halo) in LDS, evaluates every voxel of
-// the extended voxel plane once (12 edge fluxes into LDS), and each node
-// thread combines the edge fluxes of the voxels around it; the terms whose
-// voxels lie in the previous plane are carried in registers.  The fused CG
-// variant also forms p = z + beta p_old on the fly, writes p, applies the
+// Kernel layout: one workgroup evaluates a VY x VZ tile of voxels in the
+// (axis 1, axis 2) plane, one voxel per thread, and marches along axis 0 over
+// a chunk of planes.  The nodes it updates are those whose in-plane voxels
+// all lie in the tile ((VY - 1) x (VZ - 1) in 3D, VZ - 1 in 2D); neighbouring
+// tiles overlap by one voxel row and column, which keeps every wave on the
+// same instruction stream (no extra round for halo voxels).  Per step the
+// workgroup stages one node plane of the tile (one extra row and column of
+// nodes) in LDS, each thread evaluates its voxel (edge fluxes into LDS), and
+// each updated node combines the fluxes of its in-plane voxels; the terms
+// whose voxels lie in the previous plane are carried in registers.  The fused
+// CG variant also forms p = z + beta p_old on the fly, writes p, applies the
 // pending u += alpha p_old and accumulates p.q in FP64.
 #include "device_common.hpp"
 
@@ -190,18 +194,20 @@ struct SK {
     int ident;         // lambda = 0, mu = 1/2 everywhere
 };
 
-// Tile shapes: TY x TZ nodes per workgroup (one node per thread); the voxel
-// plane of a tile needs one extra row (y0 - 1) and column (z0 - 1), which
-// the first NV - TY*TZ threads evaluate in a second round.
+// Tile shapes: VY x VZ voxels per workgroup (one per thread).  HY = 1 when
+// the tile has an axis-1 extent (3D); the node plane of the tile is
+// (VY + HY) x (VZ + 1), the updated nodes advance by SY x SZ between tiles.
 template <int DIM>
 struct Tile;
 template <>
 struct Tile<3> {
-    static constexpr int TY = 8, TZ = 32, HY = 1, NC = 3, NEDGE = 12;
+    static constexpr int VY = 8, VZ = 32, HY = 1, NC = 3, NEDGE = 12;
+    static constexpr int SY = VY - 1, SZ = VZ - 1;
 };
 template <>
 struct Tile<2> {
-    static constexpr int TY = 1, TZ = 256, HY = 0, NC = 2, NEDGE = 4;
+    static constexpr int VY = 1, VZ = 256, HY = 0, NC = 2, NEDGE = 4;
+    static constexpr int SY = 1, SZ = VZ - 1;
 };
 
 constexpr int kStencilThreads = 256;
@@ -209,15 +215,14 @@ constexpr int kStencilThreads = 256;
 template <typename T, int DIM, int MODE, bool UNIT>
 __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
     using TL = Tile<DIM>;
-    constexpr int TY = TL::TY, TZ = TL::TZ, HY = TL::HY, NC = TL::NC, NEDGE = TL::NEDGE;
-    constexpr int EY = TY + 2 * HY, EZ = TZ + 2, VY = TY + HY, VZ = TZ + 1;
-    constexpr int NE = EY * EZ, NV = VY * VZ, NT = kStencilThreads;
+    constexpr int VY = TL::VY, VZ = TL::VZ, HY = TL::HY, NC = TL::NC, NEDGE = TL::NEDGE;
+    constexpr int EY = VY + HY, EZ = VZ + 1;     // node plane of the tile
+    constexpr int NE = EY * EZ, NT = kStencilThreads;
     constexpr int NQ = NEDGE * NC;               // edge-flux values per voxel
     constexpr int NSE = (NE + NT - 1) / NT;      // node-plane slots per thread
-    constexpr int NSV = (NV + NT - 1) / NT;      // voxel slots per thread
-    static_assert(TY * TZ == NT, "one node per thread");
+    static_assert(VY * VZ == NT, "one voxel per thread");
     __shared__ T Pl[3][NC][NE];                  // ring of three node planes
-    __shared__ T Es[NQ][NV];
+    __shared__ T Es[NQ][NT];                     // edge fluxes, one column per voxel
     __shared__ double red[NT / 64];
 
     const int tid = threadIdx.x;
@@ -253,133 +258,102 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
         }
     }
 
-    const int y0 = ty_t * TY, z0 = tz_t * TZ;
+    // in-plane origin of the tile's node plane (extended index (0, 0)); the
+    // updated nodes start one row (3D) and one column further on
+    const int y0 = ty_t * TL::SY - HY, z0 = tz_t * TL::SZ - 1;
     const int x0 = ch * a.xc;
     const int x1 = min(x0 + a.xc, a.n0);
     const long long N = a.N;
     const long long plane = (long long)a.n1 * a.n2;
     const long long lcoff = (long long)lc * NC * N;
-    const int ty = tid / TZ, tz = tid - (tid / TZ) * TZ;
+    const int ty = tid / VZ, tz = tid - (tid / VZ) * VZ;
+    // the thread's voxel has its origin at node (ty, tz) of the tile; that
+    // node is updated here when all of its in-plane voxels are in the tile
+    const bool owner = ty >= HY && tz >= 1 && y0 + ty < a.n1 && z0 + tz < a.n2;
 
-    // ---- per-thread slots, fixed for the whole march.  Node-plane slot 0 is
-    // the thread's own node (extended index (ty + HY, tz + 1)); later slots
-    // cover the halo ring.  Voxel slot 0 is the voxel at the thread's node,
-    // later slots the halo row / column of voxels.
+    // ---- per-thread node slots, fixed for the whole march.  Slot 0 is the
+    // thread's own node; later slots cover the last row and column.
     int e_lds[NSE];        // extended node index, -1 if unused
     long long e_off[NSE];  // in-plane global offset
-    bool e_in[NSE];        // node owned (written) by this tile
     #pragma unroll
     for (int s = 0; s < NSE; ++s) {
         int ey = -1, ez = -1;
         if (s == 0) {
-            ey = ty + HY;
-            ez = tz + 1;
+            ey = ty;
+            ez = tz;
         } else {
-            const int hh = tid + (s - 1) * NT;  // halo node number
-            constexpr int NH = NE - TY * TZ;
+            const int hh = tid + (s - 1) * NT;  // extra node number
+            constexpr int NH = NE - NT;
             if (hh < NH) {
                 if constexpr (HY == 0) {
-                    // single row: the two end nodes
-                    ey = 0;
-                    ez = (hh & 1) ? EZ - 1 : 0;
+                    ey = 0;  // single row: its last node
+                    ez = EZ - 1;
                 } else if (hh < EZ) {
-                    ey = 0;  // row y0 - 1
+                    ey = EY - 1;  // last row
                     ez = hh;
-                } else if (hh < 2 * EZ) {
-                    ey = EY - 1;  // row y0 + TY
-                    ez = hh - EZ;
                 } else {
-                    const int r = hh - 2 * EZ;  // columns z0 - 1 and z0 + TZ
-                    ey = HY + r / 2;
-                    ez = (r & 1) ? EZ - 1 : 0;
+                    ey = hh - EZ;  // last column, rows 0 .. EY - 2
+                    ez = EZ - 1;
                 }
             }
         }
         if (ey >= 0) {
-            const int yy = y0 - HY + ey, zz = z0 - 1 + ez;
             e_lds[s] = ey * EZ + ez;
-            e_off[s] = (long long)wrap(yy, a.n1) * a.n2 + wrap(zz, a.n2);
-            e_in[s] = (s == 0) && yy < a.n1 && zz < a.n2;
+            e_off[s] = (long long)wrap(y0 + ey, a.n1) * a.n2 + wrap(z0 + ez, a.n2);
         } else {
-            e_lds[s] = -1;
-            e_off[s] = 0;
-            e_in[s] = false;
+            e_lds[s] = -1;  // not staged; its loads re-read the own node
+            e_off[s] = e_off[0];
         }
     }
-    int v_lds[NSV];
-    long long v_off[NSV];
-    #pragma unroll
-    for (int s = 0; s < NSV; ++s) {
-        int vy = -1, vz = -1;
-        if (s == 0) {
-            vy = ty + HY;
-            vz = tz + 1;
-        } else {
-            const int hh = tid + (s - 1) * NT;
-            constexpr int NHV = NV - TY * TZ;
-            if (hh < NHV) {
-                if (hh < VZ) {
-                    vy = 0;
-                    vz = hh;
-                } else {
-                    vy = hh - VZ + 1;
-                    vz = 0;
-                }
-            }
-        }
-        if (vy >= 0) {
-            v_lds[s] = vy * VZ + vz;
-            v_off[s] = (long long)wrap(y0 - HY + vy, a.n1) * a.n2 + wrap(z0 - 1 + vz, a.n2);
-        } else {
-            v_lds[s] = -1;
-            v_off[s] = 0;
-        }
-    }
+    const long long v_off = (long long)wrap(y0 + ty, a.n1) * a.n2 + wrap(z0 + tz, a.n2);
 
-    // ---- prefetch registers: node plane P (values needed to form p) and the
-    // material of one voxel plane
-    T rz[NSE][NC], rp[NSE][NC], ru[NC];  // u only at the thread's own node (slot 0)
-    T mlam[NSV], mmu[NSV], clam[NSV], cmu[NSV];
-    auto fetch_nodes = [&](int P) __attribute__((always_inline)) {
+    // ---- prefetch registers, two sets: node plane P goes to set
+    // (P - x0 + 1) & 1 two steps before it is staged, and so does the material
+    // of voxel plane V, so that two planes of loads are in flight per thread.
+    // Every load is unconditional (unused slots and planes past the chunk
+    // re-read valid addresses) so the waits for a set never cover the other.
+    T rz[2][NSE][NC], rp[2][NSE][NC], ru[2][NC];  // u only at the thread's own node (slot 0)
+    T mlam[2] = {T(0), T(0)}, mmu[2] = {T(0), T(0)};
+    auto fetch_nodes = [&](auto S, int P) __attribute__((always_inline)) {
+        constexpr int B = decltype(S)::value;
         const long long base = (long long)wrap(P, a.n0) * plane;
         #pragma unroll
         for (int s = 0; s < NSE; ++s) {
-            if (e_lds[s] >= 0) {
             #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const long long gi = lcoff + c * N + base + e_off[s];
                 if constexpr (MODE == ST_APPLY) {
-                    rz[s][c] = a.in0[gi];
+                    rz[B][s][c] = a.in0[gi];
                 } else if constexpr (MODE == ST_CG) {
                     // before the first search direction beta = alpha_pend = 0
                     // and both p buffers are zero-filled, so no branch is needed
-                    rz[s][c] = a.in0[gi];
-                    rp[s][c] = pold[gi];
-                    if (s == 0) ru[c] = a.u[gi];
+                    rz[B][s][c] = a.in0[gi];
+                    rp[B][s][c] = pold[gi];
+                    if (s == 0) ru[B][c] = a.u[gi];
                 } else if constexpr (MODE == ST_RESID) {
-                    rz[s][c] = a.in0 ? a.in0[gi] : T(0);
+                    rz[B][s][c] = a.in0 ? a.in0[gi] : T(0);
                 }
-            }
             }
         }
     };
-    auto commit_nodes = [&](int P) __attribute__((always_inline)) {
+    auto commit_nodes = [&](auto S, int P) __attribute__((always_inline)) {
+        constexpr int B = decltype(S)::value;
         const long long base = (long long)wrap(P, a.n0) * plane;
         const bool interior_plane = P >= x0 && P < x1;
         const int buf = (P + 3) % 3;
         #pragma unroll
         for (int s = 0; s < NSE; ++s) {
             if (e_lds[s] >= 0) {
-            const bool inter = interior_plane && e_in[s];
+            const bool inter = interior_plane && s == 0 && owner;
             #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                T v = rz[s][c];
+                T v = rz[B][s][c];
                 if constexpr (MODE == ST_CG) {
                     const long long gi = lcoff + c * N + base + e_off[s];
-                    v = rz[s][c] + beta * rp[s][c];
+                    v = rz[B][s][c] + beta * rp[B][s][c];
                     if (inter) {
                         pnew[gi] = v;
-                        if (s == 0) a.u[gi] = ru[c] + alpha_pend * rp[s][c];
+                        if (s == 0) a.u[gi] = ru[B][c] + alpha_pend * rp[B][s][c];
                     }
                 }
                 Pl[buf][c][e_lds[s]] = v;
@@ -387,16 +361,14 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
             }
         }
     };
-    auto fetch_material = [&](int V) __attribute__((always_inline)) {
+    auto fetch_material = [&](auto S, int V) __attribute__((always_inline)) {
+        constexpr int B = decltype(S)::value;
         const long long base = (long long)wrap(V, a.n0) * plane;
-        #pragma unroll
-        for (int s = 0; s < NSV; ++s) {
-            if (v_lds[s] >= 0 && !a.ident) {
-                mlam[s] = a.lam[base + v_off[s]];
-                mmu[s] = a.mu[base + v_off[s]];
-            }
-        }
+        mlam[B] = a.lam[base + v_off];  // unused (but allocated) for the identity material
+        mmu[B] = a.mu[base + v_off];
     };
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, 1>;
 
     // carried terms: raw axis-0 edge fluxes of the previous voxel plane, and
     // the differences of the other axes' edges whose voxels lie in the
@@ -411,44 +383,44 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
     double acc = 0.0;
 
     if constexpr (MODE != ST_DIV) {
-        fetch_nodes(x0 - 1);
-        commit_nodes(x0 - 1);
-        fetch_nodes(x0);
+        fetch_nodes(S0{}, x0 - 1);
+        commit_nodes(S0{}, x0 - 1);
+        fetch_nodes(S1{}, x0);
+        fetch_nodes(S0{}, min(x0 + 1, x1));
     }
-    fetch_material(x0 - 1);
+    fetch_material(S0{}, x0 - 1);
+    fetch_material(S1{}, x0);
 
-    for (int X = x0 - 1; X < x1; ++X) {
-        // ---- stage plane X+1, prefetch plane X+2 and the material of voxel plane X+1
-        if constexpr (MODE != ST_DIV) commit_nodes(X + 1);
-        #pragma unroll
-        for (int s = 0; s < NSV; ++s) {
-            clam[s] = mlam[s];
-            cmu[s] = mmu[s];
-        }
-        if (X + 2 <= x1) {
-            if constexpr (MODE != ST_DIV) fetch_nodes(X + 2);
-        }
-        if (X + 1 < x1) fetch_material(X + 1);
+    // voxel column of the node's in-plane voxels at offset (-dy, -dz); threads
+    // that update no node read an interior column instead (results unused)
+    const int vo = (ty >= HY && tz >= 1) ? tid : HY * VZ + 1;
+    auto vix = [&](int dy, int dz) { return vo - dy * VZ - dz; };
+
+    // one step: voxel plane X, whose nodes are staged in planes X and X + 1;
+    // SN is the register set of node plane X + 1, SM that of voxel plane X
+    auto step = [&](auto SN, auto SM, int X) __attribute__((always_inline)) {
+        constexpr int BM = decltype(SM)::value;
+        // ---- stage plane X+1, prefetch plane X+3 and the material of voxel plane X+2
+        if constexpr (MODE != ST_DIV) commit_nodes(SN, X + 1);
+        const T clam = mlam[BM], cmu = mmu[BM];
+        if constexpr (MODE != ST_DIV) fetch_nodes(SN, min(X + 3, x1));
+        fetch_material(SM, min(X + 2, x1 - 1));
         __syncthreads();
-        // ---- voxel phase: voxel plane X of the extended tile
+        // ---- voxel phase: the thread's voxel in plane X
         const int b0 = (X + 3) % 3, b1 = (X + 4) % 3;
-        #pragma unroll
-        for (int s = 0; s < NSV; ++s) {
-            const int v = v_lds[s];
-            if (v >= 0) {
-            const int vy = v / VZ, vz = v - (v / VZ) * VZ;
+        {
             T lam, mu;
             if (a.ident) {
                 lam = T(0);
                 mu = T(0.5) * a.vol;
             } else {
-                lam = clam[s] * a.vol;
-                mu = cmu[s] * a.vol;
+                lam = clam * a.vol;
+                mu = cmu * a.vol;
             }
             if constexpr (DIM == 3) {
                 T E[36];
                 if constexpr (MODE == ST_DIV) {
-                    const long long vidx = (long long)wrap(X, a.n0) * plane + v_off[s];
+                    const long long vidx = (long long)wrap(X, a.n0) * plane + v_off;
                     const T *e = a.in0 + ((long long)lc * N + vidx) * 54;
                     #pragma unroll
                     for (int j = 0; j < 36; ++j) E[j] = T(0);
@@ -465,16 +437,16 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
                         const int cyb = (c >> 1) & 1, czb = (c >> 2) & 1;
                         const int bb = (c & 1) ? b1 : b0;
                         #pragma unroll
-                        for (int i = 0; i < 3; ++i) P[c][i] = Pl[bb][i][(vy + cyb) * EZ + vz + czb];
+                        for (int i = 0; i < 3; ++i) P[c][i] = Pl[bb][i][(ty + cyb) * EZ + tz + czb];
                     }
                     voxel3<T, UNIT, MODE == ST_RESID>(P, lam, mu, a.ih, Eb, E);
                 }
                 #pragma unroll
-                for (int j = 0; j < 36; ++j) Es[j][v] = E[j];
+                for (int j = 0; j < 36; ++j) Es[j][tid] = E[j];
             } else {
                 T E[8];
                 if constexpr (MODE == ST_DIV) {
-                    const long long vidx = (long long)wrap(X, a.n0) * plane + v_off[s];
+                    const long long vidx = (long long)wrap(X, a.n0) * plane + v_off;
                     voxel2_div<T>(a.in0 + ((long long)lc * N + vidx) * 8, a.vol, a.ih[0], a.ih[1], E);
                 } else {
                     T P[4][2];
@@ -483,18 +455,17 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
                         const int c1 = (c >> 1) & 1;
                         const int bb = (c & 1) ? b1 : b0;
                         #pragma unroll
-                        for (int i = 0; i < 2; ++i) P[c][i] = Pl[bb][i][vz + c1];
+                        for (int i = 0; i < 2; ++i) P[c][i] = Pl[bb][i][tz + c1];
                     }
                     const T Eb2[3] = {Eb[0], Eb[1], Eb[2]};
                     voxel2<T>(P, lam, mu, a.ih[0], a.ih[1], Eb2, E);
                 }
                 #pragma unroll
-                for (int j = 0; j < 8; ++j) Es[j][v] = E[j];
-            }
+                for (int j = 0; j < 8; ++j) Es[j][tid] = E[j];
             }
         }
         __syncthreads();
-        // ---- node phase (one node per thread)
+        // ---- node phase (the thread's own node)
         {
             T q[NC], nq[NC];
             #pragma unroll
@@ -502,8 +473,6 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
                 q[i] = cq[i];
                 nq[i] = T(0);
             }
-            // voxel of the node's plane at in-plane offset (-dy, -dz)
-            auto vix = [&](int dy, int dz) { return (ty + HY - dy) * VZ + (tz + 1 - dz); };
             if constexpr (DIM == 3) {
                 // axis-0 edges: E_{0,k}(n - e_x - c) - E_{0,k}(n - c), c = (0, cy, cz), k = cy + 2 cz
                 #pragma unroll
@@ -556,7 +525,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
                     nq[i] += Es[(1 * 2 + 1) * 2 + i][vlo] - Es[(1 * 2 + 1) * 2 + i][vhi];
                 }
             }
-            if (X >= x0 && e_in[0]) {
+            if (X >= x0 && owner) {
                 const long long idx = (long long)X * plane + e_off[0];
                 #pragma unroll
                 for (int i = 0; i < NC; ++i) {
@@ -574,6 +543,11 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
             #pragma unroll
             for (int i = 0; i < NC; ++i) cq[i] = nq[i];
         }
+    };
+
+    for (int X = x0 - 1; X < x1; X += 2) {
+        step(S1{}, S0{}, X);
+        if (X + 1 < x1) step(S0{}, S1{}, X + 1);
     }
     if constexpr (MODE == ST_CG) {
         const double s = block_sum<NT>(acc, red);
@@ -620,8 +594,8 @@ int launch_t(const feh_plan &p, int mode, const StencilArgs &sa) {
     a.N = p.N;
     a.xc = xchunk(a.n0);
     a.nchunk = (a.n0 + a.xc - 1) / a.xc;
-    a.nty = (a.n1 + TL::TY - 1) / TL::TY;
-    a.ntz = (a.n2 + TL::TZ - 1) / TL::TZ;
+    a.nty = (a.n1 + TL::SY - 1) / TL::SY;
+    a.ntz = (a.n2 + TL::SZ - 1) / TL::SZ;
     a.total = p.L * a.nchunk * a.nty * a.ntz;
     a.part_stride = (int)p.part_stride;
     dim3 grid(a.total), block(kStencilThreads);
@@ -649,10 +623,10 @@ int stencil_num_parts(const feh_plan &p) {
     const int xc = xchunk(n0);
     const int nchunk = (n0 + xc - 1) / xc;
     if (p.dim == 3) {
-        return nchunk * (int)((p.n[1] + Tile<3>::TY - 1) / Tile<3>::TY) *
-               (int)((p.n[2] + Tile<3>::TZ - 1) / Tile<3>::TZ);
+        return nchunk * (int)((p.n[1] + Tile<3>::SY - 1) / Tile<3>::SY) *
+               (int)((p.n[2] + Tile<3>::SZ - 1) / Tile<3>::SZ);
     }
-    return nchunk * (int)((p.n[1] + Tile<2>::TZ - 1) / Tile<2>::TZ);
+    return nchunk * (int)((p.n[1] + Tile<2>::SZ - 1) / Tile<2>::SZ);
 }
 
 int launch_stencil(const feh_plan &p, int mode, const StencilArgs &a) {
