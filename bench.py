@@ -33,28 +33,29 @@ def kernel_bytes(dim, s, n_last, iters, n_voxels):
 
     Per voxel and active load case (V = D s for a nodal vector, Vh = D 2 s
     (n_last/2+1)/n_last for the half spectrum):
-      stencil      read z, p_old, u; write p, q, u: 6V (3V in a load case's
-                   first iteration: no p_old, no pending u update); plus the
-                   (lambda, mu) material once per launch: 2 s per voxel
+      stencil      read p, write q: 2V; plus the (lambda, mu) material once
+                   per launch: 2 s per voxel
       last fwd     read r, q; write r and the half spectrum: 3V + Vh
       middle       read + write the spectrum: 2 Vh (each direction, 3D)
       first+solve  read + write the spectrum: 2 Vh
-      last inv     read the spectrum, write z: Vh + V
+      last inv     read the spectrum, p and u; write p and u: Vh + 4V
+    The inverse passes do not run in the iteration at which a load case
+    stops (its last u += alpha p is applied by the finalisation).
     """
     V = dim * s
     Vh = dim * 2 * s * (n_last // 2 + 1) / n_last
     lc_it = float(sum(iters))
-    firsts = float(sum(1 for i in iters if i > 0))
+    stops = float(sum(1 for i in iters if i > 0))
     launches = float(max(iters)) if iters else 0.0
     out = {
-        "stencil": ((lc_it - firsts) * 6 * V + firsts * 3 * V) * n_voxels + launches * 2 * s * n_voxels,
+        "stencil": lc_it * 2 * V * n_voxels + launches * 2 * s * n_voxels,
         "fft_last_fwd": lc_it * (3 * V + Vh) * n_voxels,
         "fft_first_ksolve": lc_it * 2 * Vh * n_voxels,
-        "fft_last_inv": lc_it * (Vh + V) * n_voxels,
+        "fft_last_inv": (lc_it - stops) * (Vh + 4 * V) * n_voxels,
     }
     if dim == 3:
         out["fft_middle_fwd"] = lc_it * 2 * Vh * n_voxels
-        out["fft_middle_inv"] = lc_it * 2 * Vh * n_voxels
+        out["fft_middle_inv"] = (lc_it - stops) * 2 * Vh * n_voxels
     return out
 
 

@@ -95,8 +95,9 @@ int feh_plan_create(feh_plan **plan, int dim, const int64_t n[], const double h[
 /* Destroy a plan (NULL is a no-op).  Does not free the workspace. */
 int feh_plan_destroy(feh_plan *plan);
 
-/* Bytes of device workspace the plan needs (vectors u, r, z, p (two), q,
- * the half spectrum, the material, tables, partial sums and CG scalars). */
+/* Bytes of device workspace the plan needs (nodal vectors u, r, p, q for
+ * every load case, the half spectrum, the material, tables, partial sums and
+ * CG scalars). */
 int feh_plan_workspace_bytes(const feh_plan *plan, size_t *bytes);
 
 /* Hand the plan a device buffer of at least feh_plan_workspace_bytes bytes,

@@ -8,11 +8,12 @@
 // vectors are nodal displacement fields; B, B^T run as real-space stencils
 // (kern_stencil.hip) and only M^+ is applied per wavevector
 // (kern_fft.hip).  Per iteration and load case:
-//   stencil:  p = z + beta p (or z), u += alpha_prev p_prev, q = K p, p.q
+//   stencil:  q = K p, p.q
 //   scalars:  alpha = rho / p.q
 //   FFT:      r -= alpha q fused into the last-axis r2c, first-axis pass with
-//             z^ = M^-1 r^ and rho_new = r.z by Parseval, inverse passes
+//             z^ = M^-1 r^ and rho_new = r.z by Parseval
 //   scalars:  stop test sqrt(rho_new / f.M^+f) <= tol, beta = rho_new / rho
+//   FFT:      inverse passes; the last one applies u += alpha p, p = z + beta p
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -81,9 +82,7 @@ static void layout(feh_plan &p) {
     };
     p.off_u = take(vec);
     p.off_r = take(vec);
-    p.off_z = take(vec);
-    p.off_p0 = take(vec);
-    p.off_p1 = take(vec);
+    p.off_p = take(vec);
     p.off_q = take(vec);
     p.off_spec = take((size_t)p.L * p.dim * p.Nspec * 2 * p.rsize);
     p.off_lam = take(p.N * p.rsize);
@@ -169,6 +168,7 @@ static int read_flag(feh_plan &p, int *flag_dev, const char *what) {
 }
 
 // z = M^+ r on SoA fields (spectrum buffer as scratch); Parseval r.z partials.
+// r is consumed by the first pass, so z may be the same buffer.
 static int precondition(const feh_plan &p, const void *r, void *z, double *partial, const LcState *st) {
     FftArgs fa;
     fa.r = r;
@@ -219,16 +219,17 @@ static void prof_drain(const feh_plan &p) {
     p.prof_used = 0;
 }
 
+// One preconditioned CG iteration for every active load case:
+//   q = K p, alpha = rho / p.q; r -= alpha q and z = M^+ r (FFT pipeline, with
+//   rho_new = r.z from the k-solve); beta = rho_new / rho; then, fused into the
+//   last inverse pass, u += alpha p and p = z + beta p.  A load case that stops
+//   at the convergence test keeps its last u += alpha p pending (applied by
+//   the finalisation).
 static int cg_iteration(const feh_plan &p, LcState *st, double tol, int max_iter) {
     double *part = p.ptr<double>(p.off_part);
     StencilArgs sa;
-    sa.in0 = p.ws + p.off_z;
-    sa.in1 = p.ws + p.off_p0;
-    sa.in1b = p.ws + p.off_p1;
+    sa.in0 = p.ws + p.off_p;
     sa.out0 = p.ws + p.off_q;
-    sa.out1 = p.ws + p.off_p0;
-    sa.out1b = p.ws + p.off_p1;
-    sa.u = p.ws + p.off_u;
     sa.partial = part;
     sa.state = st;
     {
@@ -244,7 +245,8 @@ static int cg_iteration(const feh_plan &p, LcState *st, double tol, int max_iter
     fa.q = p.ws + p.off_q;
     fa.r_out = p.ws + p.off_r;
     fa.spec = p.ws + p.off_spec;
-    fa.z = p.ws + p.off_z;
+    fa.p_upd = p.ws + p.off_p;
+    fa.u_upd = p.ws + p.off_u;
     fa.partial = part;
     fa.state = st;
     fa.out_scale = 1.0 / (double)p.N;
@@ -260,16 +262,16 @@ static int cg_iteration(const feh_plan &p, LcState *st, double tol, int max_iter
         ProfScope ps(p, 4);
         CK(launch_first_fused(p, fa));
     }
+    {
+        ProfScope ps(p, 7);
+        CK(launch_finish_rho(p, st, part, first_num_parts(p), 2, tol, max_iter));
+    }
     if (p.dim == 3) {
         ProfScope ps(p, 5);
         CK(launch_middle(p, fa, true));
     }
-    {
-        ProfScope ps(p, 6);
-        CK(launch_inverse_last(p, fa));
-    }
-    ProfScope ps(p, 7);
-    return launch_finish_rho(p, st, part, first_num_parts(p), 2, tol, max_iter);
+    ProfScope ps(p, 6);
+    return launch_inverse_last(p, fa);
 }
 
 static void invert(int n, std::vector<double> &A, bool &ok) {
@@ -481,8 +483,6 @@ int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
         double *part = p.ptr<double>(p.off_part);
         const size_t nvec = (size_t)p.L * D * p.N;
         CK(launch_init_state(p, st, p.L));
-        CK(launch_fill(p, p.ws + p.off_p0, nvec, 0.0));
-        CK(launch_fill(p, p.ws + p.off_p1, nvec, 0.0));
         StencilArgs sa;
         sa.Ebar = ebar_dev;
         if (u0_dev) {
@@ -493,17 +493,17 @@ int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
             sa.in0 = nullptr;
             sa.out0 = p.ws + p.off_q;
             CK(launch_stencil(p, ST_RESID, sa));
-            CK(precondition(p, p.ws + p.off_q, p.ws + p.off_z, part, nullptr));
+            CK(precondition(p, p.ws + p.off_q, p.ws + p.off_q, part, nullptr));
             CK(launch_finish_rho(p, st, part, first_num_parts(p), 0, tol, max_iter));
             sa.in0 = p.ws + p.off_u;
         } else {
             CK(launch_fill(p, p.ws + p.off_u, nvec, 0.0));
             sa.in0 = nullptr;
         }
-        // r = f - K u0
+        // r = f - K u0, first search direction p = M^+ r
         sa.out0 = p.ws + p.off_r;
         CK(launch_stencil(p, ST_RESID, sa));
-        CK(precondition(p, p.ws + p.off_r, p.ws + p.off_z, part, nullptr));
+        CK(precondition(p, p.ws + p.off_r, p.ws + p.off_p, part, nullptr));
         CK(launch_finish_rho(p, st, part, first_num_parts(p), u0_dev ? 1 : 11, tol, max_iter));
 
         std::vector<LcState> hs(p.L);
@@ -521,7 +521,7 @@ int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
             done += c;
             if (chunk < 16) chunk *= 2;
         }
-        CK(launch_finalize_u(p, p.ws + p.off_u, p.ws + p.off_p0, p.ws + p.off_p1, st));
+        CK(launch_finalize_u(p, p.ws + p.off_u, p.ws + p.off_p, st));
         double *sums = p.ptr<double>(p.off_sums);
         CK(launch_post_sums(p, p.ws + p.off_u, ebar_dev, strain_dev, stress_dev, part, sums));
         if (u_dev) CK(launch_soa_to_aos(p, p.ws + p.off_u, u_dev));
@@ -631,9 +631,9 @@ int feh_apply_operator(feh_plan *plan, const void *p_dev, void *q_dev) {
     CK(check_plan(plan, true));
     if (!p_dev || !q_dev) return set_error(FEH_EINVAL, "null argument");
     feh_plan &p = *plan;
-    CK(launch_aos_to_soa(p, p_dev, p.ws + p.off_p0));
+    CK(launch_aos_to_soa(p, p_dev, p.ws + p.off_p));
     StencilArgs sa;
-    sa.in0 = p.ws + p.off_p0;
+    sa.in0 = p.ws + p.off_p;
     sa.out0 = p.ws + p.off_q;
     CK(launch_stencil(p, ST_APPLY, sa));
     CK(launch_soa_to_aos(p, p.ws + p.off_q, q_dev));
@@ -645,8 +645,8 @@ int feh_apply_preconditioner(feh_plan *plan, const void *r_dev, void *z_dev) {
     if (!r_dev || !z_dev) return set_error(FEH_EINVAL, "null argument");
     feh_plan &p = *plan;
     CK(launch_aos_to_soa(p, r_dev, p.ws + p.off_r));
-    CK(precondition(p, p.ws + p.off_r, p.ws + p.off_z, nullptr, nullptr));
-    CK(launch_soa_to_aos(p, p.ws + p.off_z, z_dev));
+    CK(precondition(p, p.ws + p.off_r, p.ws + p.off_q, nullptr, nullptr));
+    CK(launch_soa_to_aos(p, p.ws + p.off_q, z_dev));
     return hip_check(hipStreamSynchronize(p.stream), "apply preconditioner");
 }
 
@@ -659,8 +659,8 @@ int feh_apply_projection(feh_plan *plan, const void *e_dev, void *Ge_dev) {
     sa.out0 = p.ws + p.off_q;
     sa.identity_material = true;
     CK(launch_stencil(p, ST_DIV, sa));
-    CK(precondition(p, p.ws + p.off_q, p.ws + p.off_z, nullptr, nullptr));
-    CK(launch_grad(p, p.ws + p.off_z, Ge_dev));
+    CK(precondition(p, p.ws + p.off_q, p.ws + p.off_q, nullptr, nullptr));
+    CK(launch_grad(p, p.ws + p.off_q, Ge_dev));
     return hip_check(hipStreamSynchronize(p.stream), "apply projection");
 }
 

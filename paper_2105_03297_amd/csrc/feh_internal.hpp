@@ -86,10 +86,8 @@ struct LcState {
     double alpha_pend; // u += alpha_pend * p still to be applied
     double relres;     // sqrt(rho / rho_ref)
     int active;        // 1 while iterating
-    int first;         // 1 before the first search direction exists
     int iters;         // completed iterations
     int status;        // FEH_OK / FEH_ENOCONV / FEH_EBREAKDOWN
-    int pbuf;          // which of the two p buffers holds the current p
     int pad;
 };
 
@@ -123,7 +121,7 @@ struct feh_plan {
     bool last_even = true;
 
     // workspace layout (byte offsets)
-    size_t off_u = 0, off_r = 0, off_z = 0, off_p0 = 0, off_p1 = 0, off_q = 0;
+    size_t off_u = 0, off_r = 0, off_p = 0, off_q = 0;
     size_t off_spec = 0, off_lam = 0, off_mu = 0;
     size_t off_tw[3] = {0, 0, 0};       // twiddles e^{-2 pi i j / n_a}, j < n_a (plan precision)
     size_t off_om[3] = {0, 0, 0};       // e^{+2 pi i m / n_a} (FP64)
@@ -173,13 +171,8 @@ enum StencilMode {
 };
 
 struct StencilArgs {
-    const void *in0 = nullptr;   // p (APPLY), z (CG), u (RESID, nullable)
-    const void *in1 = nullptr;   // p_old (CG): buffer 0
-    const void *in1b = nullptr;  // p_old (CG): buffer 1
+    const void *in0 = nullptr;   // p (APPLY, CG), u (RESID, nullable)
     void *out0 = nullptr;        // q (APPLY, CG), r (RESID)
-    void *out1 = nullptr;        // p_new buffer 0 (CG)
-    void *out1b = nullptr;       // p_new buffer 1 (CG)
-    void *u = nullptr;           // u (CG)
     const double *Ebar = nullptr;// device [L][D][D] (RESID)
     double *partial = nullptr;   // [L][part_stride] (CG)
     const LcState *state = nullptr;
@@ -195,6 +188,8 @@ struct FftArgs {
     void *r_out = nullptr;       // updated r (fused axpy)
     void *spec = nullptr;        // half spectrum [L][n0][..][nh][D]
     void *z = nullptr;           // real output
+    void *p_upd = nullptr;       // CG update fused into the last inverse pass (nullable):
+    void *u_upd = nullptr;       //   u += alpha_pend p, then p = z + beta p, in place (z not stored)
     double *partial = nullptr;   // Parseval r.z partials
     const LcState *state = nullptr;  // active mask, alpha (nullable: all active, no axpy)
     double out_scale = 1.0;      // c2r output scale
@@ -216,7 +211,7 @@ int launch_init_state(const feh_plan &p, LcState *st, int n_load);
 int launch_finish_rho(const feh_plan &p, LcState *st, const double *partial, int nparts, int mode,
                       double tol, int max_iter);
 int launch_finish_pq(const feh_plan &p, LcState *st, const double *partial, int nparts);
-int launch_finalize_u(const feh_plan &p, void *u, const void *p0, const void *p1, const LcState *st);
+int launch_finalize_u(const feh_plan &p, void *u, const void *pv, const LcState *st);
 int launch_material_lame(const feh_plan &p, const void *lam, const void *mu, int *flag);
 int launch_material_phases(const feh_plan &p, const int32_t *phase, const double *tab, int n_phase,
                            int *flag);

@@ -44,8 +44,6 @@ __global__ void k_init_state(LcState *st, int L) {
     if (l < L) {
         LcState s{};
         s.active = 1;
-        s.first = 1;
-        s.pbuf = 0;
         st[l] = s;
     }
 }
@@ -122,8 +120,6 @@ __global__ void k_finish_pq(LcState *st, const double *part, int nparts, int str
     const double v = sum_parts(part + (long long)l * stride, nparts, sh);
     if (threadIdx.x != 0) return;
     s.pq = v;
-    s.pbuf ^= 1;  // the stencil wrote the new p into the other buffer
-    s.first = 0;
     if (!(v > 0.0) || !isfinite(v)) {
         s.active = 0;
         s.status = FEH_EBREAKDOWN;
@@ -138,15 +134,12 @@ __global__ void k_finish_pq(LcState *st, const double *part, int nparts, int str
 // u += alpha_pend * p for every load case (the update still pending when a
 // load case stopped), then clear the pending step.
 template <typename T>
-__global__ void k_finalize_u(T *u, const T *p0, const T *p1, const LcState *st, long long per_lc, int L) {
+__global__ void k_finalize_u(T *u, const T *p, const LcState *st, long long per_lc, int L) {
     const long long total = per_lc * L;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
         const int l = (int)(i / per_lc);
         const double a = st[l].alpha_pend;
-        if (a != 0.0) {
-            const T *p = st[l].pbuf ? p1 : p0;
-            u[i] += T(a) * p[i];
-        }
+        if (a != 0.0) u[i] += T(a) * p[i];
     }
 }
 
@@ -311,15 +304,15 @@ int launch_finish_pq(const feh_plan &p, LcState *st, const double *partial, int 
     return hip_check(hipGetLastError(), "finish pq");
 }
 
-int launch_finalize_u(const feh_plan &p, void *u, const void *p0, const void *p1, const LcState *st) {
+int launch_finalize_u(const feh_plan &p, void *u, const void *pv, const LcState *st) {
     const long long per = p.N * p.dim;
     const int g = grid_for(per * p.L);
     if (p.prec == FEH_FP64)
-        hipLaunchKernelGGL(k_finalize_u<double>, dim3(g), dim3(kThreads), 0, p.stream, (double *)u, (const double *)p0,
-                           (const double *)p1, st, per, p.L);
+        hipLaunchKernelGGL(k_finalize_u<double>, dim3(g), dim3(kThreads), 0, p.stream, (double *)u, (const double *)pv,
+                           st, per, p.L);
     else
-        hipLaunchKernelGGL(k_finalize_u<float>, dim3(g), dim3(kThreads), 0, p.stream, (float *)u, (const float *)p0,
-                           (const float *)p1, st, per, p.L);
+        hipLaunchKernelGGL(k_finalize_u<float>, dim3(g), dim3(kThreads), 0, p.stream, (float *)u, (const float *)pv,
+                           st, per, p.L);
     hipLaunchKernelGGL(k_clear_pending, dim3(1), dim3(kMaxLoad), 0, p.stream, (LcState *)st, p.L);
     return hip_check(hipGetLastError(), "finalize u");
 }

@@ -249,6 +249,8 @@ struct FK {
     T *r_out;
     Cx<T> *spec;
     T *z;
+    T *p_upd;                 // fused CG update in the last inverse pass
+    T *u_upd;
     double *partial;
     const LcState *st;
     const Cx<T> *tw;          // twiddles of the transformed axis (full length)
@@ -388,9 +390,11 @@ __global__ __launch_bounds__(kFftThreads) void k_last_fwd(FK<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// last axis, half spectrum -> real (times out_scale)
+// last axis, half spectrum -> real (times out_scale).  UPD: the real result z
+// is not stored; instead the CG update u += alpha_pend p, p = z + beta p is
+// applied in place (one pass over p and u while z is in registers).
 // ---------------------------------------------------------------------------
-template <typename T, int PPT, bool GEN>
+template <typename T, int PPT, bool GEN, bool UPD>
 __global__ __launch_bounds__(kFftThreads) void k_last_inv(FK<T> a) {
     constexpr int NT = kFftThreads;
     __shared__ Cx<T> buf[PPT * NT];
@@ -468,17 +472,65 @@ __global__ __launch_bounds__(kFftThreads) void k_last_inv(FK<T> a) {
         y[k] = buf[j * nb + b];
     }
     const long long lbase = (long long)lc * D * N + s0 * a.nlast;
-    #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int e0 = threadIdx.x + k * NT;
-        const int b = (int)a.d_nc.div((uint32_t)e0);
-        const int j = e0 - b * nc;
-        const int sl = (int)a.d_D.div((uint32_t)b);
-        const int c = b - sl * D;
-        if (e0 < cnt && sl < nrows) {
-            const long long o = lbase + (long long)c * N + (long long)sl * a.nlast;
-            if (even) reinterpret_cast<Cx<T> *>(a.z + o)[j] = Cx<T>{y[k].x * sc, y[k].y * sc};
-            else a.z[o + j] = y[k].x * sc;
+    if constexpr (UPD) {
+        const T beta = T(a.st[lc].beta), ap = T(a.st[lc].alpha_pend);
+        constexpr int CH = 8;  // slots per round: two loads each in flight
+        #pragma unroll
+        for (int h = 0; h < PPT; h += CH) {
+            Cx<T> pv[CH], uv[CH];
+            #pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int e0 = threadIdx.x + (h + k) * NT;
+                const int e = e0 < cnt ? e0 : 0;
+                const int b = (int)a.d_nc.div((uint32_t)e);
+                const int j = e - b * nc;
+                const int sl0 = (int)a.d_D.div((uint32_t)b);
+                const int c = b - sl0 * D;
+                const int sl = sl0 < nrows ? sl0 : nrows - 1;
+                const long long o = lbase + (long long)c * N + (long long)sl * a.nlast + (even ? 2 * j : j);
+                if (even) {
+                    pv[k] = *reinterpret_cast<const Cx<T> *>(a.p_upd + o);
+                    uv[k] = *reinterpret_cast<const Cx<T> *>(a.u_upd + o);
+                } else {
+                    pv[k] = Cx<T>{a.p_upd[o], T(0)};
+                    uv[k] = Cx<T>{a.u_upd[o], T(0)};
+                }
+            }
+            #pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int e0 = threadIdx.x + (h + k) * NT;
+                const int b = (int)a.d_nc.div((uint32_t)e0);
+                const int j = e0 - b * nc;
+                const int sl = (int)a.d_D.div((uint32_t)b);
+                const int c = b - sl * D;
+                if (e0 < cnt && sl < nrows) {
+                    const long long o = lbase + (long long)c * N + (long long)sl * a.nlast + (even ? 2 * j : j);
+                    const Cx<T> z = {y[h + k].x * sc, y[h + k].y * sc};
+                    const Cx<T> un = {uv[k].x + ap * pv[k].x, uv[k].y + ap * pv[k].y};
+                    const Cx<T> pn = {z.x + beta * pv[k].x, z.y + beta * pv[k].y};
+                    if (even) {
+                        *reinterpret_cast<Cx<T> *>(a.u_upd + o) = un;
+                        *reinterpret_cast<Cx<T> *>(a.p_upd + o) = pn;
+                    } else {
+                        a.u_upd[o] = un.x;
+                        a.p_upd[o] = pn.x;
+                    }
+                }
+            }
+        }
+    } else {
+        #pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int e0 = threadIdx.x + k * NT;
+            const int b = (int)a.d_nc.div((uint32_t)e0);
+            const int j = e0 - b * nc;
+            const int sl = (int)a.d_D.div((uint32_t)b);
+            const int c = b - sl * D;
+            if (e0 < cnt && sl < nrows) {
+                const long long o = lbase + (long long)c * N + (long long)sl * a.nlast;
+                if (even) reinterpret_cast<Cx<T> *>(a.z + o)[j] = Cx<T>{y[k].x * sc, y[k].y * sc};
+                else a.z[o + j] = y[k].x * sc;
+            }
         }
     }
 }
@@ -746,6 +798,8 @@ FK<T> base_args(const feh_plan &p, const FftArgs &fa) {
     a.r_out = static_cast<T *>(fa.r_out);
     a.spec = static_cast<Cx<T> *>(fa.spec);
     a.z = static_cast<T *>(fa.z);
+    a.p_upd = static_cast<T *>(fa.p_upd);
+    a.u_upd = static_cast<T *>(fa.u_upd);
     a.partial = fa.partial;
     a.st = fa.state;
     a.dim = p.dim;
@@ -801,8 +855,16 @@ int last_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     const bool gen = !pow2_len(a.ax.n);
     const size_t dyn = (size_t)a.nlast * sizeof(Cx<T>);
     if (inverse) {
-        if (gen) hipLaunchKernelGGL((k_last_inv<T, PPT, true>), g, b, dyn, p.stream, a);
-        else hipLaunchKernelGGL((k_last_inv<T, PPT, false>), g, b, dyn, p.stream, a);
+        const bool upd = fa.p_upd != nullptr;
+        if (upd && (fa.u_upd == nullptr || fa.state == nullptr))
+            return set_error(FEH_EINVAL, "fused CG update needs p, u and the CG state");
+        if (upd) {
+            if (gen) hipLaunchKernelGGL((k_last_inv<T, PPT, true, true>), g, b, dyn, p.stream, a);
+            else hipLaunchKernelGGL((k_last_inv<T, PPT, false, true>), g, b, dyn, p.stream, a);
+        } else {
+            if (gen) hipLaunchKernelGGL((k_last_inv<T, PPT, true, false>), g, b, dyn, p.stream, a);
+            else hipLaunchKernelGGL((k_last_inv<T, PPT, false, false>), g, b, dyn, p.stream, a);
+        }
     } else {
         if (a.use_axpy) {
             if (gen) hipLaunchKernelGGL((k_last_fwd<T, PPT, true, true>), g, b, dyn, p.stream, a);

@@ -27,8 +27,8 @@
 // nodes) in LDS, each thread evaluates its voxel (edge fluxes into LDS), and
 // each updated node combines the fluxes of its in-plane voxels; the terms
 // whose voxels lie in the previous plane are carried in registers.  The fused
-// CG variant also forms p = z + beta p_old on the fly, writes p, applies the
-// pending u += alpha p_old and accumulates p.q in FP64.
+// CG variant accumulates p.q in FP64 for the step length (the update of p
+// and u is fused into the last inverse FFT pass).
 #include "device_common.hpp"
 
 namespace feh {
@@ -173,13 +173,8 @@ __device__ __forceinline__ void voxel2_div(const T *e, T vol, T ihx, T ihy, T (&
 
 template <typename T>
 struct SK {
-    const T *in0;      // p / z / u
-    const T *pold0;    // CG: p buffer 0
-    const T *pold1;    // CG: p buffer 1
+    const T *in0;      // p / u
     T *out0;           // q / r
-    T *pnew0;          // CG: p buffer 0
-    T *pnew1;          // CG: p buffer 1
-    T *u;              // CG
     const T *lam;
     const T *mu;
     const double *Ebar;
@@ -212,6 +207,19 @@ struct Tile<2> {
 
 constexpr int kStencilThreads = 256;
 
+// The value held by lane - 1 of the wavefront (DPP shift of the whole wave
+// right by one lane; lane 0 receives zero).  In the 3D tile a row of 32
+// voxels lies inside one wavefront, so lane - 1 holds the voxel at z - 1.
+__device__ __forceinline__ int lane_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
+__device__ __forceinline__ float from_left(float v) {
+    return __builtin_bit_cast(float, lane_shr1(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double from_left(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)lane_shr1((int)(unsigned)b), hi = (unsigned)lane_shr1((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 template <typename T, int DIM, int MODE, bool UNIT>
 __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
     using TL = Tile<DIM>;
@@ -221,8 +229,12 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
     constexpr int NQ = NEDGE * NC;               // edge-flux values per voxel
     constexpr int NSE = (NE + NT - 1) / NT;      // node-plane slots per thread
     static_assert(VY * VZ == NT, "one voxel per thread");
-    __shared__ T Pl[3][NC][NE];                  // ring of three node planes
-    __shared__ T Es[NQ][NT];                     // edge fluxes, one column per voxel
+    static_assert(DIM == 2 || VZ == 32, "3D: one row of voxels per half wavefront");
+    __shared__ T Pl[NC][NE];                     // one node plane
+    // edge fluxes passed through LDS, one column per voxel: in 3D only the 24
+    // values the next row of voxels needs (the left neighbour's come by DPP)
+    constexpr int NX = DIM == 3 ? 24 : NQ;
+    __shared__ T Es[NX][NT];
     __shared__ double red[NT / 64];
 
     const int tid = threadIdx.x;
@@ -235,17 +247,9 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
     const int lc = t / a.nchunk;
     const int blk_in_lc = (ch * a.nty + ty_t) * a.ntz + tz_t;
 
-    // CG scalars of this load case
-    T beta = T(0), alpha_pend = T(0);
-    const T *pold = nullptr;
-    T *pnew = nullptr;
+    // load cases that have stopped iterating
     if constexpr (MODE == ST_CG) {
-        const LcState &s = a.st[lc];
-        if (!s.active) return;
-        beta = T(s.beta);
-        alpha_pend = T(s.alpha_pend);
-        pold = s.pbuf ? a.pold1 : a.pold0;
-        pnew = s.pbuf ? a.pnew0 : a.pnew1;
+        if (!a.st[lc].active) return;
     }
     T Eb[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     if constexpr (MODE == ST_RESID) {
@@ -307,68 +311,52 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
     }
     const long long v_off = (long long)wrap(y0 + ty, a.n1) * a.n2 + wrap(z0 + tz, a.n2);
 
-    // ---- prefetch registers, two sets: node plane P goes to set
-    // (P - x0 + 1) & 1 two steps before it is staged, and so does the material
-    // of voxel plane V, so that two planes of loads are in flight per thread.
-    // Every load is unconditional (unused slots and planes past the chunk
-    // re-read valid addresses) so the waits for a set never cover the other.
-    T rz[2][NSE][NC], rp[2][NSE][NC], ru[2][NC];  // u only at the thread's own node (slot 0)
-    T mlam[2] = {T(0), T(0)}, mmu[2] = {T(0), T(0)};
-    auto fetch_nodes = [&](auto S, int P) __attribute__((always_inline)) {
-        constexpr int B = decltype(S)::value;
+    // ---- prefetch registers: node plane P and the material of one voxel
+    // plane.  Every load is unconditional (unused slots and planes past the
+    // chunk re-read valid addresses).
+    T rz[NSE][NC];
+    T mlam = T(0), mmu = T(0);
+    auto fetch_nodes = [&](int P) __attribute__((always_inline)) {
         const long long base = (long long)wrap(P, a.n0) * plane;
         #pragma unroll
         for (int s = 0; s < NSE; ++s) {
             #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const long long gi = lcoff + c * N + base + e_off[s];
-                if constexpr (MODE == ST_APPLY) {
-                    rz[B][s][c] = a.in0[gi];
-                } else if constexpr (MODE == ST_CG) {
-                    // before the first search direction beta = alpha_pend = 0
-                    // and both p buffers are zero-filled, so no branch is needed
-                    rz[B][s][c] = a.in0[gi];
-                    rp[B][s][c] = pold[gi];
-                    if (s == 0) ru[B][c] = a.u[gi];
+                if constexpr (MODE == ST_APPLY || MODE == ST_CG) {
+                    rz[s][c] = a.in0[gi];
                 } else if constexpr (MODE == ST_RESID) {
-                    rz[B][s][c] = a.in0 ? a.in0[gi] : T(0);
+                    rz[s][c] = a.in0 ? a.in0[gi] : T(0);
                 }
             }
         }
     };
-    auto commit_nodes = [&](auto S, int P) __attribute__((always_inline)) {
-        constexpr int B = decltype(S)::value;
-        const long long base = (long long)wrap(P, a.n0) * plane;
-        const bool interior_plane = P >= x0 && P < x1;
-        const int buf = (P + 3) % 3;
+    // stage the fetched node plane in LDS (one plane only: the previous plane's corners
+    // stay in registers); returns the thread's own node value in own[]
+    T own[NC];
+    auto commit_nodes = [&]() __attribute__((always_inline)) {
         #pragma unroll
         for (int s = 0; s < NSE; ++s) {
             if (e_lds[s] >= 0) {
-            const bool inter = interior_plane && s == 0 && owner;
             #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                T v = rz[B][s][c];
-                if constexpr (MODE == ST_CG) {
-                    const long long gi = lcoff + c * N + base + e_off[s];
-                    v = rz[B][s][c] + beta * rp[B][s][c];
-                    if (inter) {
-                        pnew[gi] = v;
-                        if (s == 0) a.u[gi] = ru[B][c] + alpha_pend * rp[B][s][c];
-                    }
-                }
-                Pl[buf][c][e_lds[s]] = v;
+                Pl[c][e_lds[s]] = rz[s][c];
+                if (s == 0) own[c] = rz[s][c];
             }
             }
         }
     };
-    auto fetch_material = [&](auto S, int V) __attribute__((always_inline)) {
-        constexpr int B = decltype(S)::value;
+    auto fetch_material = [&](int V) __attribute__((always_inline)) {
         const long long base = (long long)wrap(V, a.n0) * plane;
-        mlam[B] = a.lam[base + v_off];  // unused (but allocated) for the identity material
-        mmu[B] = a.mu[base + v_off];
+        mlam = a.lam[base + v_off];  // unused (but allocated) for the identity material
+        mmu = a.mu[base + v_off];
     };
-    using S0 = std::integral_constant<int, 0>;
-    using S1 = std::integral_constant<int, 1>;
+
+    // in-plane corners of the thread's voxel: k = cy + 2 cz (3D), k = cz (2D);
+    // Pc holds them in the lower node plane of the current voxel plane
+    constexpr int NK = DIM == 3 ? 4 : 2;
+    T Pc[NK][NC];
+    auto corner_lds = [&](int k) { return DIM == 3 ? (ty + (k & 1)) * EZ + tz + (k >> 1) : tz + k; };
 
     // carried terms: raw axis-0 edge fluxes of the previous voxel plane, and
     // the differences of the other axes' edges whose voxels lie in the
@@ -383,31 +371,40 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
     double acc = 0.0;
 
     if constexpr (MODE != ST_DIV) {
-        fetch_nodes(S0{}, x0 - 1);
-        commit_nodes(S0{}, x0 - 1);
-        fetch_nodes(S1{}, x0);
-        fetch_nodes(S0{}, min(x0 + 1, x1));
+        fetch_nodes(x0 - 1);
+        commit_nodes();
+        fetch_nodes(x0);
+        __syncthreads();
+        #pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            #pragma unroll
+            for (int c = 0; c < NC; ++c) Pc[k][c] = (k == 0) ? own[c] : Pl[c][corner_lds(k)];
+        }
+        __syncthreads();
     }
-    fetch_material(S0{}, x0 - 1);
-    fetch_material(S1{}, x0);
+    fetch_material(x0 - 1);
 
     // voxel column of the node's in-plane voxels at offset (-dy, -dz); threads
     // that update no node read an interior column instead (results unused)
     const int vo = (ty >= HY && tz >= 1) ? tid : HY * VZ + 1;
     auto vix = [&](int dy, int dz) { return vo - dy * VZ - dz; };
 
-    // one step: voxel plane X, whose nodes are staged in planes X and X + 1;
-    // SN is the register set of node plane X + 1, SM that of voxel plane X
-    auto step = [&](auto SN, auto SM, int X) __attribute__((always_inline)) {
-        constexpr int BM = decltype(SM)::value;
-        // ---- stage plane X+1, prefetch plane X+3 and the material of voxel plane X+2
-        if constexpr (MODE != ST_DIV) commit_nodes(SN, X + 1);
-        const T clam = mlam[BM], cmu = mmu[BM];
-        if constexpr (MODE != ST_DIV) fetch_nodes(SN, min(X + 3, x1));
-        fetch_material(SM, min(X + 2, x1 - 1));
+    for (int X = x0 - 1; X < x1; ++X) {
+        // ---- stage plane X+1, prefetch plane X+2 and the material of voxel plane X+1
+        if constexpr (MODE != ST_DIV) commit_nodes();
+        const T clam = mlam, cmu = mmu;
+        if constexpr (MODE != ST_DIV) fetch_nodes(min(X + 2, x1));
+        fetch_material(min(X + 1, x1 - 1));
         __syncthreads();
         // ---- voxel phase: the thread's voxel in plane X
-        const int b0 = (X + 3) % 3, b1 = (X + 4) % 3;
+        T pown[NC];  // p at the thread's own node of plane X
+        T q[NC], nq[NC];
+        #pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            q[i] = cq[i];
+            nq[i] = T(0);
+        }
+        T oy[12];    // 3D: the own voxel's axis-1 edge fluxes, kept for the node phase
         {
             T lam, mu;
             if (a.ident) {
@@ -431,34 +428,72 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
                     tet_div<T, 2, 0, 1>(e + 36, a.vol, a.ih, E);
                     tet_div<T, 2, 1, 0>(e + 45, a.vol, a.ih, E);
                 } else {
+                    // corner c = cx + 2 cy + 4 cz; cx = 0 from registers, cx = 1 staged
                     T P[8][3];
                     #pragma unroll
-                    for (int c = 0; c < 8; ++c) {
-                        const int cyb = (c >> 1) & 1, czb = (c >> 2) & 1;
-                        const int bb = (c & 1) ? b1 : b0;
+                    for (int k = 0; k < 4; ++k) {
                         #pragma unroll
-                        for (int i = 0; i < 3; ++i) P[c][i] = Pl[bb][i][(ty + cyb) * EZ + tz + czb];
+                        for (int i = 0; i < 3; ++i) {
+                            P[2 * k][i] = Pc[k][i];
+                            P[2 * k + 1][i] = (k == 0) ? own[i] : Pl[i][corner_lds(k)];
+                        }
                     }
                     voxel3<T, UNIT, MODE == ST_RESID>(P, lam, mu, a.ih, Eb, E);
+                    #pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        #pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            if (k == 0) pown[i] = Pc[0][i];
+                            Pc[k][i] = P[2 * k + 1][i];
+                        }
+                    }
                 }
+                // export the fluxes the row below needs: x1, x3, y0..y3, z2, z3
                 #pragma unroll
-                for (int j = 0; j < 36; ++j) Es[j][tid] = E[j];
+                for (int j = 0; j < 24; ++j) Es[j][tid] = E[j < 6 ? (j < 3 ? 3 + j : 6 + j) : (j < 18 ? 6 + j : 12 + j)];
+                #pragma unroll
+                for (int j = 0; j < 12; ++j) oy[j] = E[12 + j];
+                // terms of the own voxel (x-edge c = 0) and of the left voxel
+                // (x-edge c = (0,0,1), z-edges c = (x,0,0) paired with the own voxel),
+                // the latter formed by lane - 1, which holds that voxel
+                #pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const T c0 = E[0 + i];
+                    q[i] += cx[0 * 3 + i] - c0;
+                    cx[0 * 3 + i] = c0;
+                    const T c2 = E[6 + i];
+                    const T d2 = cx[2 * 3 + i] - c2;
+                    cx[2 * 3 + i] = c2;
+                    q[i] += from_left(d2);
+                    q[i] += from_left(E[24 + i]) - E[24 + i];
+                    nq[i] += from_left(E[27 + i]) - E[27 + i];
+                }
             } else {
                 T E[8];
                 if constexpr (MODE == ST_DIV) {
                     const long long vidx = (long long)wrap(X, a.n0) * plane + v_off;
                     voxel2_div<T>(a.in0 + ((long long)lc * N + vidx) * 8, a.vol, a.ih[0], a.ih[1], E);
                 } else {
+                    // corner c = cx + 2 cz
                     T P[4][2];
                     #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        const int c1 = (c >> 1) & 1;
-                        const int bb = (c & 1) ? b1 : b0;
+                    for (int k = 0; k < 2; ++k) {
                         #pragma unroll
-                        for (int i = 0; i < 2; ++i) P[c][i] = Pl[bb][i][tz + c1];
+                        for (int i = 0; i < 2; ++i) {
+                            P[2 * k][i] = Pc[k][i];
+                            P[2 * k + 1][i] = (k == 0) ? own[i] : Pl[i][corner_lds(k)];
+                        }
                     }
                     const T Eb2[3] = {Eb[0], Eb[1], Eb[2]};
                     voxel2<T>(P, lam, mu, a.ih[0], a.ih[1], Eb2, E);
+                    #pragma unroll
+                    for (int k = 0; k < 2; ++k) {
+                        #pragma unroll
+                        for (int i = 0; i < 2; ++i) {
+                            if (k == 0) pown[i] = Pc[0][i];
+                            Pc[k][i] = P[2 * k + 1][i];
+                        }
+                    }
                 }
                 #pragma unroll
                 for (int j = 0; j < 8; ++j) Es[j][tid] = E[j];
@@ -467,43 +502,31 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
         __syncthreads();
         // ---- node phase (the thread's own node)
         {
-            T q[NC], nq[NC];
-            #pragma unroll
-            for (int i = 0; i < NC; ++i) {
-                q[i] = cq[i];
-                nq[i] = T(0);
-            }
             if constexpr (DIM == 3) {
-                // axis-0 edges: E_{0,k}(n - e_x - c) - E_{0,k}(n - c), c = (0, cy, cz), k = cy + 2 cz
+                // fluxes of the voxel above (row ty - 1); row 0 reads its own
+                // column (it updates no node and feeds no neighbour that does)
+                const int ia = ty >= 1 ? tid - VZ : tid;
+                T A[24];
                 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int v = vix(k & 1, k >> 1);
-                    #pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        const T cur = Es[(0 * 4 + k) * 3 + i][v];
-                        q[i] += cx[k * 3 + i] - cur;
-                        cx[k * 3 + i] = cur;
-                    }
-                }
-                // axis-1 edges: c = (cx, 0, cz), k = cx + 2 cz; voxels n - e_y - c and n - c
+                for (int j = 0; j < 24; ++j) A[j] = Es[j][ia];
                 #pragma unroll
-                for (int cz = 0; cz < 2; ++cz) {
-                    const int vlo = vix(1, cz), vhi = vix(0, cz);
-                    #pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        q[i] += Es[(1 * 4 + 2 * cz) * 3 + i][vlo] - Es[(1 * 4 + 2 * cz) * 3 + i][vhi];
-                        nq[i] += Es[(1 * 4 + 1 + 2 * cz) * 3 + i][vlo] - Es[(1 * 4 + 1 + 2 * cz) * 3 + i][vhi];
-                    }
-                }
-                // axis-2 edges: c = (cx, cy, 0), k = cx + 2 cy; voxels n - e_z - c and n - c
-                #pragma unroll
-                for (int cy = 0; cy < 2; ++cy) {
-                    const int vlo = vix(cy, 1), vhi = vix(cy, 0);
-                    #pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        q[i] += Es[(2 * 4 + 2 * cy) * 3 + i][vlo] - Es[(2 * 4 + 2 * cy) * 3 + i][vhi];
-                        nq[i] += Es[(2 * 4 + 1 + 2 * cy) * 3 + i][vlo] - Es[(2 * 4 + 1 + 2 * cy) * 3 + i][vhi];
-                    }
+                for (int i = 0; i < 3; ++i) {
+                    // x-edges c = (0,1,0) (voxel above) and c = (0,1,1) (above-left, from lane - 1)
+                    const T c1 = A[0 + i];
+                    q[i] += cx[1 * 3 + i] - c1;
+                    cx[1 * 3 + i] = c1;
+                    const T c3 = A[3 + i];
+                    const T d3 = cx[3 * 3 + i] - c3;
+                    cx[3 * 3 + i] = c3;
+                    q[i] += from_left(d3);
+                    // y-edges: above - own (k = 0, 1); above-left - left (k = 2, 3) from lane - 1
+                    q[i] += A[6 + i] - oy[0 + i];
+                    nq[i] += A[9 + i] - oy[3 + i];
+                    q[i] += from_left(A[12 + i] - oy[6 + i]);
+                    nq[i] += from_left(A[15 + i] - oy[9 + i]);
+                    // z-edges: above-left (from lane - 1) - above (k = 2, 3)
+                    q[i] += from_left(A[18 + i]) - A[18 + i];
+                    nq[i] += from_left(A[21 + i]) - A[21 + i];
                 }
             } else {
                 // axis-0 edges: c = (0, c1), k = c1
@@ -534,20 +557,12 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
                     } else {
                         a.out0[lcoff + i * N + idx] = q[i];
                     }
-                    if constexpr (MODE == ST_CG) {
-                        const T pv = Pl[b0][i][e_lds[0]];
-                        acc += double(pv) * double(q[i]);
-                    }
+                    if constexpr (MODE == ST_CG) acc += double(pown[i]) * double(q[i]);
                 }
             }
             #pragma unroll
             for (int i = 0; i < NC; ++i) cq[i] = nq[i];
         }
-    };
-
-    for (int X = x0 - 1; X < x1; X += 2) {
-        step(S1{}, S0{}, X);
-        if (X + 1 < x1) step(S0{}, S1{}, X + 1);
     }
     if constexpr (MODE == ST_CG) {
         const double s = block_sum<NT>(acc, red);
@@ -562,12 +577,7 @@ int launch_t(const feh_plan &p, int mode, const StencilArgs &sa) {
     using TL = Tile<DIM>;
     SK<T> a{};
     a.in0 = static_cast<const T *>(sa.in0);
-    a.pold0 = static_cast<const T *>(sa.in1);
-    a.pold1 = static_cast<const T *>(sa.in1b);
     a.out0 = static_cast<T *>(sa.out0);
-    a.pnew0 = static_cast<T *>(sa.out1);
-    a.pnew1 = static_cast<T *>(sa.out1b);
-    a.u = static_cast<T *>(sa.u);
     a.lam = p.ptr<const T>(p.off_lam);
     a.mu = p.ptr<const T>(p.off_mu);
     a.Ebar = sa.Ebar;

@@ -60,8 +60,9 @@ def test_bad_voxel_size():
 def test_plan_sizes_and_workspace_checks():
     p = feh.feh_plan_create(3, (256, 256, 256), None, 6, feh.FEH_FP32)
     b = feh.feh_plan_workspace_bytes(p)
-    # 6 vectors + half spectrum + material: about 8.6 GB at 256^3 x 6 load cases in FP32
-    assert 8.0e9 < b < 9.5e9
+    # 4 nodal vectors (u, r, p, q) + half spectrum + material: about 6.2 GB at
+    # 256^3 x 6 load cases in FP32
+    assert 5.8e9 < b < 6.6e9
     # calls that need a workspace fail before touching the device
     Eb = ms.unit_loads(3)
     with pytest.raises(feh.FehError) as ei:
