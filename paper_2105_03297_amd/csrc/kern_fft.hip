@@ -173,7 +173,7 @@ struct Dft<T, 8> {
 // wavefront reads and writes consecutive LDS words.
 template <typename T, int R, int PPT>
 __device__ __forceinline__ void stockham_pass(Cx<T> *buf, int nb, const FastDiv &nbd, int n,
-                                              const PassInfo &ps, const Cx<T> *tw, int tws, bool inv) {
+                                              const PassInfo &ps, const Cx<T> *tw, int tws, bool inv, int tx) {
     constexpr int NT = kFftThreads;
     constexpr int K = (PPT + R - 1) / R;
     const int nbf = nb * (n / R);
@@ -183,7 +183,7 @@ __device__ __forceinline__ void stockham_pass(Cx<T> *buf, int nb, const FastDiv 
     int obase[K];
     #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const int t = threadIdx.x + k * NT;
+        const int t = tx + k * NT;
         obase[k] = -1;
         if (t < nbf) {
             const int w = (int)nbd.div((uint32_t)t);
@@ -219,21 +219,21 @@ __device__ __forceinline__ void stockham_pass(Cx<T> *buf, int nb, const FastDiv 
 // which keeps the register footprint of the common case small.
 template <typename T, int PPT, bool GEN>
 __device__ __forceinline__ void lds_fft(Cx<T> *buf, int nb, const FastDiv &nbd, const AxisFFT &ax,
-                                        const Cx<T> *tw, int tws, bool inv) {
+                                        const Cx<T> *tw, int tws, bool inv, int tx = threadIdx.x) {
     for (int s = 0; s < ax.npass; ++s) {
         const PassInfo &ps = ax.pass[s];
         switch (ps.R) {
-        case 2: stockham_pass<T, 2, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv); break;
-        case 4: stockham_pass<T, 4, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv); break;
-        case 8: stockham_pass<T, 8, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv); break;
+        case 2: stockham_pass<T, 2, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv, tx); break;
+        case 4: stockham_pass<T, 4, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv, tx); break;
+        case 8: stockham_pass<T, 8, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv, tx); break;
         default:
             if constexpr (GEN) {
                 switch (ps.R) {
-                case 3: stockham_pass<T, 3, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv); break;
-                case 5: stockham_pass<T, 5, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv); break;
-                case 7: stockham_pass<T, 7, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv); break;
-                case 11: stockham_pass<T, 11, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv); break;
-                case 13: stockham_pass<T, 13, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv); break;
+                case 3: stockham_pass<T, 3, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv, tx); break;
+                case 5: stockham_pass<T, 5, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv, tx); break;
+                case 7: stockham_pass<T, 7, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv, tx); break;
+                case 11: stockham_pass<T, 11, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv, tx); break;
+                case 13: stockham_pass<T, 13, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv, tx); break;
                 default: break;
                 }
             }
@@ -596,59 +596,59 @@ __global__ __launch_bounds__(kFftThreads) void k_middle(FK<T> a, int inv) {
 __device__ __forceinline__ Cx<double> ld2(const double *p, int i) { return Cx<double>{p[2 * i], p[2 * i + 1]}; }
 __device__ __forceinline__ double nrm(Cx<double> a) { return a.x * a.x + a.y * a.y; }
 
-// Solve M z = r for Hermitian positive definite M (upper triangle given).
+// Inverse of the Hermitian positive definite M (diagonal Md, upper triangle
+// Mo = (M01, M02, M12)) by the adjugate: Mi = (real diagonal, M01', M02', M12').
 template <int D>
-__device__ __forceinline__ void herm_solve(const double (&Md)[D], const Cx<double> (&Mo)[3], Cx<double> (&r)[D]) {
+__device__ __forceinline__ void herm_inverse(const double (&Md)[D], const Cx<double> (&Mo)[3], double (&Id)[D],
+                                             Cx<double> (&Io)[3]) {
     if constexpr (D == 2) {
-        // M = [[d0, o01], [conj o01, d1]]
-        const double det = Md[0] * Md[1] - nrm(Mo[0]);
-        const double id = 1.0 / det;
-        const Cx<double> r0 = r[0], r1 = r[1];
-        const Cx<double> t0 = csub(cscale(r0, Md[1]), cmul(Mo[0], r1));
-        const Cx<double> t1 = csub(cscale(r1, Md[0]), cmul(cconj(Mo[0]), r0));
-        r[0] = cscale(t0, id);
-        r[1] = cscale(t1, id);
+        const double id = 1.0 / (Md[0] * Md[1] - nrm(Mo[0]));
+        Id[0] = Md[1] * id;
+        Id[1] = Md[0] * id;
+        Io[0] = cscale(Mo[0], -id);
+        Io[1] = Io[2] = Cx<double>{0.0, 0.0};
     } else {
-        // Cholesky M = L L^H; Mo = (M01, M02, M12)
-        const double l00 = sqrt(Md[0]);
-        const double i00 = 1.0 / l00;
-        const Cx<double> l10 = cscale(cconj(Mo[0]), i00);  // M10 / l00
-        const Cx<double> l20 = cscale(cconj(Mo[1]), i00);  // M20 / l00
-        const double l11 = sqrt(Md[1] - nrm(l10));
-        const double i11 = 1.0 / l11;
-        const Cx<double> l21 = cscale(csub(cconj(Mo[2]), cmulc(l20, l10)), i11);  // (M21 - l20 conj(l10)) / l11
-        const double l22 = sqrt(Md[2] - nrm(l20) - nrm(l21));
-        const double i22 = 1.0 / l22;
-        const Cx<double> y0 = cscale(r[0], i00);
-        const Cx<double> y1 = cscale(csub(r[1], cmul(l10, y0)), i11);
-        const Cx<double> y2 = cscale(csub(csub(r[2], cmul(l20, y0)), cmul(l21, y1)), i22);
-        const Cx<double> z2 = cscale(y2, i22);
-        const Cx<double> z1 = cscale(csub(y1, cmul(cconj(l21), z2)), i11);
-        const Cx<double> z0 = cscale(csub(csub(y0, cmul(cconj(l10), z1)), cmul(cconj(l20), z2)), i00);
-        r[0] = z0;
-        r[1] = z1;
-        r[2] = z2;
+        const Cx<double> a = Mo[0], b = Mo[1], c = Mo[2];
+        const double C0 = Md[1] * Md[2] - nrm(c);
+        const double C1 = Md[0] * Md[2] - nrm(b);
+        const double C2 = Md[0] * Md[1] - nrm(a);
+        const Cx<double> A01 = csub(cmulc(b, c), cscale(a, Md[2]));  // b conj(c) - a d2
+        const Cx<double> A02 = csub(cmul(a, c), cscale(b, Md[1]));   // a c - b d1
+        const Cx<double> A12 = csub(cmulc(b, a), cscale(c, Md[0]));  // b conj(a) - c d0
+        // det = d0 C00 + Re(a conj(A01)) + Re(b conj(A02))
+        const double det = Md[0] * C0 + (a.x * A01.x + a.y * A01.y) + (b.x * A02.x + b.y * A02.y);
+        const double id = 1.0 / det;
+        Id[0] = C0 * id;
+        Id[1] = C1 * id;
+        Id[2] = C2 * id;
+        Io[0] = cscale(A01, id);
+        Io[1] = cscale(A02, id);
+        Io[2] = cscale(A12, id);
     }
 }
 
+// First axis, one workgroup per block of PB pencils for every load case in
+// turn: forward transform, per-wavevector z^ = M(k)^-1 r^ with the Parseval
+// partial of r.z (mode 0), inverse transform.  Mode 1: forward only; mode 2:
+// inverse only.  In mode 0 the inverses of the workgroup's wavevectors are
+// formed once (FP64, adjugate) and kept in registers in the plan precision for
+// all load cases.
 template <typename T, int PPT, int DIM, int MODE, bool GEN>
 __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
     constexpr int NT = kFftThreads;
     constexpr int D = DIM;
+    constexpr int KW = (PPT + D - 1) / D;  // wavevector slots per thread: PB n0 <= PPT NT / D
     __shared__ Cx<T> buf[PPT * NT];
     __shared__ double red[NT / 64];
-    int t = xcd_remap(blockIdx.x, a.total);
-    const int lc = t / a.nblk;
-    const int blk = t - lc * a.nblk;
-    if (a.st && !a.st[lc].active) return;
+    const int blk = xcd_remap(blockIdx.x, a.total);
     const int PB = a.PB;
     const int nb = PB * D;
     const int n0 = a.n0;
     const long long inner = a.inner_total;
     const long long in0 = (long long)blk * PB;
     const int lim = (int)min((long long)PB, inner - in0) * D;
-    Cx<T> *base = a.spec + ((long long)lc * n0 * inner + in0) * D;
-    // dynamic LDS: twiddles of axis 0, then (FP64) the axis-0 phase tables and
+    const int cnt = nb * n0;
+    // dynamic LDS: twiddles of axis 0, then (mode 0) the axis-0 phase tables and
     // the phase factors of this block's PB inner wavevector indices
     Cx<T> *twl = reinterpret_cast<Cx<T> *>(feh_dyn_lds);
     const int tw_bytes = ((n0 * (int)sizeof(Cx<T>) + 15) / 16) * 16;
@@ -656,7 +656,11 @@ __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
     Cx<double> *om0 = aa0 + n0;
     Cx<double> *pin = om0 + n0;  // [PB][4]: aa1, om1, aa2, om2 (2D: aa1, om1)
     stage(twl, a.tw, n0);
-    if (MODE == 0) {
+    // per slot: real diagonal of M^-1, then its upper triangle (complex)
+    T Mid[KW][D];
+    Cx<T> Mio[KW][DIM == 3 ? 3 : 1];
+    unsigned half_w = 0;  // bit kw: wavevector counted once in the half-spectrum Parseval sum
+    if constexpr (MODE == 0) {
         stage(aa0, reinterpret_cast<const Cx<double> *>(a.aa[0]), n0);
         stage(om0, reinterpret_cast<const Cx<double> *>(a.om[0]), n0);
         for (int b = threadIdx.x; b < PB; b += NT) {
@@ -675,56 +679,27 @@ __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
                 }
             }
         }
-    }
-    const int cnt = nb * n0;
-    {
-        Cx<T> v[PPT];
-        #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const int e0 = threadIdx.x + k * NT;
-            const int e = e0 < cnt ? e0 : 0;
-            const int j = (int)a.nbd.div((uint32_t)e);
-            const int bc = e - j * nb;
-            v[k] = base[(long long)j * inner * D + (bc < lim ? bc : lim - 1)];
-        }
-        #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const int e0 = threadIdx.x + k * NT;
-            const int j = (int)a.nbd.div((uint32_t)e0);
-            const int bc = e0 - j * nb;
-            if (e0 < cnt) buf[e0] = (bc < lim) ? v[k] : Cx<T>{T(0), T(0)};
-        }
-    }
-    __syncthreads();
-    if (MODE != 2) lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, twl, 1, false);
-    double acc = 0.0;
-    if (MODE == 0) {
+        __syncthreads();
         const double ch = a.chalf;
-        for (int e = threadIdx.x; e < PB * n0; e += NT) {
+        #pragma unroll
+        for (int kw = 0; kw < KW; ++kw) {
+            const int e = threadIdx.x + kw * NT;
             const int j = (int)a.d_PB.div((uint32_t)e);
             const int b = e - j * PB;
             const long long inn = in0 + b;
-            if (b * D >= lim) continue;
-            int m1 = 0, kh;
-            if (DIM == 3) {
-                m1 = (int)a.d_nh.div((uint32_t)inn);
-                kh = (int)(inn - (long long)m1 * a.nh);
-            } else {
-                kh = (int)inn;
-            }
-            Cx<T> *pt = buf + j * nb + b * D;
-            Cx<double> r[D];
-            #pragma unroll
-            for (int c = 0; c < D; ++c) r[c] = Cx<double>{double(pt[c].x), double(pt[c].y)};
-            Cx<double> zz[D];
-            if (j == 0 && inn == 0) {
-                #pragma unroll
-                for (int c = 0; c < D; ++c) zz[c] = Cx<double>{0.0, 0.0};
-            } else {
+            double Id[D] = {};
+            Cx<double> Io[3] = {};
+            if (e < PB * n0 && b * D < lim && !(j == 0 && inn == 0)) {
+                int m1 = 0, kh;
+                if (DIM == 3) {
+                    m1 = (int)a.d_nh.div((uint32_t)inn);
+                    kh = (int)(inn - (long long)m1 * a.nh);
+                } else {
+                    kh = (int)inn;
+                }
+                if (kh == 0 || (a.last_even && kh == a.nh - 1)) half_w |= 1u << kw;
                 double Md[D];
                 Cx<double> Mo[3];
-                #pragma unroll
-                for (int c = 0; c < D; ++c) zz[c] = r[c];
                 if (DIM == 3) {
                     const Cx<double> a0 = aa0[j], a1 = pin[4 * b + 0], a2 = pin[4 * b + 2];
                     const Cx<double> w0 = om0[j], w1 = pin[4 * b + 1], w2 = pin[4 * b + 3];
@@ -750,38 +725,96 @@ __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
                     Mo[0] = cscale(cmul(cmulc(a0, a1), f), ch);
                     Mo[1] = Mo[2] = Cx<double>{0.0, 0.0};
                 }
-                herm_solve<D>(Md, Mo, zz);
+                herm_inverse<D>(Md, Mo, Id, Io);
             }
-            const double wk = (kh == 0 || (a.last_even && kh == a.nh - 1)) ? 1.0 : 2.0;
-            double dot = 0.0;
             #pragma unroll
-            for (int c = 0; c < D; ++c) {
-                dot += r[c].x * zz[c].x + r[c].y * zz[c].y;
-                pt[c] = Cx<T>{T(zz[c].x), T(zz[c].y)};
+            for (int c = 0; c < D; ++c) Mid[kw][c] = T(Id[c]);
+            #pragma unroll
+            for (int c = 0; c < (DIM == 3 ? 3 : 1); ++c) Mio[kw][c] = Cx<T>{T(Io[c].x), T(Io[c].y)};
+        }
+    }
+    for (int lc = 0; lc < a.L; ++lc) {
+        if (a.st && !a.st[lc].active) continue;
+        // the thread index passes through an empty asm statement so that the
+        // index arithmetic is redone per load case instead of being hoisted
+        // out of the loop into registers
+        int tx = threadIdx.x;
+        asm volatile("" : "+v"(tx));
+        Cx<T> *base = a.spec + ((long long)lc * n0 * inner + in0) * D;
+        {
+            Cx<T> v[PPT];
+            #pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int e0 = tx + k * NT;
+                const int e = e0 < cnt ? e0 : 0;
+                const int j = (int)a.nbd.div((uint32_t)e);
+                const int bc = e - j * nb;
+                v[k] = base[(long long)j * inner * D + (bc < lim ? bc : lim - 1)];
             }
-            acc += wk * dot;
+            #pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int e0 = tx + k * NT;
+                const int j = (int)a.nbd.div((uint32_t)e0);
+                const int bc = e0 - j * nb;
+                if (e0 < cnt) buf[e0] = (bc < lim) ? v[k] : Cx<T>{T(0), T(0)};
+            }
         }
         __syncthreads();
-    }
-    if (MODE != 1) lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, twl, 1, true);
-    {
-        Cx<T> v[PPT];
-        #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const int e0 = threadIdx.x + k * NT;
-            v[k] = buf[e0 < cnt ? e0 : 0];
+        if (MODE != 2) lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, twl, 1, false, tx);
+        double acc = 0.0;
+        if constexpr (MODE == 0) {
+            #pragma unroll
+            for (int kw = 0; kw < KW; ++kw) {
+                const int e = tx + kw * NT;
+                const int j = (int)a.d_PB.div((uint32_t)e);
+                const int b = e - j * PB;
+                if (e < PB * n0 && b * D < lim) {
+                    Cx<T> *pt = buf + j * nb + b * D;
+                    Cx<T> r[D], z[D];
+                    #pragma unroll
+                    for (int c = 0; c < D; ++c) r[c] = pt[c];
+                    if constexpr (DIM == 3) {
+                        const Cx<T> o01 = Mio[kw][0], o02 = Mio[kw][1], o12 = Mio[kw][2];
+                        z[0] = cadd(cadd(cscale(r[0], Mid[kw][0]), cmul(o01, r[1])), cmul(o02, r[2]));
+                        z[1] = cadd(cadd(cmulc(r[0], o01), cscale(r[1], Mid[kw][1])), cmul(o12, r[2]));
+                        z[2] = cadd(cadd(cmulc(r[0], o02), cmulc(r[1], o12)), cscale(r[2], Mid[kw][2]));
+                    } else {
+                        const Cx<T> o01 = Mio[kw][0];
+                        z[0] = cadd(cscale(r[0], Mid[kw][0]), cmul(o01, r[1]));
+                        z[1] = cadd(cmulc(r[0], o01), cscale(r[1], Mid[kw][1]));
+                    }
+                    double dot = 0.0;
+                    #pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        dot += double(r[c].x) * double(z[c].x) + double(r[c].y) * double(z[c].y);
+                        pt[c] = z[c];
+                    }
+                    acc += ((half_w >> kw) & 1u) ? dot : 2.0 * dot;
+                }
+            }
+            __syncthreads();
         }
-        #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const int e0 = threadIdx.x + k * NT;
-            const int j = (int)a.nbd.div((uint32_t)e0);
-            const int bc = e0 - j * nb;
-            if (e0 < cnt && bc < lim) base[(long long)j * inner * D + bc] = v[k];
+        if (MODE != 1) lds_fft<T, PPT, GEN>(buf, nb, a.nbd, a.ax, twl, 1, true, tx);
+        {
+            Cx<T> v[PPT];
+            #pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int e0 = tx + k * NT;
+                v[k] = buf[e0 < cnt ? e0 : 0];
+            }
+            #pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int e0 = tx + k * NT;
+                const int j = (int)a.nbd.div((uint32_t)e0);
+                const int bc = e0 - j * nb;
+                if (e0 < cnt && bc < lim) base[(long long)j * inner * D + bc] = v[k];
+            }
         }
-    }
-    if (MODE == 0 && a.partial) {
-        const double s = block_sum<NT>(acc, red);
-        if (threadIdx.x == 0) a.partial[(long long)lc * a.part_stride + blk] = s * a.invN;
+        if (MODE == 0 && a.partial) {
+            const double s = block_sum<NT>(acc, red);
+            if (threadIdx.x == 0) a.partial[(long long)lc * a.part_stride + blk] = s * a.invN;
+        }
+        __syncthreads();  // the next load case reuses buf
     }
 }
 
@@ -919,7 +952,7 @@ int first_t(const feh_plan &p, const FftArgs &fa, int mode) {
     a.d_PB = FastDiv::make((uint32_t)PB);
     a.nbd = FastDiv::make((uint32_t)(PB * DIM));
     a.nblk = (int)((a.inner_total + PB - 1) / PB);
-    a.total = a.nblk * p.L;
+    a.total = a.nblk;  // every block runs through the load cases
     dim3 g(a.total), b(kFftThreads);
     const bool gen = !pow2_len(a.ax.n);
     const size_t dyn = ((a.n0 * sizeof(Cx<T>) + 15) / 16) * 16 + (2 * (size_t)a.n0 + 4 * (size_t)PB) * sizeof(Cx<double>);
