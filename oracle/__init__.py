@@ -13,4 +13,6 @@ Modules
               operator of the paper's small-strain appendix; dense brute force
   pcg         the paper's projected conjugate gradients in strain space
   cg          ctypes wrapper of the plain C CSR conjugate-gradient solver
+  adjoint     sensitivities of the effective stiffness to the per-voxel
+              Lame constants (energy form, no second solve)
 """
