@@ -146,6 +146,32 @@ int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
 int feh_effective_stiffness(int dim, int n_load, const double *Ebar_host,
                             const double *energy_host, double *C_host);
 
+/* Host helper: the weights dJ/dW_lm = (E^-1 G E^-T)_lm of an objective
+ * J = sum_IJ G[I][J] C_eff[I][J] (C_eff from feh_effective_stiffness with the
+ * same n_load = nv load cases), for feh_energy_sensitivity.
+ *   G_host [nv][nv], weight_host [nv][nv] output.  FEH_EINVAL as above. */
+int feh_effective_stiffness_weights(int dim, int n_load, const double *Ebar_host, const double *G_host,
+                                    double *weight_host);
+
+/* Sensitivities of the energy matrix to the per-voxel Lame constants, for an
+ * objective J = sum_lm weight[l][m] W_lm with W_lm = < e_l : C : e_m > (the
+ * energy form of the effective stiffness, Sec. "Compatibility projection":
+ * the weak form makes each W_ll an energy minimum over compatible
+ * fluctuations, so only the explicit dependence on C counts, and the
+ * off-diagonal entries follow by polarisation; the adjoint field of W_lm is
+ * the forward fluctuation of load case m, no second solve):
+ *   grad_lam[v] = sum_lm weight[l][m] < tr e_l tr e_m >_v
+ *   grad_mu[v]  = sum_lm weight[l][m] < 2 e_l : e_m >_v
+ * where < . >_v sums the elements of voxel v with the weights of the cell
+ * average.  For J = sum_IJ G_IJ C_eff_IJ pass weight = E^-1 G E^-T (E the
+ * engineering Voigt strain columns of the load cases).
+ *   weight_host   [n_load][n_load] host, FP64, finite (not necessarily symmetric)
+ *   grad_lam_dev, grad_mu_dev  outputs [N] in the plan precision (caller-owned)
+ * Uses the fluctuations left in the workspace by the last feh_solve on this
+ * plan (FEH_OK or FEH_ENOCONV); FEH_EINVAL if there is none (no solve yet, a
+ * breakdown, or the material or workspace changed since).  Blocking. */
+int feh_energy_sensitivity(feh_plan *plan, const double *weight_host, void *grad_lam_dev, void *grad_mu_dev);
+
 /* Test export: q = K p with K = sum_e |e| B_e^T C_e B_e, p and q
  * [n_load][N][D] in the plan precision. */
 int feh_apply_operator(feh_plan *plan, const void *p_dev, void *q_dev);

@@ -21,7 +21,8 @@ __all__ = [
     "FEH_FP64", "FEH_FP32", "FehError", "feh_report", "library_path", "load",
     "feh_plan_create", "feh_plan_destroy", "feh_plan_workspace_bytes", "feh_plan_set_workspace",
     "feh_set_material_lame", "feh_set_material_phases", "feh_set_material_field", "feh_solve",
-    "feh_effective_stiffness", "feh_apply_operator", "feh_apply_preconditioner", "feh_apply_projection",
+    "feh_effective_stiffness", "feh_effective_stiffness_weights", "feh_energy_sensitivity",
+    "feh_apply_operator", "feh_apply_preconditioner", "feh_apply_projection",
     "feh_fft_forward", "feh_fft_inverse", "feh_profile_enable", "feh_profile_read", "PROFILE_KINDS",
     "feh_last_error", "feh_version", "Homogenizer",
 ]
@@ -60,6 +61,8 @@ _SIGS = {
     "feh_solve": (ctypes.c_int, [_vp, _dp, ctypes.c_double, ctypes.c_int, _vp, _vp, _vp, _vp, _dp, _dp,
                                  ctypes.POINTER(feh_report)]),
     "feh_effective_stiffness": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]),
+    "feh_effective_stiffness_weights": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]),
+    "feh_energy_sensitivity": (ctypes.c_int, [_vp, _dp, _vp, _vp]),
     "feh_apply_operator": (ctypes.c_int, [_vp, _vp, _vp]),
     "feh_apply_preconditioner": (ctypes.c_int, [_vp, _vp, _vp]),
     "feh_apply_projection": (ctypes.c_int, [_vp, _vp, _vp]),
@@ -194,6 +197,22 @@ def feh_profile_read(plan):
     return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PROFILE_KINDS)}
 
 
+def feh_effective_stiffness_weights(dim, Ebar, G):
+    """dJ/dW for J = sum G_IJ C_eff_IJ (host helper of the C ABI)."""
+    nv = 3 if dim == 2 else 6
+    Eb = np.ascontiguousarray(Ebar, dtype=np.float64).reshape(nv, dim, dim)
+    Gm = np.ascontiguousarray(G, dtype=np.float64).reshape(nv, nv)
+    W = np.zeros((nv, nv))
+    _check(load().feh_effective_stiffness_weights(dim, nv, Eb.ctypes.data_as(_dp), Gm.ctypes.data_as(_dp),
+                                                  W.ctypes.data_as(_dp)))
+    return W
+
+
+def feh_energy_sensitivity(plan, weight, glam_ptr, gmu_ptr):
+    w = np.ascontiguousarray(weight, dtype=np.float64)
+    return _check(load().feh_energy_sensitivity(plan, w.ctypes.data_as(_dp), _vp(glam_ptr), _vp(gmu_ptr)))
+
+
 def feh_apply_operator(plan, p_ptr, q_ptr):
     return _check(load().feh_apply_operator(plan, _vp(p_ptr), _vp(q_ptr)))
 
@@ -279,6 +298,7 @@ class Homogenizer:
                                       strain.data_ptr() if strain is not None else 0,
                                       stress.data_ptr() if stress is not None else 0)
         out = dict(status=rc, stress_mean=smean, energy=W, report=rep, u=u, strain=strain, stress=stress)
+        self._last_Ebar = Ebar
         nv = 3 if D == 2 else 6
         if L == nv:
             try:
@@ -286,6 +306,19 @@ class Homogenizer:
             except FehError:
                 pass
         return out
+
+    def energy_sensitivity(self, weight):
+        """Per-voxel (dJ/dlambda, dJ/dmu) for J = sum weight_lm W_lm of the last solve."""
+        g_lam = self.torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        g_mu = self.torch.empty_like(g_lam)
+        feh_energy_sensitivity(self.plan, np.asarray(weight, dtype=np.float64).reshape(self.n_load, self.n_load),
+                               g_lam.data_ptr(), g_mu.data_ptr())
+        return g_lam, g_mu
+
+    def c_eff_sensitivity(self, G):
+        """Per-voxel (dJ/dlambda, dJ/dmu) for J = sum G_IJ C_eff_IJ of the last solve
+        (which must have used nv load cases)."""
+        return self.energy_sensitivity(feh_effective_stiffness_weights(self.dim, self._last_Ebar, G))
 
     def apply_operator(self, p):
         p = self._dev(p).reshape(self.n_load, self.N, self.dim)

@@ -104,6 +104,7 @@ static void layout(feh_plan &p) {
     p.off_part = take(parts * sizeof(double));
     p.off_state = take((size_t)p.L * sizeof(LcState));
     p.off_flag = take(256);
+    p.off_pairs = take((size_t)kMaxLoad * (kMaxLoad + 1) / 2 * (2 * sizeof(int) + sizeof(double)));
     p.total = o;
 }
 
@@ -404,6 +405,7 @@ int feh_plan_set_workspace(feh_plan *plan, void *dev_ptr, size_t bytes) {
         plan->ws = static_cast<char *>(dev_ptr);
         plan->ws_bytes = bytes;
         plan->material_set = false;
+        plan->solved = false;
         return upload_tables(*plan);
     } catch (...) {
         return set_error(FEH_EINVAL, "unexpected host exception");
@@ -418,6 +420,7 @@ int feh_set_material_lame(feh_plan *plan, const void *lambda_dev, const void *mu
     CK(launch_material_lame(*plan, lambda_dev, mu_dev, flag));
     CK(read_flag(*plan, flag, "feh_set_material_lame"));
     plan->material_set = true;
+    plan->solved = false;
     return FEH_OK;
 }
 
@@ -441,6 +444,7 @@ int feh_set_material_phases(feh_plan *plan, const int32_t *phase_dev, const doub
     CK(launch_material_phases(*plan, phase_dev, dtab, n_phase, flag));
     CK(read_flag(*plan, flag, "feh_set_material_phases"));
     plan->material_set = true;
+    plan->solved = false;
     return FEH_OK;
 }
 
@@ -453,6 +457,7 @@ int feh_set_material_field(feh_plan *plan, const void *E_dev, double nu) {
     CK(launch_material_field(*plan, E_dev, nu, flag));
     CK(read_flag(*plan, flag, "feh_set_material_field"));
     plan->material_set = true;
+    plan->solved = false;
     return FEH_OK;
 }
 
@@ -464,6 +469,7 @@ int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
         feh_plan &p = *plan;
         if (!Ebar_host) return set_error(FEH_EINVAL, "null Ebar");
         if (!(tol >= 0.0) || !std::isfinite(tol)) return set_error(FEH_EINVAL, "tol must be finite and >= 0");
+        p.solved = false;
         if (max_iter < 1) return set_error(FEH_EINVAL, "max_iter must be >= 1");
         const int D = p.dim;
         for (int l = 0; l < p.L; ++l)
@@ -564,6 +570,7 @@ int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
             if (hs[l].status == FEH_EBREAKDOWN) rc = FEH_EBREAKDOWN;
             else if ((hs[l].status == FEH_ENOCONV || hs[l].active) && rc == FEH_OK) rc = FEH_ENOCONV;
         }
+        p.solved = rc != FEH_EBREAKDOWN;
         if (rc == FEH_ENOCONV) return set_error(rc, "max_iter reached before the tolerance");
         if (rc == FEH_EBREAKDOWN) return set_error(rc, "CG breakdown (p.q <= 0 or not finite)");
         return FEH_OK;
@@ -574,14 +581,12 @@ int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
     }
 }
 
-int feh_effective_stiffness(int dim, int n_load, const double *Ebar_host, const double *energy_host, double *C_host) {
-    if (dim != 2 && dim != 3) return set_error(FEH_EINVAL, "dim must be 2 or 3");
+// Inverse of the engineering Voigt strain matrix E[v][l] of nv load cases.
+static int voigt_load_inverse(int dim, const double *Ebar_host, std::vector<double> &E) {
     const int nv = dim == 3 ? 6 : 3;
-    if (n_load != nv) return set_error(FEH_EINVAL, "need exactly nv load cases");
-    if (!Ebar_host || !energy_host || !C_host) return set_error(FEH_EINVAL, "null argument");
     static const int P2[3][2] = {{0, 0}, {1, 1}, {0, 1}};
     static const int P3[6][2] = {{0, 0}, {1, 1}, {2, 2}, {1, 2}, {0, 2}, {0, 1}};
-    std::vector<double> E(nv * nv);  // E[v][l]: engineering Voigt strain of load l
+    E.assign(nv * nv, 0.0);
     for (int l = 0; l < nv; ++l)
         for (int v = 0; v < nv; ++v) {
             const int a = dim == 3 ? P3[v][0] : P2[v][0], b = dim == 3 ? P3[v][1] : P2[v][1];
@@ -590,6 +595,16 @@ int feh_effective_stiffness(int dim, int n_load, const double *Ebar_host, const 
     bool ok = false;
     invert(nv, E, ok);
     if (!ok) return set_error(FEH_EINVAL, "load-case strains are linearly dependent");
+    return FEH_OK;
+}
+
+int feh_effective_stiffness(int dim, int n_load, const double *Ebar_host, const double *energy_host, double *C_host) {
+    if (dim != 2 && dim != 3) return set_error(FEH_EINVAL, "dim must be 2 or 3");
+    const int nv = dim == 3 ? 6 : 3;
+    if (n_load != nv) return set_error(FEH_EINVAL, "need exactly nv load cases");
+    if (!Ebar_host || !energy_host || !C_host) return set_error(FEH_EINVAL, "null argument");
+    std::vector<double> E;
+    CK(voigt_load_inverse(dim, Ebar_host, E));
     // C = Einv^T W Einv
     std::vector<double> T(nv * nv, 0.0);
     for (int i = 0; i < nv; ++i)
@@ -603,6 +618,31 @@ int feh_effective_stiffness(int dim, int n_load, const double *Ebar_host, const 
             double s = 0.0;
             for (int k = 0; k < nv; ++k) s += E[k * nv + i] * T[k * nv + j];
             C_host[i * nv + j] = s;
+        }
+    return FEH_OK;
+}
+
+int feh_effective_stiffness_weights(int dim, int n_load, const double *Ebar_host, const double *G_host,
+                                    double *weight_host) {
+    if (dim != 2 && dim != 3) return set_error(FEH_EINVAL, "dim must be 2 or 3");
+    const int nv = dim == 3 ? 6 : 3;
+    if (n_load != nv) return set_error(FEH_EINVAL, "need exactly nv load cases");
+    if (!Ebar_host || !G_host || !weight_host) return set_error(FEH_EINVAL, "null argument");
+    std::vector<double> E;  // Einv[l][v]
+    CK(voigt_load_inverse(dim, Ebar_host, E));
+    // weight = Einv G Einv^T
+    std::vector<double> T(nv * nv, 0.0);
+    for (int i = 0; i < nv; ++i)
+        for (int j = 0; j < nv; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < nv; ++k) s += E[i * nv + k] * G_host[k * nv + j];
+            T[i * nv + j] = s;
+        }
+    for (int i = 0; i < nv; ++i)
+        for (int j = 0; j < nv; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < nv; ++k) s += T[i * nv + k] * E[j * nv + k];
+            weight_host[i * nv + j] = s;
         }
     return FEH_OK;
 }
@@ -625,6 +665,44 @@ int feh_profile_read(const feh_plan *plan, double *ms_total, int64_t *launches, 
         launches[k] = k < feh_plan::kProfKinds ? plan->prof_n[k] : 0;
     }
     return FEH_OK;
+}
+
+int feh_energy_sensitivity(feh_plan *plan, const double *weight_host, void *grad_lam_dev, void *grad_mu_dev) {
+    try {
+        CK(check_plan(plan, true));
+        feh_plan &p = *plan;
+        if (!weight_host || !grad_lam_dev || !grad_mu_dev) return set_error(FEH_EINVAL, "null argument");
+        if (!p.solved) return set_error(FEH_EINVAL, "no solution in the plan (call feh_solve first)");
+        std::vector<int> pl, pm;
+        std::vector<double> pw;
+        for (int l = 0; l < p.L; ++l)
+            for (int m = l; m < p.L; ++m) {
+                const double a = weight_host[l * p.L + m], b = weight_host[m * p.L + l];
+                if (!std::isfinite(a) || !std::isfinite(b)) return set_error(FEH_EINVAL, "weights must be finite");
+                const double w = (l == m) ? a : a + b;
+                if (w == 0.0) continue;
+                pl.push_back(l);
+                pm.push_back(m);
+                pw.push_back(w);
+            }
+        const int np = (int)pl.size();
+        const size_t ni = (size_t)kMaxLoad * (kMaxLoad + 1) / 2;
+        int *dpl = p.ptr<int>(p.off_pairs);
+        int *dpm = dpl + ni;
+        double *dpw = reinterpret_cast<double *>(dpm + ni);
+        if (np > 0) {
+            CK(hip_check(hipMemcpyAsync(dpl, pl.data(), np * sizeof(int), hipMemcpyHostToDevice, p.stream), "pairs"));
+            CK(hip_check(hipMemcpyAsync(dpm, pm.data(), np * sizeof(int), hipMemcpyHostToDevice, p.stream), "pairs"));
+            CK(hip_check(hipMemcpyAsync(dpw, pw.data(), np * sizeof(double), hipMemcpyHostToDevice, p.stream), "pairs"));
+        }
+        CK(launch_sensitivity(p, p.ws + p.off_u, p.ptr<double>(p.off_ebar), dpl, dpm, dpw, np, grad_lam_dev,
+                              grad_mu_dev));
+        return hip_check(hipStreamSynchronize(p.stream), "sensitivity");
+    } catch (const std::bad_alloc &) {
+        return set_error(FEH_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return set_error(FEH_EINVAL, "unexpected host exception");
+    }
 }
 
 int feh_apply_operator(feh_plan *plan, const void *p_dev, void *q_dev) {

@@ -128,12 +128,14 @@ struct feh_plan {
     size_t off_aa[3] = {0, 0, 0};       // (e^{+2 pi i m / n_a} - 1) / h_a (FP64)
     size_t off_tab = 0, off_ebar = 0, off_sums = 0;
     size_t off_part = 0, off_state = 0, off_flag = 0;
+    size_t off_pairs = 0;               // load-case pair list of the sensitivity pass
     size_t part_stride = 0;             // doubles per load case in the partials
     size_t total = 0;
 
     char *ws = nullptr;
     size_t ws_bytes = 0;
     bool material_set = false;
+    bool solved = false;                // off_u holds the fluctuations of the last feh_solve
 
     // optional per-kernel event timing of the CG loop
     static constexpr int kProfKinds = 8;
@@ -225,6 +227,9 @@ int launch_remove_mean(const feh_plan &p, void *x, double *partial, double *mean
 int launch_post_sums(const feh_plan &p, const void *u, const double *Ebar_dev, void *strain, void *stress,
                      double *partial, double *sums);
 int launch_grad(const feh_plan &p, const void *u, void *e);   // e = sym(B u) element field
+// g_lam, g_mu = sum over pairs (l <= m, weight w) of the voxel's share of dW_lm/dlambda, dW_lm/dmu
+int launch_sensitivity(const feh_plan &p, const void *u, const double *Ebar_dev, const int *pl, const int *pm,
+                       const double *pw, int npair, void *g_lam, void *g_mu);
 int post_num_slots(const feh_plan &p);
 
 // partial-sum sizes

@@ -237,6 +237,58 @@ __global__ __launch_bounds__(kThreads) void k_grad(PK<T> a) {
     }
 }
 
+// Sensitivities of sum_lm w_lm W_lm to the per-voxel Lame constants.  W_lm is
+// stationary in the fluctuations (energy minimum of the weak form), so only
+// the explicit dependence on C counts:
+//   g_lam[v] = sum_pairs w <tr e_l tr e_m>_v,  g_mu[v] = sum_pairs w <2 e_l : e_m>_v,
+// <.>_v the element terms of voxel v with the weights of the cell average
+// (scale = 1 / (N n_e)).  The pair list holds l <= m; an off-diagonal pair's
+// weight already carries w_lm + w_ml.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kThreads) void k_sens(PK<T> a, const int *pl, const int *pm, const double *pw, int npair,
+                                                   double scale, T *g_lam, T *g_mu) {
+    constexpr int NE = DIM == 3 ? 6 : 2;
+    constexpr int NS = DIM == 3 ? 6 : 3;
+    for (long long v = blockIdx.x * (long long)kThreads + threadIdx.x; v < a.N; v += (long long)gridDim.x * kThreads) {
+        double gl = 0.0, gm = 0.0;
+        for (int q = 0; q < npair; ++q) {
+            const int l = pl[q], m = pm[q];
+            const double w = pw[q];
+            double e[NE][NS], f[NE][NS];
+            voxel_strains<T, DIM>(a, l, v, true, e);
+            if (m != l) {
+                voxel_strains<T, DIM>(a, m, v, true, f);
+            } else {
+                #pragma unroll
+                for (int t = 0; t < NE; ++t)
+                    #pragma unroll
+                    for (int k = 0; k < NS; ++k) f[t][k] = e[t][k];
+            }
+            double sl = 0.0, sm = 0.0;
+            #pragma unroll
+            for (int t = 0; t < NE; ++t) {
+                double te, tf, dd;
+                if constexpr (DIM == 3) {
+                    te = e[t][0] + e[t][1] + e[t][2];
+                    tf = f[t][0] + f[t][1] + f[t][2];
+                    dd = e[t][0] * f[t][0] + e[t][1] * f[t][1] + e[t][2] * f[t][2] +
+                         2.0 * (e[t][3] * f[t][3] + e[t][4] * f[t][4] + e[t][5] * f[t][5]);
+                } else {
+                    te = e[t][0] + e[t][1];
+                    tf = f[t][0] + f[t][1];
+                    dd = e[t][0] * f[t][0] + e[t][1] * f[t][1] + 2.0 * e[t][2] * f[t][2];
+                }
+                sl += te * tf;
+                sm += 2.0 * dd;
+            }
+            gl += w * sl;
+            gm += w * sm;
+        }
+        g_lam[v] = T(gl * scale);
+        g_mu[v] = T(gm * scale);
+    }
+}
+
 __global__ void k_reduce_slots(const double *part, int nblk, double *out, double scale) {
     __shared__ double red[kThreads / 64];
     const int slot = blockIdx.x;
@@ -328,6 +380,31 @@ static int grad_t(const feh_plan &p, const void *u, void *e) {
 
 int launch_grad(const feh_plan &p, const void *u, void *e) {
     return p.prec == FEH_FP64 ? grad_t<double>(p, u, e) : grad_t<float>(p, u, e);
+}
+
+template <typename T>
+static int sens_t(const feh_plan &p, const void *u, const double *Ebar, const int *pl, const int *pm, const double *pw,
+                  int npair, void *g_lam, void *g_mu) {
+    PK<T> a = post_args<T>(p);
+    a.u = static_cast<const T *>(u);
+    a.Ebar = Ebar;
+    long long g = (p.N + kThreads - 1) / kThreads;
+    if (g > 4096) g = 4096;
+    const int ne = p.dim == 3 ? 6 : 2;
+    const double scale = 1.0 / ((double)p.N * ne);
+    if (p.dim == 3)
+        hipLaunchKernelGGL((k_sens<T, 3>), dim3((unsigned)g), dim3(kThreads), 0, p.stream, a, pl, pm, pw, npair, scale,
+                           static_cast<T *>(g_lam), static_cast<T *>(g_mu));
+    else
+        hipLaunchKernelGGL((k_sens<T, 2>), dim3((unsigned)g), dim3(kThreads), 0, p.stream, a, pl, pm, pw, npair, scale,
+                           static_cast<T *>(g_lam), static_cast<T *>(g_mu));
+    return hip_check(hipGetLastError(), "sensitivity launch");
+}
+
+int launch_sensitivity(const feh_plan &p, const void *u, const double *Ebar_dev, const int *pl, const int *pm,
+                       const double *pw, int npair, void *g_lam, void *g_mu) {
+    return p.prec == FEH_FP64 ? sens_t<double>(p, u, Ebar_dev, pl, pm, pw, npair, g_lam, g_mu)
+                              : sens_t<float>(p, u, Ebar_dev, pl, pm, pw, npair, g_lam, g_mu);
 }
 
 }  // namespace feh

@@ -95,3 +95,23 @@ def test_effective_stiffness_helper_matches_oracle(dim):
     np.testing.assert_allclose(got, C, rtol=1e-9, atol=1e-10)
     with pytest.raises(feh.FehError):
         feh.feh_effective_stiffness(dim, np.zeros((nv, dim, dim)), W)
+
+
+def test_effective_stiffness_weights_match_oracle():
+    """Host helper E^-1 G E^-T against the oracle's chain rule, general loads."""
+    from oracle import adjoint
+    rng = np.random.default_rng(4)
+    for dim in (2, 3):
+        nv = 3 if dim == 2 else 6
+        Eb = np.array([0.5 * (a + a.T) for a in rng.standard_normal((nv, dim, dim))])
+        G = rng.standard_normal((nv, nv))
+        W = feh.feh_effective_stiffness_weights(dim, Eb, G)
+        np.testing.assert_allclose(W, adjoint.objective_weights(Eb, G), rtol=1e-10, atol=1e-12)
+
+
+def test_energy_sensitivity_needs_workspace_and_solution():
+    p = feh.feh_plan_create(2, (8, 6), None, 3, feh.FEH_FP64)
+    with pytest.raises(feh.FehError) as ei:
+        feh.feh_energy_sensitivity(p, np.eye(3), 0, 0)
+    assert ei.value.status in (feh.FEH_ENOMEM, feh.FEH_EINVAL)
+    feh.feh_plan_destroy(p)
