@@ -209,6 +209,27 @@ def main():
     cg_ms = sum(v[0] for v in prof.values())
     all_bytes = sum(kb.values())
 
+    # sensitivity pass of the adjoint row (d trace(C_eff) / d lambda_v, d mu_v;
+    # reads every load case's fluctuation once, writes two fields)
+    sens = None
+    nv = 3 if dim == 2 else 6
+    if L == nv and C32 is not None:
+        hz.c_eff_sensitivity(np.eye(nv))
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record()
+        for _ in range(reps):
+            hz.c_eff_sensitivity(np.eye(nv))
+        e1.record()
+        torch.cuda.synchronize()
+        sms = e0.elapsed_time(e1) / reps
+        sbytes = (L * dim * s + 2 * s) * N
+        sens = {"objective": "trace C_eff", "ms": round(sms, 3), "GBps_algorithmic": round(sbytes / (sms / 1e3) / 1e9, 1),
+                "algorithmic_bytes": sbytes}
+        log("sensitivity", sens)
+
     # FP32 vs FP64 on the same input (untimed)
     fp_err = None
     if precname == "fp32" and not args.no_fp64_check and C32 is not None:
@@ -252,6 +273,7 @@ def main():
         "cg_loop_GBps_algorithmic": round(all_bytes / (cg_ms / 1e3) / 1e9, 1) if cg_ms > 0 else None,
         "roofline": roof,
         "kernels": kernels,
+        "sensitivity": sens,
         "cpu_baseline": cpu,
         "C_eff": np.round(C32, 8).tolist() if C32 is not None else None,
     }
