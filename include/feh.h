@@ -74,6 +74,7 @@ enum {
 enum { FEH_FP64 = 0, FEH_FP32 = 1 };
 
 typedef struct feh_plan feh_plan;
+typedef struct feh_batch feh_batch;
 
 typedef struct {
     int32_t iterations;   /* CG iterations performed for this load case           */
@@ -92,6 +93,18 @@ typedef struct {
 int feh_plan_create(feh_plan **plan, int dim, const int64_t n[], const double h[],
                     int n_load, int precision, void *hip_stream);
 
+/* Batched plan: n_batch microstructures of the same grid, each with its own
+ * material and n_load load cases; the plan then carries n_batch * n_load
+ * load cases (<= 64), numbered l = b * n_load + j for microstructure b.
+ * Every per-load-case array of the entry points below keeps its layout with
+ * this numbering; material arrays become [n_batch][N]; load cases of
+ * different microstructures never interact (their energy-matrix entries are
+ * zero).  Each load case stops on its own, so a batch of easy and hard
+ * microstructures costs the hard ones' iterations only for them.
+ * feh_plan_create is the case n_batch = 1. */
+int feh_plan_create_batch(feh_plan **plan, int dim, const int64_t n[], const double h[],
+                          int n_batch, int n_load, int precision, void *hip_stream);
+
 /* Destroy a plan (NULL is a no-op).  Does not free the workspace. */
 int feh_plan_destroy(feh_plan *plan);
 
@@ -105,19 +118,21 @@ int feh_plan_workspace_bytes(const feh_plan *plan, size_t *bytes);
  * The material must be set again after a new workspace. */
 int feh_plan_set_workspace(feh_plan *plan, void *dev_ptr, size_t bytes);
 
-/* Material from per-voxel Lame constants (device arrays of N values in the
- * plan precision).  lambda and mu must be finite with mu >= 0 and
+/* Material from per-voxel Lame constants (device arrays of N values, or
+ * [n_batch][N] for a batched plan, in the plan precision).  lambda and mu must be finite with mu >= 0 and
  * lambda + 2 mu / dim >= 0 (checked on the device; FEH_EINVAL otherwise). */
 int feh_set_material_lame(feh_plan *plan, const void *lambda_dev, const void *mu_dev);
 
-/* Material from a phase map (device int32[N], values in [0, n_phase)) and a
+/* Material from a phase map (device int32[N] or [n_batch][N], values in
+ * [0, n_phase)) and a
  * host table E_nu[n_phase][2] = (E, nu) with E >= 0 and -1 < nu < 0.5.
  * Plane strain in 2D: lambda = E nu/((1+nu)(1-2nu)), mu = E/(2(1+nu)). */
 int feh_set_material_phases(feh_plan *plan, const int32_t *phase_dev,
                             const double *E_nu_host, int n_phase);
 
-/* Material from a per-voxel Young's modulus field (device, N values in the
- * plan precision, E >= 0) and a uniform Poisson ratio (-1 < nu < 0.5). */
+/* Material from a per-voxel Young's modulus field (device, N or [n_batch][N]
+ * values in the plan precision, E >= 0) and a uniform Poisson ratio
+ * (-1 < nu < 0.5). */
 int feh_set_material_field(feh_plan *plan, const void *E_dev, double nu);
 
 /* Solve all load cases: find the periodic fluctuation u with zero mean such
@@ -138,6 +153,37 @@ int feh_set_material_field(feh_plan *plan, const void *E_dev, double nu);
 int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
               const void *u0_dev, void *u_dev, void *strain_dev, void *stress_dev,
               double *stress_mean_host, double *energy_host, feh_report *report_host);
+
+/* Uneven batches: plans of different grids (each possibly a batched plan)
+ * that share one created HIP stream, solved together.  After each plan's
+ * set-up, the CG iterations of all plans run in chunks of 4, 8, then 16
+ * iterations per plan; with use_graph != 0 each chunk is one hipGraphLaunch
+ * of a graph captured once per (chunk, tol, max_iter) and replayed, so a
+ * batch of many small grids costs one launch per chunk instead of one per
+ * kernel.  Every load case stops on its own (converged load cases return
+ * at once from every kernel).  The batch keeps pointers to the plans (the
+ * caller keeps them, their workspaces and materials alive and unchanged
+ * while the batch exists; otherwise destroy and re-create the batch).
+ * FEH_EINVAL for null or repeated plans, plans on different streams or on
+ * the null stream. */
+int feh_batch_create(feh_batch **batch, feh_plan *const *plans, int n_plans);
+int feh_batch_destroy(feh_batch *batch);
+
+/* Solve every plan of the batch (no warm start, no field outputs; the
+ * fluctuations stay in each plan's workspace for feh_energy_sensitivity).
+ *   Ebar_host         [n_plans] pointers, each [n_load of that plan][D][D]
+ *   stress_mean_host, energy_host, report_host   nullable tables of
+ *                     [n_plans] nullable pointers, per-plan layouts as in
+ *                     feh_solve
+ * Returns FEH_OK, or the worst per-plan status (FEH_EBREAKDOWN over
+ * FEH_ENOCONV); outputs are filled either way. */
+int feh_batch_solve(feh_batch *batch, const double *const *Ebar_host, double tol, int max_iter, int use_graph,
+                    double *const *stress_mean_host, double *const *energy_host,
+                    feh_report *const *report_host);
+
+/* Chunks launched by the last feh_batch_solve (graph launches when
+ * use_graph != 0); -1 for a null batch. */
+int feh_batch_graph_launches(const feh_batch *batch);
 
 /* Host helper: effective Voigt stiffness C[nv][nv] (engineering shear,
  * order 2D (xx,yy,xy), 3D (xx,yy,zz,yz,xz,xy)) from an energy matrix W of
@@ -166,7 +212,9 @@ int feh_effective_stiffness_weights(int dim, int n_load, const double *Ebar_host
  * average.  For J = sum_IJ G_IJ C_eff_IJ pass weight = E^-1 G E^-T (E the
  * engineering Voigt strain columns of the load cases).
  *   weight_host   [n_load][n_load] host, FP64, finite (not necessarily symmetric)
- *   grad_lam_dev, grad_mu_dev  outputs [N] in the plan precision (caller-owned)
+ *   grad_lam_dev, grad_mu_dev  outputs [N] ([n_batch][N] for a batched plan)
+ *                 in the plan precision (caller-owned); weights between load
+ *                 cases of different microstructures must be zero
  * Uses the fluctuations left in the workspace by the last feh_solve on this
  * plan (FEH_OK or FEH_ENOCONV); FEH_EINVAL if there is none (no solve yet, a
  * breakdown, or the material or workspace changed since).  Blocking. */

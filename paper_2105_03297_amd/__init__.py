@@ -19,12 +19,13 @@ import numpy as np
 __all__ = [
     "FEH_OK", "FEH_EINVAL", "FEH_ENOMEM", "FEH_EHIP", "FEH_ENOCONV", "FEH_EBREAKDOWN", "FEH_ENOTSUP",
     "FEH_FP64", "FEH_FP32", "FehError", "feh_report", "library_path", "load",
-    "feh_plan_create", "feh_plan_destroy", "feh_plan_workspace_bytes", "feh_plan_set_workspace",
+    "feh_plan_create", "feh_plan_create_batch", "feh_plan_destroy", "feh_plan_workspace_bytes", "feh_plan_set_workspace",
     "feh_set_material_lame", "feh_set_material_phases", "feh_set_material_field", "feh_solve",
     "feh_effective_stiffness", "feh_effective_stiffness_weights", "feh_energy_sensitivity",
     "feh_apply_operator", "feh_apply_preconditioner", "feh_apply_projection",
     "feh_fft_forward", "feh_fft_inverse", "feh_profile_enable", "feh_profile_read", "PROFILE_KINDS",
-    "feh_last_error", "feh_version", "Homogenizer",
+    "feh_batch_create", "feh_batch_destroy", "feh_batch_solve", "feh_batch_graph_launches",
+    "feh_last_error", "feh_version", "Homogenizer", "UnevenBatch",
 ]
 
 FEH_OK, FEH_EINVAL, FEH_ENOMEM, FEH_EHIP, FEH_ENOCONV, FEH_EBREAKDOWN, FEH_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
@@ -52,6 +53,8 @@ _dp = ctypes.POINTER(ctypes.c_double)
 _SIGS = {
     "feh_plan_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
                                        _dp, ctypes.c_int, ctypes.c_int, _vp]),
+    "feh_plan_create_batch": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                             _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
     "feh_plan_destroy": (ctypes.c_int, [_vp]),
     "feh_plan_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     "feh_plan_set_workspace": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
@@ -70,6 +73,11 @@ _SIGS = {
     "feh_fft_inverse": (ctypes.c_int, [_vp, _vp, _vp]),
     "feh_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "feh_profile_read": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
+    "feh_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int]),
+    "feh_batch_destroy": (ctypes.c_int, [_vp]),
+    "feh_batch_solve": (ctypes.c_int, [_vp, ctypes.POINTER(_dp), ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(_dp), ctypes.POINTER(_dp), ctypes.POINTER(ctypes.POINTER(feh_report))]),
+    "feh_batch_graph_launches": (ctypes.c_int, [_vp]),
     "feh_last_error": (ctypes.c_char_p, []),
     "feh_version": (ctypes.c_int, []),
 }
@@ -130,6 +138,18 @@ def feh_plan_create(dim, n, h=None, n_load=1, precision=FEH_FP64, stream=0):
     return plan
 
 
+def feh_plan_create_batch(dim, n, h=None, n_batch=1, n_load=1, precision=FEH_FP64, stream=0):
+    n_arr = (ctypes.c_int64 * 3)(*(list(n) + [1] * (3 - len(n))))
+    h_ptr = None
+    if h is not None:
+        h_keep = (ctypes.c_double * 3)(*(list(h) + [1.0] * (3 - len(h))))
+        h_ptr = ctypes.cast(h_keep, _dp)
+    plan = _vp()
+    _check(load().feh_plan_create_batch(ctypes.byref(plan), int(dim), n_arr, h_ptr, int(n_batch), int(n_load),
+                                        int(precision), _vp(stream or 0)))
+    return plan
+
+
 def feh_plan_destroy(plan):
     return _check(load().feh_plan_destroy(plan))
 
@@ -178,6 +198,38 @@ def feh_effective_stiffness(dim, Ebar, W):
     C = np.zeros((nv, nv))
     _check(load().feh_effective_stiffness(int(dim), int(Eb.shape[0]), Ebp, Wp, C.ctypes.data_as(_dp)))
     return C
+
+
+def feh_batch_create(plans):
+    arr = (_vp * len(plans))(*[p.value if isinstance(p, _vp) else p for p in plans])
+    b = _vp()
+    _check(load().feh_batch_create(ctypes.byref(b), arr, len(plans)))
+    return b
+
+
+def feh_batch_destroy(batch):
+    return _check(load().feh_batch_destroy(batch))
+
+
+def feh_batch_solve(batch, Ebars, tol, max_iter, use_graph=True, allow_noconv=True):
+    """Ebars: per plan [L][D][D].  Returns (status, stress_means, energies, reports) per plan."""
+    n = len(Ebars)
+    keep = [np.ascontiguousarray(e, dtype=np.float64) for e in Ebars]
+    eb = (_dp * n)(*[k.ctypes.data_as(_dp) for k in keep])
+    sm = [np.zeros((k.shape[0], k.shape[1], k.shape[2])) for k in keep]
+    W = [np.zeros((k.shape[0], k.shape[0])) for k in keep]
+    reps = [(feh_report * k.shape[0])() for k in keep]
+    smp = (_dp * n)(*[a.ctypes.data_as(_dp) for a in sm])
+    Wp = (_dp * n)(*[a.ctypes.data_as(_dp) for a in W])
+    rp = (ctypes.POINTER(feh_report) * n)(*[ctypes.cast(r, ctypes.POINTER(feh_report)) for r in reps])
+    rc = load().feh_batch_solve(batch, eb, float(tol), int(max_iter), 1 if use_graph else 0, smp, Wp, rp)
+    _check(rc, allow=(FEH_ENOCONV,) if allow_noconv else ())
+    out_rep = [[dict(iterations=r.iterations, status=r.status, rel_residual=r.rel_residual) for r in rr] for rr in reps]
+    return rc, sm, W, out_rep
+
+
+def feh_batch_graph_launches(batch):
+    return load().feh_batch_graph_launches(batch)
 
 
 PROFILE_KINDS = ["stencil", "alpha", "fft_last_fwd", "fft_middle_fwd", "fft_first_ksolve", "fft_middle_inv",
@@ -239,18 +291,22 @@ def feh_fft_inverse(plan, X_ptr, x_ptr):
 class Homogenizer:
     """One plan bound to a torch device and stream, with a torch-owned workspace.
 
-    shape: grid (Nx, Ny[, Nz]); n_load: load cases solved together;
-    precision: "fp64" or "fp32" (FP32 fields/FFT/stencils, FP64 CG scalars
-    and per-wavevector solve); h: voxel sizes (default 1).
+    shape: grid (Nx, Ny[, Nz]); n_load: load cases solved together (per
+    microstructure); n_batch: microstructures of this shape in one plan (their
+    materials stacked along a leading axis, load cases numbered
+    b * n_load + j); precision: "fp64" or "fp32" (FP32 fields/FFT/stencils,
+    FP64 CG scalars and per-wavevector inverses); h: voxel sizes (default 1).
     """
 
-    def __init__(self, shape, n_load=1, precision="fp64", h=None, device="cuda", stream=None):
+    def __init__(self, shape, n_load=1, precision="fp64", h=None, device="cuda", stream=None, n_batch=1):
         import torch
         self.torch = torch
         self.shape = tuple(int(s) for s in shape)
         self.dim = len(self.shape)
         self.N = int(np.prod(self.shape))
-        self.n_load = int(n_load)
+        self.n_batch = int(n_batch)
+        self.n_per = int(n_load)
+        self.n_load = self.n_batch * self.n_per  # load cases in the plan
         self.precision = precision
         self.prec = FEH_FP64 if precision == "fp64" else FEH_FP32
         self.dtype = torch.float64 if self.prec == FEH_FP64 else torch.float32
@@ -259,7 +315,8 @@ class Homogenizer:
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
-        self.plan = feh_plan_create(self.dim, self.shape, h, self.n_load, self.prec, stream.cuda_stream)
+        self.plan = feh_plan_create_batch(self.dim, self.shape, h, self.n_batch, self.n_per, self.prec,
+                                          stream.cuda_stream)
         nbytes = feh_plan_workspace_bytes(self.plan)
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
         feh_plan_set_workspace(self.plan, self.workspace.data_ptr(), self.workspace.numel())
@@ -300,16 +357,26 @@ class Homogenizer:
         out = dict(status=rc, stress_mean=smean, energy=W, report=rep, u=u, strain=strain, stress=stress)
         self._last_Ebar = Ebar
         nv = 3 if D == 2 else 6
-        if L == nv:
-            try:
-                out["C_eff"] = feh_effective_stiffness(D, Ebar, W)
-            except FehError:
-                pass
+        if self.n_per == nv:
+            G = self.n_per
+            Cs = []
+            for b in range(self.n_batch):
+                sl = slice(b * G, (b + 1) * G)
+                try:
+                    Cs.append(feh_effective_stiffness(D, Ebar[sl], W[sl, sl]))
+                except FehError:
+                    Cs.append(None)
+            if self.n_batch == 1:
+                if Cs[0] is not None:
+                    out["C_eff"] = Cs[0]
+            else:
+                out["C_eff_batch"] = Cs
         return out
 
     def energy_sensitivity(self, weight):
         """Per-voxel (dJ/dlambda, dJ/dmu) for J = sum weight_lm W_lm of the last solve."""
-        g_lam = self.torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        gshape = self.shape if self.n_batch == 1 else (self.n_batch,) + self.shape
+        g_lam = self.torch.empty(gshape, dtype=self.dtype, device=self.device)
         g_mu = self.torch.empty_like(g_lam)
         feh_energy_sensitivity(self.plan, np.asarray(weight, dtype=np.float64).reshape(self.n_load, self.n_load),
                                g_lam.data_ptr(), g_mu.data_ptr())
@@ -317,8 +384,17 @@ class Homogenizer:
 
     def c_eff_sensitivity(self, G):
         """Per-voxel (dJ/dlambda, dJ/dmu) for J = sum G_IJ C_eff_IJ of the last solve
-        (which must have used nv load cases)."""
-        return self.energy_sensitivity(feh_effective_stiffness_weights(self.dim, self._last_Ebar, G))
+        (nv load cases per microstructure); G one nv x nv matrix, or one per
+        microstructure for a batched plan."""
+        nv, Gp = self.n_per, self.n_per
+        Gs = np.asarray(G, dtype=np.float64)
+        if Gs.ndim == 2:
+            Gs = np.broadcast_to(Gs, (self.n_batch, nv, nv))
+        W = np.zeros((self.n_load, self.n_load))
+        for b in range(self.n_batch):
+            sl = slice(b * Gp, (b + 1) * Gp)
+            W[sl, sl] = feh_effective_stiffness_weights(self.dim, self._last_Ebar[sl], Gs[b])
+        return self.energy_sensitivity(W)
 
     def apply_operator(self, p):
         p = self._dev(p).reshape(self.n_load, self.N, self.dim)
@@ -364,3 +440,87 @@ class Homogenizer:
             self.close()
         except Exception:
             pass
+
+
+class UnevenBatch:
+    """Microstructures of uneven sizes solved together on one dedicated stream.
+
+    maps: list of (lam, mu) per-voxel arrays (any grid shapes, one dimension);
+    maps of the same shape share a batched plan (at most 64 load cases per
+    plan), and all plans form one ``feh_batch`` whose CG chunks run as
+    captured HIP graphs.  n_load load cases per map (default: the nv unit
+    Voigt loads)."""
+
+    def __init__(self, maps, n_load=None, precision="fp32", device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.dim = np.ndim(maps[0][0])
+        nv = 3 if self.dim == 2 else 6
+        self.n_load = int(n_load or nv)
+        self.stream = torch.cuda.Stream(device=self.device)  # default priority
+        cap = max(1, 64 // self.n_load)
+        groups = {}
+        for i, (lam, mu) in enumerate(maps):
+            groups.setdefault(tuple(np.shape(lam)), []).append(i)
+        self.plans = []   # (Homogenizer, [map indices])
+        self.where = {}   # map index -> (plan number, slot)
+        with torch.cuda.stream(self.stream):
+            for shape, idx in sorted(groups.items()):
+                for k in range(0, len(idx), cap):
+                    part = idx[k:k + cap]
+                    hz = Homogenizer(shape, n_load=self.n_load, precision=precision, device=self.device,
+                                     stream=self.stream, n_batch=len(part))
+                    lam = np.stack([np.asarray(maps[i][0], dtype=np.float64) for i in part])
+                    mu = np.stack([np.asarray(maps[i][1], dtype=np.float64) for i in part])
+                    hz.set_material(lam=lam, mu=mu)
+                    for s_, i in enumerate(part):
+                        self.where[i] = (len(self.plans), s_)
+                    self.plans.append((hz, part))
+        self.n_maps = len(maps)
+        self.batch = feh_batch_create([hz.plan for hz, _ in self.plans])
+
+    def solve(self, Ebar, tol=1e-5, max_iter=5000, use_graph=True):
+        """Ebar: [n_load][D][D] for every map.  Returns a list per map with
+        C_eff (when n_load = nv), stress_mean, energy block and reports."""
+        Ebar = np.asarray(Ebar, dtype=np.float64).reshape(self.n_load, self.dim, self.dim)
+        Ebs = [np.concatenate([Ebar] * hz.n_batch) for hz, _ in self.plans]
+        for (hz, _), e in zip(self.plans, Ebs):
+            hz._last_Ebar = e
+        rc, sm, W, rep = feh_batch_solve(self.batch, Ebs, tol, max_iter, use_graph)
+        self.stream.synchronize()
+        G = self.n_load
+        nv = 3 if self.dim == 2 else 6
+        out = [None] * self.n_maps
+        for p, (hz, part) in enumerate(self.plans):
+            for s_, i in enumerate(part):
+                sl = slice(s_ * G, (s_ + 1) * G)
+                r = dict(stress_mean=sm[p][sl], energy=W[p][sl, sl], report=rep[p][sl], status=rc)
+                if G == nv:
+                    r["C_eff"] = feh_effective_stiffness(self.dim, Ebar, W[p][sl, sl])
+                out[i] = r
+        return out
+
+    def graph_launches(self):
+        return feh_batch_graph_launches(self.batch)
+
+    def c_eff_sensitivity(self, G):
+        """Per map (dJ/dlambda, dJ/dmu) for J = sum G_IJ C_eff_IJ (one nv x nv G
+        for every map) after solve()."""
+        res = [None] * self.n_maps
+        for hz, part in self.plans:
+            gl, gm = hz.c_eff_sensitivity(G)
+            if hz.n_batch == 1:
+                gl, gm = gl[None], gm[None]
+            for s_, i in enumerate(part):
+                res[i] = (gl[s_], gm[s_])
+        return res
+
+    def close(self):
+        if self.batch is not None:
+            feh_batch_destroy(self.batch)
+            self.batch = None
+        for hz, _ in self.plans:
+            hz.close()
+        self.plans = []
+

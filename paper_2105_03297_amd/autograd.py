@@ -42,8 +42,8 @@ class EffectiveStiffness(torch.autograd.Function):
     @staticmethod
     def forward(ctx, E, nu, hz, tol, max_iter):
         nv = 3 if hz.dim == 2 else 6
-        if hz.n_load != nv:
-            raise ValueError("the homogenizer must batch the nv unit load cases")
+        if hz.n_per != nv or hz.n_batch != 1:
+            raise ValueError("the homogenizer must hold one microstructure and its nv unit load cases")
         hz.set_material(E=E.detach(), nu=float(nu))
         out = hz.solve(unit_loads(hz.dim), tol=tol, max_iter=max_iter)
         ctx.hz = hz

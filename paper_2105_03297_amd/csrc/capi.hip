@@ -14,6 +14,7 @@
 //             z^ = M^-1 r^ and rho_new = r.z by Parseval
 //   scalars:  stop test sqrt(rho_new / f.M^+f) <= tol, beta = rho_new / rho
 //   FFT:      inverse passes; the last one applies u += alpha p, p = z + beta p
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -85,8 +86,8 @@ static void layout(feh_plan &p) {
     p.off_p = take(vec);
     p.off_q = take(vec);
     p.off_spec = take((size_t)p.L * p.dim * p.Nspec * 2 * p.rsize);
-    p.off_lam = take(p.N * p.rsize);
-    p.off_mu = take(p.N * p.rsize);
+    p.off_lam = take(p.nbatch * p.N * p.rsize);
+    p.off_mu = take(p.nbatch * p.N * p.rsize);
     for (int a = 0; a < 3; ++a) {
         const size_t na = (size_t)p.n[a];
         p.off_tw[a] = take(na * 2 * p.rsize);
@@ -104,7 +105,10 @@ static void layout(feh_plan &p) {
     p.off_part = take(parts * sizeof(double));
     p.off_state = take((size_t)p.L * sizeof(LcState));
     p.off_flag = take(256);
-    p.off_pairs = take((size_t)kMaxLoad * (kMaxLoad + 1) / 2 * (2 * sizeof(int) + sizeof(double)));
+    // sensitivity pair list: l, m (int), group offsets (2 kMaxLoad ints, keeps the
+    // weights 8-byte aligned), weights (double)
+    p.off_pairs = take((size_t)kMaxLoad * (kMaxLoad + 1) / 2 * (2 * sizeof(int) + sizeof(double)) +
+                       2 * kMaxLoad * sizeof(int));
     p.total = o;
 }
 
@@ -320,18 +324,21 @@ const char *feh_last_error(void) { return g_err.c_str(); }
 
 int feh_version(void) { return 10000; }
 
-int feh_plan_create(feh_plan **plan, int dim, const int64_t n[], const double h[], int n_load, int precision,
-                    void *hip_stream) {
+static int plan_create(feh_plan **plan, int dim, const int64_t n[], const double h[], int n_batch, int n_load,
+                       int precision, void *hip_stream) {
     try {
         if (!plan) return set_error(FEH_EINVAL, "null plan pointer");
         *plan = nullptr;
         if (dim != 2 && dim != 3) return set_error(FEH_EINVAL, "dim must be 2 or 3");
         if (!n) return set_error(FEH_EINVAL, "null size array");
-        if (n_load < 1 || n_load > kMaxLoad) return set_error(FEH_EINVAL, "n_load must be in [1, 64]");
+        if (n_batch < 1 || n_load < 1 || (long long)n_batch * n_load > kMaxLoad)
+            return set_error(FEH_EINVAL, "n_batch * n_load must be in [1, 64]");
         if (precision != FEH_FP64 && precision != FEH_FP32) return set_error(FEH_EINVAL, "bad precision");
         auto p = new feh_plan();
         p->dim = dim;
-        p->L = n_load;
+        p->nbatch = n_batch;
+        p->G = n_load;
+        p->L = n_batch * n_load;
         p->prec = precision;
         p->rsize = precision == FEH_FP64 ? 8 : 4;
         p->stream = static_cast<hipStream_t>(hip_stream);
@@ -382,6 +389,16 @@ int feh_plan_create(feh_plan **plan, int dim, const int64_t n[], const double h[
     } catch (...) {
         return set_error(FEH_EINVAL, "unexpected host exception");
     }
+}
+
+int feh_plan_create(feh_plan **plan, int dim, const int64_t n[], const double h[], int n_load, int precision,
+                    void *hip_stream) {
+    return plan_create(plan, dim, n, h, 1, n_load, precision, hip_stream);
+}
+
+int feh_plan_create_batch(feh_plan **plan, int dim, const int64_t n[], const double h[], int n_batch, int n_load,
+                          int precision, void *hip_stream) {
+    return plan_create(plan, dim, n, h, n_batch, n_load, precision, hip_stream);
 }
 
 int feh_plan_destroy(feh_plan *plan) {
@@ -461,125 +478,294 @@ int feh_set_material_field(feh_plan *plan, const void *E_dev, double nu) {
     return FEH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// solve stages: set-up (right-hand side, first search direction), CG loop,
+// finalisation (pending u update, post-processing, host outputs)
+// ---------------------------------------------------------------------------
+static int solve_begin(feh_plan &p, const double *Ebar_host, double tol, int max_iter, const void *u0_dev) {
+    if (!Ebar_host) return set_error(FEH_EINVAL, "null Ebar");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return set_error(FEH_EINVAL, "tol must be finite and >= 0");
+    p.solved = false;
+    if (max_iter < 1) return set_error(FEH_EINVAL, "max_iter must be >= 1");
+    const int D = p.dim;
+    for (int l = 0; l < p.L; ++l)
+        for (int i = 0; i < D; ++i)
+            for (int j = 0; j < D; ++j) {
+                const double a = Ebar_host[(l * D + i) * D + j], b = Ebar_host[(l * D + j) * D + i];
+                if (!std::isfinite(a)) return set_error(FEH_EINVAL, "Ebar must be finite");
+                if (std::fabs(a - b) > 1e-12 * (std::fabs(a) + std::fabs(b)) + 1e-300)
+                    return set_error(FEH_EINVAL, "Ebar must be symmetric");
+            }
+    // the kernels read D x D per load case
+    std::vector<double> eb(Ebar_host, Ebar_host + (size_t)p.L * D * D);
+    double *ebar_dev = p.ptr<double>(p.off_ebar);
+    CK(hip_check(hipMemcpyAsync(ebar_dev, eb.data(), eb.size() * sizeof(double), hipMemcpyHostToDevice, p.stream),
+                 "upload Ebar"));
+    // the host vector must outlive the asynchronous copy
+    CK(hip_check(hipStreamSynchronize(p.stream), "upload Ebar"));
+    LcState *st = p.ptr<LcState>(p.off_state);
+    double *part = p.ptr<double>(p.off_part);
+    const size_t nvec = (size_t)p.L * D * p.N;
+    CK(launch_init_state(p, st, p.L));
+    StencilArgs sa;
+    sa.Ebar = ebar_dev;
+    if (u0_dev) {
+        CK(launch_aos_to_soa(p, u0_dev, p.ws + p.off_u));
+        // the fluctuation is fixed up to a rigid translation: start from zero mean
+        CK(launch_remove_mean(p, p.ws + p.off_u, part, p.ptr<double>(p.off_sums)));
+        // reference f.M^+f from the right-hand side alone
+        sa.in0 = nullptr;
+        sa.out0 = p.ws + p.off_q;
+        CK(launch_stencil(p, ST_RESID, sa));
+        CK(precondition(p, p.ws + p.off_q, p.ws + p.off_q, part, nullptr));
+        CK(launch_finish_rho(p, st, part, first_num_parts(p), 0, tol, max_iter));
+        sa.in0 = p.ws + p.off_u;
+    } else {
+        CK(launch_fill(p, p.ws + p.off_u, nvec, 0.0));
+        sa.in0 = nullptr;
+    }
+    // r = f - K u0, first search direction p = M^+ r
+    sa.out0 = p.ws + p.off_r;
+    CK(launch_stencil(p, ST_RESID, sa));
+    CK(precondition(p, p.ws + p.off_r, p.ws + p.off_p, part, nullptr));
+    return launch_finish_rho(p, st, part, first_num_parts(p), u0_dev ? 1 : 11, tol, max_iter);
+}
+
+static int solve_end(feh_plan &p, void *u_dev, void *strain_dev, void *stress_dev, double *stress_mean_host,
+                     double *energy_host, feh_report *report_host) {
+    const int D = p.dim;
+    LcState *st = p.ptr<LcState>(p.off_state);
+    double *part = p.ptr<double>(p.off_part);
+    CK(launch_finalize_u(p, p.ws + p.off_u, p.ws + p.off_p, st));
+    double *sums = p.ptr<double>(p.off_sums);
+    CK(launch_post_sums(p, p.ws + p.off_u, p.ptr<double>(p.off_ebar), strain_dev, stress_dev, part, sums));
+    if (u_dev) CK(launch_soa_to_aos(p, p.ws + p.off_u, u_dev));
+    const int ns = D == 3 ? 6 : 3;
+    std::vector<double> hsum(post_num_slots(p));
+    std::vector<LcState> hs(p.L);
+    CK(hip_check(hipMemcpyAsync(hsum.data(), sums, hsum.size() * sizeof(double), hipMemcpyDeviceToHost, p.stream),
+                 "read sums"));
+    CK(hip_check(hipMemcpyAsync(hs.data(), st, p.L * sizeof(LcState), hipMemcpyDeviceToHost, p.stream),
+                 "read CG state"));
+    CK(hip_check(hipStreamSynchronize(p.stream), "solve"));
+    if (stress_mean_host) {
+        for (int l = 0; l < p.L; ++l) {
+            const double *s = hsum.data() + l * ns;
+            double *o = stress_mean_host + (size_t)l * D * D;
+            if (D == 3) {
+                const double full[9] = {s[0], s[5], s[4], s[5], s[1], s[3], s[4], s[3], s[2]};
+                std::memcpy(o, full, sizeof(full));
+            } else {
+                const double full[4] = {s[0], s[2], s[2], s[1]};
+                std::memcpy(o, full, sizeof(full));
+            }
+        }
+    }
+    if (energy_host) {
+        // pairs within each microstructure; load cases of different
+        // microstructures do not interact (zero)
+        std::fill(energy_host, energy_host + (size_t)p.L * p.L, 0.0);
+        int k = 0;
+        for (int b = 0; b < p.nbatch; ++b)
+            for (int li = 0; li < p.G; ++li)
+                for (int mi = li; mi < p.G; ++mi, ++k) {
+                    const int l = b * p.G + li, m = b * p.G + mi;
+                    const double w = hsum[(size_t)p.L * ns + k];
+                    energy_host[l * p.L + m] = w;
+                    energy_host[m * p.L + l] = w;
+                }
+    }
+    int rc = FEH_OK;
+    for (int l = 0; l < p.L; ++l) {
+        if (report_host) {
+            report_host[l].iterations = hs[l].iters;
+            report_host[l].status = hs[l].status;
+            report_host[l].rel_residual = hs[l].relres;
+        }
+        if (hs[l].status == FEH_EBREAKDOWN) rc = FEH_EBREAKDOWN;
+        else if ((hs[l].status == FEH_ENOCONV || hs[l].active) && rc == FEH_OK) rc = FEH_ENOCONV;
+    }
+    p.solved = rc != FEH_EBREAKDOWN;
+    if (rc == FEH_ENOCONV) return set_error(rc, "max_iter reached before the tolerance");
+    if (rc == FEH_EBREAKDOWN) return set_error(rc, "CG breakdown (p.q <= 0 or not finite)");
+    return FEH_OK;
+}
+
+// Copy the CG states of the plans to the host (one synchronisation); true if
+// any load case is still iterating.
+static int any_active(feh_plan *const *plans, int n, std::vector<std::vector<LcState>> &hs, bool &any) {
+    for (int i = 0; i < n; ++i) {
+        feh_plan &p = *plans[i];
+        hs[i].resize(p.L);
+        CK(hip_check(hipMemcpyAsync(hs[i].data(), p.ptr<LcState>(p.off_state), p.L * sizeof(LcState),
+                                    hipMemcpyDeviceToHost, p.stream),
+                     "read CG state"));
+    }
+    for (int i = 0; i < n; ++i) CK(hip_check(hipStreamSynchronize(plans[i]->stream), "CG"));
+    any = false;
+    for (int i = 0; i < n; ++i)
+        for (const LcState &s : hs[i]) any = any || s.active;
+    return FEH_OK;
+}
+
 int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter, const void *u0_dev, void *u_dev,
               void *strain_dev, void *stress_dev, double *stress_mean_host, double *energy_host,
               feh_report *report_host) {
     try {
         CK(check_plan(plan, true));
         feh_plan &p = *plan;
-        if (!Ebar_host) return set_error(FEH_EINVAL, "null Ebar");
-        if (!(tol >= 0.0) || !std::isfinite(tol)) return set_error(FEH_EINVAL, "tol must be finite and >= 0");
-        p.solved = false;
-        if (max_iter < 1) return set_error(FEH_EINVAL, "max_iter must be >= 1");
-        const int D = p.dim;
-        for (int l = 0; l < p.L; ++l)
-            for (int i = 0; i < D; ++i)
-                for (int j = 0; j < D; ++j) {
-                    const double a = Ebar_host[(l * D + i) * D + j], b = Ebar_host[(l * D + j) * D + i];
-                    if (!std::isfinite(a)) return set_error(FEH_EINVAL, "Ebar must be finite");
-                    if (std::fabs(a - b) > 1e-12 * (std::fabs(a) + std::fabs(b)) + 1e-300)
-                        return set_error(FEH_EINVAL, "Ebar must be symmetric");
-                }
-        // Ebar padded to 3x3 stride per load case is not needed: the kernels read D x D
-        std::vector<double> eb(Ebar_host, Ebar_host + (size_t)p.L * D * D);
-        double *ebar_dev = p.ptr<double>(p.off_ebar);
-        CK(hip_check(hipMemcpyAsync(ebar_dev, eb.data(), eb.size() * sizeof(double), hipMemcpyHostToDevice, p.stream),
-                     "upload Ebar"));
+        CK(solve_begin(p, Ebar_host, tol, max_iter, u0_dev));
         LcState *st = p.ptr<LcState>(p.off_state);
-        double *part = p.ptr<double>(p.off_part);
-        const size_t nvec = (size_t)p.L * D * p.N;
-        CK(launch_init_state(p, st, p.L));
-        StencilArgs sa;
-        sa.Ebar = ebar_dev;
-        if (u0_dev) {
-            CK(launch_aos_to_soa(p, u0_dev, p.ws + p.off_u));
-            // the fluctuation is fixed up to a rigid translation: start from zero mean
-            CK(launch_remove_mean(p, p.ws + p.off_u, part, p.ptr<double>(p.off_sums)));
-            // reference f.M^+f from the right-hand side alone
-            sa.in0 = nullptr;
-            sa.out0 = p.ws + p.off_q;
-            CK(launch_stencil(p, ST_RESID, sa));
-            CK(precondition(p, p.ws + p.off_q, p.ws + p.off_q, part, nullptr));
-            CK(launch_finish_rho(p, st, part, first_num_parts(p), 0, tol, max_iter));
-            sa.in0 = p.ws + p.off_u;
-        } else {
-            CK(launch_fill(p, p.ws + p.off_u, nvec, 0.0));
-            sa.in0 = nullptr;
-        }
-        // r = f - K u0, first search direction p = M^+ r
-        sa.out0 = p.ws + p.off_r;
-        CK(launch_stencil(p, ST_RESID, sa));
-        CK(precondition(p, p.ws + p.off_r, p.ws + p.off_p, part, nullptr));
-        CK(launch_finish_rho(p, st, part, first_num_parts(p), u0_dev ? 1 : 11, tol, max_iter));
-
-        std::vector<LcState> hs(p.L);
+        std::vector<std::vector<LcState>> hs(1);
         int done = 0, chunk = 4;
         while (done < max_iter) {
-            CK(hip_check(hipMemcpyAsync(hs.data(), st, p.L * sizeof(LcState), hipMemcpyDeviceToHost, p.stream),
-                         "read CG state"));
-            CK(hip_check(hipStreamSynchronize(p.stream), "CG"));
-            prof_drain(p);
             bool any = false;
-            for (int l = 0; l < p.L; ++l) any = any || hs[l].active;
+            CK(any_active(&plan, 1, hs, any));
+            prof_drain(p);
             if (!any) break;
             const int c = chunk < max_iter - done ? chunk : max_iter - done;
             for (int i = 0; i < c; ++i) CK(cg_iteration(p, st, tol, max_iter));
             done += c;
             if (chunk < 16) chunk *= 2;
         }
-        CK(launch_finalize_u(p, p.ws + p.off_u, p.ws + p.off_p, st));
-        double *sums = p.ptr<double>(p.off_sums);
-        CK(launch_post_sums(p, p.ws + p.off_u, ebar_dev, strain_dev, stress_dev, part, sums));
-        if (u_dev) CK(launch_soa_to_aos(p, p.ws + p.off_u, u_dev));
-        const int ns = D == 3 ? 6 : 3;
-        std::vector<double> hsum(post_num_slots(p));
-        CK(hip_check(hipMemcpyAsync(hsum.data(), sums, hsum.size() * sizeof(double), hipMemcpyDeviceToHost, p.stream),
-                     "read sums"));
-        CK(hip_check(hipMemcpyAsync(hs.data(), st, p.L * sizeof(LcState), hipMemcpyDeviceToHost, p.stream),
-                     "read CG state"));
-        CK(hip_check(hipStreamSynchronize(p.stream), "solve"));
-        if (stress_mean_host) {
-            for (int l = 0; l < p.L; ++l) {
-                const double *s = hsum.data() + l * ns;
-                double *o = stress_mean_host + (size_t)l * D * D;
-                if (D == 3) {
-                    const double full[9] = {s[0], s[5], s[4], s[5], s[1], s[3], s[4], s[3], s[2]};
-                    std::memcpy(o, full, sizeof(full));
-                } else {
-                    const double full[4] = {s[0], s[2], s[2], s[1]};
-                    std::memcpy(o, full, sizeof(full));
-                }
-            }
-        }
-        if (energy_host) {
-            int k = 0;
-            for (int l = 0; l < p.L; ++l)
-                for (int m = l; m < p.L; ++m, ++k) {
-                    const double w = hsum[(size_t)p.L * ns + k];
-                    energy_host[l * p.L + m] = w;
-                    energy_host[m * p.L + l] = w;
-                }
-        }
-        int rc = FEH_OK;
-        for (int l = 0; l < p.L; ++l) {
-            if (report_host) {
-                report_host[l].iterations = hs[l].iters;
-                report_host[l].status = hs[l].status;
-                report_host[l].rel_residual = hs[l].relres;
-            }
-            if (hs[l].status == FEH_EBREAKDOWN) rc = FEH_EBREAKDOWN;
-            else if ((hs[l].status == FEH_ENOCONV || hs[l].active) && rc == FEH_OK) rc = FEH_ENOCONV;
-        }
-        p.solved = rc != FEH_EBREAKDOWN;
-        if (rc == FEH_ENOCONV) return set_error(rc, "max_iter reached before the tolerance");
-        if (rc == FEH_EBREAKDOWN) return set_error(rc, "CG breakdown (p.q <= 0 or not finite)");
-        return FEH_OK;
+        return solve_end(p, u_dev, strain_dev, stress_dev, stress_mean_host, energy_host, report_host);
     } catch (const std::bad_alloc &) {
         return set_error(FEH_ENOMEM, "host allocation failed");
     } catch (...) {
         return set_error(FEH_EINVAL, "unexpected host exception");
     }
 }
+
+// ---------------------------------------------------------------------------
+// batches of plans: one HIP graph per chunk of CG iterations of every plan
+// ---------------------------------------------------------------------------
+
+struct feh_batch {
+    std::vector<feh_plan *> plans;
+    hipStream_t stream = nullptr;
+    // instantiated graphs, keyed by (chunk length, tol, max_iter): the CG
+    // kernels read their state from device memory, so a graph replays for as
+    // long as the plans, their workspaces and the stopping rule are unchanged
+    struct Entry {
+        int chunk;
+        double tol;
+        int max_iter;
+        hipGraphExec_t exec;
+    };
+    std::vector<Entry> graphs;
+    int launches = 0;  // graph launches of the last solve (for tests)
+};
+
+static void batch_clear(feh_batch &b) {
+    for (auto &e : b.graphs) hipGraphExecDestroy(e.exec);
+    b.graphs.clear();
+}
+
+static int batch_graph(feh_batch &b, int chunk, double tol, int max_iter, hipGraphExec_t &exec) {
+    for (auto &e : b.graphs)
+        if (e.chunk == chunk && e.tol == tol && e.max_iter == max_iter) {
+            exec = e.exec;
+            return FEH_OK;
+        }
+    CK(hip_check(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal), "begin capture"));
+    int rc = FEH_OK;
+    for (int i = 0; i < chunk && rc == FEH_OK; ++i)
+        for (feh_plan *p : b.plans) {
+            rc = cg_iteration(*p, p->ptr<LcState>(p->off_state), tol, max_iter);
+            if (rc != FEH_OK) break;
+        }
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b.stream, &g);
+    if (rc != FEH_OK) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    CK(hip_check(ec, "end capture"));
+    const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    CK(hip_check(ei, "instantiate graph"));
+    b.graphs.push_back({chunk, tol, max_iter, exec});
+    return FEH_OK;
+}
+
+int feh_batch_create(feh_batch **out, feh_plan *const *plans, int n_plans) {
+    try {
+        if (!out) return set_error(FEH_EINVAL, "null batch pointer");
+        *out = nullptr;
+        if (!plans || n_plans < 1) return set_error(FEH_EINVAL, "need at least one plan");
+        for (int i = 0; i < n_plans; ++i) {
+            if (!plans[i]) return set_error(FEH_EINVAL, "null plan");
+            if (plans[i]->stream != plans[0]->stream) return set_error(FEH_EINVAL, "plans must share one stream");
+            for (int j = 0; j < i; ++j)
+                if (plans[j] == plans[i]) return set_error(FEH_EINVAL, "a plan appears twice");
+        }
+        if (plans[0]->stream == nullptr) return set_error(FEH_EINVAL, "a batch needs a created (non-null) stream");
+        auto b = new feh_batch();
+        b->plans.assign(plans, plans + n_plans);
+        b->stream = plans[0]->stream;
+        *out = b;
+        return FEH_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error(FEH_ENOMEM, "host allocation failed");
+    }
+}
+
+int feh_batch_destroy(feh_batch *b) {
+    if (!b) return FEH_OK;
+    batch_clear(*b);
+    delete b;
+    return FEH_OK;
+}
+
+int feh_batch_solve(feh_batch *b, const double *const *Ebar_host, double tol, int max_iter, int use_graph,
+                    double *const *stress_mean_host, double *const *energy_host, feh_report *const *report_host) {
+    try {
+        if (!b) return set_error(FEH_EINVAL, "null batch");
+        if (!Ebar_host) return set_error(FEH_EINVAL, "null Ebar table");
+        const int n = (int)b->plans.size();
+        for (int i = 0; i < n; ++i) {
+            CK(check_plan(b->plans[i], true));
+            if (b->plans[i]->prof_on) return set_error(FEH_EINVAL, "profiling is not available in a batch");
+        }
+        for (int i = 0; i < n; ++i) CK(solve_begin(*b->plans[i], Ebar_host[i], tol, max_iter, nullptr));
+        std::vector<std::vector<LcState>> hs(n);
+        int done = 0, chunk = 4;
+        b->launches = 0;
+        while (done < max_iter) {
+            bool any = false;
+            CK(any_active(b->plans.data(), n, hs, any));
+            if (!any) break;
+            const int c = chunk < max_iter - done ? chunk : max_iter - done;
+            if (use_graph) {
+                hipGraphExec_t exec = nullptr;
+                CK(batch_graph(*b, c, tol, max_iter, exec));
+                CK(hip_check(hipGraphLaunch(exec, b->stream), "graph launch"));
+            } else {
+                for (int it = 0; it < c; ++it)
+                    for (feh_plan *p : b->plans) CK(cg_iteration(*p, p->ptr<LcState>(p->off_state), tol, max_iter));
+            }
+            ++b->launches;
+            done += c;
+            if (chunk < 16) chunk *= 2;
+        }
+        int rc = FEH_OK;
+        for (int i = 0; i < n; ++i) {
+            const int r = solve_end(*b->plans[i], nullptr, nullptr, nullptr, stress_mean_host ? stress_mean_host[i] : nullptr,
+                                    energy_host ? energy_host[i] : nullptr, report_host ? report_host[i] : nullptr);
+            if (r == FEH_EBREAKDOWN || (r != FEH_OK && rc == FEH_OK)) rc = r;
+        }
+        if (rc == FEH_ENOCONV) return set_error(rc, "max_iter reached before the tolerance (some plan)");
+        if (rc == FEH_EBREAKDOWN) return set_error(rc, "CG breakdown (some plan)");
+        return rc;
+    } catch (const std::bad_alloc &) {
+        return set_error(FEH_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return set_error(FEH_EINVAL, "unexpected host exception");
+    }
+}
+
+int feh_batch_graph_launches(const feh_batch *b) { return b ? b->launches : -1; }
+
 
 // Inverse of the engineering Voigt strain matrix E[v][l] of nv load cases.
 static int voigt_load_inverse(int dim, const double *Ebar_host, std::vector<double> &E) {
@@ -673,29 +859,38 @@ int feh_energy_sensitivity(feh_plan *plan, const double *weight_host, void *grad
         feh_plan &p = *plan;
         if (!weight_host || !grad_lam_dev || !grad_mu_dev) return set_error(FEH_EINVAL, "null argument");
         if (!p.solved) return set_error(FEH_EINVAL, "no solution in the plan (call feh_solve first)");
-        std::vector<int> pl, pm;
-        std::vector<double> pw;
+        for (int i = 0; i < p.L * p.L; ++i)
+            if (!std::isfinite(weight_host[i])) return set_error(FEH_EINVAL, "weights must be finite");
         for (int l = 0; l < p.L; ++l)
-            for (int m = l; m < p.L; ++m) {
-                const double a = weight_host[l * p.L + m], b = weight_host[m * p.L + l];
-                if (!std::isfinite(a) || !std::isfinite(b)) return set_error(FEH_EINVAL, "weights must be finite");
-                const double w = (l == m) ? a : a + b;
-                if (w == 0.0) continue;
-                pl.push_back(l);
-                pm.push_back(m);
-                pw.push_back(w);
-            }
+            for (int m = 0; m < p.L; ++m)
+                if (l / p.G != m / p.G && weight_host[l * p.L + m] != 0.0)
+                    return set_error(FEH_EINVAL, "weights across microstructures must be zero");
+        std::vector<int> pl, pm, gofs(1, 0);
+        std::vector<double> pw;
+        for (int b = 0; b < p.nbatch; ++b) {
+            for (int l = b * p.G; l < (b + 1) * p.G; ++l)
+                for (int m = l; m < (b + 1) * p.G; ++m) {
+                    const double w = (l == m) ? weight_host[l * p.L + l] : weight_host[l * p.L + m] + weight_host[m * p.L + l];
+                    if (w == 0.0) continue;
+                    pl.push_back(l);
+                    pm.push_back(m);
+                    pw.push_back(w);
+                }
+            gofs.push_back((int)pl.size());
+        }
         const int np = (int)pl.size();
         const size_t ni = (size_t)kMaxLoad * (kMaxLoad + 1) / 2;
         int *dpl = p.ptr<int>(p.off_pairs);
         int *dpm = dpl + ni;
-        double *dpw = reinterpret_cast<double *>(dpm + ni);
+        int *dgo = dpm + ni;  // kMaxLoad + 1 entries
+        double *dpw = reinterpret_cast<double *>(dgo + 2 * kMaxLoad);
         if (np > 0) {
             CK(hip_check(hipMemcpyAsync(dpl, pl.data(), np * sizeof(int), hipMemcpyHostToDevice, p.stream), "pairs"));
             CK(hip_check(hipMemcpyAsync(dpm, pm.data(), np * sizeof(int), hipMemcpyHostToDevice, p.stream), "pairs"));
             CK(hip_check(hipMemcpyAsync(dpw, pw.data(), np * sizeof(double), hipMemcpyHostToDevice, p.stream), "pairs"));
         }
-        CK(launch_sensitivity(p, p.ws + p.off_u, p.ptr<double>(p.off_ebar), dpl, dpm, dpw, np, grad_lam_dev,
+        CK(hip_check(hipMemcpyAsync(dgo, gofs.data(), gofs.size() * sizeof(int), hipMemcpyHostToDevice, p.stream), "pairs"));
+        CK(launch_sensitivity(p, p.ws + p.off_u, p.ptr<double>(p.off_ebar), dpl, dpm, dpw, dgo, grad_lam_dev,
                               grad_mu_dev));
         return hip_check(hipStreamSynchronize(p.stream), "sensitivity");
     } catch (const std::bad_alloc &) {

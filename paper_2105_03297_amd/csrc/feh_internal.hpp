@@ -107,7 +107,9 @@ struct feh_plan {
     int dim = 0;
     int64_t n[3] = {1, 1, 1};
     double h[3] = {1, 1, 1};
-    int L = 1;
+    int L = 1;            // load cases in the plan: nbatch groups of G
+    int nbatch = 1;       // microstructures of this shape (one material each)
+    int G = 1;            // load cases per microstructure; load case l uses material l / G
     int prec = FEH_FP64;
     hipStream_t stream = nullptr;
 
@@ -227,9 +229,10 @@ int launch_remove_mean(const feh_plan &p, void *x, double *partial, double *mean
 int launch_post_sums(const feh_plan &p, const void *u, const double *Ebar_dev, void *strain, void *stress,
                      double *partial, double *sums);
 int launch_grad(const feh_plan &p, const void *u, void *e);   // e = sym(B u) element field
-// g_lam, g_mu = sum over pairs (l <= m, weight w) of the voxel's share of dW_lm/dlambda, dW_lm/dmu
+// g_lam, g_mu [nbatch][N] = sum over the pairs of each microstructure (l <= m,
+// weight w; pairs gofs[b] .. gofs[b+1] - 1) of the voxel's share of dW_lm/dlambda, dW_lm/dmu
 int launch_sensitivity(const feh_plan &p, const void *u, const double *Ebar_dev, const int *pl, const int *pm,
-                       const double *pw, int npair, void *g_lam, void *g_mu);
+                       const double *pw, const int *gofs, void *g_lam, void *g_mu);
 int post_num_slots(const feh_plan &p);
 
 // partial-sum sizes

@@ -318,39 +318,39 @@ int launch_finalize_u(const feh_plan &p, void *u, const void *pv, const LcState 
 }
 
 int launch_material_lame(const feh_plan &p, const void *lam, const void *mu, int *flag) {
-    const int g = grid_for(p.N);
+    const int g = grid_for(p.N * p.nbatch);
     if (p.prec == FEH_FP64)
         hipLaunchKernelGGL(k_mat_lame<double>, dim3(g), dim3(kThreads), 0, p.stream, (const double *)lam,
-                           (const double *)mu, p.ptr<double>(p.off_lam), p.ptr<double>(p.off_mu), (long long)p.N,
+                           (const double *)mu, p.ptr<double>(p.off_lam), p.ptr<double>(p.off_mu), (long long)p.N * p.nbatch,
                            p.dim, flag);
     else
         hipLaunchKernelGGL(k_mat_lame<float>, dim3(g), dim3(kThreads), 0, p.stream, (const float *)lam,
-                           (const float *)mu, p.ptr<float>(p.off_lam), p.ptr<float>(p.off_mu), (long long)p.N, p.dim,
+                           (const float *)mu, p.ptr<float>(p.off_lam), p.ptr<float>(p.off_mu), (long long)p.N * p.nbatch, p.dim,
                            flag);
     return hip_check(hipGetLastError(), "material lame");
 }
 
 int launch_material_phases(const feh_plan &p, const int32_t *phase, const double *tab, int n_phase, int *flag) {
-    const int g = grid_for(p.N);
+    const int g = grid_for(p.N * p.nbatch);
     if (p.prec == FEH_FP64)
         hipLaunchKernelGGL(k_mat_phases_d, dim3(g), dim3(kThreads), 0, p.stream, phase, tab, n_phase,
-                           p.ptr<double>(p.off_lam), p.ptr<double>(p.off_mu), (long long)p.N, flag);
+                           p.ptr<double>(p.off_lam), p.ptr<double>(p.off_mu), (long long)p.N * p.nbatch, flag);
     else
         hipLaunchKernelGGL(k_mat_phases_f, dim3(g), dim3(kThreads), 0, p.stream, phase, tab, n_phase,
-                           p.ptr<float>(p.off_lam), p.ptr<float>(p.off_mu), (long long)p.N, flag);
+                           p.ptr<float>(p.off_lam), p.ptr<float>(p.off_mu), (long long)p.N * p.nbatch, flag);
     return hip_check(hipGetLastError(), "material phases");
 }
 
 int launch_material_field(const feh_plan &p, const void *E, double nu, int *flag) {
     const double cl = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
     const double cm = 1.0 / (2.0 * (1.0 + nu));
-    const int g = grid_for(p.N);
+    const int g = grid_for(p.N * p.nbatch);
     if (p.prec == FEH_FP64)
         hipLaunchKernelGGL(k_mat_field<double>, dim3(g), dim3(kThreads), 0, p.stream, (const double *)E,
-                           p.ptr<double>(p.off_lam), p.ptr<double>(p.off_mu), (long long)p.N, cl, cm, flag);
+                           p.ptr<double>(p.off_lam), p.ptr<double>(p.off_mu), (long long)p.N * p.nbatch, cl, cm, flag);
     else
         hipLaunchKernelGGL(k_mat_field<float>, dim3(g), dim3(kThreads), 0, p.stream, (const float *)E,
-                           p.ptr<float>(p.off_lam), p.ptr<float>(p.off_mu), (long long)p.N, cl, cm, flag);
+                           p.ptr<float>(p.off_lam), p.ptr<float>(p.off_mu), (long long)p.N * p.nbatch, cl, cm, flag);
     return hip_check(hipGetLastError(), "material field");
 }
 

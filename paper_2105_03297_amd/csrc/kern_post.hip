@@ -72,6 +72,7 @@ struct PK {
     int n0, n1, n2;     // 2D: n1 = 1, n2 = n[1]
     long long N;
     int L, nblk, nsym;
+    int G, nbatch;      // load cases per microstructure, microstructures
     T ih[3];
     int grad_only;      // projection test: write sym(grad u) only (no Ebar, no sums)
 };
@@ -179,17 +180,22 @@ __global__ __launch_bounds__(kThreads) void k_post(PK<T> a) {
     for (int k = 0; k < NS; ++k) acc[k] = 0.0;
     int l = qslot, m = -1;
     if (qslot >= a.L) {
-        // pair index -> (l, m), l <= m
+        // pair index -> microstructure b and (l, m), l <= m, both in its group
         int rem = qslot - a.L;
-        l = 0;
-        while (rem >= a.L - l) {
-            rem -= a.L - l;
-            ++l;
+        const int npg = a.G * (a.G + 1) / 2;
+        const int b = rem / npg;
+        rem -= b * npg;
+        int li = 0;
+        while (rem >= a.G - li) {
+            rem -= a.G - li;
+            ++li;
         }
+        l = b * a.G + li;
         m = l + rem;
     }
+    const long long mo = (long long)(l / a.G) * a.N;
     for (long long v = blk * (long long)kThreads + threadIdx.x; v < a.N; v += (long long)a.nblk * kThreads) {
-        const double lam = double(a.lam[v]), mu = double(a.mu[v]);
+        const double lam = double(a.lam[mo + v]), mu = double(a.mu[mo + v]);
         double e[NE][NS];
         voxel_strains<T, DIM>(a, l, v, true, e);
         if (m < 0) {
@@ -242,16 +248,18 @@ __global__ __launch_bounds__(kThreads) void k_grad(PK<T> a) {
 // the explicit dependence on C counts:
 //   g_lam[v] = sum_pairs w <tr e_l tr e_m>_v,  g_mu[v] = sum_pairs w <2 e_l : e_m>_v,
 // <.>_v the element terms of voxel v with the weights of the cell average
-// (scale = 1 / (N n_e)).  The pair list holds l <= m; an off-diagonal pair's
-// weight already carries w_lm + w_ml.
+// (scale = 1 / (N n_e)).  The pair list holds l <= m within one
+// microstructure, grouped by microstructure (pairs gofs[b] .. gofs[b+1] - 1
+// write field b); an off-diagonal pair's weight already carries w_lm + w_ml.
 template <typename T, int DIM>
-__global__ __launch_bounds__(kThreads) void k_sens(PK<T> a, const int *pl, const int *pm, const double *pw, int npair,
-                                                   double scale, T *g_lam, T *g_mu) {
+__global__ __launch_bounds__(kThreads) void k_sens(PK<T> a, const int *pl, const int *pm, const double *pw,
+                                                   const int *gofs, double scale, T *g_lam, T *g_mu) {
     constexpr int NE = DIM == 3 ? 6 : 2;
     constexpr int NS = DIM == 3 ? 6 : 3;
     for (long long v = blockIdx.x * (long long)kThreads + threadIdx.x; v < a.N; v += (long long)gridDim.x * kThreads) {
+      for (int bb = 0; bb < a.nbatch; ++bb) {
         double gl = 0.0, gm = 0.0;
-        for (int q = 0; q < npair; ++q) {
+        for (int q = gofs[bb]; q < gofs[bb + 1]; ++q) {
             const int l = pl[q], m = pm[q];
             const double w = pw[q];
             double e[NE][NS], f[NE][NS];
@@ -284,8 +292,9 @@ __global__ __launch_bounds__(kThreads) void k_sens(PK<T> a, const int *pl, const
             gl += w * sl;
             gm += w * sm;
         }
-        g_lam[v] = T(gl * scale);
-        g_mu[v] = T(gm * scale);
+        g_lam[(long long)bb * a.N + v] = T(gl * scale);
+        g_mu[(long long)bb * a.N + v] = T(gm * scale);
+      }
     }
 }
 
@@ -314,6 +323,8 @@ PK<T> post_args(const feh_plan &p) {
     }
     a.N = p.N;
     a.L = p.L;
+    a.G = p.G;
+    a.nbatch = p.nbatch;
     for (int i = 0; i < 3; ++i) a.ih[i] = T(1.0 / p.h[i]);
     a.nsym = p.dim == 3 ? 6 : 3;
     return a;
@@ -329,7 +340,7 @@ int post_num_parts(const feh_plan &p) {
 
 int post_num_slots(const feh_plan &p) {
     const int ns = p.dim == 3 ? 6 : 3;
-    return p.L * ns + p.L * (p.L + 1) / 2;
+    return p.L * ns + p.nbatch * (p.G * (p.G + 1) / 2);
 }
 
 template <typename T>
@@ -342,7 +353,7 @@ static int post_t(const feh_plan &p, const void *u, const double *Ebar, void *st
     a.stress = static_cast<T *>(stress);
     a.partial = partial;
     a.nblk = post_num_parts(p);
-    const int nq = p.L + p.L * (p.L + 1) / 2;
+    const int nq = p.L + p.nbatch * (p.G * (p.G + 1) / 2);
     dim3 g(a.nblk, nq);
     if (p.dim == 3)
         hipLaunchKernelGGL((k_post<T, 3>), g, dim3(kThreads), 0, p.stream, a);
@@ -384,7 +395,7 @@ int launch_grad(const feh_plan &p, const void *u, void *e) {
 
 template <typename T>
 static int sens_t(const feh_plan &p, const void *u, const double *Ebar, const int *pl, const int *pm, const double *pw,
-                  int npair, void *g_lam, void *g_mu) {
+                  const int *gofs, void *g_lam, void *g_mu) {
     PK<T> a = post_args<T>(p);
     a.u = static_cast<const T *>(u);
     a.Ebar = Ebar;
@@ -393,18 +404,18 @@ static int sens_t(const feh_plan &p, const void *u, const double *Ebar, const in
     const int ne = p.dim == 3 ? 6 : 2;
     const double scale = 1.0 / ((double)p.N * ne);
     if (p.dim == 3)
-        hipLaunchKernelGGL((k_sens<T, 3>), dim3((unsigned)g), dim3(kThreads), 0, p.stream, a, pl, pm, pw, npair, scale,
+        hipLaunchKernelGGL((k_sens<T, 3>), dim3((unsigned)g), dim3(kThreads), 0, p.stream, a, pl, pm, pw, gofs, scale,
                            static_cast<T *>(g_lam), static_cast<T *>(g_mu));
     else
-        hipLaunchKernelGGL((k_sens<T, 2>), dim3((unsigned)g), dim3(kThreads), 0, p.stream, a, pl, pm, pw, npair, scale,
+        hipLaunchKernelGGL((k_sens<T, 2>), dim3((unsigned)g), dim3(kThreads), 0, p.stream, a, pl, pm, pw, gofs, scale,
                            static_cast<T *>(g_lam), static_cast<T *>(g_mu));
     return hip_check(hipGetLastError(), "sensitivity launch");
 }
 
 int launch_sensitivity(const feh_plan &p, const void *u, const double *Ebar_dev, const int *pl, const int *pm,
-                       const double *pw, int npair, void *g_lam, void *g_mu) {
-    return p.prec == FEH_FP64 ? sens_t<double>(p, u, Ebar_dev, pl, pm, pw, npair, g_lam, g_mu)
-                              : sens_t<float>(p, u, Ebar_dev, pl, pm, pw, npair, g_lam, g_mu);
+                       const double *pw, const int *gofs, void *g_lam, void *g_mu) {
+    return p.prec == FEH_FP64 ? sens_t<double>(p, u, Ebar_dev, pl, pm, pw, gofs, g_lam, g_mu)
+                              : sens_t<float>(p, u, Ebar_dev, pl, pm, pw, gofs, g_lam, g_mu);
 }
 
 }  // namespace feh

@@ -187,6 +187,7 @@ struct SK {
     T ih[3];
     T vol;
     int ident;         // lambda = 0, mu = 1/2 everywhere
+    int G;             // load cases per microstructure (material of load case l: l / G)
 };
 
 // Tile shapes: VY x VZ voxels per workgroup (one per thread).  HY = 1 when
@@ -270,6 +271,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
     const long long N = a.N;
     const long long plane = (long long)a.n1 * a.n2;
     const long long lcoff = (long long)lc * NC * N;
+    const long long moff = (long long)(lc / a.G) * N;  // this load case's microstructure
     const int ty = tid / VZ, tz = tid - (tid / VZ) * VZ;
     // the thread's voxel has its origin at node (ty, tz) of the tile; that
     // node is updated here when all of its in-plane voxels are in the tile
@@ -348,8 +350,8 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
     };
     auto fetch_material = [&](int V) __attribute__((always_inline)) {
         const long long base = (long long)wrap(V, a.n0) * plane;
-        mlam = a.lam[base + v_off];  // unused (but allocated) for the identity material
-        mmu = a.mu[base + v_off];
+        mlam = a.lam[moff + base + v_off];  // unused (but allocated) for the identity material
+        mmu = a.mu[moff + base + v_off];
     };
 
     // in-plane corners of the thread's voxel: k = cy + 2 cz (3D), k = cz (2D);
@@ -584,6 +586,7 @@ int launch_t(const feh_plan &p, int mode, const StencilArgs &sa) {
     a.partial = sa.partial;
     a.st = sa.state;
     a.ident = sa.identity_material ? 1 : 0;
+    a.G = p.G;
     if (DIM == 3) {
         a.n0 = (int)p.n[0];
         a.n1 = (int)p.n[1];

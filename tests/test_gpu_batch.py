@@ -1,0 +1,144 @@
+"""Batched plans and uneven batches (several grids solved together, CG chunks
+replayed as captured HIP graphs).
+
+  * a batched plan of several microstructures of one shape reproduces the
+    single-microstructure solves (FP64, bitwise iteration counts, C_eff to
+    1e-13) and keeps load cases of different microstructures apart;
+  * sensitivities of a batched plan equal the single-plan ones;
+  * the uneven-batch workload (48 two-phase 2D maps of sizes 64^2 .. 512^2,
+    laminates and circular inclusions, contrast log-uniform in [2, 1000],
+    3 load cases each, FP32): laminates against their closed form, a sample of
+    circle maps against the oracle's direct solve, graph replay against
+    eager launches (bitwise), and C_eff_1111 sensitivities against separate
+    single-map plans."""
+import numpy as np
+import pytest
+
+import microstructures as ms
+from gpu_util import random_material, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _single(shape, lam, mu, Eb, prec, tol):
+    import paper_2105_03297_amd as feh
+    h = feh.Homogenizer(shape, n_load=len(Eb), precision=prec)
+    h.set_material(lam=lam, mu=mu)
+    out = h.solve(Eb, tol=tol, max_iter=5000)
+    h.close()
+    return out
+
+
+@pytest.mark.parametrize("shape", [(20, 14), (6, 7, 5)])
+def test_batched_plan_matches_single_plans(shape):
+    import paper_2105_03297_amd as feh
+    say("batched plan vs single", shape)
+    dim = len(shape)
+    Eb = ms.unit_loads(dim)
+    mats = [random_material(shape, 30 + b) for b in range(3)]
+    h = feh.Homogenizer(shape, n_load=len(Eb), precision="fp64", n_batch=3)
+    h.set_material(lam=np.stack([m[0] for m in mats]), mu=np.stack([m[1] for m in mats]))
+    out = h.solve(np.concatenate([Eb] * 3), tol=1e-12, max_iter=5000)
+    W = out["energy"]
+    G = len(Eb)
+    for b in range(3):
+        one = _single(shape, mats[b][0], mats[b][1], Eb, "fp64", 1e-12)
+        assert rel(out["C_eff_batch"][b], one["C_eff"]) < 1e-13
+        assert [r["iterations"] for r in out["report"][b * G:(b + 1) * G]] == [r["iterations"] for r in one["report"]]
+        for c in range(3):
+            if c != b:
+                assert np.all(W[b * G:(b + 1) * G, c * G:(c + 1) * G] == 0.0)
+    # sensitivities of microstructure b equal the single-plan ones
+    Gm = np.random.default_rng(3).standard_normal((G, G))
+    gl, gm = h.c_eff_sensitivity(Gm)
+    h.close()
+    for b in range(3):
+        h1 = feh.Homogenizer(shape, n_load=G, precision="fp64")
+        h1.set_material(lam=mats[b][0], mu=mats[b][1])
+        h1.solve(Eb, tol=1e-12, max_iter=5000)
+        l1, m1 = h1.c_eff_sensitivity(Gm)
+        h1.close()
+        assert rel(gl[b].cpu().numpy(), l1.cpu().numpy()) < 1e-11
+        assert rel(gm[b].cpu().numpy(), m1.cpu().numpy()) < 1e-11
+
+
+def _c5_maps():
+    from oracle import fe
+    maps = ms.uneven_batch()
+    return maps, [fe.lame(m.E, m.nu) for m in maps]
+
+
+@pytest.fixture(scope="module")
+def c5():
+    import paper_2105_03297_amd as feh
+    maps, lm = _c5_maps()
+    lm32 = [(l.astype(np.float32).astype(np.float64), m.astype(np.float32).astype(np.float64)) for l, m in lm]
+    ub = feh.UnevenBatch(lm32, precision="fp32")
+    out = ub.solve(ms.unit_loads(2)[:, :, :], tol=1e-5, max_iter=5000, use_graph=True)
+    yield maps, lm32, ub, out
+    ub.close()
+
+
+def test_uneven_batch_laminates_closed_form(c5):
+    from test_oracle_fe import _laminate_closed_form, _voigt_C
+    from oracle import fe
+    say("uneven batch laminates")
+    maps, lm, ub, out = c5
+    n_lam = 0
+    for m, o in zip(maps, out):
+        assert o["status"] in (0,)
+        if m.extra["kind"] != "laminate":
+            continue
+        n_lam += 1
+        c = m.extra["contrast"]
+        lam1, mu1 = fe.lame(c, 0.3)
+        lam2, mu2 = fe.lame(1.0, 0.3)
+        C1, C2 = _voigt_C(np.float32(lam1), np.float32(mu1), 2), _voigt_C(np.float32(lam2), np.float32(mu2), 2)
+        ref = _laminate_closed_form(C1, C2, 0.5, 2, m.extra["axis"])
+        assert rel(o["C_eff"], ref) < 1e-5, (m.recipe, rel(o["C_eff"], ref))
+    assert n_lam > 5
+
+
+def test_uneven_batch_circles_match_oracle(c5):
+    from oracle import fe
+    say("uneven batch circles vs oracle")
+    maps, lm, ub, out = c5
+    checked = 0
+    for i, (m, o) in enumerate(zip(maps, out)):
+        if m.extra["kind"] != "circle" or m.shape[0] > 128:
+            continue
+        ref = fe.homogenize(None, None, ms.unit_loads(2), lam_mu=lm[i])
+        assert rel(o["C_eff"], ref["C_eff"]) < 1e-5, (m.recipe, rel(o["C_eff"], ref["C_eff"]))
+        checked += 1
+    assert checked >= 3
+
+
+def test_uneven_batch_graph_replay_equals_eager(c5):
+    say("uneven batch graph vs eager")
+    maps, lm, ub, out = c5
+    eager = ub.solve(ms.unit_loads(2), tol=1e-5, max_iter=5000, use_graph=False)
+    again = ub.solve(ms.unit_loads(2), tol=1e-5, max_iter=5000, use_graph=True)
+    for a, b, c in zip(out, eager, again):
+        assert np.array_equal(a["C_eff"], b["C_eff"])
+        assert np.array_equal(a["C_eff"], c["C_eff"])
+        assert [r["iterations"] for r in a["report"]] == [r["iterations"] for r in b["report"]]
+    assert ub.graph_launches() >= 1
+
+
+def test_uneven_batch_sensitivity_matches_single_plans(c5):
+    """Per-pixel d C_eff_1111 / d(lambda, mu) of a few maps from the batch
+    equal those of separate single-map plans."""
+    import paper_2105_03297_amd as feh
+    say("uneven batch sensitivities")
+    maps, lm, ub, out = c5
+    G = np.zeros((3, 3))
+    G[0, 0] = 1.0
+    sens = ub.c_eff_sensitivity(G)
+    for i in (0, 7, 23, 41):
+        h = feh.Homogenizer(maps[i].shape, n_load=3, precision="fp32")
+        h.set_material(lam=lm[i][0], mu=lm[i][1])
+        h.solve(ms.unit_loads(2), tol=1e-5, max_iter=5000)
+        gl, gm = h.c_eff_sensitivity(G)
+        h.close()
+        assert rel(sens[i][0].cpu().numpy(), gl.cpu().numpy()) < 1e-4
+        assert rel(sens[i][1].cpu().numpy(), gm.cpu().numpy()) < 1e-4
