@@ -85,6 +85,60 @@ def traffic_from_profiles(kernel, workload):
     return tj.get("bytes_per_launch")
 
 
+def uneven_batch_measure(log):
+    """The uneven-batch workload: 48 two-phase 2D maps of sizes 64^2 .. 512^2
+    (laminates and circular inclusions, contrast log-uniform in [2, 1000]),
+    3 load cases each, FP32 fields / FP64 scalars, tol 1e-5.  Timed three
+    ways (second run of each): all maps in batched plans with CG chunks
+    replayed as captured HIP graphs; the same with eager launches; and one
+    plan per map solved one after the other.  The C_eff of the three agree
+    (asserted to 1e-6)."""
+    import torch
+    import microstructures as ms
+    import paper_2105_03297_amd as feh
+    maps = ms.uneven_batch()
+    # plane-strain Lame constants of each map
+    lm = [(m.E * m.nu / ((1 + m.nu) * (1 - 2 * m.nu)), m.E / (2 * (1 + m.nu))) for m in maps]
+    Eb = ms.unit_loads(2)
+    ub = feh.UnevenBatch(lm, precision="fp32")
+    res = {}
+    for mode in ("graph", "eager"):
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = ub.solve(Eb, tol=1e-5, max_iter=5000, use_graph=(mode == "graph"))
+            t = time.perf_counter() - t0
+        res[mode] = (t, out, ub.graph_launches())
+    ub.close()
+    # one plan per map, one after the other
+    t_seq = 0.0
+    seq = []
+    for rep in range(2):
+        seq = []
+        t_seq = 0.0
+        for (lam, mu), m in zip(lm, maps):
+            h = feh.Homogenizer(m.shape, n_load=3, precision="fp32")
+            h.set_material(lam=lam, mu=mu)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            seq.append(h.solve(Eb, tol=1e-5, max_iter=5000))
+            torch.cuda.synchronize()
+            t_seq += time.perf_counter() - t0
+            h.close()
+    dof_it = sum(2 * m.E.size * sum(r["iterations"] for r in o["report"]) for m, o in zip(maps, res["graph"][1]))
+    worst = max(float(np.abs(a["C_eff"] - b["C_eff"]).max() / np.abs(b["C_eff"]).max())
+                for a, b in zip(res["graph"][1], seq))
+    assert worst < 1e-6, worst
+    u = {"maps": len(maps), "voxels": int(sum(m.E.size for m in maps)), "load_cases_per_map": 3,
+         "s_graph": round(res["graph"][0], 4), "s_eager": round(res["eager"][0], 4), "s_one_plan_per_map": round(t_seq, 4),
+         "graph_launches": res["graph"][2],
+         "DOF_CG_iterations_per_s_graph": dof_it / res["graph"][0],
+         "max_cg_iterations": max(max(r["iterations"] for r in o["report"]) for o in res["graph"][1]),
+         "C_eff_graph_vs_one_plan_per_map": worst}
+    log("uneven batch", u)
+    return u
+
+
 def cpu_baseline(n=40, iters=6000):
     """Oracle timing on the host: the same random-field recipe on an n^3 grid
     (correlation length scaled to the same fraction of the cell), one load
@@ -124,6 +178,8 @@ def main():
     ap.add_argument("--workload", default="grf256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-check", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="tune the FFT schedule before timing (not timed)")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch measurement")
     ap.add_argument("--copy-ref", action="store_true",
                     help="after the steps, copy a 1 GiB buffer once (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -155,6 +211,14 @@ def main():
     else:
         hz.set_material(E=torch.as_tensor(m.E, dtype=dt), nu=float(m.nu.flat[0]))
     torch.cuda.synchronize()
+    tuning = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        tuning = hz.autotune(reps=3)
+        tuning["seconds"] = round(time.perf_counter() - t0, 3)
+        log("autotune", tuning)
+    else:
+        tuning = feh.feh_plan_tuning(hz.plan)
 
     max_iter = 5000
     for i in range(args.warmup):
@@ -244,6 +308,10 @@ def main():
         del h64
         torch.cuda.empty_cache()
 
+    uneven = None
+    if not args.no_uneven:
+        uneven = uneven_batch_measure(log)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -274,6 +342,8 @@ def main():
         "roofline": roof,
         "kernels": kernels,
         "sensitivity": sens,
+        "fft_schedule": tuning,
+        "uneven_batch": uneven,
         "cpu_baseline": cpu,
         "C_eff": np.round(C32, 8).tolist() if C32 is not None else None,
     }

@@ -154,6 +154,24 @@ int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
               const void *u0_dev, void *u_dev, void *strain_dev, void *stress_dev,
               double *stress_mean_host, double *energy_host, feh_report *report_host);
 
+/* FFT autotuner: times, on the plan's workspace and stream (blocking), the
+ * candidate radix orders of each axis (the orders of the default
+ * factorisation and of the radix-4 one) and then fewer rows / pencils per
+ * workgroup (1/2, 1/4 of the default) for the last, middle and first axis
+ * passes, each over `reps` runs (< 1: 3), and keeps the fastest.  The
+ * transforms stay exact to rounding whatever is chosen; repeated solves on
+ * one plan stay bitwise reproducible, two tunings may differ in rounding.
+ * Overwrites the workspace vectors (set the material again only if the
+ * workspace was also replaced; the material is not touched). */
+int feh_plan_autotune(feh_plan *plan, int reps);
+
+/* The plan's FFT schedule: values = [rows per workgroup (last axis),
+ * pencils per workgroup (axis 1), pencils per workgroup (axis 0)] (0 =
+ * default heuristic), then for each axis 0..2 the number of passes followed
+ * by the radices in pass order.  Writes at most n_values entries and
+ * returns the full length. */
+int feh_plan_tuning(const feh_plan *plan, int *values, int n_values);
+
 /* Uneven batches: plans of different grids (each possibly a batched plan)
  * that share one created HIP stream, solved together.  After each plan's
  * set-up, the CG iterations of all plans run in chunks of 4, 8, then 16

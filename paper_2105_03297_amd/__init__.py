@@ -25,6 +25,7 @@ __all__ = [
     "feh_apply_operator", "feh_apply_preconditioner", "feh_apply_projection",
     "feh_fft_forward", "feh_fft_inverse", "feh_profile_enable", "feh_profile_read", "PROFILE_KINDS",
     "feh_batch_create", "feh_batch_destroy", "feh_batch_solve", "feh_batch_graph_launches",
+    "feh_plan_autotune", "feh_plan_tuning",
     "feh_last_error", "feh_version", "Homogenizer", "UnevenBatch",
 ]
 
@@ -78,6 +79,8 @@ _SIGS = {
     "feh_batch_solve": (ctypes.c_int, [_vp, ctypes.POINTER(_dp), ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                        ctypes.POINTER(_dp), ctypes.POINTER(_dp), ctypes.POINTER(ctypes.POINTER(feh_report))]),
     "feh_batch_graph_launches": (ctypes.c_int, [_vp]),
+    "feh_plan_autotune": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "feh_plan_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "feh_last_error": (ctypes.c_char_p, []),
     "feh_version": (ctypes.c_int, []),
 }
@@ -232,6 +235,25 @@ def feh_batch_graph_launches(batch):
     return load().feh_batch_graph_launches(batch)
 
 
+def feh_plan_autotune(plan, reps=3):
+    return _check(load().feh_plan_autotune(plan, int(reps)))
+
+
+def feh_plan_tuning(plan):
+    """{'rows_last': .., 'pencils_mid': .., 'pencils_first': .., 'radices': [[..] per axis]}"""
+    buf = (ctypes.c_int * 64)()
+    n = load().feh_plan_tuning(plan, buf, 64)
+    if n < 0:
+        raise FehError(n, feh_last_error())
+    v = list(buf[:n])
+    rad, i = [], 3
+    for _ in range(3):
+        k = v[i]
+        rad.append(v[i + 1:i + 1 + k])
+        i += 1 + k
+    return {"rows_last": v[0], "pencils_mid": v[1], "pencils_first": v[2], "radices": rad}
+
+
 PROFILE_KINDS = ["stencil", "alpha", "fft_last_fwd", "fft_middle_fwd", "fft_first_ksolve", "fft_middle_inv",
                  "fft_last_inv", "beta"]
 
@@ -372,6 +394,11 @@ class Homogenizer:
             else:
                 out["C_eff_batch"] = Cs
         return out
+
+    def autotune(self, reps=3):
+        """Pick the FFT radix orders and launch geometry by timing (see feh_plan_autotune)."""
+        feh_plan_autotune(self.plan, reps)
+        return feh_plan_tuning(self.plan)
 
     def energy_sensitivity(self, weight):
         """Per-voxel (dJ/dlambda, dJ/dmu) for J = sum weight_lm W_lm of the last solve."""

@@ -16,6 +16,7 @@
 //   FFT:      inverse passes; the last one applies u += alpha p, p = z + beta p
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <cstring>
 #include <new>
 #include <string>
@@ -45,23 +46,13 @@ int hip_check(hipError_t e, const char *what) {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-static bool factorize(int n, AxisFFT &ax) {
+// Stockham passes for the radix sequence rad (product n).
+static bool make_axis(int n, const std::vector<int> &rad, AxisFFT &ax) {
+    if ((int)rad.size() > kMaxRadixCount) return false;
     ax = AxisFFT{};
     ax.n = n;
-    int rad[64];
-    int nr = 0;
-    int m = n;
-    const int order[] = {8, 4, 2, 3, 5, 7, 11, 13};
-    for (int r : order) {
-        while (m % r == 0 && m > 1) {
-            if (nr >= kMaxRadixCount) return false;
-            rad[nr++] = r;
-            m /= r;
-        }
-    }
-    if (m != 1) return false;
     int Lstar = 1;
-    for (int s = 0; s < nr; ++s) {
+    for (size_t s = 0; s < rad.size(); ++s) {
         PassInfo ps;
         ps.R = rad[s];
         ps.Lstar = Lstar;
@@ -69,8 +60,56 @@ static bool factorize(int n, AxisFFT &ax) {
         ax.pass[s] = ps;
         Lstar *= rad[s];
     }
-    ax.npass = nr;
+    if (Lstar != n) return false;
+    ax.npass = (int)rad.size();
     return true;
+}
+
+// Default factorisation: greedily the largest supported radices.
+static bool default_radices(int n, std::vector<int> &rad) {
+    rad.clear();
+    int m = n;
+    const int order[] = {8, 4, 2, 3, 5, 7, 11, 13};
+    for (int r : order)
+        while (m % r == 0 && m > 1) {
+            rad.push_back(r);
+            m /= r;
+        }
+    return m == 1;
+}
+
+static bool factorize(int n, AxisFFT &ax) {
+    std::vector<int> rad;
+    return default_radices(n, rad) && make_axis(n, rad, ax);
+}
+
+// Candidate radix sequences of the autotuner: the distinct orders of the
+// default factorisation and of the one with the power-of-two part in
+// radix-4 passes (at most 12).
+static std::vector<std::vector<int>> radix_candidates(int n) {
+    std::vector<std::vector<int>> out;
+    auto add_orders = [&](std::vector<int> r) {
+        std::sort(r.begin(), r.end());
+        do {
+            if (std::find(out.begin(), out.end(), r) == out.end()) out.push_back(r);
+        } while (out.size() < 12 && std::next_permutation(r.begin(), r.end()));
+    };
+    std::vector<int> d;
+    if (!default_radices(n, d)) return out;
+    out.push_back(d);  // the default first
+    add_orders(d);
+    int m = n, e = 0;
+    while (m % 2 == 0) {
+        m /= 2;
+        ++e;
+    }
+    std::vector<int> f;
+    for (int i = 0; i < e / 2; ++i) f.push_back(4);
+    if (e % 2) f.push_back(2);
+    for (int r : d)
+        if (r % 2) f.push_back(r);
+    if (!f.empty()) add_orders(f);
+    return out;
 }
 
 static void layout(feh_plan &p) {
@@ -97,7 +136,10 @@ static void layout(feh_plan &p) {
     p.off_tab = take(kMaxPhase * 2 * sizeof(double));
     p.off_ebar = take((size_t)p.L * 9 * sizeof(double));
     p.off_sums = take((size_t)post_num_slots(p) * sizeof(double));
-    const int sp = stencil_num_parts(p), fp = first_num_parts(p);
+    // the autotuner may go down to a quarter of the default first-axis pencils
+    const long long inner0 = p.dim == 3 ? p.n[1] * p.nh : p.nh;
+    const int pbmin = std::max(1, first_pencils_default(p) / 4);
+    const int sp = stencil_num_parts(p), fp = (int)((inner0 + pbmin - 1) / pbmin);
     p.part_stride = (size_t)(sp > fp ? sp : fp);
     size_t parts = p.part_stride * p.L;
     const size_t post_parts = (size_t)post_num_slots(p) * post_num_parts(p);
@@ -203,11 +245,11 @@ struct ProfScope {
             p.prof_ev.push_back(b);
             p.prof_kind.push_back(0);
         }
-        hipEventRecord(p.prof_ev[2 * p.prof_used], p.stream);
+        (void)hipEventRecord(p.prof_ev[2 * p.prof_used], p.stream);
     }
     ~ProfScope() {
         if (!p.prof_on || 2 * p.prof_used + 2 > p.prof_ev.size()) return;
-        hipEventRecord(p.prof_ev[2 * p.prof_used + 1], p.stream);
+        (void)hipEventRecord(p.prof_ev[2 * p.prof_used + 1], p.stream);
         p.prof_kind[p.prof_used] = kind;
         ++p.prof_used;
     }
@@ -403,7 +445,7 @@ int feh_plan_create_batch(feh_plan **plan, int dim, const int64_t n[], const dou
 
 int feh_plan_destroy(feh_plan *plan) {
     if (plan)
-        for (hipEvent_t e : plan->prof_ev) hipEventDestroy(e);
+        for (hipEvent_t e : plan->prof_ev) (void)hipEventDestroy(e);
     delete plan;
     return FEH_OK;
 }
@@ -657,7 +699,7 @@ struct feh_batch {
 };
 
 static void batch_clear(feh_batch &b) {
-    for (auto &e : b.graphs) hipGraphExecDestroy(e.exec);
+    for (auto &e : b.graphs) (void)hipGraphExecDestroy(e.exec);
     b.graphs.clear();
 }
 
@@ -677,12 +719,12 @@ static int batch_graph(feh_batch &b, int chunk, double tol, int max_iter, hipGra
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(b.stream, &g);
     if (rc != FEH_OK) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return rc;
     }
     CK(hip_check(ec, "end capture"));
     const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     CK(hip_check(ei, "instantiate graph"));
     b.graphs.push_back({chunk, tol, max_iter, exec});
     return FEH_OK;
@@ -831,6 +873,116 @@ int feh_effective_stiffness_weights(int dim, int n_load, const double *Ebar_host
             weight_host[i * nv + j] = s;
         }
     return FEH_OK;
+}
+
+// Mean time of `reps` runs after one warm-up run (events on the plan's stream).
+static int time_runs(feh_plan &p, const std::function<int()> &run, int reps, double &ms) {
+    hipEvent_t a, b;
+    CK(hip_check(hipEventCreate(&a), "event"));
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return set_error(FEH_EHIP, "event");
+    }
+    int rc = run();
+    if (rc == FEH_OK) rc = hip_check(hipEventRecord(a, p.stream), "event");
+    for (int i = 0; i < reps && rc == FEH_OK; ++i) rc = run();
+    if (rc == FEH_OK) rc = hip_check(hipEventRecord(b, p.stream), "event");
+    if (rc == FEH_OK) rc = hip_check(hipEventSynchronize(b), "event");
+    float t = 0.f;
+    if (rc == FEH_OK) rc = hip_check(hipEventElapsedTime(&t, a, b), "event");
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    ms = t / reps;
+    return rc;
+}
+
+int feh_plan_autotune(feh_plan *plan, int reps) {
+    try {
+        CK(check_plan(plan, false));
+        feh_plan &p = *plan;
+        if (reps < 1) reps = 3;
+        const int D = p.dim;
+        // transform zeros: the timing does not depend on the values
+        const size_t nvec = (size_t)p.L * D * p.N;
+        CK(launch_fill(p, p.ws + p.off_r, nvec, 0.0));
+        CK(launch_fill(p, p.ws + p.off_spec, (size_t)p.L * D * p.Nspec * 2, 0.0));
+        FftArgs fa;
+        fa.r = p.ws + p.off_r;
+        fa.spec = p.ws + p.off_spec;
+        fa.z = p.ws + p.off_q;
+        fa.out_scale = 1.0 / (double)p.N;
+        auto tune_axis = [&](int ax, int len, const std::function<int()> &run, int *geom, int gdef, int gmin) -> int {
+            // radix order first (default geometry), then the launch geometry
+            double best = 1e30;
+            AxisFFT keep = p.fft[ax];
+            for (const auto &rad : radix_candidates(len)) {
+                AxisFFT cand;
+                if (!make_axis(len, rad, cand)) continue;
+                p.fft[ax] = cand;
+                double ms = 0;
+                CK(time_runs(p, run, reps, ms));
+                if (ms < best) {
+                    best = ms;
+                    keep = cand;
+                }
+            }
+            p.fft[ax] = keep;
+            if (!geom) return FEH_OK;
+            int bestg = 0;
+            for (int g = gdef; g >= gmin; g /= 2) {
+                *geom = (g == gdef) ? 0 : g;
+                double ms = 0;
+                CK(time_runs(p, run, reps, ms));
+                if (ms < best * 0.98 || g == gdef) {
+                    if (g == gdef) best = ms;
+                    else { best = ms; bestg = g; }
+                }
+                if (g == 1) break;
+            }
+            *geom = bestg;
+            return FEH_OK;
+        };
+        const int PPT = p.prec == FEH_FP32 ? 24 : 16;
+        // last axis: forward and inverse
+        {
+            const int last = D - 1;
+            const int nc = p.fft[last].n;
+            int rr = std::min((PPT * 256) / (nc * D), 64);
+            CK(tune_axis(last, nc, [&]() -> int {
+                CK(launch_forward_last(p, fa));
+                return launch_inverse_last(p, fa);
+            }, &p.tune_rr_last, rr, std::max(1, rr / 4)));
+        }
+        if (D == 3) {
+            int pb = std::min((PPT * 256) / (int)p.n[1], 32);
+            CK(tune_axis(1, (int)p.n[1], [&]() -> int {
+                CK(launch_middle(p, fa, false));
+                return launch_middle(p, fa, true);
+            }, &p.tune_pb_mid, pb, std::max(1, pb / 4)));
+        }
+        {
+            const int pb = first_pencils_default(p);
+            CK(tune_axis(0, (int)p.n[0], [&]() -> int { return launch_first_fused(p, fa); }, &p.tune_pb_first, pb,
+                         std::max(1, pb / 4)));
+        }
+        return hip_check(hipStreamSynchronize(p.stream), "autotune");
+    } catch (const std::bad_alloc &) {
+        return set_error(FEH_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return set_error(FEH_EINVAL, "unexpected host exception");
+    }
+}
+
+int feh_plan_tuning(const feh_plan *plan, int *values, int n_values) {
+    if (!plan || !values) return set_error(FEH_EINVAL, "null argument");
+    std::vector<int> v = {plan->tune_rr_last, plan->tune_pb_mid, plan->tune_pb_first};
+    for (int a = 0; a < 3; ++a) {
+        const int np = a < plan->dim ? plan->fft[a].npass : 0;
+        v.push_back(np);
+        for (int s = 0; s < np; ++s) v.push_back(plan->fft[a].pass[s].R);
+    }
+    for (int i = 0; i < n_values; ++i) values[i] = i < (int)v.size() ? v[i] : 0;
+    return (int)v.size();
 }
 
 int feh_profile_enable(feh_plan *plan, int enable) {

@@ -137,6 +137,11 @@ struct feh_plan {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     bool material_set = false;
+    // launch geometry chosen by feh_plan_autotune (0: the default heuristic);
+    // the radix orders are the pass lists of fft[]
+    int tune_rr_last = 0;               // rows per workgroup, last axis
+    int tune_pb_mid = 0;                // pencils per workgroup, axis 1 (3D)
+    int tune_pb_first = 0;              // pencils per workgroup, axis 0
     bool solved = false;                // off_u holds the fluctuations of the last feh_solve
 
     // optional per-kernel event timing of the CG loop
@@ -238,6 +243,7 @@ int post_num_slots(const feh_plan &p);
 // partial-sum sizes
 int stencil_num_parts(const feh_plan &p);
 int first_num_parts(const feh_plan &p);
+int first_pencils_default(const feh_plan &p);  // before tuning
 int post_num_parts(const feh_plan &p);
 
 }  // namespace feh

@@ -877,6 +877,7 @@ int last_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     int RR = (PPT * kFftThreads) / (nc * a.D);
     if (RR < 1) return set_error(FEH_ENOTSUP, "last axis too long for the LDS transform");
     if (RR > 64) RR = 64;
+    if (p.tune_rr_last > 0 && p.tune_rr_last < RR) RR = p.tune_rr_last;
     if (RR > a.rows) RR = (int)a.rows;
     a.RR = RR;
     a.nbd = FastDiv::make((uint32_t)(a.D * RR));
@@ -922,6 +923,7 @@ int middle_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     int PB = (PPT * kFftThreads) / a.n1;
     if (PB < 1) return set_error(FEH_ENOTSUP, "middle axis too long for the LDS transform");
     if (PB > 32) PB = 32;
+    if (p.tune_pb_mid > 0 && p.tune_pb_mid < PB) PB = p.tune_pb_mid;
     if (PB > inner) PB = (int)inner;
     a.PB = PB;
     a.d_PB = FastDiv::make((uint32_t)PB);
@@ -947,6 +949,7 @@ int first_t(const feh_plan &p, const FftArgs &fa, int mode) {
     int PB = (PPT * kFftThreads) / (a.n0 * DIM);
     if (PB < 1) return set_error(FEH_ENOTSUP, "first axis too long for the LDS transform");
     if (PB > 32) PB = 32;
+    if (p.tune_pb_first > 0 && p.tune_pb_first < PB) PB = p.tune_pb_first;
     if (PB > a.inner_total) PB = (int)a.inner_total;
     a.PB = PB;
     a.d_PB = FastDiv::make((uint32_t)PB);
@@ -974,11 +977,17 @@ int first_dispatch(const feh_plan &p, const FftArgs &fa, int mode) {
 
 }  // namespace
 
-int first_num_parts(const feh_plan &p) {
+int first_pencils_default(const feh_plan &p) {
     const int PPT = p.prec == FEH_FP32 ? 24 : 16;
     int PB = (PPT * kFftThreads) / (int)(p.n[0] * p.dim);
     if (PB < 1) PB = 1;
     if (PB > 32) PB = 32;
+    return PB;
+}
+
+int first_num_parts(const feh_plan &p) {
+    int PB = first_pencils_default(p);
+    if (p.tune_pb_first > 0 && p.tune_pb_first < PB) PB = p.tune_pb_first;
     const long long inner = p.dim == 3 ? p.n[1] * p.nh : p.nh;
     if (PB > inner) PB = (int)inner;
     return (int)((inner + PB - 1) / PB);

@@ -115,3 +115,12 @@ def test_energy_sensitivity_needs_workspace_and_solution():
         feh.feh_energy_sensitivity(p, np.eye(3), 0, 0)
     assert ei.value.status in (feh.FEH_ENOMEM, feh.FEH_EINVAL)
     feh.feh_plan_destroy(p)
+
+
+def test_plan_tuning_reports_default_schedule():
+    p = feh.feh_plan_create(3, (256, 96, 30), None, 2, feh.FEH_FP32)
+    t = feh.feh_plan_tuning(p)
+    feh.feh_plan_destroy(p)
+    assert (t["rows_last"], t["pencils_mid"], t["pencils_first"]) == (0, 0, 0)
+    assert np.prod(t["radices"][0]) == 256 and np.prod(t["radices"][1]) == 96 and np.prod(t["radices"][2]) == 15
+    assert t["radices"][0] == [8, 8, 4]

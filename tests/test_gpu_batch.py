@@ -142,3 +142,26 @@ def test_uneven_batch_sensitivity_matches_single_plans(c5):
         h.close()
         assert rel(sens[i][0].cpu().numpy(), gl.cpu().numpy()) < 1e-4
         assert rel(sens[i][1].cpu().numpy(), gm.cpu().numpy()) < 1e-4
+
+
+@pytest.mark.parametrize("shape,prec", [((24, 20, 18), "fp64"), ((64, 48, 32), "fp32"), ((96, 80), "fp64")])
+def test_autotuned_plan_matches_default(shape, prec):
+    """After autotuning (any radix order and launch geometry) the solve equals
+    the default plan's to rounding, and repeats bitwise."""
+    import paper_2105_03297_amd as feh
+    say("autotune", shape, prec)
+    dim = len(shape)
+    lam, mu = random_material(shape, 12, prec)
+    Eb = ms.unit_loads(dim)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    ref = _single(shape, lam, mu, Eb, prec, tol)
+    h = feh.Homogenizer(shape, n_load=len(Eb), precision=prec)
+    h.set_material(lam=lam, mu=mu)
+    tun = h.autotune(reps=2)
+    print("tuning", tun)
+    assert all(np.prod(r) == n for r, n in zip(tun["radices"], shape[:-1] + (shape[-1] // 2,)))
+    a = h.solve(Eb, tol=tol, max_iter=5000)
+    b = h.solve(Eb, tol=tol, max_iter=5000)
+    h.close()
+    assert np.array_equal(a["C_eff"], b["C_eff"])
+    assert rel(a["C_eff"], ref["C_eff"]) < (1e-12 if prec == "fp64" else 1e-5)
