@@ -238,6 +238,68 @@ int feh_effective_stiffness_weights(int dim, int n_load, const double *Ebar_host
  * breakdown, or the material or workspace changed since).  Blocking. */
 int feh_energy_sensitivity(feh_plan *plan, const double *weight_host, void *grad_lam_dev, void *grad_mu_dev);
 
+/* Discrete derivatives of the strain-space solver (Sec. "Discrete
+ * projection": the projection is built from the Fourier symbol D(k) of a
+ * discrete derivative, one symbol per evaluation point T of a voxel):
+ *   FEH_DERIV_FE        linear finite elements: n_e = 2 (2D) / 6 (3D) points,
+ *                       the element gradients (Sec. "Linear finite elements")
+ *   FEH_DERIV_FD        forward differences, 1 point (Sec. "Finite differences")
+ *   FEH_DERIV_CD        central differences, 1 point (same section)
+ *   FEH_DERIV_LS        least-squares voxel gradient, 1 point, 2D only
+ *                       (Sec. "Least squares")
+ *   FEH_DERIV_FOURIER   Fourier derivative i k, 1 point (Eq. original-G)
+ *   FEH_DERIV_FOURIER2  Fourier derivative at the two triangle centroids,
+ *                       2 points, 2D only (two-point Fourier appendix)
+ * Wavevectors k_a = 2 pi m / (n_a h_a) with m in [-n/2, n/2 - 1] (even n) or
+ * [-(n-1)/2, (n-1)/2] (odd n). */
+enum {
+    FEH_DERIV_FE = 0,
+    FEH_DERIV_FD = 1,
+    FEH_DERIV_CD = 2,
+    FEH_DERIV_LS = 3,
+    FEH_DERIV_FOURIER = 4,
+    FEH_DERIV_FOURIER2 = 5
+};
+
+/* Evaluation points per voxel n_e of a derivative kind in dim dimensions;
+ * FEH_ENOTSUP if the kind is not defined there. */
+int feh_strain_cg_points(int kind, int dim, int *n_points);
+
+/* Device workspace bytes of feh_strain_cg_solve for this plan and kind: the
+ * strain-space Krylov vectors x, r, p, q (n_load * n_e * nsym * N reals each,
+ * nsym = 3 in 2D, 6 in 3D), their half spectrum, CG scalars and partial
+ * sums. */
+int feh_strain_cg_workspace_bytes(const feh_plan *plan, int kind, size_t *bytes);
+
+/* Projected CG in strain space (Sec. "Compatibility projection": CG on
+ * G(C : e~) = -G(C : Ebar) from e~ = 0, which keeps every iterate compatible)
+ * with the projection G of the small-strain appendix built from the symbol of
+ * `kind`, applied per wavevector through the FFT:
+ *   G(s)_T = sym(D_T (x) M^-1 sum_L s_L . conj(D_L)),
+ *   M = 1/2 (|D|^2 I + sum_L D_L D_L^H);
+ * modes where the symbol vanishes (k = 0; on even grids also the central
+ * difference and least-squares modes where every D_T is zero) are projected
+ * out.  The Fourier kinds apply the Hermitian part of G at Nyquist indices
+ * (real fields).  Inner product: Frobenius, equal weights per point.
+ * Uses the plan's material, grid and FFT tables (plans of one
+ * microstructure: FEH_EINVAL for a batched plan) and leaves the plan's own
+ * workspace vectors untouched.
+ *   Ebar_host         [n_load][D][D] symmetric macroscopic strains
+ *   tol               stop a load case when ||r|| / ||r_0|| <= tol
+ *   max_iter          per load case, >= 1
+ *   work_dev          caller-owned device buffer, 256-byte aligned, of at
+ *                     least feh_strain_cg_workspace_bytes bytes
+ *   strain_dev        nullable output [n_load][N][n_e][D][D] (Ebar + e~) in the
+ *                     plan precision
+ *   stress_mean_host  nullable [n_load][D][D], average of C : e over all points
+ *   energy_host       nullable [n_load][n_load], W_lm = < e_l : C : e_m >
+ *   report_host       nullable [n_load]; rel_residual = ||r|| / ||r_0||
+ * Returns FEH_OK, FEH_ENOCONV or FEH_EBREAKDOWN like feh_solve (outputs
+ * filled), FEH_ENOMEM for a missing or short workspace. */
+int feh_strain_cg_solve(feh_plan *plan, int kind, const double *Ebar_host, double tol, int max_iter,
+                        void *work_dev, size_t work_bytes, void *strain_dev, double *stress_mean_host,
+                        double *energy_host, feh_report *report_host);
+
 /* Test export: q = K p with K = sum_e |e| B_e^T C_e B_e, p and q
  * [n_load][N][D] in the plan precision. */
 int feh_apply_operator(feh_plan *plan, const void *p_dev, void *q_dev);

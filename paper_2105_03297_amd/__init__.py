@@ -26,11 +26,16 @@ __all__ = [
     "feh_fft_forward", "feh_fft_inverse", "feh_profile_enable", "feh_profile_read", "PROFILE_KINDS",
     "feh_batch_create", "feh_batch_destroy", "feh_batch_solve", "feh_batch_graph_launches",
     "feh_plan_autotune", "feh_plan_tuning",
+    "FEH_DERIV_FE", "FEH_DERIV_FD", "FEH_DERIV_CD", "FEH_DERIV_LS", "FEH_DERIV_FOURIER", "FEH_DERIV_FOURIER2",
+    "DERIV_KINDS", "feh_strain_cg_points", "feh_strain_cg_workspace_bytes", "feh_strain_cg_solve",
     "feh_last_error", "feh_version", "Homogenizer", "UnevenBatch",
 ]
 
 FEH_OK, FEH_EINVAL, FEH_ENOMEM, FEH_EHIP, FEH_ENOCONV, FEH_EBREAKDOWN, FEH_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 FEH_FP64, FEH_FP32 = 0, 1
+FEH_DERIV_FE, FEH_DERIV_FD, FEH_DERIV_CD, FEH_DERIV_LS, FEH_DERIV_FOURIER, FEH_DERIV_FOURIER2 = 0, 1, 2, 3, 4, 5
+DERIV_KINDS = {"fe": FEH_DERIV_FE, "fd": FEH_DERIV_FD, "cd": FEH_DERIV_CD, "ls": FEH_DERIV_LS,
+               "fourier": FEH_DERIV_FOURIER, "fourier2": FEH_DERIV_FOURIER2}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libfeh.so")
@@ -81,6 +86,10 @@ _SIGS = {
     "feh_batch_graph_launches": (ctypes.c_int, [_vp]),
     "feh_plan_autotune": (ctypes.c_int, [_vp, ctypes.c_int]),
     "feh_plan_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
+    "feh_strain_cg_points": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "feh_strain_cg_workspace_bytes": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "feh_strain_cg_solve": (ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_int, _vp,
+                                           ctypes.c_size_t, _vp, _dp, _dp, ctypes.POINTER(feh_report)]),
     "feh_last_error": (ctypes.c_char_p, []),
     "feh_version": (ctypes.c_int, []),
 }
@@ -190,6 +199,32 @@ def feh_solve(plan, Ebar, tol, max_iter, u0_ptr=0, u_ptr=0, strain_ptr=0, stress
     rc = load().feh_solve(plan, Ebp, float(tol), int(max_iter), _vp(u0_ptr or 0), _vp(u_ptr or 0),
                           _vp(strain_ptr or 0), _vp(stress_ptr or 0), smean.ctypes.data_as(_dp),
                           W.ctypes.data_as(_dp), rep)
+    _check(rc, allow=(FEH_ENOCONV,) if allow_noconv else ())
+    return rc, smean, W, [dict(iterations=r.iterations, status=r.status, rel_residual=r.rel_residual) for r in rep]
+
+
+def feh_strain_cg_points(kind, dim):
+    n = ctypes.c_int(0)
+    _check(load().feh_strain_cg_points(int(kind), int(dim), ctypes.byref(n)))
+    return n.value
+
+
+def feh_strain_cg_workspace_bytes(plan, kind):
+    n = ctypes.c_size_t(0)
+    _check(load().feh_strain_cg_workspace_bytes(plan, int(kind), ctypes.byref(n)))
+    return n.value
+
+
+def feh_strain_cg_solve(plan, kind, Ebar, tol, max_iter, work_ptr, work_bytes, strain_ptr=0, allow_noconv=True):
+    """Returns (status, stress_mean[L,D,D], energy[L,L], reports)."""
+    Eb, Ebp = _f64(Ebar)
+    L, D = Eb.shape[0], Eb.shape[1]
+    smean = np.zeros((L, D, D))
+    W = np.zeros((L, L))
+    rep = (feh_report * L)()
+    rc = load().feh_strain_cg_solve(plan, int(kind), Ebp, float(tol), int(max_iter), _vp(work_ptr),
+                                    ctypes.c_size_t(int(work_bytes)), _vp(strain_ptr or 0),
+                                    smean.ctypes.data_as(_dp), W.ctypes.data_as(_dp), rep)
     _check(rc, allow=(FEH_ENOCONV,) if allow_noconv else ())
     return rc, smean, W, [dict(iterations=r.iterations, status=r.status, rel_residual=r.rel_residual) for r in rep]
 
@@ -393,6 +428,28 @@ class Homogenizer:
                     out["C_eff"] = Cs[0]
             else:
                 out["C_eff_batch"] = Cs
+        return out
+
+    def strain_cg_solve(self, Ebar, kind="fe", tol=1e-10, max_iter=1000, fields=False):
+        """Projected CG in strain space with the derivative `kind` (one of
+        DERIV_KINDS); the plan's material.  Returns a dict like solve (strain
+        field [L, N, n_e, D, D] when fields) plus C_eff for nv load cases."""
+        torch = self.torch
+        k = DERIV_KINDS[kind] if isinstance(kind, str) else int(kind)
+        Ebar = np.asarray(Ebar, dtype=np.float64).reshape(self.n_load, self.dim, self.dim)
+        L, D, N = self.n_load, self.dim, self.N
+        ne = feh_strain_cg_points(k, D)
+        nbytes = feh_strain_cg_workspace_bytes(self.plan, k)
+        work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        strain = torch.empty((L, N, ne, D, D), dtype=self.dtype, device=self.device) if fields else None
+        rc, smean, W, rep = feh_strain_cg_solve(self.plan, k, Ebar, tol, max_iter, work.data_ptr(), nbytes,
+                                                strain.data_ptr() if strain is not None else 0)
+        out = dict(status=rc, stress_mean=smean, energy=W, report=rep, strain=strain)
+        if self.n_per == (3 if D == 2 else 6) and self.n_batch == 1:
+            try:
+                out["C_eff"] = feh_effective_stiffness(D, Ebar, W)
+            except FehError:
+                pass
         return out
 
     def autotune(self, reps=3):

@@ -38,12 +38,6 @@ int hip_check(hipError_t e, const char *what) {
     return set_error(FEH_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define CK(x)                        \
-    do {                             \
-        int rc__ = (x);              \
-        if (rc__ != FEH_OK) return rc__; \
-    } while (0)
-
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Stockham passes for the radix sequence rad (product n).
@@ -154,6 +148,36 @@ static void layout(feh_plan &p) {
     p.total = o;
 }
 
+// e^{+2 pi i j / n} with the symmetries of the circle applied exactly: the
+// angle is reduced to [0, pi/4] in integer arithmetic, so the table is exactly
+// conjugate-symmetric and exact at multiples of pi/2.
+static void cis_exact(long long j, long long n, double &c, double &s) {
+    j %= n;
+    if (j < 0) j += n;
+    bool neg_s = false, neg_c = false;
+    if (2 * j > n) {
+        j = n - j;
+        neg_s = true;
+    }
+    long long a = 2 * j, b = n;  // angle = pi a / b, a / b in [0, 1]
+    if (2 * a > b) {
+        a = b - a;               // pi - angle
+        neg_c = true;
+    }
+    double cc, ss;
+    if (4 * a > b) {             // pi/2 - pi u with u = (b - 2a) / (2b) in [0, 1/4)
+        const double u = (double)(b - 2 * a) / (double)(2 * b);
+        cc = std::sin(M_PI * u);
+        ss = std::cos(M_PI * u);
+    } else {
+        const double t = (double)a / (double)b;
+        cc = std::cos(M_PI * t);
+        ss = std::sin(M_PI * t);
+    }
+    c = neg_c ? -cc : cc;
+    s = neg_s ? -ss : ss;
+}
+
 static void tables(feh_plan &p) {
     for (int a = 0; a < 3; ++a) {
         const int n = (int)p.n[a];
@@ -161,16 +185,17 @@ static void tables(feh_plan &p) {
         p.om_host[a].assign(2 * n, 0.0);
         p.aa_host[a].assign(2 * n, 0.0);
         for (int j = 0; j < n; ++j) {
-            const double th = 2.0 * M_PI * (double)j / (double)n;
-            // twiddle exp(-i th)
-            p.tw_host[a][2 * j] = std::cos(th);
-            p.tw_host[a][2 * j + 1] = -std::sin(th);
+            double c, s, ch, sh;
+            cis_exact(j, n, c, s);
+            cis_exact(j, 2 * (long long)n, ch, sh);  // half angle
+            // twiddle exp(-i th), th = 2 pi j / n
+            p.tw_host[a][2 * j] = c;
+            p.tw_host[a][2 * j + 1] = -s;
             // omega = exp(+i th); a = (omega - 1)/h = (-2 sin^2(th/2) + i sin th)/h
-            p.om_host[a][2 * j] = std::cos(th);
-            p.om_host[a][2 * j + 1] = std::sin(th);
-            const double s2 = std::sin(0.5 * th);
-            p.aa_host[a][2 * j] = -2.0 * s2 * s2 / p.h[a];
-            p.aa_host[a][2 * j + 1] = std::sin(th) / p.h[a];
+            p.om_host[a][2 * j] = c;
+            p.om_host[a][2 * j + 1] = s;
+            p.aa_host[a][2 * j] = -2.0 * sh * sh / p.h[a];
+            p.aa_host[a][2 * j + 1] = s / p.h[a];
         }
     }
 }

@@ -35,6 +35,8 @@ template <typename T>
 __host__ __device__ __forceinline__ Cx<T> csub(Cx<T> a, Cx<T> b) { return {a.x - b.x, a.y - b.y}; }
 template <typename T>
 __host__ __device__ __forceinline__ Cx<T> cconj(Cx<T> a) { return {a.x, -a.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ Cx<T> cscale(Cx<T> a, T s) { return {a.x * s, a.y * s}; }
 
 // ---------------------------------------------------------------------------
 // limits and shapes
@@ -168,6 +170,13 @@ namespace feh {
 int set_error(int code, const std::string &msg);
 int hip_check(hipError_t e, const char *what);
 
+// return the error code of a failing call
+#define CK(...)                          \
+    do {                                 \
+        int rc__ = (__VA_ARGS__);        \
+        if (rc__ != FEH_OK) return rc__; \
+    } while (0)
+
 // ---------------------------------------------------------------------------
 // kernel launchers (defined in the kern_*.hip files)
 // ---------------------------------------------------------------------------
@@ -204,12 +213,14 @@ struct FftArgs {
     double out_scale = 1.0;      // c2r output scale
     int ksolve = 1;              // apply (B^*B)^-1 between forward and inverse first axis
     bool identity_test = false;  // forward/inverse only (no k-solve)
+    int comps = 0;               // components per point (0: the dimension)
 };
 
 int launch_forward_last(const feh_plan &p, const FftArgs &a);   // r2c along the last axis
 int launch_middle(const feh_plan &p, const FftArgs &a, bool inverse);  // c2c axis 1 (3D)
 int launch_first_fused(const feh_plan &p, const FftArgs &a);    // c2c axis 0 fwd, k-solve, inv
 int launch_first(const feh_plan &p, const FftArgs &a, bool inverse);  // c2c axis 0 only
+int launch_first_plain(const feh_plan &p, const FftArgs &a, bool inverse);  // c2c axis 0, any a.comps
 int launch_inverse_last(const feh_plan &p, const FftArgs &a);   // c2r along the last axis
 
 // scalar / vector kernels (kern_cg.hip)
@@ -220,6 +231,10 @@ int launch_init_state(const feh_plan &p, LcState *st, int n_load);
 int launch_finish_rho(const feh_plan &p, LcState *st, const double *partial, int nparts, int mode,
                       double tol, int max_iter);
 int launch_finish_pq(const feh_plan &p, LcState *st, const double *partial, int nparts);
+// the same with an explicit partial-sum stride (doubles per load case)
+int launch_finish_rho_stride(const feh_plan &p, LcState *st, const double *partial, int nparts, int stride,
+                             int mode, double tol, int max_iter);
+int launch_finish_pq_stride(const feh_plan &p, LcState *st, const double *partial, int nparts, int stride);
 int launch_finalize_u(const feh_plan &p, void *u, const void *pv, const LcState *st);
 int launch_material_lame(const feh_plan &p, const void *lam, const void *mu, int *flag);
 int launch_material_phases(const feh_plan &p, const int32_t *phase, const double *tab, int n_phase,

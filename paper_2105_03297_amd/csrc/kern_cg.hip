@@ -299,6 +299,19 @@ int launch_finish_rho(const feh_plan &p, LcState *st, const double *partial, int
     return hip_check(hipGetLastError(), "finish rho");
 }
 
+int launch_finish_rho_stride(const feh_plan &p, LcState *st, const double *partial, int nparts, int stride,
+                             int mode, double tol, int max_iter) {
+    const int ref_too = mode >= 10 ? 1 : 0;
+    hipLaunchKernelGGL(k_finish_rho, dim3(p.L), dim3(kThreads), 0, p.stream, st, partial, nparts, stride, mode % 10,
+                       ref_too, tol, max_iter);
+    return hip_check(hipGetLastError(), "finish rho");
+}
+
+int launch_finish_pq_stride(const feh_plan &p, LcState *st, const double *partial, int nparts, int stride) {
+    hipLaunchKernelGGL(k_finish_pq, dim3(p.L), dim3(kThreads), 0, p.stream, st, partial, nparts, stride);
+    return hip_check(hipGetLastError(), "finish pq");
+}
+
 int launch_finish_pq(const feh_plan &p, LcState *st, const double *partial, int nparts) {
     hipLaunchKernelGGL(k_finish_pq, dim3(p.L), dim3(kThreads), 0, p.stream, st, partial, nparts, (int)p.part_stride);
     return hip_check(hipGetLastError(), "finish pq");

@@ -446,6 +446,12 @@ __global__ __launch_bounds__(kFftThreads) void k_last_inv(FK<T> a) {
             const int c = e - kk * D;
             const int sl = (int)a.d_nc.div((uint32_t)kk);
             const int kx = kk - sl * nc;
+            // the DC and Nyquist samples of a real signal's spectrum are real:
+            // their imaginary parts (rounding residue) are dropped
+            if (kx == 0) {
+                Xa[k].y = T(0);
+                Xb[k].y = T(0);
+            }
             Cx<T> Z;
             if (even) {
                 const Cx<T> Xm = cconj(Xb[k]);
@@ -836,7 +842,7 @@ FK<T> base_args(const feh_plan &p, const FftArgs &fa) {
     a.partial = fa.partial;
     a.st = fa.state;
     a.dim = p.dim;
-    a.D = p.dim;
+    a.D = fa.comps > 0 ? fa.comps : p.dim;
     a.L = p.L;
     a.n0 = (int)p.n[0];
     a.n1 = p.dim == 3 ? (int)p.n[1] : 1;
@@ -939,6 +945,38 @@ int middle_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     return hip_check(hipGetLastError(), "middle-axis fft launch");
 }
 
+// c2c along axis 0 of a spectrum with fa.comps components, no k-solve: the
+// middle-axis kernel with one outer slice, the whole axis-0 pencil set of a
+// load case and the contiguous (axis 1, kh, component) index as pencils.
+template <typename T>
+int first_plain_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
+    constexpr int PPT = ppt<T>();
+    FK<T> a = base_args<T>(p, fa);
+    a.ax = p.fft[0];
+    a.tw = p.ptr<const Cx<T>>(p.off_tw[0]);
+    a.tws = 1;
+    const long long inner = a.inner_total * a.D;
+    const int len = a.n0;
+    int PB = (PPT * kFftThreads) / len;
+    if (PB < 1) return set_error(FEH_ENOTSUP, "first axis too long for the LDS transform");
+    if (PB > 32) PB = 32;
+    if (PB > inner) PB = (int)inner;
+    a.PB = PB;
+    a.d_PB = FastDiv::make((uint32_t)PB);
+    a.inner_total = inner;
+    a.n1 = len;   // transform length
+    a.n0 = 1;     // one outer slice per load case
+    a.nblk = (int)((inner + PB - 1) / PB);
+    a.total = a.nblk * p.L;
+    if (pow2_len(a.ax.n))
+        hipLaunchKernelGGL((k_middle<T, PPT, false>), dim3(a.total), dim3(kFftThreads), (size_t)len * sizeof(Cx<T>),
+                           p.stream, a, inverse ? 1 : 0);
+    else
+        hipLaunchKernelGGL((k_middle<T, PPT, true>), dim3(a.total), dim3(kFftThreads), (size_t)len * sizeof(Cx<T>),
+                           p.stream, a, inverse ? 1 : 0);
+    return hip_check(hipGetLastError(), "first-axis fft launch");
+}
+
 template <typename T, int DIM>
 int first_t(const feh_plan &p, const FftArgs &fa, int mode) {
     constexpr int PPT = ppt<T>();
@@ -1004,6 +1042,9 @@ int launch_middle(const feh_plan &p, const FftArgs &a, bool inverse) {
 }
 int launch_first_fused(const feh_plan &p, const FftArgs &a) {
     return p.prec == FEH_FP64 ? first_dispatch<double>(p, a, 0) : first_dispatch<float>(p, a, 0);
+}
+int launch_first_plain(const feh_plan &p, const FftArgs &a, bool inverse) {
+    return p.prec == FEH_FP64 ? first_plain_t<double>(p, a, inverse) : first_plain_t<float>(p, a, inverse);
 }
 int launch_first(const feh_plan &p, const FftArgs &a, bool inverse) {
     const int mode = inverse ? 2 : 1;
