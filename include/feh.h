@@ -68,7 +68,8 @@ enum {
     FEH_EHIP = -3,        /* HIP runtime error                                 */
     FEH_ENOCONV = -4,     /* max_iter reached; outputs hold the last iterate   */
     FEH_EBREAKDOWN = -5,  /* CG breakdown (p.q <= 0 or not finite)             */
-    FEH_ENOTSUP = -6      /* unsupported size (FFT length with a prime > 13)   */
+    FEH_ENOTSUP = -6      /* unsupported (axis too long for the LDS transform,
+                             derivative kind outside its dimension)           */
 };
 
 enum { FEH_FP64 = 0, FEH_FP32 = 1 };
@@ -86,8 +87,11 @@ typedef struct {
 /* Create a plan for a dim-dimensional periodic grid n[] with voxel sizes h[]
  * (NULL = unit), n_load load cases solved together, precision FEH_FP64 or
  * FEH_FP32, and a HIP stream (hipStream_t; NULL = default stream).
- * Each n[a] must lie in [2, 4096] and factor into primes <= 13 (else
- * FEH_ENOTSUP); n_load in [1, 64]; N <= 2^31.  Host-side only: computes the
+ * Each n[a] must lie in [2, 4096]; any size is accepted: prime factors up
+ * to 13 run as radix butterflies, larger primes (e.g. 17, 151) as direct-DFT
+ * passes (O(p) work per output of that pass).  An axis whose points times
+ * the components of a transform exceed the LDS tile (4096 points in FP64,
+ * 6144 in FP32) gives FEH_ENOTSUP; n_load in [1, 64]; N <= 2^31.  Host-side only: computes the
  * FFT factorisations, twiddle and phase tables (Discrete Fourier transform
  * appendix: k_a = 2 pi m / (n_a h_a)). */
 int feh_plan_create(feh_plan **plan, int dim, const int64_t n[], const double h[],

@@ -77,6 +77,17 @@ def circle(n=32, radius=8.0, centre=None, E=(1.0, 10.0), nu=(0.3, 0.3)):
                        f"circle n={n} R={radius} centre={centre}")
 
 
+def eshelby(n=151, frac=0.1, E_hard=1.0, contrast=10.0, nu=0.33):
+    """Circular soft inhomogeneity (phase 1, E_hard / contrast) in a hard
+    matrix (phase 0), radius frac * n voxels, centred on the middle voxel of
+    an odd n x n grid so the discretised disc keeps the square's symmetries
+    (the paper's 2D Eshelby-inhomogeneity setup: 151 x 151, half axes 10 % of
+    the edge, stiffness ratio 10, equal Poisson ratios)."""
+    m = circle(n, frac * n, (n / 2.0, n / 2.0), E=(E_hard, E_hard / contrast), nu=(nu, nu))
+    m.recipe = f"eshelby n={n} R={frac * n} contrast={contrast} nu={nu}"
+    return m
+
+
 def sphere(n=16, radius=4.0, E=(1.0, 10.0), nu=(0.3, 0.3)):
     X, Y, Z = _centres((n, n, n))
     c = n / 2.0
@@ -248,6 +259,12 @@ def workload(name):
         Eb = np.zeros((1, 2, 2))
         Eb[0, 0, 0] = UNIT_STRAIN
         return m, Eb, 1e-10, "fp64"
+    if name.startswith("eshelby"):
+        # biaxial macroscopic strain exx = eyy = 1 %
+        n = int(name[7:] or 151)
+        Eb = np.zeros((1, 2, 2))
+        Eb[0, 0, 0] = Eb[0, 1, 1] = UNIT_STRAIN
+        return eshelby(n), Eb, 1e-10, "fp64"
     if name == "voronoi1024":
         m = voronoi((1024, 1024), 64, 1002)
         return m, unit_loads(2), 1e-10, "fp64"

@@ -59,7 +59,9 @@ static bool make_axis(int n, const std::vector<int> &rad, AxisFFT &ax) {
     return true;
 }
 
-// Default factorisation: greedily the largest supported radices.
+// Default factorisation: greedily the largest radices with butterflies
+// (8, 4, 2, 3, 5, 7, 11, 13), then each remaining prime factor as one
+// direct-DFT pass.
 static bool default_radices(int n, std::vector<int> &rad) {
     rad.clear();
     int m = n;
@@ -69,7 +71,13 @@ static bool default_radices(int n, std::vector<int> &rad) {
             rad.push_back(r);
             m /= r;
         }
-    return m == 1;
+    for (int f = 17; m > 1 && f * f <= m; f += 2)
+        while (m % f == 0) {
+            rad.push_back(f);
+            m /= f;
+        }
+    if (m > 1) rad.push_back(m);  // the last prime factor
+    return n >= 1;
 }
 
 static bool factorize(int n, AxisFFT &ax) {
@@ -437,7 +445,7 @@ static int plan_create(feh_plan **plan, int dim, const int64_t n[], const double
             if (a == dim - 1 && p->last_even) len /= 2;
             if (!factorize(len, p->fft[a])) {
                 delete p;
-                return set_error(FEH_ENOTSUP, "grid size has a prime factor above 13");
+                return set_error(FEH_ENOTSUP, "grid size needs more FFT passes than supported");
             }
         }
         // LDS capacity of the transforms (points per workgroup)

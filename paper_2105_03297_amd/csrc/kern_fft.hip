@@ -215,6 +215,49 @@ __device__ __forceinline__ void stockham_pass(Cx<T> *buf, int nb, const FastDiv 
     __syncthreads();
 }
 
+// Pass with a prime radix R > 13 (known at run time only): every output is
+// the R-term sum of its Stockham butterfly evaluated directly, with the pass
+// twiddle and the DFT root folded into one exponent,
+//   y[q + m (p + L* d)] = sum_c w_n^{c m (p + L* d)} x[q + c m + m R p],
+// read from LDS (O(R) work per output instead of O(log R)).
+template <typename T, int PPT>
+__device__ __forceinline__ void direct_pass(Cx<T> *buf, int nb, int n, const PassInfo &ps, const Cx<T> *tw, int tws,
+                                         bool inv, int tx) {
+    constexpr int NT = kFftThreads;
+    const int R = ps.R, m = (int)ps.m.d, Ls = ps.Lstar;
+    const int tot = nb * n;
+    Cx<T> y[PPT];
+    #pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int t = tx + k * NT;
+        y[k] = Cx<T>{T(0), T(0)};
+        if (t < tot) {
+            const int j = t / nb;  // output element of the batch
+            const int b = t - j * nb;
+            const int q = j % m;
+            const int pd = j / m;
+            const int pp = pd % Ls;
+            const int E = m * pd;  // m (p + L* d) < n
+            const int ib = (q + m * R * pp) * nb + b;
+            Cx<T> acc = Cx<T>{T(0), T(0)};
+            int e = 0;
+            for (int c = 0; c < R; ++c) {
+                acc = cadd(acc, cmul(buf[ib + c * m * nb], twid(tw, tws, e, inv)));
+                e += E;
+                if (e >= n) e -= n;
+            }
+            y[k] = acc;
+        }
+    }
+    __syncthreads();
+    #pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int t = tx + k * NT;
+        if (t < tot) buf[t] = y[k];
+    }
+    __syncthreads();
+}
+
 // GEN = false instantiates only the radices of power-of-two lengths (2, 4, 8),
 // which keeps the register footprint of the common case small.
 template <typename T, int PPT, bool GEN>
@@ -234,7 +277,7 @@ __device__ __forceinline__ void lds_fft(Cx<T> *buf, int nb, const FastDiv &nbd, 
                 case 7: stockham_pass<T, 7, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv, tx); break;
                 case 11: stockham_pass<T, 11, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv, tx); break;
                 case 13: stockham_pass<T, 13, PPT>(buf, nb, nbd, ax.n, ps, tw, tws, inv, tx); break;
-                default: break;
+                default: direct_pass<T, PPT>(buf, nb, ax.n, ps, tw, tws, inv, tx); break;
                 }
             }
             break;

@@ -42,13 +42,25 @@ def test_version_and_error_string():
     (2, (8, 8), 0, 0, feh.FEH_EINVAL),
     (2, (8, 8), 65, 0, feh.FEH_EINVAL),
     (2, (8, 8), 1, 7, feh.FEH_EINVAL),
-    (2, (17 * 2, 8), 1, 0, feh.FEH_ENOTSUP),
+    (2, (4096, 8), 1, 0, feh.FEH_ENOTSUP),
     (3, (8, 8, 8192), 1, 0, feh.FEH_EINVAL),
 ])
 def test_plan_validation(dim, n, nl, prec, code):
     with pytest.raises(feh.FehError) as ei:
         feh.feh_plan_create(dim, n, None, nl, prec)
     assert ei.value.status == code
+
+
+@pytest.mark.parametrize("n,passes", [((34, 8), [[2, 17], [4]]), ((151, 302), [[151], [151]]),
+                                      ((17, 17), [[17], [17]]), ((26, 39), [[2, 13], [3, 13]])])
+def test_prime_sizes_factorise(n, passes):
+    """Prime factors above 13 become single direct-DFT passes; the last axis
+    of even length is transformed at half length (two reals per point)."""
+    p = feh.feh_plan_create(2, n, None, 1, feh.FEH_FP64)
+    t = feh.feh_plan_tuning(p)
+    got = [sorted(r) for r in t["radices"][:2]]
+    assert got == [sorted(r) for r in passes]
+    feh.feh_plan_destroy(p)
 
 
 def test_bad_voxel_size():

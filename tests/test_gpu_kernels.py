@@ -13,7 +13,9 @@ from gpu_util import random_material, rel, say
 pytestmark = pytest.mark.gpu
 
 FFT_SHAPES = [(8, 8), (6, 10), (5, 7), (32, 32), (12, 9), (64, 512), (20, 13),
-              (4, 6, 8), (3, 5, 7), (16, 16, 16), (8, 12, 10), (6, 20, 9), (2, 2, 2)]
+              (4, 6, 8), (3, 5, 7), (16, 16, 16), (8, 12, 10), (6, 20, 9), (2, 2, 2),
+              # prime factors above 13 (direct-DFT passes)
+              (17, 34), (151, 12), (34, 151), (4, 2039), (1661, 6), (17, 6, 34), (5, 151, 4)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

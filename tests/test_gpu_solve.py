@@ -58,7 +58,8 @@ def test_circle32_iterations_at_paper_tolerance():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("shape", [(24, 20), (9, 300), (6, 5, 7), (10, 8, 70), (18, 4, 6)])
+@pytest.mark.parametrize("shape", [(24, 20), (9, 300), (6, 5, 7), (10, 8, 70), (18, 4, 6),
+                                   (17, 17), (151, 34), (17, 6, 5)])
 def test_random_material_matches_oracle(shape, prec):
     say("random material", shape, prec)
     from oracle import fe
