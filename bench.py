@@ -139,6 +139,72 @@ def uneven_batch_measure(log):
     return u
 
 
+def strain_bytes_per_iteration(dim, ne, s, n_last, n_voxels):
+    """Algorithmic HBM bytes of one strain-space CG iteration of one load case.
+
+    Per voxel, with C = n_e * nsym strain components (nsym = 3 in 2D, 6 in 3D)
+    of s bytes and Ch = C 2 s (n_last/2+1)/n_last bytes of half spectrum:
+      stress       read r, p; write p, q: 4 C s (+ lambda, mu: 2 s)
+      FFT forward  last axis: read C s, write Ch; each other axis: 2 Ch
+      projection   read + write the spectrum: 2 Ch
+      FFT inverse  each non-last axis: 2 Ch; last axis: read Ch, write C s
+      p.q          read p, q: 2 C s
+      update       read x, p, r, q; write x, r: 6 C s
+    """
+    C = ne * (3 if dim == 2 else 6)
+    Ch = C * 2 * s * (n_last // 2 + 1) / n_last
+    other = dim - 1
+    per = 4 * C * s + 2 * s + (C * s + Ch) + other * 2 * Ch + 2 * Ch + other * 2 * Ch + (Ch + C * s) \
+        + 2 * C * s + 6 * C * s
+    return per * n_voxels
+
+
+def strain_space_measure(log):
+    """Strain-space projected CG with each discrete derivative (one-point
+    Fourier, central, forward, least squares, two-point Fourier and linear FE)
+    on the 2D Eshelby-inhomogeneity setup refined to 1661^2 voxels (soft disc
+    of radius 166.1, stiffness ratio 10, biaxial 1 % strain; 11 x 151 points
+    per axis: radix-11 and direct 151-point passes), FP64, tol 1e-8; and the
+    FE kind in 3D on the 128^3 sphere packing (6 load cases, FP32, tol 1e-5).
+    Each case is solved twice; the second solve is timed."""
+    import torch
+    import microstructures as ms
+    import paper_2105_03297_amd as feh
+    res = {}
+    cases = [("eshelby1661", k, "fp64", 1e-8) for k in ("fe", "fd", "cd", "ls", "fourier", "fourier2")]
+    cases.append(("spheres128", "fe", "fp32", 1e-5))
+    hz = None
+    for wl, kind, prec, tol in cases:
+        m, Eb, _, _ = ms.workload(wl)
+        lam = m.E * m.nu / ((1 + m.nu) * (1 - 2 * m.nu))
+        mu = m.E / (2 * (1 + m.nu))
+        if hz is None or hz.shape != m.shape or hz.precision != prec or hz.n_load != len(Eb):
+            if hz is not None:
+                hz.close()
+            hz = feh.Homogenizer(m.shape, n_load=len(Eb), precision=prec)
+            hz.set_material(lam=lam, mu=mu)
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = hz.strain_cg_solve(Eb, kind=kind, tol=tol, max_iter=5000)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+        its = [r["iterations"] for r in out["report"]]
+        dim = m.E.ndim
+        s = 8 if prec == "fp64" else 4
+        ne = feh.feh_strain_cg_points(feh.DERIV_KINDS[kind], dim)
+        b_it = strain_bytes_per_iteration(dim, ne, s, m.shape[-1], m.E.size)
+        ms_it = 1e3 * t / max(1, max(its))
+        key = f"{wl}_{kind}"
+        res[key] = {"grid": list(m.shape), "precision": prec, "tol": tol, "load_cases": len(Eb),
+                    "iterations": its, "s_solve": round(t, 4), "ms_per_iteration": round(ms_it, 4),
+                    "GBps_algorithmic": round(b_it * sum(its) / max(1, max(its)) / (ms_it / 1e3) / 1e9, 1),
+                    "stress_mean": np.round(out["stress_mean"][0], 10).tolist()}
+        log("strain space", key, res[key])
+    hz.close()
+    return res
+
+
 def cpu_baseline(n=40, iters=6000):
     """Oracle timing on the host: the same random-field recipe on an n^3 grid
     (correlation length scaled to the same fraction of the cell), one load
@@ -180,6 +246,9 @@ def main():
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the FFT schedule before timing (not timed)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch measurement")
+    ap.add_argument("--no-strain-space", action="store_true", help="skip the strain-space solver measurement")
+    ap.add_argument("--strain-space-only", action="store_true",
+                    help="run only the strain-space measurement and print it as the JSON line")
     ap.add_argument("--copy-ref", action="store_true",
                     help="after the steps, copy a 1 GiB buffer once (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -194,6 +263,9 @@ def main():
     import paper_2105_03297_amd as feh
 
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
+    if args.strain_space_only:
+        print(json.dumps({"strain_space": strain_space_measure(log)}), flush=True)
+        return
     m, Ebars, tol, precname = ms.workload(args.workload)
     shape = m.shape
     dim = len(shape)
@@ -308,6 +380,10 @@ def main():
         del h64
         torch.cuda.empty_cache()
 
+    strain = None
+    if not args.no_strain_space:
+        strain = strain_space_measure(log)
+
     uneven = None
     if not args.no_uneven:
         uneven = uneven_batch_measure(log)
@@ -344,6 +420,7 @@ def main():
         "sensitivity": sens,
         "fft_schedule": tuning,
         "uneven_batch": uneven,
+        "strain_space": strain,
         "cpu_baseline": cpu,
         "C_eff": np.round(C32, 8).tolist() if C32 is not None else None,
     }
