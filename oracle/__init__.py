@@ -15,4 +15,6 @@ Modules
   cg          ctypes wrapper of the plain C CSR conjugate-gradient solver
   adjoint     sensitivities of the effective stiffness to the per-voxel
               Lame constants (energy form, no second solve)
+  finite      finite strain: Saint Venant-Kirchhoff law, gradient projection,
+              Newton + projected CG, and the canonical nonlinear FE solve
 """
