@@ -304,6 +304,48 @@ int feh_strain_cg_solve(feh_plan *plan, int kind, const double *Ebar_host, doubl
                         void *work_dev, size_t work_bytes, void *strain_dev, double *stress_mean_host,
                         double *energy_host, feh_report *report_host);
 
+/* Per load case outcome of feh_finite_strain_solve. */
+typedef struct {
+    int32_t newton_iterations;  /* Newton steps over all load steps                 */
+    int32_t cg_iterations;      /* CG iterations summed over the Newton steps        */
+    int32_t status;             /* FEH_OK or FEH_ENOCONV (max_newton in a load step) */
+    int32_t pad;
+    double rel_equilibrium;     /* ||G P(F)|| / ||P(F)|| at the last check            */
+    double rel_increment;       /* ||dF|| / ||F|| of the last Newton step             */
+} feh_finite_report;
+
+/* Device workspace bytes of feh_finite_strain_solve: five deformation-gradient
+ * fields (F, dF and the CG vectors r, p, q; n_load * n_e * D^2 * N reals each),
+ * their half spectrum, CG scalars and partial sums. */
+int feh_finite_strain_workspace_bytes(const feh_plan *plan, int kind, size_t *bytes);
+
+/* Finite-strain homogenization (Sec. "Compatibility projection"): find the
+ * deformation gradient F = Fbar + F~ (F~ compatible, zero mean; n_e points
+ * per voxel for the derivative `kind`, see FEH_DERIV_*) with G P(F) = 0,
+ * where G is the gradient projection built from the kind's symbol (Eq.
+ * original-G / discrete_projection_op) and P the first Piola-Kirchhoff stress
+ * of the isotropic finite-strain linear elastic (Saint Venant-Kirchhoff) law
+ * with the plan's per-voxel Lame constants, P = F (lambda tr(E) I + 2 mu E),
+ * E = (F^T F - I) / 2; lambda = mu = 0 (vacuum) is allowed.
+ * Newton: each step solves G (dP/dF : dF) = -G P(F) by CG from dF = 0 (the
+ * right-hand side projected twice), F += dF.  A load case stops when
+ * ||G P|| <= equil_tol ||P|| before a step or ||dF|| <= newton_tol ||F||
+ * after one (Frobenius norms over the field).  Fbar moves linearly from I in
+ * n_steps load steps, each starting from the previous solution plus the
+ * uniform increment.  Plans of one microstructure (FEH_EINVAL otherwise).
+ *   Fbar_host       [n_load][D][D], det > 0 (F_{i a} = d chi_i / d r_a)
+ *   max_newton      Newton steps per load step; max_cg CG iterations per step
+ *   work_dev        caller-owned, 256-byte aligned, >= the workspace bytes
+ *   F_dev, P_dev    nullable outputs [n_load][N][n_e][D][D], plan precision
+ *   P_mean_host     nullable [n_load][D][D], average of P over the points
+ *   report_host     nullable [n_load]
+ * Returns FEH_OK, or FEH_ENOCONV if a load case did not converge (outputs
+ * filled from the last iterate). */
+int feh_finite_strain_solve(feh_plan *plan, int kind, const double *Fbar_host, int n_steps, double newton_tol,
+                            double equil_tol, double cg_tol, int max_newton, int max_cg, void *work_dev,
+                            size_t work_bytes, void *F_dev, void *P_dev, double *P_mean_host,
+                            feh_finite_report *report_host);
+
 /* Test export: q = K p with K = sum_e |e| B_e^T C_e B_e, p and q
  * [n_load][N][D] in the plan precision. */
 int feh_apply_operator(feh_plan *plan, const void *p_dev, void *q_dev);

@@ -88,6 +88,31 @@ def eshelby(n=151, frac=0.1, E_hard=1.0, contrast=10.0, nu=0.33):
     return m
 
 
+def single_voxel(n=17, E_hard=1.0, contrast=10.0, nu=0.33):
+    """One soft voxel (phase 1, E_hard / contrast) at the centre of an odd n x n
+    hard matrix (phase 0), equal Poisson ratios (the paper's single-voxel
+    inhomogeneity, 17 x 17)."""
+    ph = np.zeros((n, n), dtype=np.int32)
+    ph[n // 2, n // 2] = 1
+    return from_phases(ph, [(E_hard, nu), (E_hard / contrast, nu)],
+                       f"single voxel n={n} contrast={contrast} nu={nu}")
+
+
+def two_pillars(n=17, left=7, E_hard=1.0, contrast=10.0, nu=0.33):
+    """Two pillars along y separated in x by zero-stiffness columns (phase 2,
+    E = 0): x-columns [vacuum][left pillar: `left` columns][vacuum][right
+    pillar: the rest]; the left pillar holds a soft line of three voxels
+    (phase 1, E_hard / contrast) along y at its centre (the paper's two-pillar
+    setup on 17 x 17: pillars of 7 and 8 columns)."""
+    ph = np.zeros((n, n), dtype=np.int32)
+    ph[0, :] = 2
+    ph[1 + left, :] = 2
+    cx = 1 + left // 2
+    ph[cx, n // 2 - 1:n // 2 + 2] = 1
+    return from_phases(ph, [(E_hard, nu), (E_hard / contrast, nu), (0.0, nu)],
+                       f"two pillars n={n} left={left} contrast={contrast} nu={nu} vacuum columns 0 and {1 + left}")
+
+
 def sphere(n=16, radius=4.0, E=(1.0, 10.0), nu=(0.3, 0.3)):
     X, Y, Z = _centres((n, n, n))
     c = n / 2.0

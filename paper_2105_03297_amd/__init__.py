@@ -28,6 +28,7 @@ __all__ = [
     "feh_plan_autotune", "feh_plan_tuning",
     "FEH_DERIV_FE", "FEH_DERIV_FD", "FEH_DERIV_CD", "FEH_DERIV_LS", "FEH_DERIV_FOURIER", "FEH_DERIV_FOURIER2",
     "DERIV_KINDS", "feh_strain_cg_points", "feh_strain_cg_workspace_bytes", "feh_strain_cg_solve",
+    "feh_finite_report", "feh_finite_strain_workspace_bytes", "feh_finite_strain_solve",
     "feh_last_error", "feh_version", "Homogenizer", "UnevenBatch",
 ]
 
@@ -50,6 +51,12 @@ class FehError(RuntimeError):
 
 class feh_report(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32), ("rel_residual", ctypes.c_double)]
+
+
+class feh_finite_report(ctypes.Structure):
+    _fields_ = [("newton_iterations", ctypes.c_int32), ("cg_iterations", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("rel_equilibrium", ctypes.c_double), ("rel_increment", ctypes.c_double)]
 
 
 _lib = None
@@ -90,6 +97,10 @@ _SIGS = {
     "feh_strain_cg_workspace_bytes": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "feh_strain_cg_solve": (ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_int, _vp,
                                            ctypes.c_size_t, _vp, _dp, _dp, ctypes.POINTER(feh_report)]),
+    "feh_finite_strain_workspace_bytes": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "feh_finite_strain_solve": (ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t,
+                                               _vp, _vp, _dp, ctypes.POINTER(feh_finite_report)]),
     "feh_last_error": (ctypes.c_char_p, []),
     "feh_version": (ctypes.c_int, []),
 }
@@ -227,6 +238,28 @@ def feh_strain_cg_solve(plan, kind, Ebar, tol, max_iter, work_ptr, work_bytes, s
                                     smean.ctypes.data_as(_dp), W.ctypes.data_as(_dp), rep)
     _check(rc, allow=(FEH_ENOCONV,) if allow_noconv else ())
     return rc, smean, W, [dict(iterations=r.iterations, status=r.status, rel_residual=r.rel_residual) for r in rep]
+
+
+def feh_finite_strain_workspace_bytes(plan, kind):
+    n = ctypes.c_size_t(0)
+    _check(load().feh_finite_strain_workspace_bytes(plan, int(kind), ctypes.byref(n)))
+    return n.value
+
+
+def feh_finite_strain_solve(plan, kind, Fbar, n_steps, newton_tol, equil_tol, cg_tol, max_newton, max_cg,
+                            work_ptr, work_bytes, F_ptr=0, P_ptr=0, allow_noconv=True):
+    """Returns (status, P_mean[L,D,D], reports)."""
+    Fb, Fbp = _f64(Fbar)
+    L, D = Fb.shape[0], Fb.shape[1]
+    pm = np.zeros((L, D, D))
+    rep = (feh_finite_report * L)()
+    rc = load().feh_finite_strain_solve(plan, int(kind), Fbp, int(n_steps), float(newton_tol), float(equil_tol),
+                                        float(cg_tol), int(max_newton), int(max_cg), _vp(work_ptr),
+                                        ctypes.c_size_t(int(work_bytes)), _vp(F_ptr or 0), _vp(P_ptr or 0),
+                                        pm.ctypes.data_as(_dp), rep)
+    _check(rc, allow=(FEH_ENOCONV,) if allow_noconv else ())
+    return rc, pm, [dict(newton_iterations=r.newton_iterations, cg_iterations=r.cg_iterations, status=r.status,
+                         rel_equilibrium=r.rel_equilibrium, rel_increment=r.rel_increment) for r in rep]
 
 
 def feh_effective_stiffness(dim, Ebar, W):
@@ -451,6 +484,28 @@ class Homogenizer:
             except FehError:
                 pass
         return out
+
+    def finite_strain_solve(self, Fbar, kind="fe", n_steps=1, newton_tol=1e-10, equil_tol=1e-11, cg_tol=1e-10,
+                            max_newton=50, max_cg=5000, fields=False):
+        """Finite-strain (Saint Venant-Kirchhoff) Newton + projected CG with the
+        derivative `kind`; the plan's Lame constants.  Returns a dict with
+        status, P_mean [L, D, D], report and, when fields, F and P
+        [L, N, n_e, D, D]."""
+        torch = self.torch
+        k = DERIV_KINDS[kind] if isinstance(kind, str) else int(kind)
+        Fbar = np.asarray(Fbar, dtype=np.float64).reshape(self.n_load, self.dim, self.dim)
+        L, D, N = self.n_load, self.dim, self.N
+        ne = feh_strain_cg_points(k, D)
+        nbytes = feh_finite_strain_workspace_bytes(self.plan, k)
+        work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        F = P = None
+        if fields:
+            F = torch.empty((L, N, ne, D, D), dtype=self.dtype, device=self.device)
+            P = torch.empty_like(F)
+        rc, pm, rep = feh_finite_strain_solve(self.plan, k, Fbar, n_steps, newton_tol, equil_tol, cg_tol, max_newton,
+                                              max_cg, work.data_ptr(), nbytes,
+                                              F.data_ptr() if F is not None else 0, P.data_ptr() if P is not None else 0)
+        return dict(status=rc, P_mean=pm, report=rep, F=F, P=P)
 
     def autotune(self, reps=3):
         """Pick the FFT radix orders and launch geometry by timing (see feh_plan_autotune)."""

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfeh.so")
-SOURCES = ["capi.hip", "kern_stencil.hip", "kern_fft.hip", "kern_cg.hip", "kern_post.hip", "spectral.hip"]
+SOURCES = ["capi.hip", "kern_stencil.hip", "kern_fft.hip", "kern_cg.hip", "kern_post.hip", "spectral.hip", "finite.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1,0 +1,165 @@
+"""Finite-strain Newton + projected CG on the GPU against the oracle
+(Sec. "Compatibility projection"; Saint Venant-Kirchhoff law; gradient
+projection of each derivative kind), field by field, on random materials and
+on the paper's two finite-strain setups: the 17 x 17 single soft voxel at 10 %
+biaxial stretch and the 17 x 17 two pillars separated by vacuum at 10 %
+stretch along y.  Both sides use the same Newton stopping rule; the fields
+agree to the Newton tolerance (bound 1e-8 of max |F|), and the paper's
+qualitative statements (symmetry lines, decoupling through the vacuum) hold
+on the GPU fields."""
+import numpy as np
+import pytest
+
+import microstructures as ms
+from gpu_util import random_material, rel, say
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["fe", "fd", "cd", "ls", "fourier", "fourier2"]
+
+
+def _gpu(shape, lam, mu, Fbar, kind, prec="fp64", **kw):
+    import torch
+    from paper_2105_03297_amd import Homogenizer
+    hz = Homogenizer(shape, n_load=len(Fbar), precision=prec)
+    hz.set_material(lam=lam, mu=mu)
+    out = hz.finite_strain_solve(Fbar, kind=kind, fields=True, **kw)
+    torch.cuda.synchronize()
+    F = out["F"].cpu().numpy().astype(np.float64)
+    P = out["P"].cpu().numpy().astype(np.float64)
+    hz.close()
+    return out, F, P
+
+
+def _oracle(lam, mu, Fbar, kind, **kw):
+    from oracle import finite
+    Fs, its = [], []
+    for Fb in Fbar:
+        F, nit, cit = finite.solve(lam, mu, Fb, kind, **kw)
+        Fs.append(F.reshape((-1,) + F.shape[-3:]))
+        its.append(nit)
+    return np.array(Fs), its
+
+
+CASES = [("fe", (8, 6)), ("fd", (8, 6)), ("cd", (9, 7)), ("ls", (9, 7)), ("fourier", (9, 7)), ("fourier2", (7, 9)),
+         ("fe", (4, 3, 5)), ("fd", (5, 4, 3)), ("fourier", (5, 3, 5))]
+
+
+@pytest.mark.parametrize("kind,shape", CASES)
+def test_finite_strain_matches_oracle(kind, shape):
+    from oracle import finite
+    say("finite strain", kind, shape)
+    dim = len(shape)
+    lam, mu = random_material(shape, seed=23, emin=1.0, emax=5.0)
+    rng = np.random.default_rng(2)
+    Fbar = np.array([np.eye(dim) + 0.06 * rng.standard_normal((dim, dim)) for _ in range(2)])
+    out, F, P = _gpu(shape, lam, mu, Fbar, kind, newton_tol=1e-12, equil_tol=1e-12, cg_tol=1e-10)
+    ref, its = _oracle(lam, mu, Fbar, kind, newton_tol=1e-12, equil_tol=1e-12, cg_tol=1e-10)
+    assert F.shape == ref.shape
+    np.testing.assert_allclose(F, ref, rtol=0, atol=1e-9)
+    for l in range(2):
+        assert out["report"][l]["status"] == 0
+        assert abs(out["report"][l]["newton_iterations"] - its[l]) <= 1
+        Pr = finite.pk1(lam.reshape(-1), mu.reshape(-1), ref[l])
+        np.testing.assert_allclose(P[l], Pr, rtol=0, atol=1e-9 * np.abs(Pr).max())
+        np.testing.assert_allclose(out["P_mean"][l], Pr.mean(axis=(0, 1)), rtol=0, atol=1e-10)
+        np.testing.assert_allclose(F[l].mean(axis=(0, 1)), Fbar[l], atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_single_voxel_inhomogeneity(kind):
+    """The paper's 17 x 17 single soft voxel at F = diag(1.1, 1.1)."""
+    from oracle import fe, finite
+    say("single voxel", kind)
+    m = ms.single_voxel()
+    lam, mu = fe.lame(m.E, m.nu)
+    Fbar = np.diag([1.1, 1.1])[None]
+    out, F, P = _gpu(m.shape, lam, mu, Fbar, kind)
+    ref, its = _oracle(lam, mu, Fbar, kind)
+    np.testing.assert_allclose(F[0], ref[0], rtol=0, atol=1e-8)
+    Pg = P[0].reshape(17, 17, -1, 2, 2)
+    line = max(np.abs(Pg[8, :, :, 0, 1]).max(), np.abs(Pg[:, 8, :, 0, 1]).max())
+    if kind in ("cd", "ls", "fourier"):
+        assert line < 1e-12
+    else:
+        assert line > 1e-3
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_two_pillars_with_vacuum(kind):
+    """The paper's 17 x 17 two pillars with vacuum columns (E = 0) at
+    F = diag(1, 1.1); decoupling for FE, FD and LS."""
+    from oracle import fe
+    say("two pillars", kind)
+    m = ms.two_pillars()
+    lam, mu = fe.lame(m.E, m.nu)
+    Fbar = np.diag([1.0, 1.1])[None]
+    out, F, P = _gpu(m.shape, lam, mu, Fbar, kind, equil_tol=1e-8)
+    ref, its = _oracle(lam, mu, Fbar, kind, equil_tol=1e-8)
+    assert out["report"][0]["status"] == 0
+    # the vacuum's own deformation is not unique (fields living only in the
+    # vacuum cost no energy; least squares has such checkerboard fields), so
+    # F is compared on the pillars and P everywhere
+    solid = (m.phase != 2).ravel()
+    np.testing.assert_allclose(F[0][solid], ref[0][solid], rtol=0, atol=1e-6)
+    from oracle import finite
+    Pr = finite.pk1(lam.reshape(-1), mu.reshape(-1), ref[0])
+    np.testing.assert_allclose(P[0], Pr, rtol=0, atol=1e-6)
+    Pg = P[0].reshape(17, 17, -1, 2, 2)
+    assert np.abs(Pg[0]).max() == 0.0 and np.abs(Pg[8]).max() == 0.0
+    right = np.abs(Pg[9:, :, :, 0, 1]).max()
+    if kind in ("fe", "fd", "ls"):
+        assert right < 1e-8
+    else:
+        assert right > 1e-4
+
+
+def test_load_steps_and_fp32():
+    """Four load steps reach the one-step solution; FP32 fields against the
+    FP64 solve; objectivity F(R Fbar) = R F(Fbar) on the GPU."""
+    say("finite strain steps / fp32 / objectivity")
+    shape = (16, 12)
+    lam, mu = random_material(shape, seed=31, emin=1.0, emax=5.0)
+    Fbar = np.diag([1.1, 1.05])[None]
+    o1, F1, _ = _gpu(shape, lam, mu, Fbar, "fe", newton_tol=1e-12, equil_tol=1e-12)
+    o4, F4, _ = _gpu(shape, lam, mu, Fbar, "fe", n_steps=4, newton_tol=1e-12, equil_tol=1e-12)
+    np.testing.assert_allclose(F4, F1, atol=1e-10)
+    assert o4["report"][0]["newton_iterations"] > o1["report"][0]["newton_iterations"]
+    lam32, mu32 = random_material(shape, seed=31, prec="fp32", emin=1.0, emax=5.0)
+    o64, F64, _ = _gpu(shape, lam32, mu32, Fbar, "fe", newton_tol=1e-12, equil_tol=1e-12)
+    o32, F32, _ = _gpu(shape, lam32, mu32, Fbar, "fe", prec="fp32", newton_tol=1e-6, equil_tol=1e-6, cg_tol=1e-6)
+    assert np.abs(F32 - F64).max() < 2e-5
+    assert rel(o32["P_mean"], o64["P_mean"]) < 1e-5
+    t = 0.6
+    R = np.array([[np.cos(t), -np.sin(t)], [np.sin(t), np.cos(t)]])
+    oR, FR, _ = _gpu(shape, lam, mu, (R @ Fbar[0])[None], "fe", newton_tol=1e-12, equil_tol=1e-12)
+    np.testing.assert_allclose(FR[0], R @ F1[0], atol=1e-9)
+
+
+def test_finite_strain_errors_and_uniform():
+    import torch
+    import paper_2105_03297_amd as m
+    from paper_2105_03297_amd import Homogenizer
+    say("finite strain errors / uniform")
+    shape = (10, 8)
+    hz = Homogenizer(shape, n_load=1, precision="fp64")
+    hz.set_material(lam=np.full(shape, 1.5), mu=np.full(shape, 0.8))
+    Fb = np.array([[[1.08, 0.03], [-0.02, 0.97]]])
+    out = hz.finite_strain_solve(Fb, kind="fd", fields=True)
+    F = out["F"].cpu().numpy()
+    np.testing.assert_allclose(F, np.broadcast_to(Fb[:, None, None], F.shape), atol=1e-14)
+    assert out["report"][0]["newton_iterations"] == 0
+    with pytest.raises(m.FehError) as ei:
+        hz.finite_strain_solve(np.array([[[-1.0, 0.0], [0.0, 1.0]]]), kind="fe")
+    assert ei.value.status == m.FEH_EINVAL
+    nbytes = m.feh_finite_strain_workspace_bytes(hz.plan, m.FEH_DERIV_FE)
+    work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    with pytest.raises(m.FehError) as ei:
+        m.feh_finite_strain_solve(hz.plan, m.FEH_DERIV_FE, Fb, 1, 1e-10, 1e-10, 1e-10, 10, 100, work.data_ptr(),
+                                  nbytes - 256)
+    assert ei.value.status == m.FEH_ENOMEM
+    lam, mu = random_material(shape, seed=5)
+    hz.set_material(lam=lam, mu=mu)
+    out = hz.finite_strain_solve(Fb, kind="fe", max_newton=1, equil_tol=1e-14, newton_tol=1e-14)
+    assert out["status"] == m.FEH_ENOCONV and out["report"][0]["newton_iterations"] == 1
+    hz.close()

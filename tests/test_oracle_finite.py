@@ -202,3 +202,48 @@ def test_load_steps_reach_the_same_solution():
     F1, _, _ = finite.solve(lam, mu, Fbar, "fe", n_steps=1, newton_tol=1e-12, equil_tol=1e-13, cg_tol=1e-10)
     F4, _, _ = finite.solve(lam, mu, Fbar, "fe", n_steps=4, newton_tol=1e-12, equil_tol=1e-13, cg_tol=1e-10)
     np.testing.assert_allclose(F4, F1, atol=1e-11)
+
+
+# ---------------------------------------------------------------------------
+# the paper's finite-strain examples (Sec. "Single voxel inhomogeneity",
+# Sec. "Two pillars and vacuum"): the qualitative statements it makes
+# ---------------------------------------------------------------------------
+def test_single_voxel_symmetry_lines():
+    """17 x 17, soft centre voxel (E/10, nu = 0.33), 10 % biaxial stretch: the
+    one-point symmetric stencils (Fourier, central differences, least squares)
+    give P_xy = 0 on the row and column through the inhomogeneity; forward
+    differences (asymmetric stencil), the two-point Fourier derivative and FE
+    (two evaluation points per voxel) do not."""
+    m = ms.single_voxel()
+    lam, mu = fe.lame(m.E, m.nu)
+    Fbar = np.diag([1.1, 1.1])
+    for kind in ("fe", "fd", "cd", "ls", "fourier", "fourier2"):
+        F, _, _ = finite.solve(lam, mu, Fbar, kind)
+        P = finite.pk1(lam, mu, F)
+        line = max(np.abs(P[8, :, :, 0, 1]).max(), np.abs(P[:, 8, :, 0, 1]).max())
+        if kind in ("cd", "ls", "fourier"):
+            assert line < 1e-14, (kind, line)
+        else:
+            assert line > 1e-3, (kind, line)
+
+
+def test_two_pillars_decoupling():
+    """17 x 17: vacuum columns (E = 0) at x = 0 and x = 8, a 7-column pillar
+    with a soft 3-voxel line and an 8-column pillar, 10 % stretch along y at
+    fixed width: forward differences, least squares and FE decouple the
+    pillars through the vacuum (no shear stress in the right pillar); the
+    Fourier derivatives and central differences (stencils reaching across the
+    vacuum column) do not.  The vacuum carries no stress."""
+    m = ms.two_pillars()
+    lam, mu = fe.lame(m.E, m.nu)
+    Fbar = np.diag([1.0, 1.1])
+    for kind in ("fe", "fd", "cd", "ls", "fourier", "fourier2"):
+        F, _, _ = finite.solve(lam, mu, Fbar, kind, equil_tol=1e-8)
+        P = finite.pk1(lam, mu, F)
+        right = np.abs(P[9:, :, :, 0, 1]).max()
+        assert np.abs(P[0]).max() == 0.0 and np.abs(P[8]).max() == 0.0
+        assert np.abs(P[1:8, :, :, 0, 1]).max() > 1e-3
+        if kind in ("fe", "fd", "ls"):
+            assert right < 1e-9, (kind, right)
+        else:
+            assert right > 1e-4, (kind, right)
