@@ -205,6 +205,54 @@ def strain_space_measure(log):
     return res
 
 
+def finite_bytes_per_cg_iteration(dim, ne, s, n_last, n_voxels):
+    """Algorithmic HBM bytes of one CG iteration of a finite-strain Newton step
+    (one load case).  Per voxel, with C = n_e D^2 components of s bytes and
+    Ch = C 2 s (n_last/2+1)/n_last bytes of half spectrum: tangent (read F, r,
+    p; write p, q) 5 C s + 2 s; FFT forward C s + Ch + 2 Ch per further axis;
+    projection 2 Ch; FFT inverse 2 Ch per non-last axis + Ch + C s; p.q 2 C s;
+    update 6 C s."""
+    C = ne * dim * dim
+    Ch = C * 2 * s * (n_last // 2 + 1) / n_last
+    other = dim - 1
+    per = 5 * C * s + 2 * s + (C * s + Ch) + other * 2 * Ch + 2 * Ch + other * 2 * Ch + (Ch + C * s) \
+        + 2 * C * s + 6 * C * s
+    return per * n_voxels
+
+
+def finite_strain_measure(log):
+    """Finite-strain Newton + projected CG (FE kind, Saint Venant-Kirchhoff) on
+    the 128^3 sphere packing (20 % spheres, stiffness ratio 10, nu = 0.3),
+    Fbar = diag(1.05, 0.98, 0.98), one load step, FP32 fields, tolerances 1e-6.
+    Solved twice; the second solve is timed."""
+    import torch
+    import microstructures as ms
+    import paper_2105_03297_amd as feh
+    m, _, _, _ = ms.workload("spheres128")
+    lam = m.E * m.nu / ((1 + m.nu) * (1 - 2 * m.nu))
+    mu = m.E / (2 * (1 + m.nu))
+    hz = feh.Homogenizer(m.shape, n_load=1, precision="fp32")
+    hz.set_material(lam=lam, mu=mu)
+    Fbar = np.diag([1.05, 0.98, 0.98])[None]
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = hz.finite_strain_solve(Fbar, kind="fe", newton_tol=1e-6, equil_tol=1e-6, cg_tol=1e-6)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+    hz.close()
+    r = out["report"][0]
+    b_it = finite_bytes_per_cg_iteration(3, 6, 4, m.shape[-1], m.E.size)
+    res = {"grid": list(m.shape), "precision": "fp32", "kind": "fe", "Fbar": Fbar[0].tolist(),
+           "newton_iterations": r["newton_iterations"], "cg_iterations": r["cg_iterations"],
+           "rel_equilibrium": r["rel_equilibrium"], "s_solve": round(t, 4),
+           "ms_per_cg_iteration": round(1e3 * t / max(1, r["cg_iterations"]), 4),
+           "GBps_algorithmic": round(b_it * r["cg_iterations"] / t / 1e9, 1),
+           "P_mean": np.round(out["P_mean"][0], 8).tolist()}
+    log("finite strain", res)
+    return res
+
+
 def cpu_baseline(n=40, iters=6000):
     """Oracle timing on the host: the same random-field recipe on an n^3 grid
     (correlation length scaled to the same fraction of the cell), one load
@@ -247,8 +295,9 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="tune the FFT schedule before timing (not timed)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch measurement")
     ap.add_argument("--no-strain-space", action="store_true", help="skip the strain-space solver measurement")
+    ap.add_argument("--no-finite-strain", action="store_true", help="skip the finite-strain measurement")
     ap.add_argument("--strain-space-only", action="store_true",
-                    help="run only the strain-space measurement and print it as the JSON line")
+                    help="run only the strain-space and finite-strain measurements and print them as the JSON line")
     ap.add_argument("--copy-ref", action="store_true",
                     help="after the steps, copy a 1 GiB buffer once (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -264,7 +313,8 @@ def main():
 
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
     if args.strain_space_only:
-        print(json.dumps({"strain_space": strain_space_measure(log)}), flush=True)
+        print(json.dumps({"strain_space": strain_space_measure(log),
+                          "finite_strain": finite_strain_measure(log)}), flush=True)
         return
     m, Ebars, tol, precname = ms.workload(args.workload)
     shape = m.shape
@@ -384,6 +434,10 @@ def main():
     if not args.no_strain_space:
         strain = strain_space_measure(log)
 
+    finite = None
+    if not args.no_finite_strain:
+        finite = finite_strain_measure(log)
+
     uneven = None
     if not args.no_uneven:
         uneven = uneven_batch_measure(log)
@@ -421,6 +475,7 @@ def main():
         "fft_schedule": tuning,
         "uneven_batch": uneven,
         "strain_space": strain,
+        "finite_strain": finite,
         "cpu_baseline": cpu,
         "C_eff": np.round(C32, 8).tolist() if C32 is not None else None,
     }
