@@ -90,9 +90,9 @@ def uneven_batch_measure(log):
     (laminates and circular inclusions, contrast log-uniform in [2, 1000]),
     3 load cases each, FP32 fields / FP64 scalars, tol 1e-5.  Timed three
     ways (second run of each): all maps in batched plans with CG chunks
-    replayed as captured HIP graphs; the same with eager launches; and one
-    plan per map solved one after the other.  The C_eff of the three agree
-    (asserted to 1e-6)."""
+    replayed as captured HIP graphs; the same with eager launches (fastest of
+    three runs each, alternating); and one plan per map solved one after the
+    other.  The C_eff of the three agree (asserted to 1e-6)."""
     import torch
     import microstructures as ms
     import paper_2105_03297_amd as feh
@@ -102,13 +102,16 @@ def uneven_batch_measure(log):
     Eb = ms.unit_loads(2)
     ub = feh.UnevenBatch(lm, precision="fp32")
     res = {}
-    for mode in ("graph", "eager"):
-        for rep in range(2):
+    # alternate the two modes and keep each one's fastest of three timed runs
+    # (after one untimed run each, which also captures the graphs)
+    for rep in range(4):
+        for mode in ("graph", "eager"):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             out = ub.solve(Eb, tol=1e-5, max_iter=5000, use_graph=(mode == "graph"))
             t = time.perf_counter() - t0
-        res[mode] = (t, out, ub.graph_launches())
+            if rep > 0 and (mode not in res or t < res[mode][0]):
+                res[mode] = (t, out, ub.graph_launches())
     ub.close()
     # one plan per map, one after the other
     t_seq = 0.0

@@ -162,7 +162,11 @@ int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
  * candidate radix orders of each axis (the orders of the default
  * factorisation and of the radix-4 one) and then fewer rows / pencils per
  * workgroup (1/2, 1/4 of the default) for the last, middle and first axis
- * passes, each over `reps` runs (< 1: 3), and keeps the fastest.  The
+ * passes and the two workgroup layouts of the first-axis pass (every load
+ * case in one workgroup with the per-wavevector inverses kept in registers,
+ * or one workgroup per load case forming them again) and, in 3D, the two
+ * stencil tile heights (8 or 16 rows of 32 voxels), each over `reps` runs
+ * (< 1: 3), and keeps the fastest.  The
  * transforms stay exact to rounding whatever is chosen; repeated solves on
  * one plan stay bitwise reproducible, two tunings may differ in rounding.
  * Overwrites the workspace vectors (set the material again only if the
@@ -170,11 +174,24 @@ int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
 int feh_plan_autotune(feh_plan *plan, int reps);
 
 /* The plan's FFT schedule: values = [rows per workgroup (last axis),
- * pencils per workgroup (axis 1), pencils per workgroup (axis 0)] (0 =
- * default heuristic), then for each axis 0..2 the number of passes followed
- * by the radices in pass order.  Writes at most n_values entries and
- * returns the full length. */
+ * pencils per workgroup (axis 1), pencils per workgroup (axis 0) (0 =
+ * default heuristic), axis-0 workgroup layout (1: one workgroup per load
+ * case, 0: every load case in one workgroup), stencil tile rows (3D: 8 or
+ * 16 rows of 32 voxels; 2D: 1)], then for each axis 0..2 the
+ * number of passes followed by the radices in pass order.  Writes at most
+ * n_values entries and returns the full length. */
 int feh_plan_tuning(const feh_plan *plan, int *values, int n_values);
+
+/* Set the FFT schedule and stencil tile explicitly (e.g. one saved from
+ * feh_plan_tuning): the same layout, workgroup sizes >= 0 (0 = default; a
+ * value above the default is clamped to it; axis-0 pencils at least a
+ * quarter of the default, which sizes the partial sums), axis-0 layout 0 or 1,
+ * stencil rows 8 or 16 in 3D (1 in 2D), and per axis radices from
+ * {2, 3, 4, 5, 7, 8, 11, 13} or primes above 13 whose product is the
+ * transformed length (n_a, n_last/2 for an even last axis).
+ * FEH_EINVAL leaves the plan unchanged.  Any valid schedule is exact to
+ * rounding. */
+int feh_plan_set_tuning(feh_plan *plan, const int *values, int n_values);
 
 /* Uneven batches: plans of different grids (each possibly a batched plan)
  * that share one created HIP stream, solved together.  After each plan's

@@ -25,7 +25,7 @@ __all__ = [
     "feh_apply_operator", "feh_apply_preconditioner", "feh_apply_projection",
     "feh_fft_forward", "feh_fft_inverse", "feh_profile_enable", "feh_profile_read", "PROFILE_KINDS",
     "feh_batch_create", "feh_batch_destroy", "feh_batch_solve", "feh_batch_graph_launches",
-    "feh_plan_autotune", "feh_plan_tuning",
+    "feh_plan_autotune", "feh_plan_tuning", "feh_plan_set_tuning",
     "FEH_DERIV_FE", "FEH_DERIV_FD", "FEH_DERIV_CD", "FEH_DERIV_LS", "FEH_DERIV_FOURIER", "FEH_DERIV_FOURIER2",
     "DERIV_KINDS", "feh_strain_cg_points", "feh_strain_cg_workspace_bytes", "feh_strain_cg_solve",
     "feh_finite_report", "feh_finite_strain_workspace_bytes", "feh_finite_strain_solve",
@@ -93,6 +93,7 @@ _SIGS = {
     "feh_batch_graph_launches": (ctypes.c_int, [_vp]),
     "feh_plan_autotune": (ctypes.c_int, [_vp, ctypes.c_int]),
     "feh_plan_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
+    "feh_plan_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "feh_strain_cg_points": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "feh_strain_cg_workspace_bytes": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "feh_strain_cg_solve": (ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_int, _vp,
@@ -308,18 +309,30 @@ def feh_plan_autotune(plan, reps=3):
 
 
 def feh_plan_tuning(plan):
-    """{'rows_last': .., 'pencils_mid': .., 'pencils_first': .., 'radices': [[..] per axis]}"""
+    """{'rows_last', 'pencils_mid', 'pencils_first', 'first_per_load_case', 'radices': [[..] per axis]}"""
     buf = (ctypes.c_int * 64)()
     n = load().feh_plan_tuning(plan, buf, 64)
     if n < 0:
         raise FehError(n, feh_last_error())
     v = list(buf[:n])
-    rad, i = [], 3
+    rad, i = [], 5
     for _ in range(3):
         k = v[i]
         rad.append(v[i + 1:i + 1 + k])
         i += 1 + k
-    return {"rows_last": v[0], "pencils_mid": v[1], "pencils_first": v[2], "radices": rad}
+    return {"rows_last": v[0], "pencils_mid": v[1], "pencils_first": v[2], "first_per_load_case": v[3],
+            "stencil_rows": v[4], "radices": rad}
+
+
+def feh_plan_set_tuning(plan, tuning):
+    """Inverse of feh_plan_tuning: a dict with the same keys."""
+    v = [int(tuning.get("rows_last", 0)), int(tuning.get("pencils_mid", 0)), int(tuning.get("pencils_first", 0)),
+         int(tuning.get("first_per_load_case", 0)), int(tuning["stencil_rows"])]
+    for r in list(tuning["radices"]) + [[]] * (3 - len(tuning["radices"])):
+        v.append(len(r))
+        v.extend(int(x) for x in r)
+    buf = (ctypes.c_int * len(v))(*v)
+    return _check(load().feh_plan_set_tuning(plan, buf, len(v)))
 
 
 PROFILE_KINDS = ["stencil", "alpha", "fft_last_fwd", "fft_middle_fwd", "fft_first_ksolve", "fft_middle_inv",

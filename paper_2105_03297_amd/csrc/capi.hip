@@ -141,7 +141,15 @@ static void layout(feh_plan &p) {
     // the autotuner may go down to a quarter of the default first-axis pencils
     const long long inner0 = p.dim == 3 ? p.n[1] * p.nh : p.nh;
     const int pbmin = std::max(1, first_pencils_default(p) / 4);
-    const int sp = stencil_num_parts(p), fp = (int)((inner0 + pbmin - 1) / pbmin);
+    int sp = stencil_num_parts(p);
+    {
+        // the most partial sums any stencil tile shape produces
+        const int keep = p.tune_stencil_vy;
+        p.tune_stencil_vy = 8;
+        sp = std::max(sp, stencil_num_parts(p));
+        p.tune_stencil_vy = keep;
+    }
+    const int fp = (int)((inner0 + pbmin - 1) / pbmin);
     p.part_stride = (size_t)(sp > fp ? sp : fp);
     size_t parts = p.part_stride * p.L;
     const size_t post_parts = (size_t)post_num_slots(p) * post_num_parts(p);
@@ -997,6 +1005,38 @@ int feh_plan_autotune(feh_plan *plan, int reps) {
             const int pb = first_pencils_default(p);
             CK(tune_axis(0, (int)p.n[0], [&]() -> int { return launch_first_fused(p, fa); }, &p.tune_pb_first, pb,
                          std::max(1, pb / 4)));
+            // workgroup layout of the axis-0 pass: all load cases per workgroup
+            // (inverses cached in registers) or one workgroup per load case
+            double best = 1e30;
+            int keep = 0;
+            for (int v : {-1, 1}) {
+                p.tune_first_perlc = v;
+                double ms = 0;
+                CK(time_runs(p, [&]() -> int { return launch_first_fused(p, fa); }, reps, ms));
+                if (ms < best) {
+                    best = ms;
+                    keep = v;
+                }
+            }
+            p.tune_first_perlc = keep;
+        }
+        if (D == 3) {
+            // stencil tile rows (8 or 16 rows of 32 voxels)
+            StencilArgs sa;
+            sa.in0 = p.ws + p.off_r;
+            sa.out0 = p.ws + p.off_q;
+            double best = 1e30;
+            int keep = 8;
+            for (int vy : {8, 16}) {
+                p.tune_stencil_vy = vy;
+                double ms = 0;
+                CK(time_runs(p, [&]() -> int { return launch_stencil(p, ST_APPLY, sa); }, reps, ms));
+                if (ms < best) {
+                    best = ms;
+                    keep = vy;
+                }
+            }
+            p.tune_stencil_vy = keep;
         }
         return hip_check(hipStreamSynchronize(p.stream), "autotune");
     } catch (const std::bad_alloc &) {
@@ -1006,9 +1046,59 @@ int feh_plan_autotune(feh_plan *plan, int reps) {
     }
 }
 
+int feh_plan_set_tuning(feh_plan *plan, const int *values, int n_values) {
+    try {
+        if (!plan || !values) return set_error(FEH_EINVAL, "null argument");
+        feh_plan &p = *plan;
+        if (n_values < 5) return set_error(FEH_EINVAL, "schedule too short");
+        const int rr = values[0], pbm = values[1], pbf = values[2], perlc = values[3], rows = values[4];
+        if (rr < 0 || pbm < 0 || pbf < 0) return set_error(FEH_EINVAL, "workgroup sizes must be >= 0");
+        if (pbf > 0 && pbf < std::max(1, first_pencils_default(p) / 4))
+            return set_error(FEH_EINVAL, "axis-0 pencils per workgroup below a quarter of the default");
+        if (perlc != 0 && perlc != 1) return set_error(FEH_EINVAL, "axis-0 layout must be 0 or 1");
+        if (p.dim == 3 ? (rows != 8 && rows != 16) : rows != 1)
+            return set_error(FEH_EINVAL, "stencil rows must be 8 or 16 (3D) or 1 (2D)");
+        AxisFFT ax[3] = {p.fft[0], p.fft[1], p.fft[2]};
+        int i = 5;
+        for (int a = 0; a < 3; ++a) {
+            if (i >= n_values) return set_error(FEH_EINVAL, "schedule too short");
+            const int np = values[i++];
+            if (np < 0 || i + np > n_values) return set_error(FEH_EINVAL, "schedule too short");
+            std::vector<int> rad(values + i, values + i + np);
+            i += np;
+            if (a >= p.dim) {
+                if (np != 0) return set_error(FEH_EINVAL, "passes given for a missing axis");
+                continue;
+            }
+            const int len = p.fft[a].n;
+            for (int r : rad) {
+                // butterfly radices, or a prime above 13 (direct-DFT pass)
+                bool ok = r == 2 || r == 3 || r == 4 || r == 5 || r == 7 || r == 8 || r == 11 || r == 13;
+                if (!ok && r > 13) {
+                    ok = true;
+                    for (int f = 2; f * f <= r; ++f)
+                        if (r % f == 0) ok = false;
+                }
+                if (!ok) return set_error(FEH_EINVAL, "radices must be 2, 3, 4, 5, 7, 8, 11, 13 or a prime above 13");
+            }
+            if (!make_axis(len, rad, ax[a])) return set_error(FEH_EINVAL, "radices do not multiply to the axis length");
+        }
+        for (int a = 0; a < 3; ++a) p.fft[a] = ax[a];
+        p.tune_rr_last = rr;
+        p.tune_pb_mid = pbm;
+        p.tune_pb_first = pbf;
+        p.tune_first_perlc = perlc ? 1 : -1;
+        p.tune_stencil_vy = p.dim == 3 ? rows : 0;
+        return FEH_OK;
+    } catch (...) {
+        return set_error(FEH_EINVAL, "unexpected host exception");
+    }
+}
+
 int feh_plan_tuning(const feh_plan *plan, int *values, int n_values) {
     if (!plan || !values) return set_error(FEH_EINVAL, "null argument");
-    std::vector<int> v = {plan->tune_rr_last, plan->tune_pb_mid, plan->tune_pb_first};
+    std::vector<int> v = {plan->tune_rr_last, plan->tune_pb_mid, plan->tune_pb_first,
+                          first_per_load_case(*plan) ? 1 : 0, stencil_rows(*plan)};
     for (int a = 0; a < 3; ++a) {
         const int np = a < plan->dim ? plan->fft[a].npass : 0;
         v.push_back(np);

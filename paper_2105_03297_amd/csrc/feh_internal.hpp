@@ -144,6 +144,8 @@ struct feh_plan {
     int tune_rr_last = 0;               // rows per workgroup, last axis
     int tune_pb_mid = 0;                // pencils per workgroup, axis 1 (3D)
     int tune_pb_first = 0;              // pencils per workgroup, axis 0
+    int tune_stencil_vy = 0;            // 3D stencil tile rows (8 or 16; 0: default)
+    int tune_first_perlc = 0;           // axis-0 pass: 1 one workgroup per load case, -1 all load cases, 0 default
     bool solved = false;                // off_u holds the fluctuations of the last feh_solve
 
     // optional per-kernel event timing of the CG loop
@@ -257,8 +259,10 @@ int post_num_slots(const feh_plan &p);
 
 // partial-sum sizes
 int stencil_num_parts(const feh_plan &p);
+int stencil_rows(const feh_plan &p);           // 3D stencil tile rows in use
 int first_num_parts(const feh_plan &p);
 int first_pencils_default(const feh_plan &p);  // before tuning
+bool first_per_load_case(const feh_plan &p);   // axis-0 pass layout (workgroup per load case)
 int post_num_parts(const feh_plan &p);
 
 }  // namespace feh

@@ -15,6 +15,8 @@
 // radix R after earlier radices of product L*, L = L* R, m = n / L:
 //   y[q + m (p + L* d)] = sum_c exp(-2 pi i c d / R) w_n^{c p m} x[q + c m + m R p]
 // for q < m, p < L*, d < R.
+#include <algorithm>
+
 #include "device_common.hpp"
 
 namespace feh {
@@ -682,14 +684,89 @@ __device__ __forceinline__ void herm_inverse(const double (&Md)[D], const Cx<dou
 // inverse only.  In mode 0 the inverses of the workgroup's wavevectors are
 // formed once (FP64, adjugate) and kept in registers in the plan precision for
 // all load cases.
-template <typename T, int PPT, int DIM, int MODE, bool GEN>
+// Inverse of the projection core at wavevector slot e of the workgroup (FP64):
+// Id = real diagonal, Io = upper triangle of M(k)^-1 (zero at k = 0 and for
+// slots past the block's pencils); the Parseval weight bit of the slot.
+template <typename T, int DIM>
+__device__ __forceinline__ void slot_inverse(const FK<T> &a, int e, int PB, long long in0, int lim,
+                                             const Cx<double> *aa0, const Cx<double> *om0, const Cx<double> *pin,
+                                             double (&Id)[DIM], Cx<double> (&Io)[3], bool &half) {
+    constexpr int D = DIM;
+    const int j = (int)a.d_PB.div((uint32_t)e);
+    const int b = e - j * PB;
+    const long long inn = in0 + b;
+    #pragma unroll
+    for (int c = 0; c < D; ++c) Id[c] = 0.0;
+    Io[0] = Io[1] = Io[2] = Cx<double>{0.0, 0.0};
+    half = false;
+    if (!(e < PB * a.n0 && b * D < lim && !(j == 0 && inn == 0))) return;
+    int m1 = 0, kh;
+    if (DIM == 3) {
+        m1 = (int)a.d_nh.div((uint32_t)inn);
+        kh = (int)(inn - (long long)m1 * a.nh);
+    } else {
+        kh = (int)inn;
+    }
+    half = kh == 0 || (a.last_even && kh == a.nh - 1);
+    const double ch = a.chalf;
+    double Md[D];
+    Cx<double> Mo[3];
+    if (DIM == 3) {
+        const Cx<double> a0 = aa0[j], a1 = pin[4 * b + 0], a2 = pin[4 * b + 2];
+        const Cx<double> w0 = om0[j], w1 = pin[4 * b + 1], w2 = pin[4 * b + 3];
+        const double n0s = nrm(a0), n1s = nrm(a1), n2s = nrm(a2);
+        const double S = 6.0 * (n0s + n1s + n2s);
+        Md[0] = ch * (S + 6.0 * n0s);
+        Md[1] = ch * (S + 6.0 * n1s);
+        Md[2] = ch * (S + 6.0 * n2s);
+        const Cx<double> two = {2.0, 0.0};
+        // M_ab = ch a_a conj(a_b) [conj(w_a)(2 + conj(w_c)) + w_b (2 + w_c)]
+        Mo[0] = cscale(cmul(cmulc(a0, a1), cadd(cmulc(cadd(two, cconj(w2)), w0), cmul(w1, cadd(two, w2)))), ch);
+        Mo[1] = cscale(cmul(cmulc(a0, a2), cadd(cmulc(cadd(two, cconj(w1)), w0), cmul(w2, cadd(two, w1)))), ch);
+        Mo[2] = cscale(cmul(cmulc(a1, a2), cadd(cmulc(cadd(two, cconj(w0)), w1), cmul(w2, cadd(two, w0)))), ch);
+    } else {
+        const Cx<double> a0 = aa0[j], a1 = pin[4 * b + 0];
+        const Cx<double> w0 = om0[j], w1 = pin[4 * b + 1];
+        const double n0s = nrm(a0), n1s = nrm(a1);
+        const double S = 2.0 * (n0s + n1s);
+        Md[0] = ch * (S + 2.0 * n0s);
+        Md[1] = ch * (S + 2.0 * n1s);
+        // M_01 = ch a0 conj(a1) (1 + w1 conj(w0))
+        const Cx<double> f = {1.0 + (w1.x * w0.x + w1.y * w0.y), w1.y * w0.x - w1.x * w0.y};
+        Mo[0] = cscale(cmul(cmulc(a0, a1), f), ch);
+        Mo[1] = Mo[2] = Cx<double>{0.0, 0.0};
+    }
+    herm_inverse<D>(Md, Mo, Id, Io);
+}
+
+// First axis: forward transform, per-wavevector z^ = M(k)^-1 r^ with the
+// Parseval partial of r.z (mode 0), inverse transform.  Mode 1: forward only;
+// mode 2: inverse only.  PERLC = false: one workgroup per block of PB pencils
+// runs through every load case, forming the inverses of its wavevectors once
+// (FP64, adjugate) and keeping them in registers in the plan precision.
+// PERLC = true: one workgroup per (load case, pencil block), the inverses
+// formed again per load case just in time (no register cache, more resident
+// workgroups to overlap memory and compute).
+template <typename T, int PPT, int DIM, int MODE, bool GEN, bool PERLC>
 __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
     constexpr int NT = kFftThreads;
     constexpr int D = DIM;
     constexpr int KW = (PPT + D - 1) / D;  // wavevector slots per thread: PB n0 <= PPT NT / D
+    constexpr int KC = PERLC ? 1 : KW;     // cached slots
     __shared__ Cx<T> buf[PPT * NT];
     __shared__ double red[NT / 64];
-    const int blk = xcd_remap(blockIdx.x, a.total);
+    int blk, lc0, lc1;
+    if constexpr (PERLC) {
+        const int t = xcd_remap(blockIdx.x, a.total);
+        lc0 = t / a.nblk;
+        blk = t - lc0 * a.nblk;
+        lc1 = lc0 + 1;
+        if (a.st && !a.st[lc0].active) return;
+    } else {
+        blk = xcd_remap(blockIdx.x, a.total);
+        lc0 = 0;
+        lc1 = a.L;
+    }
     const int PB = a.PB;
     const int nb = PB * D;
     const int n0 = a.n0;
@@ -705,9 +782,9 @@ __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
     Cx<double> *om0 = aa0 + n0;
     Cx<double> *pin = om0 + n0;  // [PB][4]: aa1, om1, aa2, om2 (2D: aa1, om1)
     stage(twl, a.tw, n0);
-    // per slot: real diagonal of M^-1, then its upper triangle (complex)
-    T Mid[KW][D];
-    Cx<T> Mio[KW][DIM == 3 ? 3 : 1];
+    // per cached slot: real diagonal of M^-1, then its upper triangle (complex)
+    T Mid[KC][D];
+    Cx<T> Mio[KC][DIM == 3 ? 3 : 1];
     unsigned half_w = 0;  // bit kw: wavevector counted once in the half-spectrum Parseval sum
     if constexpr (MODE == 0) {
         stage(aa0, reinterpret_cast<const Cx<double> *>(a.aa[0]), n0);
@@ -729,61 +806,23 @@ __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
             }
         }
         __syncthreads();
-        const double ch = a.chalf;
-        #pragma unroll
-        for (int kw = 0; kw < KW; ++kw) {
-            const int e = threadIdx.x + kw * NT;
-            const int j = (int)a.d_PB.div((uint32_t)e);
-            const int b = e - j * PB;
-            const long long inn = in0 + b;
-            double Id[D] = {};
-            Cx<double> Io[3] = {};
-            if (e < PB * n0 && b * D < lim && !(j == 0 && inn == 0)) {
-                int m1 = 0, kh;
-                if (DIM == 3) {
-                    m1 = (int)a.d_nh.div((uint32_t)inn);
-                    kh = (int)(inn - (long long)m1 * a.nh);
-                } else {
-                    kh = (int)inn;
-                }
-                if (kh == 0 || (a.last_even && kh == a.nh - 1)) half_w |= 1u << kw;
-                double Md[D];
-                Cx<double> Mo[3];
-                if (DIM == 3) {
-                    const Cx<double> a0 = aa0[j], a1 = pin[4 * b + 0], a2 = pin[4 * b + 2];
-                    const Cx<double> w0 = om0[j], w1 = pin[4 * b + 1], w2 = pin[4 * b + 3];
-                    const double n0s = nrm(a0), n1s = nrm(a1), n2s = nrm(a2);
-                    const double S = 6.0 * (n0s + n1s + n2s);
-                    Md[0] = ch * (S + 6.0 * n0s);
-                    Md[1] = ch * (S + 6.0 * n1s);
-                    Md[2] = ch * (S + 6.0 * n2s);
-                    const Cx<double> two = {2.0, 0.0};
-                    // M_ab = ch a_a conj(a_b) [conj(w_a)(2 + conj(w_c)) + w_b (2 + w_c)]
-                    Mo[0] = cscale(cmul(cmulc(a0, a1), cadd(cmulc(cadd(two, cconj(w2)), w0), cmul(w1, cadd(two, w2)))), ch);
-                    Mo[1] = cscale(cmul(cmulc(a0, a2), cadd(cmulc(cadd(two, cconj(w1)), w0), cmul(w2, cadd(two, w1)))), ch);
-                    Mo[2] = cscale(cmul(cmulc(a1, a2), cadd(cmulc(cadd(two, cconj(w0)), w1), cmul(w2, cadd(two, w0)))), ch);
-                } else {
-                    const Cx<double> a0 = aa0[j], a1 = pin[4 * b + 0];
-                    const Cx<double> w0 = om0[j], w1 = pin[4 * b + 1];
-                    const double n0s = nrm(a0), n1s = nrm(a1);
-                    const double S = 2.0 * (n0s + n1s);
-                    Md[0] = ch * (S + 2.0 * n0s);
-                    Md[1] = ch * (S + 2.0 * n1s);
-                    // M_01 = ch a0 conj(a1) (1 + w1 conj(w0))
-                    const Cx<double> f = {1.0 + (w1.x * w0.x + w1.y * w0.y), w1.y * w0.x - w1.x * w0.y};
-                    Mo[0] = cscale(cmul(cmulc(a0, a1), f), ch);
-                    Mo[1] = Mo[2] = Cx<double>{0.0, 0.0};
-                }
-                herm_inverse<D>(Md, Mo, Id, Io);
+        if constexpr (!PERLC) {
+            #pragma unroll
+            for (int kw = 0; kw < KW; ++kw) {
+                double Id[D];
+                Cx<double> Io[3];
+                bool half;
+                slot_inverse<T, DIM>(a, threadIdx.x + kw * NT, PB, in0, lim, aa0, om0, pin, Id, Io, half);
+                if (half) half_w |= 1u << kw;
+                #pragma unroll
+                for (int c = 0; c < D; ++c) Mid[kw][c] = T(Id[c]);
+                #pragma unroll
+                for (int c = 0; c < (DIM == 3 ? 3 : 1); ++c) Mio[kw][c] = Cx<T>{T(Io[c].x), T(Io[c].y)};
             }
-            #pragma unroll
-            for (int c = 0; c < D; ++c) Mid[kw][c] = T(Id[c]);
-            #pragma unroll
-            for (int c = 0; c < (DIM == 3 ? 3 : 1); ++c) Mio[kw][c] = Cx<T>{T(Io[c].x), T(Io[c].y)};
         }
     }
-    for (int lc = 0; lc < a.L; ++lc) {
-        if (a.st && !a.st[lc].active) continue;
+    for (int lc = lc0; lc < lc1; ++lc) {
+        if (!PERLC && a.st && !a.st[lc].active) continue;
         // the thread index passes through an empty asm statement so that the
         // index arithmetic is redone per load case instead of being hoisted
         // out of the loop into registers
@@ -818,19 +857,37 @@ __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
                 const int j = (int)a.d_PB.div((uint32_t)e);
                 const int b = e - j * PB;
                 if (e < PB * n0 && b * D < lim) {
+                    T md[D];
+                    Cx<T> mo[3];
+                    bool half;
+                    if constexpr (PERLC) {
+                        double Id[D];
+                        Cx<double> Io[3];
+                        slot_inverse<T, DIM>(a, e, PB, in0, lim, aa0, om0, pin, Id, Io, half);
+                        #pragma unroll
+                        for (int c = 0; c < D; ++c) md[c] = T(Id[c]);
+                        #pragma unroll
+                        for (int c = 0; c < 3; ++c) mo[c] = Cx<T>{T(Io[c].x), T(Io[c].y)};
+                    } else {
+                        #pragma unroll
+                        for (int c = 0; c < D; ++c) md[c] = Mid[kw][c];
+                        #pragma unroll
+                        for (int c = 0; c < (DIM == 3 ? 3 : 1); ++c) mo[c] = Mio[kw][c];
+                        half = (half_w >> kw) & 1u;
+                    }
                     Cx<T> *pt = buf + j * nb + b * D;
                     Cx<T> r[D], z[D];
                     #pragma unroll
                     for (int c = 0; c < D; ++c) r[c] = pt[c];
                     if constexpr (DIM == 3) {
-                        const Cx<T> o01 = Mio[kw][0], o02 = Mio[kw][1], o12 = Mio[kw][2];
-                        z[0] = cadd(cadd(cscale(r[0], Mid[kw][0]), cmul(o01, r[1])), cmul(o02, r[2]));
-                        z[1] = cadd(cadd(cmulc(r[0], o01), cscale(r[1], Mid[kw][1])), cmul(o12, r[2]));
-                        z[2] = cadd(cadd(cmulc(r[0], o02), cmulc(r[1], o12)), cscale(r[2], Mid[kw][2]));
+                        const Cx<T> o01 = mo[0], o02 = mo[1], o12 = mo[2];
+                        z[0] = cadd(cadd(cscale(r[0], md[0]), cmul(o01, r[1])), cmul(o02, r[2]));
+                        z[1] = cadd(cadd(cmulc(r[0], o01), cscale(r[1], md[1])), cmul(o12, r[2]));
+                        z[2] = cadd(cadd(cmulc(r[0], o02), cmulc(r[1], o12)), cscale(r[2], md[2]));
                     } else {
-                        const Cx<T> o01 = Mio[kw][0];
-                        z[0] = cadd(cscale(r[0], Mid[kw][0]), cmul(o01, r[1]));
-                        z[1] = cadd(cmulc(r[0], o01), cscale(r[1], Mid[kw][1]));
+                        const Cx<T> o01 = mo[0];
+                        z[0] = cadd(cscale(r[0], md[0]), cmul(o01, r[1]));
+                        z[1] = cadd(cmulc(r[0], o01), cscale(r[1], md[1]));
                     }
                     double dot = 0.0;
                     #pragma unroll
@@ -838,7 +895,7 @@ __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
                         dot += double(r[c].x) * double(z[c].x) + double(r[c].y) * double(z[c].y);
                         pt[c] = z[c];
                     }
-                    acc += ((half_w >> kw) & 1u) ? dot : 2.0 * dot;
+                    acc += half ? dot : 2.0 * dot;
                 }
             }
             __syncthreads();
@@ -1030,24 +1087,33 @@ int first_t(const feh_plan &p, const FftArgs &fa, int mode) {
     int PB = (PPT * kFftThreads) / (a.n0 * DIM);
     if (PB < 1) return set_error(FEH_ENOTSUP, "first axis too long for the LDS transform");
     if (PB > 32) PB = 32;
-    if (p.tune_pb_first > 0 && p.tune_pb_first < PB) PB = p.tune_pb_first;
+    // tuned value, never below a quarter of the default: the partial-sum
+    // buffer holds one slot per pencil block for that size
+    if (p.tune_pb_first > 0 && p.tune_pb_first < PB) PB = std::max(p.tune_pb_first, std::max(1, PB / 4));
     if (PB > a.inner_total) PB = (int)a.inner_total;
     a.PB = PB;
     a.d_PB = FastDiv::make((uint32_t)PB);
     a.nbd = FastDiv::make((uint32_t)(PB * DIM));
     a.nblk = (int)((a.inner_total + PB - 1) / PB);
-    a.total = a.nblk;  // every block runs through the load cases
+    const bool perlc = first_per_load_case(p);
+    a.total = perlc ? a.nblk * p.L : a.nblk;  // one block per (load case, pencils) or per pencils
     dim3 g(a.total), b(kFftThreads);
     const bool gen = !pow2_len(a.ax.n);
     const size_t dyn = ((a.n0 * sizeof(Cx<T>) + 15) / 16) * 16 + (2 * (size_t)a.n0 + 4 * (size_t)PB) * sizeof(Cx<double>);
+#define FEH_FIRST(M, G)                                                                                   \
+    do {                                                                                                  \
+        if (perlc) hipLaunchKernelGGL((k_first<T, PPT, DIM, M, G, true>), g, b, dyn, p.stream, a);       \
+        else hipLaunchKernelGGL((k_first<T, PPT, DIM, M, G, false>), g, b, dyn, p.stream, a);            \
+    } while (0)
     switch (mode * 2 + (gen ? 1 : 0)) {
-    case 0: hipLaunchKernelGGL((k_first<T, PPT, DIM, 0, false>), g, b, dyn, p.stream, a); break;
-    case 1: hipLaunchKernelGGL((k_first<T, PPT, DIM, 0, true>), g, b, dyn, p.stream, a); break;
-    case 2: hipLaunchKernelGGL((k_first<T, PPT, DIM, 1, false>), g, b, dyn, p.stream, a); break;
-    case 3: hipLaunchKernelGGL((k_first<T, PPT, DIM, 1, true>), g, b, dyn, p.stream, a); break;
-    case 4: hipLaunchKernelGGL((k_first<T, PPT, DIM, 2, false>), g, b, dyn, p.stream, a); break;
-    default: hipLaunchKernelGGL((k_first<T, PPT, DIM, 2, true>), g, b, dyn, p.stream, a); break;
+    case 0: FEH_FIRST(0, false); break;
+    case 1: FEH_FIRST(0, true); break;
+    case 2: FEH_FIRST(1, false); break;
+    case 3: FEH_FIRST(1, true); break;
+    case 4: FEH_FIRST(2, false); break;
+    default: FEH_FIRST(2, true); break;
     }
+#undef FEH_FIRST
     return hip_check(hipGetLastError(), "first-axis fft launch");
 }
 
@@ -1057,6 +1123,11 @@ int first_dispatch(const feh_plan &p, const FftArgs &fa, int mode) {
 }
 
 }  // namespace
+
+bool first_per_load_case(const feh_plan &p) {
+    if (p.tune_first_perlc != 0) return p.tune_first_perlc > 0;
+    return false;
+}
 
 int first_pencils_default(const feh_plan &p) {
     const int PPT = p.prec == FEH_FP32 ? 24 : 16;
@@ -1068,7 +1139,9 @@ int first_pencils_default(const feh_plan &p) {
 
 int first_num_parts(const feh_plan &p) {
     int PB = first_pencils_default(p);
-    if (p.tune_pb_first > 0 && p.tune_pb_first < PB) PB = p.tune_pb_first;
+    // tuned value, never below a quarter of the default: the partial-sum
+    // buffer holds one slot per pencil block for that size
+    if (p.tune_pb_first > 0 && p.tune_pb_first < PB) PB = std::max(p.tune_pb_first, std::max(1, PB / 4));
     const long long inner = p.dim == 3 ? p.n[1] * p.nh : p.nh;
     if (PB > inner) PB = (int)inner;
     return (int)((inner + PB - 1) / PB);

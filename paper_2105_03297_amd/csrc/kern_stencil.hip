@@ -193,20 +193,21 @@ struct SK {
 // Tile shapes: VY x VZ voxels per workgroup (one per thread).  HY = 1 when
 // the tile has an axis-1 extent (3D); the node plane of the tile is
 // (VY + HY) x (VZ + 1), the updated nodes advance by SY x SZ between tiles.
-template <int DIM>
+// 3D tiles are 8 or 16 rows of 32 voxels (256 or 512 threads): the taller
+// tile re-reads fewer halo nodes ((VY + 1) 33 loaded per (VY - 1) 31 updated)
+// at twice the LDS of the edge-flux exchange.
+template <int DIM, int VYT>
 struct Tile;
-template <>
-struct Tile<3> {
-    static constexpr int VY = 8, VZ = 32, HY = 1, NC = 3, NEDGE = 12;
-    static constexpr int SY = VY - 1, SZ = VZ - 1;
+template <int VYT>
+struct Tile<3, VYT> {
+    static constexpr int VY = VYT, VZ = 32, HY = 1, NC = 3, NEDGE = 12;
+    static constexpr int SY = VY - 1, SZ = VZ - 1, NT = VY * VZ;
 };
-template <>
-struct Tile<2> {
+template <int VYT>
+struct Tile<2, VYT> {
     static constexpr int VY = 1, VZ = 256, HY = 0, NC = 2, NEDGE = 4;
-    static constexpr int SY = 1, SZ = VZ - 1;
+    static constexpr int SY = 1, SZ = VZ - 1, NT = 256;
 };
-
-constexpr int kStencilThreads = 256;
 
 // The value held by lane - 1 of the wavefront (DPP shift of the whole wave
 // right by one lane; lane 0 receives zero).  In the 3D tile a row of 32
@@ -221,12 +222,12 @@ __device__ __forceinline__ double from_left(double v) {
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-template <typename T, int DIM, int MODE, bool UNIT>
-__global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
-    using TL = Tile<DIM>;
+template <typename T, int DIM, int MODE, bool UNIT, int VYT>
+__global__ __launch_bounds__((Tile<DIM, VYT>::NT)) void k_stencil(SK<T> a) {
+    using TL = Tile<DIM, VYT>;
     constexpr int VY = TL::VY, VZ = TL::VZ, HY = TL::HY, NC = TL::NC, NEDGE = TL::NEDGE;
     constexpr int EY = VY + HY, EZ = VZ + 1;     // node plane of the tile
-    constexpr int NE = EY * EZ, NT = kStencilThreads;
+    constexpr int NE = EY * EZ, NT = TL::NT;
     constexpr int NQ = NEDGE * NC;               // edge-flux values per voxel
     constexpr int NSE = (NE + NT - 1) / NT;      // node-plane slots per thread
     static_assert(VY * VZ == NT, "one voxel per thread");
@@ -574,9 +575,9 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil(SK<T> a) {
 
 int xchunk(int n0) { return n0 < 32 ? n0 : 32; }
 
-template <typename T, int DIM>
+template <typename T, int DIM, int VYT>
 int launch_t(const feh_plan &p, int mode, const StencilArgs &sa) {
-    using TL = Tile<DIM>;
+    using TL = Tile<DIM, VYT>;
     SK<T> a{};
     a.in0 = static_cast<const T *>(sa.in0);
     a.out0 = static_cast<T *>(sa.out0);
@@ -611,12 +612,12 @@ int launch_t(const feh_plan &p, int mode, const StencilArgs &sa) {
     a.ntz = (a.n2 + TL::SZ - 1) / TL::SZ;
     a.total = p.L * a.nchunk * a.nty * a.ntz;
     a.part_stride = (int)p.part_stride;
-    dim3 grid(a.total), block(kStencilThreads);
+    dim3 grid(a.total), block(TL::NT);
     const bool unit = p.h[0] == 1.0 && p.h[1] == 1.0 && (DIM == 2 || p.h[2] == 1.0);
 #define FEH_STENCIL_CASE(M)                                                                                   \
     case M:                                                                                                   \
-        if (unit) hipLaunchKernelGGL((k_stencil<T, DIM, M, true>), grid, block, 0, p.stream, a);             \
-        else hipLaunchKernelGGL((k_stencil<T, DIM, M, false>), grid, block, 0, p.stream, a);                 \
+        if (unit) hipLaunchKernelGGL((k_stencil<T, DIM, M, true, VYT>), grid, block, 0, p.stream, a);             \
+        else hipLaunchKernelGGL((k_stencil<T, DIM, M, false, VYT>), grid, block, 0, p.stream, a);                 \
         break;
     switch (mode) {
         FEH_STENCIL_CASE(ST_APPLY)
@@ -631,22 +632,29 @@ int launch_t(const feh_plan &p, int mode, const StencilArgs &sa) {
 
 }  // namespace
 
+int stencil_rows(const feh_plan &p) {
+    if (p.dim != 3) return 1;
+    if (p.tune_stencil_vy == 8 || p.tune_stencil_vy == 16) return p.tune_stencil_vy;
+    return 8;
+}
+
 int stencil_num_parts(const feh_plan &p) {
     const int n0 = (int)p.n[0];
     const int xc = xchunk(n0);
     const int nchunk = (n0 + xc - 1) / xc;
     if (p.dim == 3) {
-        return nchunk * (int)((p.n[1] + Tile<3>::SY - 1) / Tile<3>::SY) *
-               (int)((p.n[2] + Tile<3>::SZ - 1) / Tile<3>::SZ);
+        const int sy = stencil_rows(p) - 1, sz = 31;
+        return nchunk * (int)((p.n[1] + sy - 1) / sy) * (int)((p.n[2] + sz - 1) / sz);
     }
-    return nchunk * (int)((p.n[1] + Tile<2>::SZ - 1) / Tile<2>::SZ);
+    return nchunk * (int)((p.n[1] + Tile<2, 1>::SZ - 1) / Tile<2, 1>::SZ);
 }
 
 int launch_stencil(const feh_plan &p, int mode, const StencilArgs &a) {
-    if (p.prec == FEH_FP64) {
-        return p.dim == 3 ? launch_t<double, 3>(p, mode, a) : launch_t<double, 2>(p, mode, a);
-    }
-    return p.dim == 3 ? launch_t<float, 3>(p, mode, a) : launch_t<float, 2>(p, mode, a);
+    if (p.dim == 2)
+        return p.prec == FEH_FP64 ? launch_t<double, 2, 1>(p, mode, a) : launch_t<float, 2, 1>(p, mode, a);
+    if (stencil_rows(p) == 16)
+        return p.prec == FEH_FP64 ? launch_t<double, 3, 16>(p, mode, a) : launch_t<float, 3, 16>(p, mode, a);
+    return p.prec == FEH_FP64 ? launch_t<double, 3, 8>(p, mode, a) : launch_t<float, 3, 8>(p, mode, a);
 }
 
 }  // namespace feh

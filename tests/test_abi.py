@@ -136,3 +136,19 @@ def test_plan_tuning_reports_default_schedule():
     assert (t["rows_last"], t["pencils_mid"], t["pencils_first"]) == (0, 0, 0)
     assert np.prod(t["radices"][0]) == 256 and np.prod(t["radices"][1]) == 96 and np.prod(t["radices"][2]) == 15
     assert t["radices"][0] == [8, 8, 4]
+
+
+def test_set_tuning_validates_and_round_trips():
+    p = feh.feh_plan_create(3, (16, 12, 10), None, 2, feh.FEH_FP32)
+    t = feh.feh_plan_tuning(p)
+    assert t["stencil_rows"] == 8 and t["first_per_load_case"] == 0
+    t2 = dict(t, stencil_rows=16, first_per_load_case=1, radices=[[4, 4], [3, 4], [5]])
+    feh.feh_plan_set_tuning(p, t2)
+    assert feh.feh_plan_tuning(p) == t2
+    for bad in (dict(t2, radices=[[4, 2], [3, 4], [5]]), dict(t2, radices=[[16], [3, 4], [5]]),
+                dict(t2, stencil_rows=4), dict(t2, first_per_load_case=2), dict(t2, pencils_first=1)):
+        with pytest.raises(feh.FehError) as ei:
+            feh.feh_plan_set_tuning(p, bad)
+        assert ei.value.status == feh.FEH_EINVAL
+        assert feh.feh_plan_tuning(p) == t2
+    feh.feh_plan_destroy(p)

@@ -165,3 +165,35 @@ def test_autotuned_plan_matches_default(shape, prec):
     h.close()
     assert np.array_equal(a["C_eff"], b["C_eff"])
     assert rel(a["C_eff"], ref["C_eff"]) < (1e-12 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("shape,prec", [((24, 20, 18), "fp64"), ((40, 36, 34), "fp32"), ((33, 17, 20), "fp64")])
+def test_explicit_schedules_match_default(shape, prec):
+    """Every schedule feh_plan_set_tuning accepts gives the default plan's
+    solution to rounding: 16-row stencil tiles (ragged tiles included), one
+    first-axis workgroup per load case, other radix orders and smaller
+    workgroups; the CG iteration counts agree."""
+    import paper_2105_03297_amd as feh
+    say("explicit schedules", shape, prec)
+    dim = len(shape)
+    lam, mu = random_material(shape, 14, prec)
+    Eb = ms.unit_loads(dim)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    ref = _single(shape, lam, mu, Eb, prec, tol)
+    h = feh.Homogenizer(shape, n_load=len(Eb), precision=prec)
+    h.set_material(lam=lam, mu=mu)
+    base = feh.feh_plan_tuning(h.plan)
+    PPT = 16 if prec == "fp64" else 24
+    first_default = min(32, max(1, PPT * 256 // (shape[0] * dim)))
+    variants = [dict(base, stencil_rows=16), dict(base, first_per_load_case=1),
+                dict(base, stencil_rows=16, first_per_load_case=1, rows_last=2, pencils_mid=2,
+                     pencils_first=max(1, first_default // 4), radices=[list(reversed(r)) for r in base["radices"]])]
+    for v in variants:
+        feh.feh_plan_set_tuning(h.plan, v)
+        assert feh.feh_plan_tuning(h.plan) == v
+        out = h.solve(Eb, tol=tol, max_iter=5000)
+        assert rel(out["C_eff"], ref["C_eff"]) < (1e-11 if prec == "fp64" else 1e-5), v
+        its = [r["iterations"] for r in out["report"]]
+        its_ref = [r["iterations"] for r in ref["report"]]
+        assert max(abs(x - y) for x, y in zip(its, its_ref)) <= (1 if prec == "fp64" else 2), (v, its, its_ref)
+    h.close()
