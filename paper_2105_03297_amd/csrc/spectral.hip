@@ -117,67 +117,98 @@ __global__ __launch_bounds__(kThreads) void k_sc_project(PK<T> a, SymArgs sa) {
     Cx<T> *spec = static_cast<Cx<T> *>(a.spec);
     const long long cs = a.Nspec;  // component stride
     for (long long k = blockIdx.x * (long long)kThreads + threadIdx.x; k < a.Nspec; k += (long long)gridDim.x * kThreads) {
-        C64 D[NE][DIM], Mi[DIM][DIM];
-        bool nyq = false;
-        const bool ok = symbol_at<DIM, KIND, false>(sa, k, D, nyq);
-        if (ok) metric_inverse<DIM, NE>(D, Mi);
-        C64 D2[NE][DIM], Mi2[DIM][DIM];
-        bool two = false;
-        if constexpr (FOUR) {
-            bool dummy;
-            two = ok && nyq;
-            if (two) {
-                symbol_at<DIM, KIND, true>(sa, k, D2, dummy);
-                metric_inverse<DIM, NE>(D2, Mi2);
+        using CT = Cx<T>;
+        // symbol and inverse in FP64, rounded once to the plan precision
+        CT Dt[NE][DIM], D2t[FOUR ? NE : 1][DIM];
+        T Md[DIM], M2d[FOUR ? DIM : 1];
+        CT Mo[3], M2o[FOUR ? 3 : 1];
+        bool two = false, ok;
+        {
+            C64 D[NE][DIM];
+            bool nyq = false;
+            double Id[DIM];
+            C64 Io[3];
+            ok = symbol_at<DIM, KIND, false>(sa, k, D, nyq);
+            if (ok) metric_inverse<DIM, NE>(D, Id, Io);
+            #pragma unroll
+            for (int t = 0; t < NE; ++t)
+                #pragma unroll
+                for (int x = 0; x < DIM; ++x) Dt[t][x] = CT{T(D[t][x].x), T(D[t][x].y)};
+            #pragma unroll
+            for (int x = 0; x < DIM; ++x) Md[x] = T(ok ? Id[x] : 0.0);
+            #pragma unroll
+            for (int u = 0; u < 3; ++u) Mo[u] = ok ? CT{T(Io[u].x), T(Io[u].y)} : CT{T(0), T(0)};
+            if constexpr (FOUR) {
+                bool dummy;
+                two = ok && nyq;
+                if (two) {
+                    symbol_at<DIM, KIND, true>(sa, k, D, dummy);
+                    metric_inverse<DIM, NE>(D, Id, Io);
+                    #pragma unroll
+                    for (int t = 0; t < NE; ++t)
+                        #pragma unroll
+                        for (int x = 0; x < DIM; ++x) D2t[t][x] = CT{T(D[t][x].x), T(D[t][x].y)};
+                    #pragma unroll
+                    for (int x = 0; x < DIM; ++x) M2d[x] = T(Id[x]);
+                    #pragma unroll
+                    for (int u = 0; u < 3; ++u) M2o[u] = CT{T(Io[u].x), T(Io[u].y)};
+                }
             }
         }
+        // w = M^-1 V from the diagonal and upper triangle
+        auto apply = [](const T (&md)[DIM], const CT (&mo)[3], const CT (&V)[DIM], CT (&w)[DIM]) {
+            if constexpr (DIM == 2) {
+                w[0] = cadd(cscale(V[0], md[0]), cmul(mo[0], V[1]));
+                w[1] = cadd(cmulc(V[0], mo[0]), cscale(V[1], md[1]));
+            } else {
+                w[0] = cadd(cadd(cscale(V[0], md[0]), cmul(mo[0], V[1])), cmul(mo[1], V[2]));
+                w[1] = cadd(cadd(cmulc(V[0], mo[0]), cscale(V[1], md[1])), cmul(mo[2], V[2]));
+                w[2] = cadd(cadd(cmulc(V[0], mo[1]), cmulc(V[1], mo[2])), cscale(V[2], md[2]));
+            }
+        };
+        const T half = T(0.5);
         for (int l = 0; l < a.L; ++l) {
+            // keep this load case's spectrum loads from being hoisted above
+            // the symbol evaluation (register pressure)
+            asm volatile("" ::: "memory");
             if (!a.st[l].active) continue;
-            Cx<T> *sp = spec + (long long)l * a.C * cs + k;
+            CT *sp = spec + (long long)l * a.C * cs + k;
             if (!ok) {
                 #pragma unroll
-                for (int c = 0; c < NE * NS; ++c) sp[c * cs] = Cx<T>{T(0), T(0)};
+                for (int c = 0; c < NE * NS; ++c) sp[c * cs] = CT{T(0), T(0)};
                 continue;
             }
-            C64 V[DIM], V2[DIM];
+            CT V[DIM], V2[DIM];
             #pragma unroll
-            for (int x = 0; x < DIM; ++x) V[x] = V2[x] = C64{0.0, 0.0};
+            for (int x = 0; x < DIM; ++x) V[x] = V2[x] = CT{T(0), T(0)};
             #pragma unroll
             for (int t = 0; t < NE; ++t)
                 #pragma unroll
                 for (int x = 0; x < DIM; ++x)
                     #pragma unroll
                     for (int y = 0; y < DIM; ++y) {
-                        const Cx<T> s = sp[(t * NS + sidx<DIM>(x, y)) * cs];
-                        const C64 sv{double(s.x), double(s.y)};
-                        V[x] = cadd(V[x], cmulc(sv, D[t][y]));
+                        const CT sv = sp[(t * NS + sidx<DIM>(x, y)) * cs];
+                        V[x] = cadd(V[x], cmulc(sv, Dt[t][y]));
                         if constexpr (FOUR)
-                            if (two) V2[x] = cadd(V2[x], cmulc(sv, D2[t][y]));
+                            if (two) V2[x] = cadd(V2[x], cmulc(sv, D2t[t][y]));
                     }
-            C64 w[DIM], w2[DIM];
-            #pragma unroll
-            for (int x = 0; x < DIM; ++x) {
-                w[x] = w2[x] = C64{0.0, 0.0};
-                #pragma unroll
-                for (int y = 0; y < DIM; ++y) {
-                    w[x] = cadd(w[x], cmul(Mi[x][y], V[y]));
-                    if constexpr (FOUR)
-                        if (two) w2[x] = cadd(w2[x], cmul(Mi2[x][y], V2[y]));
-                }
-            }
+            CT w[DIM], w2[DIM];
+            apply(Md, Mo, V, w);
+            if constexpr (FOUR)
+                if (two) apply(M2d, M2o, V2, w2);
             #pragma unroll
             for (int t = 0; t < NE; ++t)
                 #pragma unroll
                 for (int x = 0; x < DIM; ++x)
                     #pragma unroll
                     for (int y = x; y < DIM; ++y) {
-                        C64 e = cscale(cadd(cmul(D[t][x], w[y]), cmul(D[t][y], w[x])), 0.5);
+                        CT e = cscale(cadd(cmul(Dt[t][x], w[y]), cmul(Dt[t][y], w[x])), half);
                         if constexpr (FOUR)
                             if (two) {
-                                const C64 e2 = cscale(cadd(cmul(D2[t][x], w2[y]), cmul(D2[t][y], w2[x])), 0.5);
-                                e = cscale(cadd(e, e2), 0.5);
+                                const CT e2 = cscale(cadd(cmul(D2t[t][x], w2[y]), cmul(D2t[t][y], w2[x])), half);
+                                e = cscale(cadd(e, e2), half);
                             }
-                        sp[(t * NS + sidx<DIM>(x, y)) * cs] = Cx<T>{T(e.x), T(e.y)};
+                        sp[(t * NS + sidx<DIM>(x, y)) * cs] = e;
                     }
         }
     }

@@ -37,76 +37,13 @@ constexpr int nsym(int dim) { return dim == 3 ? 6 : 3; }
 
 // Symbol description passed by value to the projection kernel.
 struct SymArgs {
-    double g[6][4][3];   // FE: shape-function gradients per element and vertex (physical units)
     double h[3];
     int n[3];
     int nh;              // half-spectrum length of the last axis
     double tiny;         // symbols with sum |D|^2 <= tiny are projected out
 };
 
-// Shape-function gradients of a simplex with vertices X[0..dim] (physical
-// units): barycentric coordinate c >= 1 is row c - 1 of J^-1 (x - X0) with
-// J = [X1 - X0, ..., Xd - X0]; coordinate 0 is one minus the others.
-void simplex_gradients(int dim, const double (*X)[3], double (*g)[3]) {
-    double J[3][3] = {}, Ji[3][3] = {};
-    for (int c = 1; c <= dim; ++c)
-        for (int a = 0; a < dim; ++a) J[a][c - 1] = X[c][a] - X[0][a];
-    if (dim == 2) {
-        const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-        Ji[0][0] = J[1][1] / det;
-        Ji[0][1] = -J[0][1] / det;
-        Ji[1][0] = -J[1][0] / det;
-        Ji[1][1] = J[0][0] / det;
-    } else {
-        const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
-                           J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
-                           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-        // (J^-1)_ij = cofactor of J_ji / det (cyclic index form)
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) {
-                const int r1 = (j + 1) % 3, r2 = (j + 2) % 3, c1 = (i + 1) % 3, c2 = (i + 2) % 3;
-                Ji[i][j] = (J[r1][c1] * J[r2][c2] - J[r1][c2] * J[r2][c1]) / det;
-            }
-    }
-    for (int a = 0; a < dim; ++a) {
-        double s = 0.0;
-        for (int c = 1; c <= dim; ++c) {
-            g[c][a] = Ji[c - 1][a];
-            s += g[c][a];
-        }
-        g[0][a] = -s;
-    }
-}
-
-// Element vertex offsets (voxel units): 2D triangles (00, 10, 01) and
-// (11, 01, 10); 3D Kuhn tetrahedra 0, e_a, e_a + e_b, (1,1,1) along the axis
-// paths (x,y,z), (x,z,y), (y,x,z), (y,z,x), (z,x,y), (z,y,x).
-void element_offsets(int dim, int e, int (*r)[3]) {
-    std::memset(r, 0, sizeof(int) * 4 * 3);
-    if (dim == 2) {
-        static const int T[2][3][2] = {{{0, 0}, {1, 0}, {0, 1}}, {{1, 1}, {0, 1}, {1, 0}}};
-        for (int c = 0; c < 3; ++c) {
-            r[c][0] = T[e][c][0];
-            r[c][1] = T[e][c][1];
-        }
-        return;
-    }
-    static const int P[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
-    for (int c = 1; c <= 3; ++c) {
-        for (int a = 0; a < 3; ++a) r[c][a] = r[c - 1][a];
-        r[c][P[e][c - 1]] += 1;
-    }
-}
-
-// FE: vertex offset of (element, vertex) as bits (bit a: +1 voxel along axis
-// a), constants so that the phase lookup below resolves at compile time.
-__host__ __device__ constexpr int fe_corner(int dim, int e, int c) {
-    constexpr int c2[2][3] = {{0, 1, 2}, {3, 2, 1}};
-    constexpr int c3[6][4] = {{0, 1, 3, 7}, {0, 1, 5, 7}, {0, 2, 3, 7}, {0, 2, 6, 7}, {0, 4, 5, 7}, {0, 4, 6, 7}};
-    return dim == 2 ? c2[e][c] : c3[e][c];
-}
-
-SymArgs make_sym_args(const feh_plan &p, int kind) {
+SymArgs make_sym_args(const feh_plan &p, int) {
     SymArgs s{};
     for (int a = 0; a < 3; ++a) {
         s.h[a] = p.h[a];
@@ -116,17 +53,6 @@ SymArgs make_sym_args(const feh_plan &p, int kind) {
     double sc = 0.0;
     for (int a = 0; a < p.dim; ++a) sc += 1.0 / (p.h[a] * p.h[a]);
     s.tiny = 1e-24 * sc;
-    if (kind == K_FE) {
-        for (int e = 0; e < points_of(K_FE, p.dim); ++e) {
-            int R[4][3];
-            element_offsets(p.dim, e, R);
-            double X[4][3] = {};
-            for (int c = 0; c <= p.dim; ++c) {
-                for (int a = 0; a < p.dim; ++a) X[c][a] = R[c][a] * p.h[a];
-            }
-            simplex_gradients(p.dim, X, s.g[e]);
-        }
-    }
     return s;
 }
 
@@ -172,6 +98,7 @@ __device__ __forceinline__ bool symbol_at(const SymArgs &sa, long long k, C64 (&
         sincospi(x, &sn[a], &cs[a]);
     }
     if constexpr (KIND == K_FE) {
+        // vertex phases e^{i k.r} of the voxel corners (bit a: +1 along axis a)
         C64 P[1 << DIM];
         #pragma unroll
         for (int r = 0; r < (1 << DIM); ++r) {
@@ -181,18 +108,29 @@ __device__ __forceinline__ bool symbol_at(const SymArgs &sa, long long k, C64 (&
                 if (r & (1 << a)) v = cmul(v, C64{cs[a], sn[a]});
             P[r] = v;
         }
+        // the gradient of a linear simplex along a voxel edge of its vertex
+        // path is the difference of the edge's end values over h_a: tetrahedron
+        // (A0, A1, A2) runs 0 -> e_A0 -> e_A0 + e_A1 -> (1,1,1); triangle 0 has
+        // edges 00-10 (x) and 00-01 (y), triangle 1 edges 01-11 (x) and 10-11 (y)
+        double ih[DIM];
         #pragma unroll
-        for (int e = 0; e < NE; ++e)
+        for (int a = 0; a < DIM; ++a) ih[a] = 1.0 / sa.h[a];
+        if constexpr (DIM == 3) {
+            constexpr int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
             #pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                C64 v{0.0, 0.0};
-                #pragma unroll
-                for (int c = 0; c <= DIM; ++c) {
-                    const C64 ph = P[fe_corner(DIM, e, c)];
-                    v = cadd(v, cscale(ph, sa.g[e][c][a]));
-                }
-                D[e][a] = v;
+            for (int e = 0; e < 6; ++e) {
+                const int A0 = perm[e][0], A1 = perm[e][1], A2 = perm[e][2];
+                const int V1 = 1 << A0, V2 = V1 | (1 << A1);
+                D[e][A0] = cscale(csub(P[V1], P[0]), ih[A0]);
+                D[e][A1] = cscale(csub(P[V2], P[V1]), ih[A1]);
+                D[e][A2] = cscale(csub(P[7], P[V2]), ih[A2]);
             }
+        } else {
+            D[0][0] = cscale(csub(P[1], P[0]), ih[0]);
+            D[0][1] = cscale(csub(P[2], P[0]), ih[1]);
+            D[1][0] = cscale(csub(P[3], P[2]), ih[0]);
+            D[1][1] = cscale(csub(P[3], P[1]), ih[1]);
+        }
     } else if constexpr (KIND == K_FD) {
         #pragma unroll
         for (int a = 0; a < DIM; ++a) D[0][a] = C64{(cs[a] - 1.0) / sa.h[a], sn[a] / sa.h[a]};
@@ -231,43 +169,50 @@ __device__ __forceinline__ bool symbol_at(const SymArgs &sa, long long k, C64 (&
     return true;
 }
 
-// Inverse of M = 1/2 (I + sum_T D_T D_T^H) (normalised symbol), by cofactors.
+// Inverse of the Hermitian M = 1/2 (I + sum_T D_T D_T^H) (normalised symbol)
+// by the adjugate: real diagonal Id and upper triangle Io = (01, 02, 12)
+// (2D: Io[0] = 01).
 template <int DIM, int NE>
-__device__ __forceinline__ void metric_inverse(const C64 (&D)[NE][DIM], C64 (&Mi)[DIM][DIM]) {
-    C64 M[DIM][DIM];
+__device__ __forceinline__ void metric_inverse(const C64 (&D)[NE][DIM], double (&Id)[DIM], C64 (&Io)[3]) {
+    double d[DIM];
+    C64 o[3] = {C64{0.0, 0.0}, C64{0.0, 0.0}, C64{0.0, 0.0}};
     #pragma unroll
-    for (int x = 0; x < DIM; ++x)
+    for (int x = 0; x < DIM; ++x) {
+        double s = 1.0;
         #pragma unroll
-        for (int y = 0; y < DIM; ++y) {
-            C64 s{x == y ? 1.0 : 0.0, 0.0};
-            #pragma unroll
-            for (int e = 0; e < NE; ++e) s = cadd(s, cmulc(D[e][x], D[e][y]));
-            M[x][y] = cscale(s, 0.5);
-        }
+        for (int e = 0; e < NE; ++e) s += D[e][x].x * D[e][x].x + D[e][x].y * D[e][x].y;
+        d[x] = 0.5 * s;
+    }
+    #pragma unroll
+    for (int u = 0; u < (DIM == 3 ? 3 : 1); ++u) {
+        const int x = (DIM == 3 && u == 2) ? 1 : 0, y = (DIM == 3 && u >= 1) ? 2 : 1;
+        C64 s{0.0, 0.0};
+        #pragma unroll
+        for (int e = 0; e < NE; ++e) s = cadd(s, cmulc(D[e][x], D[e][y]));
+        o[u] = cscale(s, 0.5);
+    }
     if constexpr (DIM == 2) {
-        const C64 det = csub(cmul(M[0][0], M[1][1]), cmul(M[0][1], M[1][0]));
-        const double dn = 1.0 / (det.x * det.x + det.y * det.y);
-        const C64 id = {det.x * dn, -det.y * dn};
-        Mi[0][0] = cmul(M[1][1], id);
-        Mi[1][1] = cmul(M[0][0], id);
-        Mi[0][1] = cmul(C64{-M[0][1].x, -M[0][1].y}, id);
-        Mi[1][0] = cmul(C64{-M[1][0].x, -M[1][0].y}, id);
+        const double id = 1.0 / (d[0] * d[1] - (o[0].x * o[0].x + o[0].y * o[0].y));
+        Id[0] = d[1] * id;
+        Id[1] = d[0] * id;
+        Io[0] = cscale(o[0], -id);
+        Io[1] = Io[2] = C64{0.0, 0.0};
     } else {
-        C64 cof[3][3];
-        #pragma unroll
-        for (int i = 0; i < 3; ++i)
-            #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const int r1 = (i + 1) % 3, r2 = (i + 2) % 3, c1 = (j + 1) % 3, c2 = (j + 2) % 3;
-                cof[i][j] = csub(cmul(M[r1][c1], M[r2][c2]), cmul(M[r1][c2], M[r2][c1]));
-            }
-        const C64 det = cadd(cadd(cmul(M[0][0], cof[0][0]), cmul(M[0][1], cof[0][1])), cmul(M[0][2], cof[0][2]));
-        const double dn = 1.0 / (det.x * det.x + det.y * det.y);
-        const C64 id = {det.x * dn, -det.y * dn};
-        #pragma unroll
-        for (int i = 0; i < 3; ++i)
-            #pragma unroll
-            for (int j = 0; j < 3; ++j) Mi[i][j] = cmul(cof[j][i], id);
+        const C64 a = o[0], b = o[1], c = o[2];
+        const double C0 = d[1] * d[2] - (c.x * c.x + c.y * c.y);
+        const double C1 = d[0] * d[2] - (b.x * b.x + b.y * b.y);
+        const double C2 = d[0] * d[1] - (a.x * a.x + a.y * a.y);
+        const C64 A01 = csub(cmulc(b, c), cscale(a, d[2]));  // b conj(c) - a d2
+        const C64 A02 = csub(cmul(a, c), cscale(b, d[1]));   // a c - b d1
+        const C64 A12 = csub(cmulc(b, a), cscale(c, d[0]));  // b conj(a) - c d0
+        const double det = d[0] * C0 + (a.x * A01.x + a.y * A01.y) + (b.x * A02.x + b.y * A02.y);
+        const double id = 1.0 / det;
+        Id[0] = C0 * id;
+        Id[1] = C1 * id;
+        Id[2] = C2 * id;
+        Io[0] = cscale(A01, id);
+        Io[1] = cscale(A02, id);
+        Io[2] = cscale(A12, id);
     }
 }
 
