@@ -217,45 +217,78 @@ __device__ __forceinline__ void stockham_pass(Cx<T> *buf, int nb, const FastDiv 
     __syncthreads();
 }
 
-// Pass with a prime radix R > 13 (known at run time only): every output is
-// the R-term sum of its Stockham butterfly evaluated directly, with the pass
-// twiddle and the DFT root folded into one exponent,
-//   y[q + m (p + L* d)] = sum_c w_n^{c m (p + L* d)} x[q + c m + m R p],
-// read from LDS (O(R) work per output instead of O(log R)).
+// Pass with a prime radix R > 13 (known at run time only), each butterfly's
+// outputs evaluated directly:
+//   y[q + m (p + L* d)] = sum_c w_n^{c m (p + L* d)} x[q + c m + m R p].
+// A thread takes B consecutive outputs d0 .. d0 + B - 1 of one butterfly and
+// reads each input once: the factor of output d0 + i at term c is
+// w_n^{c E0} (w_n^{c n / R})^i with E0 = m (p + L* d0), so per term it reads
+// the input and two twiddles from LDS and steps the other B - 1 factors by
+// complex multiplication (error growth over at most B - 1 steps).
 template <typename T, int PPT>
 __device__ __forceinline__ void direct_pass(Cx<T> *buf, int nb, int n, const PassInfo &ps, const Cx<T> *tw, int tws,
-                                         bool inv, int tx) {
+                                            bool inv, int tx) {
     constexpr int NT = kFftThreads;
+    constexpr int B = 8;
+    constexpr int KI = PPT / B + PPT / 17 + 2;  // work items per thread (R >= 17)
     const int R = ps.R, m = (int)ps.m.d, Ls = ps.Lstar;
-    const int tot = nb * n;
-    Cx<T> y[PPT];
+    const int nR = n / R;                       // butterflies per batch (= m L*)
+    const int nd = (R + B - 1) / B;             // output blocks per butterfly
+    const int items = nb * nR * nd;
+    Cx<T> y[KI][B];
     #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int t = tx + k * NT;
-        y[k] = Cx<T>{T(0), T(0)};
-        if (t < tot) {
-            const int j = t / nb;  // output element of the batch
-            const int b = t - j * nb;
-            const int q = j % m;
-            const int pd = j / m;
-            const int pp = pd % Ls;
-            const int E = m * pd;  // m (p + L* d) < n
+    for (int k = 0; k < KI; ++k) {
+        const int it = tx + k * NT;
+        #pragma unroll
+        for (int i = 0; i < B; ++i) y[k][i] = Cx<T>{T(0), T(0)};
+        if (it < items) {
+            const int b = it % nb;
+            const int r1 = it / nb;
+            const int db = r1 % nd;
+            const int pair = r1 / nd;
+            const int q = pair % m;
+            const int pp = pair / m;
+            const int E0 = m * (pp + Ls * db * B);  // < n
             const int ib = (q + m * R * pp) * nb + b;
-            Cx<T> acc = Cx<T>{T(0), T(0)};
-            int e = 0;
+            int e0 = 0, es = 0;
+            Cx<T> acc[B];
+            #pragma unroll
+            for (int i = 0; i < B; ++i) acc[i] = Cx<T>{T(0), T(0)};
             for (int c = 0; c < R; ++c) {
-                acc = cadd(acc, cmul(buf[ib + c * m * nb], twid(tw, tws, e, inv)));
-                e += E;
-                if (e >= n) e -= n;
+                const Cx<T> x = buf[ib + c * m * nb];
+                Cx<T> w = twid(tw, tws, e0, inv);
+                const Cx<T> st = twid(tw, tws, es, inv);
+                #pragma unroll
+                for (int i = 0; i < B; ++i) {
+                    acc[i] = cadd(acc[i], cmul(x, w));
+                    if (i + 1 < B) w = cmul(w, st);
+                }
+                e0 += E0;
+                if (e0 >= n) e0 -= n;
+                es += nR;
+                if (es >= n) es -= n;
             }
-            y[k] = acc;
+            #pragma unroll
+            for (int i = 0; i < B; ++i) y[k][i] = acc[i];
         }
     }
     __syncthreads();
     #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int t = tx + k * NT;
-        if (t < tot) buf[t] = y[k];
+    for (int k = 0; k < KI; ++k) {
+        const int it = tx + k * NT;
+        if (it < items) {
+            const int b = it % nb;
+            const int r1 = it / nb;
+            const int db = r1 % nd;
+            const int pair = r1 / nd;
+            const int q = pair % m;
+            const int pp = pair / m;
+            #pragma unroll
+            for (int i = 0; i < B; ++i) {
+                const int d = db * B + i;
+                if (d < R) buf[(q + m * (pp + Ls * d)) * nb + b] = y[k][i];
+            }
+        }
     }
     __syncthreads();
 }
