@@ -276,11 +276,20 @@ def cpu_baseline(n=40, iters=6000):
     t_cg = time.perf_counter() - t0
     dof = 3 * n ** 3
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": dof * iters / t_cg,
         "unit": "DOF-CG-iterations/s",
         "cores": cores,
         "kind": "oracle",
+        "host": {"cpu_model": model, "nproc": os.cpu_count(), "omp_num_threads": os.environ.get("OMP_NUM_THREADS")},
         "sample": (f"oracle plain CG (C CSR, OpenMP) on the same E=exp(GRF) recipe at {n}^3 "
                    f"(ell={16.0 * n / 256.0:g}), 1 load case, {iters} iterations in {t_cg:.2f} s; "
                    f"sparse assembly {t_asm:.2f} s excluded; nnz={K.nnz}"),
@@ -388,13 +397,28 @@ def main():
         torch.cuda.synchronize()
         del xs, ys
     traffic = traffic_from_profiles(dom, args.workload)
+    # measured ceiling: a plain 1 GiB device-to-device copy (read + write),
+    # fastest of three, timed with events on the current stream
+    cbuf = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    cdst = torch.empty_like(cbuf)
+    copy_gbs = 0.0
+    for _ in range(3):
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record()
+        cdst.copy_(cbuf)
+        c1.record()
+        torch.cuda.synchronize()
+        copy_gbs = max(copy_gbs, 2.0 * cbuf.numel() * 4 / (c0.elapsed_time(c1) / 1e3) / 1e9)
+    del cbuf, cdst
     kernels = {k: {"ms_total": round(v[0], 3), "launches": v[1],
                    "GBps_algorithmic": (round(kb[k] / (v[0] / 1e3) / 1e9, 1) if v[0] > 0 and kb[k] > 0 else None)}
                for k, v in prof.items()}
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             "avg_launch_ms": round(dom_ms / max(dom_n, 1), 4),
-            "algorithmic_bytes_per_launch": round(kb[dom] / max(dom_n, 1))}
+            "algorithmic_bytes_per_launch": round(kb[dom] / max(dom_n, 1)),
+            "copy_ceiling_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
     cg_ms = sum(v[0] for v in prof.values())
     all_bytes = sum(kb.values())
 
@@ -472,6 +496,10 @@ def main():
         "ms_per_cg_iteration": 1e3 * t / max(1, sum(max(x) for x in iters_all)),
         "fp32_vs_fp64_C_eff_rel_err": fp_err,
         "cg_loop_GBps_algorithmic": round(all_bytes / (cg_ms / 1e3) / 1e9, 1) if cg_ms > 0 else None,
+        # the floor 8 V per voxel and load case per iteration (u, r, p read and
+        # written once, one transform round trip) over the CG-loop kernel time
+        "floor_efficiency": round(8 * dim * s * N * lc_iters / (cg_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)
+        if cg_ms > 0 else None,
         "roofline": roof,
         "kernels": kernels,
         "sensitivity": sens,
