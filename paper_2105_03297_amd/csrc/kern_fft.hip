@@ -39,9 +39,15 @@ __device__ __forceinline__ Cx<T> twid(const Cx<T> *tw, int tws, int e, bool inv)
 }
 
 // Dynamic LDS holds the twiddle table of the transformed axis (and, in the
-// first-axis pass, the per-wavevector phase tables): staged once per
-// workgroup so the butterflies never wait on global memory.
+// fused first-axis pass, the phase factors of the block's inner wavevector
+// indices): staged once per workgroup so the butterflies never wait on global
+// memory.
 extern __shared__ double feh_dyn_lds[];
+
+// LDS one workgroup may hold on gfx950 (160 KiB).  Every launch checks its
+// static plus dynamic LDS against it on the host and reports FEH_ENOTSUP
+// instead of dispatching a workgroup the hardware cannot allocate.
+constexpr size_t kLdsPerWorkgroup = 160 * 1024;
 
 template <typename T>
 __device__ __forceinline__ void stage(T *dst, const T *src, int count) {
@@ -722,8 +728,8 @@ __device__ __forceinline__ void herm_inverse(const double (&Md)[D], const Cx<dou
 // slots past the block's pencils); the Parseval weight bit of the slot.
 template <typename T, int DIM>
 __device__ __forceinline__ void slot_inverse(const FK<T> &a, int e, int PB, long long in0, int lim,
-                                             const Cx<double> *aa0, const Cx<double> *om0, const Cx<double> *pin,
-                                             double (&Id)[DIM], Cx<double> (&Io)[3], bool &half) {
+                                             const Cx<double> *pin, double (&Id)[DIM], Cx<double> (&Io)[3],
+                                             bool &half) {
     constexpr int D = DIM;
     const int j = (int)a.d_PB.div((uint32_t)e);
     const int b = e - j * PB;
@@ -734,7 +740,7 @@ __device__ __forceinline__ void slot_inverse(const FK<T> &a, int e, int PB, long
     half = false;
     if (!(e < PB * a.n0 && b * D < lim && !(j == 0 && inn == 0))) return;
     int m1 = 0, kh;
-    if (DIM == 3) {
+    if constexpr (DIM == 3) {
         m1 = (int)a.d_nh.div((uint32_t)inn);
         kh = (int)(inn - (long long)m1 * a.nh);
     } else {
@@ -744,9 +750,9 @@ __device__ __forceinline__ void slot_inverse(const FK<T> &a, int e, int PB, long
     const double ch = a.chalf;
     double Md[D];
     Cx<double> Mo[3];
-    if (DIM == 3) {
-        const Cx<double> a0 = aa0[j], a1 = pin[4 * b + 0], a2 = pin[4 * b + 2];
-        const Cx<double> w0 = om0[j], w1 = pin[4 * b + 1], w2 = pin[4 * b + 3];
+    if constexpr (DIM == 3) {
+        const Cx<double> a0 = ld2(a.aa[0], j), a1 = pin[4 * b + 0], a2 = pin[4 * b + 2];
+        const Cx<double> w0 = ld2(a.om[0], j), w1 = pin[4 * b + 1], w2 = pin[4 * b + 3];
         const double n0s = nrm(a0), n1s = nrm(a1), n2s = nrm(a2);
         const double S = 6.0 * (n0s + n1s + n2s);
         Md[0] = ch * (S + 6.0 * n0s);
@@ -758,8 +764,8 @@ __device__ __forceinline__ void slot_inverse(const FK<T> &a, int e, int PB, long
         Mo[1] = cscale(cmul(cmulc(a0, a2), cadd(cmulc(cadd(two, cconj(w1)), w0), cmul(w2, cadd(two, w1)))), ch);
         Mo[2] = cscale(cmul(cmulc(a1, a2), cadd(cmulc(cadd(two, cconj(w0)), w1), cmul(w2, cadd(two, w0)))), ch);
     } else {
-        const Cx<double> a0 = aa0[j], a1 = pin[4 * b + 0];
-        const Cx<double> w0 = om0[j], w1 = pin[4 * b + 1];
+        const Cx<double> a0 = ld2(a.aa[0], j), a1 = pin[4 * b + 0];
+        const Cx<double> w0 = ld2(a.om[0], j), w1 = pin[4 * b + 1];
         const double n0s = nrm(a0), n1s = nrm(a1);
         const double S = 2.0 * (n0s + n1s);
         Md[0] = ch * (S + 2.0 * n0s);
@@ -807,25 +813,22 @@ __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
     const long long in0 = (long long)blk * PB;
     const int lim = (int)min((long long)PB, inner - in0) * D;
     const int cnt = nb * n0;
-    // dynamic LDS: twiddles of axis 0, then (mode 0) the axis-0 phase tables and
-    // the phase factors of this block's PB inner wavevector indices
+    // dynamic LDS: twiddles of axis 0, then (mode 0) the phase factors of this
+    // block's PB inner wavevector indices; the axis-0 phase factors are read
+    // from the plan's tables (once per wavevector slot, L2-resident)
     Cx<T> *twl = reinterpret_cast<Cx<T> *>(feh_dyn_lds);
     const int tw_bytes = ((n0 * (int)sizeof(Cx<T>) + 15) / 16) * 16;
-    Cx<double> *aa0 = reinterpret_cast<Cx<double> *>(reinterpret_cast<char *>(feh_dyn_lds) + tw_bytes);
-    Cx<double> *om0 = aa0 + n0;
-    Cx<double> *pin = om0 + n0;  // [PB][4]: aa1, om1, aa2, om2 (2D: aa1, om1)
+    Cx<double> *pin = reinterpret_cast<Cx<double> *>(reinterpret_cast<char *>(feh_dyn_lds) + tw_bytes);  // [PB][4]: aa1, om1, aa2, om2 (2D: aa1, om1)
     stage(twl, a.tw, n0);
     // per cached slot: real diagonal of M^-1, then its upper triangle (complex)
     T Mid[KC][D];
     Cx<T> Mio[KC][DIM == 3 ? 3 : 1];
     unsigned half_w = 0;  // bit kw: wavevector counted once in the half-spectrum Parseval sum
     if constexpr (MODE == 0) {
-        stage(aa0, reinterpret_cast<const Cx<double> *>(a.aa[0]), n0);
-        stage(om0, reinterpret_cast<const Cx<double> *>(a.om[0]), n0);
         for (int b = threadIdx.x; b < PB; b += NT) {
             const long long inn = in0 + b;
             if (inn < inner) {
-                if (DIM == 3) {
+                if constexpr (DIM == 3) {
                     const int m1 = (int)a.d_nh.div((uint32_t)inn);
                     const int kh = (int)(inn - (long long)m1 * a.nh);
                     pin[4 * b + 0] = ld2(a.aa[1], m1);
@@ -845,7 +848,7 @@ __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
                 double Id[D];
                 Cx<double> Io[3];
                 bool half;
-                slot_inverse<T, DIM>(a, threadIdx.x + kw * NT, PB, in0, lim, aa0, om0, pin, Id, Io, half);
+                slot_inverse<T, DIM>(a, threadIdx.x + kw * NT, PB, in0, lim, pin, Id, Io, half);
                 if (half) half_w |= 1u << kw;
                 #pragma unroll
                 for (int c = 0; c < D; ++c) Mid[kw][c] = T(Id[c]);
@@ -896,7 +899,7 @@ __global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
                     if constexpr (PERLC) {
                         double Id[D];
                         Cx<double> Io[3];
-                        slot_inverse<T, DIM>(a, e, PB, in0, lim, aa0, om0, pin, Id, Io, half);
+                        slot_inverse<T, DIM>(a, e, PB, in0, lim, pin, Id, Io, half);
                         #pragma unroll
                         for (int c = 0; c < D; ++c) md[c] = T(Id[c]);
                         #pragma unroll
@@ -1027,6 +1030,8 @@ int last_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     const dim3 g(a.total), b(kFftThreads);
     const bool gen = !pow2_len(a.ax.n);
     const size_t dyn = (size_t)a.nlast * sizeof(Cx<T>);
+    if (PPT * kFftThreads * sizeof(Cx<T>) + dyn > kLdsPerWorkgroup)
+        return set_error(FEH_ENOTSUP, "last axis too long for the LDS transform");
     if (inverse) {
         const bool upd = fa.p_upd != nullptr;
         if (upd && (fa.u_upd == nullptr || fa.state == nullptr))
@@ -1069,6 +1074,8 @@ int middle_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     a.inner_total = inner;
     a.nblk = (int)((inner + PB - 1) / PB);
     a.total = a.nblk * a.n0 * p.L;
+    if (PPT * kFftThreads * sizeof(Cx<T>) + (size_t)a.n1 * sizeof(Cx<T>) > kLdsPerWorkgroup)
+        return set_error(FEH_ENOTSUP, "middle axis too long for the LDS transform");
     if (pow2_len(a.ax.n))
         hipLaunchKernelGGL((k_middle<T, PPT, false>), dim3(a.total), dim3(kFftThreads), (size_t)a.n1 * sizeof(Cx<T>),
                            p.stream, a, inverse ? 1 : 0);
@@ -1101,6 +1108,8 @@ int first_plain_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     a.n0 = 1;     // one outer slice per load case
     a.nblk = (int)((inner + PB - 1) / PB);
     a.total = a.nblk * p.L;
+    if (PPT * kFftThreads * sizeof(Cx<T>) + (size_t)len * sizeof(Cx<T>) > kLdsPerWorkgroup)
+        return set_error(FEH_ENOTSUP, "first axis too long for the LDS transform");
     if (pow2_len(a.ax.n))
         hipLaunchKernelGGL((k_middle<T, PPT, false>), dim3(a.total), dim3(kFftThreads), (size_t)len * sizeof(Cx<T>),
                            p.stream, a, inverse ? 1 : 0);
@@ -1132,7 +1141,9 @@ int first_t(const feh_plan &p, const FftArgs &fa, int mode) {
     a.total = perlc ? a.nblk * p.L : a.nblk;  // one block per (load case, pencils) or per pencils
     dim3 g(a.total), b(kFftThreads);
     const bool gen = !pow2_len(a.ax.n);
-    const size_t dyn = ((a.n0 * sizeof(Cx<T>) + 15) / 16) * 16 + (2 * (size_t)a.n0 + 4 * (size_t)PB) * sizeof(Cx<double>);
+    const size_t dyn = ((a.n0 * sizeof(Cx<T>) + 15) / 16) * 16 + (mode == 0 ? 4 * (size_t)PB * sizeof(Cx<double>) : 0);
+    if (PPT * kFftThreads * sizeof(Cx<T>) + (kFftThreads / 64) * sizeof(double) + dyn > kLdsPerWorkgroup)
+        return set_error(FEH_ENOTSUP, "first axis too long for the LDS transform");
 #define FEH_FIRST(M, G)                                                                                   \
     do {                                                                                                  \
         if (perlc) hipLaunchKernelGGL((k_first<T, PPT, DIM, M, G, true>), g, b, dyn, p.stream, a);       \

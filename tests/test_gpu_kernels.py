@@ -18,7 +18,7 @@ FFT_SHAPES = [(8, 8), (6, 10), (5, 7), (32, 32), (12, 9), (64, 512), (20, 13),
               (17, 34), (151, 12), (34, 151), (4, 2039), (1661, 6), (17, 6, 34), (5, 151, 4),
               # the longest axes the LDS tiles take (first axis 2048 (FP64) / 3072 (FP32) in 2D,
               # last axis 4096)
-              (2048, 16), (16, 4096)]
+              (2048, 16), (16, 4096), (1365, 3, 2)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

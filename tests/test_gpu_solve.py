@@ -76,6 +76,24 @@ def test_random_material_matches_oracle(shape, prec):
         assert rel(out["stress_mean"][l], ref["sig_mean"][l]) < (1e-10 if prec == "fp64" else 1e-4)
 
 
+@pytest.mark.parametrize("shape,prec", [((2048, 16), "fp64"), ((3072, 16), "fp32"),
+                                        ((1365, 3, 2), "fp64"), ((2048, 2, 3), "fp32")])
+def test_longest_first_axis_matches_oracle(shape, prec):
+    """The longest first axis whose pencils fill one workgroup's LDS tile
+    (one pencil block of all D components): the fused first-axis pass at its
+    largest LDS footprint, against the direct solve."""
+    say("longest first axis", shape, prec)
+    from oracle import fe
+    dim = len(shape)
+    lam, mu = random_material(shape, 11, prec)
+    Eb = ms.unit_loads(dim)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    out = _solve(shape, lam, mu, Eb, prec, tol, max_iter=5000)
+    assert out["status"] == 0
+    ref = fe.homogenize(None, None, Eb, lam_mu=(lam, mu))
+    assert rel(out["C_eff"], ref["C_eff"]) < (1e-10 if prec == "fp64" else 1e-5)
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_laminate_exact(dim):
     """Laminate with interfaces on voxel faces: FE exact, C_eff equals the
