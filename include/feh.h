@@ -176,7 +176,8 @@ int feh_plan_autotune(feh_plan *plan, int reps);
 /* The plan's FFT schedule: values = [rows per workgroup (last axis),
  * pencils per workgroup (axis 1), pencils per workgroup (axis 0) (0 =
  * default heuristic), axis-0 workgroup layout (1: one workgroup per load
- * case, 0: every load case in one workgroup), stencil tile rows (3D: 8 or
+ * case, the default for a power-of-two axis 0; 0: every load case in one
+ * workgroup, the default otherwise), stencil tile rows (3D: 8 or
  * 16 rows of 32 voxels; 2D: 1)], then for each axis 0..2 the
  * number of passes followed by the radices in pass order.  Writes at most
  * n_values entries and returns the full length. */

@@ -49,6 +49,30 @@ extern __shared__ double feh_dyn_lds[];
 // instead of dispatching a workgroup the hardware cannot allocate.
 constexpr size_t kLdsPerWorkgroup = 160 * 1024;
 
+// Streaming global accesses with the nontemporal hint.  The last inverse pass
+// uses them for p, u and z: it reads and writes each element of those fields
+// once, and nothing reads them again before the next operator pass.  Measured
+// per pass, the hint pays only there: on the forward pass (q fresh from the
+// stencil) and on the spectrum passes it made the kernels slower.
+template <typename T>
+__device__ __forceinline__ Cx<T> ldc_nt(const Cx<T> *p) {
+    typedef T V __attribute__((ext_vector_type(2)));
+    const V v = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+    return Cx<T>{v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void stc_nt(Cx<T> *p, Cx<T> c) {
+    typedef T V __attribute__((ext_vector_type(2)));
+    V v;
+    v.x = c.x;
+    v.y = c.y;
+    __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
+}
+template <typename T>
+__device__ __forceinline__ T ldr_nt(const T *p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ __forceinline__ void str_nt(T *p, T v) { __builtin_nontemporal_store(v, p); }
+
 template <typename T>
 __device__ __forceinline__ void stage(T *dst, const T *src, int count) {
     for (int i = threadIdx.x; i < count; i += kFftThreads) dst[i] = src[i];
@@ -579,11 +603,11 @@ __global__ __launch_bounds__(kFftThreads) void k_last_inv(FK<T> a) {
                 const int sl = sl0 < nrows ? sl0 : nrows - 1;
                 const long long o = lbase + (long long)c * N + (long long)sl * a.nlast + (even ? 2 * j : j);
                 if (even) {
-                    pv[k] = *reinterpret_cast<const Cx<T> *>(a.p_upd + o);
-                    uv[k] = *reinterpret_cast<const Cx<T> *>(a.u_upd + o);
+                    pv[k] = ldc_nt(reinterpret_cast<const Cx<T> *>(a.p_upd + o));
+                    uv[k] = ldc_nt(reinterpret_cast<const Cx<T> *>(a.u_upd + o));
                 } else {
-                    pv[k] = Cx<T>{a.p_upd[o], T(0)};
-                    uv[k] = Cx<T>{a.u_upd[o], T(0)};
+                    pv[k] = Cx<T>{ldr_nt(a.p_upd + o), T(0)};
+                    uv[k] = Cx<T>{ldr_nt(a.u_upd + o), T(0)};
                 }
             }
             #pragma unroll
@@ -599,11 +623,11 @@ __global__ __launch_bounds__(kFftThreads) void k_last_inv(FK<T> a) {
                     const Cx<T> un = {uv[k].x + ap * pv[k].x, uv[k].y + ap * pv[k].y};
                     const Cx<T> pn = {z.x + beta * pv[k].x, z.y + beta * pv[k].y};
                     if (even) {
-                        *reinterpret_cast<Cx<T> *>(a.u_upd + o) = un;
-                        *reinterpret_cast<Cx<T> *>(a.p_upd + o) = pn;
+                        stc_nt(reinterpret_cast<Cx<T> *>(a.u_upd + o), un);
+                        stc_nt(reinterpret_cast<Cx<T> *>(a.p_upd + o), pn);
                     } else {
-                        a.u_upd[o] = un.x;
-                        a.p_upd[o] = pn.x;
+                        str_nt(a.u_upd + o, un.x);
+                        str_nt(a.p_upd + o, pn.x);
                     }
                 }
             }
@@ -618,8 +642,8 @@ __global__ __launch_bounds__(kFftThreads) void k_last_inv(FK<T> a) {
             const int c = b - sl * D;
             if (e0 < cnt && sl < nrows) {
                 const long long o = lbase + (long long)c * N + (long long)sl * a.nlast;
-                if (even) reinterpret_cast<Cx<T> *>(a.z + o)[j] = Cx<T>{y[k].x * sc, y[k].y * sc};
-                else a.z[o + j] = y[k].x * sc;
+                if (even) stc_nt(reinterpret_cast<Cx<T> *>(a.z + o) + j, Cx<T>{y[k].x * sc, y[k].y * sc});
+                else str_nt(a.z + o + j, y[k].x * sc);
             }
         }
     }
@@ -785,9 +809,10 @@ __device__ __forceinline__ void slot_inverse(const FK<T> &a, int e, int PB, long
 // (FP64, adjugate) and keeping them in registers in the plan precision.
 // PERLC = true: one workgroup per (load case, pencil block), the inverses
 // formed again per load case just in time (no register cache, more resident
-// workgroups to overlap memory and compute).
+// workgroups to overlap memory and compute).  The power-of-two PERLC
+// instantiations are held to 3 waves per SIMD (at most 168 VGPRs, no spills).
 template <typename T, int PPT, int DIM, int MODE, bool GEN, bool PERLC>
-__global__ __launch_bounds__(kFftThreads) void k_first(FK<T> a) {
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu((PERLC && !GEN) ? 3 : 1))) void k_first(FK<T> a) {
     constexpr int NT = kFftThreads;
     constexpr int D = DIM;
     constexpr int KW = (PPT + D - 1) / D;  // wavevector slots per thread: PB n0 <= PPT NT / D
@@ -1168,9 +1193,15 @@ int first_dispatch(const feh_plan &p, const FftArgs &fa, int mode) {
 
 }  // namespace
 
+// Default first-axis layout: one workgroup per (load case, pencil block) when
+// the axis length is a power of two.  That variant forms the inverses again per
+// load case but fits 3 waves per SIMD (FP32; 2 in FP64, bound by LDS) against 2
+// (FP32) or 1 (FP64) for the register-cached variant, and runs faster at every
+// measured size.  General lengths keep the cached variant (both hold about as
+// many registers there).
 bool first_per_load_case(const feh_plan &p) {
     if (p.tune_first_perlc != 0) return p.tune_first_perlc > 0;
-    return false;
+    return pow2_len((int)p.n[0]);
 }
 
 int first_pencils_default(const feh_plan &p) {

@@ -141,8 +141,12 @@ def test_plan_tuning_reports_default_schedule():
 def test_set_tuning_validates_and_round_trips():
     p = feh.feh_plan_create(3, (16, 12, 10), None, 2, feh.FEH_FP32)
     t = feh.feh_plan_tuning(p)
-    assert t["stencil_rows"] == 8 and t["first_per_load_case"] == 0
-    t2 = dict(t, stencil_rows=16, first_per_load_case=1, radices=[[4, 4], [3, 4], [5]])
+    # default axis-0 layout: one workgroup per load case for a power-of-two axis 0
+    assert t["stencil_rows"] == 8 and t["first_per_load_case"] == 1
+    q = feh.feh_plan_create(3, (15, 12, 10), None, 2, feh.FEH_FP32)
+    assert feh.feh_plan_tuning(q)["first_per_load_case"] == 0
+    feh.feh_plan_destroy(q)
+    t2 = dict(t, stencil_rows=16, first_per_load_case=0, radices=[[4, 4], [3, 4], [5]])
     feh.feh_plan_set_tuning(p, t2)
     assert feh.feh_plan_tuning(p) == t2
     for bad in (dict(t2, radices=[[4, 2], [3, 4], [5]]), dict(t2, radices=[[16], [3, 4], [5]]),
