@@ -396,6 +396,14 @@ int feh_profile_enable(feh_plan *plan, int enable);
  * kinds beyond 7 read as zero). */
 int feh_profile_read(const feh_plan *plan, double *ms_total, int64_t *launches, int n_kinds);
 
+/* Measurement: copy `bytes` (a multiple of 16; 16-byte aligned, non-overlapping
+ * device buffers) from src_dev to dst_dev on the given HIP stream with
+ * nontemporal 16-byte loads and stores, asynchronously.  It gives the
+ * read+write bandwidth the device attains for a plain streaming copy, the
+ * practical ceiling the HBM-bound kernels are compared with.  FEH_EINVAL for
+ * null, misaligned or overlapping arguments. */
+int feh_stream_copy(void *dst_dev, const void *src_dev, size_t bytes, void *hip_stream);
+
 /* Message of the last error on this thread ("" if none). */
 const char *feh_last_error(void);
 

@@ -23,7 +23,7 @@ __all__ = [
     "feh_set_material_lame", "feh_set_material_phases", "feh_set_material_field", "feh_solve",
     "feh_effective_stiffness", "feh_effective_stiffness_weights", "feh_energy_sensitivity",
     "feh_apply_operator", "feh_apply_preconditioner", "feh_apply_projection",
-    "feh_fft_forward", "feh_fft_inverse", "feh_profile_enable", "feh_profile_read", "PROFILE_KINDS",
+    "feh_fft_forward", "feh_fft_inverse", "feh_profile_enable", "feh_profile_read", "feh_stream_copy", "PROFILE_KINDS",
     "feh_batch_create", "feh_batch_destroy", "feh_batch_solve", "feh_batch_graph_launches",
     "feh_plan_autotune", "feh_plan_tuning", "feh_plan_set_tuning",
     "FEH_DERIV_FE", "FEH_DERIV_FD", "FEH_DERIV_CD", "FEH_DERIV_LS", "FEH_DERIV_FOURIER", "FEH_DERIV_FOURIER2",
@@ -86,6 +86,7 @@ _SIGS = {
     "feh_fft_inverse": (ctypes.c_int, [_vp, _vp, _vp]),
     "feh_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "feh_profile_read": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
+    "feh_stream_copy": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
     "feh_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int]),
     "feh_batch_destroy": (ctypes.c_int, [_vp]),
     "feh_batch_solve": (ctypes.c_int, [_vp, ctypes.POINTER(_dp), ctypes.c_double, ctypes.c_int, ctypes.c_int,
@@ -341,6 +342,11 @@ PROFILE_KINDS = ["stencil", "alpha", "fft_last_fwd", "fft_middle_fwd", "fft_firs
 
 def feh_profile_enable(plan, enable=True):
     return _check(load().feh_profile_enable(plan, 1 if enable else 0))
+
+
+def feh_stream_copy(dst_ptr, src_ptr, nbytes, stream=None):
+    """Nontemporal streaming copy of nbytes between device buffers (measurement)."""
+    return _check(load().feh_stream_copy(dst_ptr, src_ptr, nbytes, stream))
 
 
 def feh_profile_read(plan):

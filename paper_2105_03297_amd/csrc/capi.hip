@@ -1119,6 +1119,17 @@ int feh_profile_enable(feh_plan *plan, int enable) {
     return FEH_OK;
 }
 
+int feh_stream_copy(void *dst_dev, const void *src_dev, size_t bytes, void *hip_stream) {
+    if (!dst_dev || !src_dev) return set_error(FEH_EINVAL, "null argument");
+    if (bytes % 16 != 0 || reinterpret_cast<uintptr_t>(dst_dev) % 16 != 0 ||
+        reinterpret_cast<uintptr_t>(src_dev) % 16 != 0)
+        return set_error(FEH_EINVAL, "stream copy needs 16-byte aligned pointers and a multiple of 16 bytes");
+    const char *d = static_cast<const char *>(dst_dev), *s = static_cast<const char *>(src_dev);
+    if (d < s + bytes && s < d + bytes) return set_error(FEH_EINVAL, "stream copy buffers overlap");
+    if (bytes == 0) return FEH_OK;
+    return launch_stream_copy(dst_dev, src_dev, bytes / 16, static_cast<hipStream_t>(hip_stream));
+}
+
 int feh_profile_read(const feh_plan *plan, double *ms_total, int64_t *launches, int n_kinds) {
     if (!plan || !ms_total || !launches) return set_error(FEH_EINVAL, "null argument");
     for (int k = 0; k < n_kinds; ++k) {

@@ -227,6 +227,7 @@ int launch_inverse_last(const feh_plan &p, const FftArgs &a);   // c2r along the
 
 // scalar / vector kernels (kern_cg.hip)
 int launch_fill(const feh_plan &p, void *x, size_t count, double value);
+int launch_stream_copy(void *dst, const void *src, size_t n16, hipStream_t stream);
 int launch_aos_to_soa(const feh_plan &p, const void *aos, void *soa);
 int launch_soa_to_aos(const feh_plan &p, const void *soa, void *aos);
 int launch_init_state(const feh_plan &p, LcState *st, int n_load);

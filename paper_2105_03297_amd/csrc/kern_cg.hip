@@ -4,6 +4,8 @@
 // chunk of iterations runs without host round trips; the host polls the
 // active flags between chunks.  Reductions over per-block partial sums use a
 // fixed summation order, so repeated solves are bitwise identical.
+#include <algorithm>
+
 #include "device_common.hpp"
 
 namespace feh {
@@ -253,7 +255,27 @@ int grid_for(long long n) {
     return (int)g;
 }
 
+// Streaming copy of n 16-byte words with nontemporal loads and stores: the
+// attainable read+write bandwidth of the device, measured beside the kernels.
+__global__ __launch_bounds__(kThreads) void k_stream_copy(const void *__restrict__ src, void *__restrict__ dst,
+                                                          long long n) {
+    typedef unsigned int U4 __attribute__((ext_vector_type(4)));
+    const U4 *a = static_cast<const U4 *>(src);
+    U4 *b = static_cast<U4 *>(dst);
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(a + i), b + i);
+}
+
 }  // namespace
+
+int launch_stream_copy(void *dst, const void *src, size_t n16, hipStream_t stream) {
+    const long long n = (long long)n16;
+    const long long want = (n + kThreads - 1) / kThreads;
+    const int g = (int)std::max(1LL, std::min(want, 32768LL));
+    hipLaunchKernelGGL(k_stream_copy, dim3(g), dim3(kThreads), 0, stream, src, dst, n);
+    return hip_check(hipGetLastError(), "stream copy launch");
+}
 
 int launch_fill(const feh_plan &p, void *x, size_t count, double value) {
     const int g = grid_for((long long)count);

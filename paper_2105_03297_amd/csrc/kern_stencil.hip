@@ -105,11 +105,14 @@ __device__ __forceinline__ void tet_from_nodes(const T (&P)[8][3], T lam, T mu, 
 }
 
 // All six tetrahedra of a voxel; lam, mu already carry the tetrahedron volume.
+// The fluxes start at -0: x + (-0) = x exactly for every x (signed zeros
+// included), so the first contribution to each edge folds into a move-free
+// assignment, which +0 does not allow without relaxed floating-point rules.
 template <typename T, bool UNIT, bool EB>
 __device__ __forceinline__ void voxel3(const T (&P)[8][3], T lam, T mu, const T (&ih)[3], const T (&Eb)[6],
                                        T (&E)[36]) {
     #pragma unroll
-    for (int j = 0; j < 36; ++j) E[j] = T(0);
+    for (int j = 0; j < 36; ++j) E[j] = T(-0.0);
     tet_from_nodes<T, 0, 1, 2, UNIT, EB>(P, lam, mu, ih, Eb, E);
     tet_from_nodes<T, 0, 2, 1, UNIT, EB>(P, lam, mu, ih, Eb, E);
     tet_from_nodes<T, 1, 0, 2, UNIT, EB>(P, lam, mu, ih, Eb, E);
@@ -210,9 +213,11 @@ struct Tile<2, VYT> {
 };
 
 // The value held by lane - 1 of the wavefront (DPP shift of the whole wave
-// right by one lane; lane 0 receives zero).  In the 3D tile a row of 32
-// voxels lies inside one wavefront, so lane - 1 holds the voxel at z - 1.
-__device__ __forceinline__ int lane_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
+// right by one lane; lane 0, which has no source lane, receives zero through
+// the bound control, so no register has to be zeroed for it).  In the 3D tile
+// a row of 32 voxels lies inside one wavefront, so lane - 1 holds the voxel
+// at z - 1.
+__device__ __forceinline__ int lane_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true); }
 __device__ __forceinline__ float from_left(float v) {
     return __builtin_bit_cast(float, lane_shr1(__builtin_bit_cast(int, v)));
 }

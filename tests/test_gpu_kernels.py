@@ -128,3 +128,24 @@ def test_projection_matches_appendix_operator(shape, prec):
         Gd = pj.dense_projection(shape)
         assert rel(Ge[0].ravel(), Gd @ e.ravel()) < tol
     h.close()
+
+
+def test_stream_copy_is_exact_and_checks_arguments():
+    """The measurement copy moves every byte; misaligned, ragged or
+    overlapping requests are rejected."""
+    import torch
+    import paper_2105_03297_amd as feh
+    say("stream copy")
+    st = torch.cuda.current_stream().cuda_stream
+    for n in (16, 4096 + 16, (1 << 22) + 48):
+        src = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda")
+        dst = torch.zeros(n + 32, dtype=torch.uint8, device="cuda")
+        feh.feh_stream_copy(dst.data_ptr(), src.data_ptr(), n, st)
+        torch.cuda.synchronize()
+        assert torch.equal(dst[:n], src) and int(dst[n:].sum()) == 0
+    buf = torch.zeros(1024, dtype=torch.uint8, device="cuda")
+    for d, s_, n in ((buf.data_ptr() + 512, buf.data_ptr(), 24), (buf.data_ptr() + 520, buf.data_ptr(), 16),
+                     (buf.data_ptr() + 256, buf.data_ptr(), 512), (0, buf.data_ptr(), 16)):
+        with pytest.raises(feh.FehError) as ei:
+            feh.feh_stream_copy(d, s_, n, st)
+        assert ei.value.status == feh.FEH_EINVAL
