@@ -495,6 +495,28 @@ def main():
         del h64
         torch.cuda.empty_cache()
 
+    # reference: the plain FP64 solve of one load case (the first unit strain)
+    # on the same GPU and grid, same tolerance; one untimed warm-up solve,
+    # then one timed (wall clock around the blocking call)
+    fp64_single = None
+    if precname == "fp32" and not args.no_fp64_check:
+        h1 = feh.Homogenizer(shape, n_load=1, precision="fp64", device=dev)
+        h1.set_material(E=torch.as_tensor(m.E, dtype=torch.float64), nu=float(m.nu.flat[0]))
+        h1.solve(Ebars[:1], tol=tol, max_iter=max_iter)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        o1 = h1.solve(Ebars[:1], tol=tol, max_iter=max_iter)
+        torch.cuda.synchronize()
+        s1 = time.perf_counter() - t1
+        it1 = o1["report"][0]["iterations"]
+        v1 = dim * N * it1 / s1
+        fp64_single = {"value": v1, "unit": "DOF-CG-iterations/s", "s_solve": round(s1, 4), "iterations": it1,
+                       "ms_per_cg_iteration": round(s1 * 1e3 / max(it1, 1), 3), "tol": tol,
+                       "batched_fp32_over_fp64_single": round(value / v1, 3)}
+        log("fp64 single load case", fp64_single)
+        del h1
+        torch.cuda.empty_cache()
+
     strain = None
     if not args.no_strain_space:
         strain = strain_space_measure(log)
@@ -538,6 +560,7 @@ def main():
         # written once, one transform round trip) over the CG-loop kernel time
         "floor_efficiency": round(8 * dim * s * N * lc_iters / (cg_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)
         if cg_ms > 0 else None,
+        "fp64_single_load_case": fp64_single,
         "roofline": roof,
         "roofline_runner_up": roof_next,
         "kernels": kernels,
