@@ -163,3 +163,45 @@ def test_finite_strain_errors_and_uniform():
     out = hz.finite_strain_solve(Fb, kind="fe", max_newton=1, equil_tol=1e-14, newton_tol=1e-14)
     assert out["status"] == m.FEH_ENOCONV and out["report"][0]["newton_iterations"] == 1
     hz.close()
+
+
+def test_spheres128_bench_configuration_properties():
+    """The configuration the benchmark times (128^3 sphere packing, FE kind,
+    FP32, Fbar = diag(1.05, 0.98, 0.98), tolerances 1e-6), at full size where
+    the oracle cannot follow: converged, the mean deformation gradient is
+    Fbar, P equals the host FP64 Saint Venant-Kirchhoff stress of the GPU's F
+    at 4096 sampled (voxel, element) pairs, <P> is the mean of the P field,
+    and P F^T is symmetric (the second Piola-Kirchhoff stress is)."""
+    import torch
+    from oracle import finite
+    from paper_2105_03297_amd import Homogenizer
+    say("finite strain spheres128 bench configuration")
+    m, _, _, _ = ms.workload("spheres128")
+    lam = m.E * m.nu / ((1 + m.nu) * (1 - 2 * m.nu))
+    mu = m.E / (2 * (1 + m.nu))
+    Fbar = np.diag([1.05, 0.98, 0.98])[None]
+    hz = Homogenizer(m.shape, n_load=1, precision="fp32")
+    hz.set_material(lam=lam, mu=mu)
+    out = hz.finite_strain_solve(Fbar, kind="fe", newton_tol=1e-6, equil_tol=1e-6, cg_tol=1e-6, fields=True)
+    torch.cuda.synchronize()
+    rep = out["report"][0]
+    assert out["status"] == 0 and rep["newton_iterations"] >= 2
+    assert rep["rel_equilibrium"] <= 1e-5
+    F = out["F"][0].reshape(-1, *out["F"].shape[-3:])
+    P = out["P"][0].reshape(F.shape)
+    Fm = F.double().mean(dim=(0, 1)).cpu().numpy()
+    np.testing.assert_allclose(Fm, Fbar[0], rtol=0, atol=2e-6)
+    Pm = P.double().mean(dim=(0, 1)).cpu().numpy()
+    pscale = float(P.abs().max())
+    np.testing.assert_allclose(out["P_mean"][0], Pm, rtol=0, atol=1e-6 * pscale)
+    rng = np.random.default_rng(128)
+    vox = rng.integers(0, F.shape[0], 4096)
+    el = rng.integers(0, F.shape[1], 4096)
+    Fs = F[vox, el].cpu().numpy().astype(np.float64)
+    Ps = P[vox, el].cpu().numpy().astype(np.float64)
+    lv, mv = lam.reshape(-1)[vox], mu.reshape(-1)[vox]
+    Pr = finite.pk1(lv, mv, Fs)
+    np.testing.assert_allclose(Ps, Pr, rtol=0, atol=2e-5 * pscale)
+    PFt = Ps @ np.swapaxes(Fs, -1, -2)
+    np.testing.assert_allclose(PFt, np.swapaxes(PFt, -1, -2), rtol=0, atol=5e-5 * pscale)
+    hz.close()

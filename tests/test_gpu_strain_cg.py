@@ -178,3 +178,34 @@ def test_uniform_material_and_edge_cases():
         hb.strain_cg_solve(_ebars(2, 2, 1), kind="fe")
     assert ei.value.status == m.FEH_EINVAL
     hb.close()
+
+
+def test_spheres128_bench_configuration_equals_factored_solver():
+    """The configuration the benchmark times (128^3 sphere packing, FE kind in
+    strain space, FP32, 6 unit load cases, tol 1e-5), at full size where the
+    oracle cannot follow: it reaches the FE solution of the factored solver on
+    the same plan (C_eff and <sigma> to the FP32 solve accuracy), its energy
+    matrix is symmetric, and <sigma> equals the energy form's columns
+    (Hill-Mandel: <sigma_l> : Ebar_m = W_lm)."""
+    import torch
+    from paper_2105_03297_amd import Homogenizer
+    say("strain_cg spheres128 bench configuration")
+    m, Eb, _, _ = ms.workload("spheres128")
+    lam = m.E * m.nu / ((1 + m.nu) * (1 - 2 * m.nu))
+    mu = m.E / (2 * (1 + m.nu))
+    hz = Homogenizer(m.shape, n_load=len(Eb), precision="fp32")
+    hz.set_material(lam=lam, mu=mu)
+    b = hz.strain_cg_solve(Eb, kind="fe", tol=1e-5, max_iter=5000)
+    a = hz.solve(Eb, tol=1e-6, max_iter=5000)
+    torch.cuda.synchronize()
+    assert b["status"] == 0 and a["status"] == 0
+    assert all(r["rel_residual"] <= 1e-5 for r in b["report"])
+    scale = np.abs(a["C_eff"]).max()
+    np.testing.assert_allclose(b["C_eff"], a["C_eff"], rtol=0, atol=2e-4 * scale)
+    np.testing.assert_allclose(b["stress_mean"], a["stress_mean"], rtol=0,
+                               atol=2e-4 * np.abs(a["stress_mean"]).max())
+    W = b["energy"]
+    np.testing.assert_allclose(W, W.T, rtol=0, atol=1e-5 * np.abs(W).max())
+    HM = np.einsum("lij,mij->lm", b["stress_mean"], Eb)
+    np.testing.assert_allclose(HM, W, rtol=0, atol=2e-4 * np.abs(W).max())
+    hz.close()
