@@ -44,6 +44,12 @@ __device__ __forceinline__ Cx<T> twid(const Cx<T> *tw, int tws, int e, bool inv)
 // memory.
 extern __shared__ double feh_dyn_lds[];
 
+// FP64 transforms of general lengths (radix 3..13 and direct passes) are held
+// to at most 256 VGPRs, two waves per SIMD; with tiles sized to the pass, two
+// workgroups then fit a CU for rows of up to about 1700 points.
+template <typename T, bool GEN>
+constexpr int kGenWaves = (GEN && sizeof(T) == 8) ? 2 : 1;
+
 // LDS one workgroup may hold on gfx950 (160 KiB).  Every launch checks its
 // static plus dynamic LDS against it on the host and reports FEH_ENOTSUP
 // instead of dispatching a workgroup the hardware cannot allocate.
@@ -260,7 +266,9 @@ __device__ __forceinline__ void direct_pass(Cx<T> *buf, int nb, int n, const Pas
                                             bool inv, int tx) {
     constexpr int NT = kFftThreads;
     constexpr int B = 8;
-    constexpr int KI = PPT / B + PPT / 17 + 2;  // work items per thread (R >= 17)
+    // work items per thread: items = nb (n / R) ceil(R / B) <= cnt / B + (cnt / R)(B - 1) / B
+    // with cnt = nb n <= PPT NT and R >= 17, so at most PPT (17 + B - 1) / (17 B) per thread
+    constexpr int KI = (PPT * (17 + B - 1) + 17 * B - 1) / (17 * B);
     const int R = ps.R, m = (int)ps.m.d, Ls = ps.Lstar;
     const int nR = n / R;                       // butterflies per batch (= m L*)
     const int nd = (R + B - 1) / B;             // output blocks per butterfly
@@ -377,6 +385,8 @@ struct FK {
     int n0, n1, nlast, nh;
     long long N, rows, inner_total;
     int RR, PB, nblk, total;
+    int lbuf;                 // entries of the LDS tile (last and middle passes): the
+                              // dynamic LDS holds the tile, then the twiddle table
     int part_stride;
     int last_even;
     int use_axpy;             // selects the AXPY instantiation on the host
@@ -392,9 +402,10 @@ struct FK {
 // then every store; r and r_out may be the same buffer.
 // ---------------------------------------------------------------------------
 template <typename T, int PPT, bool GEN, bool AXPY>
-__global__ __launch_bounds__(kFftThreads) void k_last_fwd(FK<T> a) {
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kGenWaves<T, GEN>))) void k_last_fwd(FK<T> a) {
     constexpr int NT = kFftThreads;
-    __shared__ Cx<T> buf[PPT * NT];
+    __shared__ Cx<T> sbuf[GEN ? 1 : PPT * NT];
+    Cx<T> *buf = GEN ? reinterpret_cast<Cx<T> *>(feh_dyn_lds) : sbuf;
     int t = xcd_remap(blockIdx.x, a.total);
     const int lc = t / a.nblk;
     const int blk = t - lc * a.nblk;
@@ -411,7 +422,7 @@ __global__ __launch_bounds__(kFftThreads) void k_last_fwd(FK<T> a) {
     const int cnt = nb * nc;
     const long long N = a.N;
     const int even = a.last_even;
-    Cx<T> *twl = reinterpret_cast<Cx<T> *>(feh_dyn_lds);
+    Cx<T> *twl = GEN ? buf + a.lbuf : reinterpret_cast<Cx<T> *>(feh_dyn_lds);
     stage(twl, a.tw_last, a.nlast);
     const long long lbase = (long long)lc * D * N + s0 * a.nlast;
     // AXPY keeps two loads per slot in flight: 8 slots per round
@@ -503,9 +514,10 @@ __global__ __launch_bounds__(kFftThreads) void k_last_fwd(FK<T> a) {
 // applied in place (one pass over p and u while z is in registers).
 // ---------------------------------------------------------------------------
 template <typename T, int PPT, bool GEN, bool UPD>
-__global__ __launch_bounds__(kFftThreads) void k_last_inv(FK<T> a) {
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kGenWaves<T, GEN>))) void k_last_inv(FK<T> a) {
     constexpr int NT = kFftThreads;
-    __shared__ Cx<T> buf[PPT * NT];
+    __shared__ Cx<T> sbuf[GEN ? 1 : PPT * NT];
+    Cx<T> *buf = GEN ? reinterpret_cast<Cx<T> *>(feh_dyn_lds) : sbuf;
     int t = xcd_remap(blockIdx.x, a.total);
     const int lc = t / a.nblk;
     const int blk = t - lc * a.nblk;
@@ -519,7 +531,7 @@ __global__ __launch_bounds__(kFftThreads) void k_last_inv(FK<T> a) {
     const int cnt = nb * nc;
     const long long N = a.N;
     const int even = a.last_even;
-    Cx<T> *twl = reinterpret_cast<Cx<T> *>(feh_dyn_lds);
+    Cx<T> *twl = GEN ? buf + a.lbuf : reinterpret_cast<Cx<T> *>(feh_dyn_lds);
     stage(twl, a.tw_last, a.nlast);
     __syncthreads();
     // gather e -> (sl, k, c), components fastest (coalesced spectrum reads);
@@ -653,9 +665,10 @@ __global__ __launch_bounds__(kFftThreads) void k_last_inv(FK<T> a) {
 // middle axis (3D), complex to complex
 // ---------------------------------------------------------------------------
 template <typename T, int PPT, bool GEN>
-__global__ __launch_bounds__(kFftThreads) void k_middle(FK<T> a, int inv) {
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kGenWaves<T, GEN>))) void k_middle(FK<T> a, int inv) {
     constexpr int NT = kFftThreads;
-    __shared__ Cx<T> buf[PPT * NT];
+    __shared__ Cx<T> sbuf[GEN ? 1 : PPT * NT];
+    Cx<T> *buf = GEN ? reinterpret_cast<Cx<T> *>(feh_dyn_lds) : sbuf;
     int t = xcd_remap(blockIdx.x, a.total);
     const int ib = t % a.nblk;
     t /= a.nblk;
@@ -669,7 +682,7 @@ __global__ __launch_bounds__(kFftThreads) void k_middle(FK<T> a, int inv) {
     const long long in0 = (long long)ib * PB;
     Cx<T> *base = a.spec + ((long long)lc * a.n0 + i0) * n1 * inner + in0;
     const int lim = (int)min((long long)PB, inner - in0);
-    Cx<T> *twl = reinterpret_cast<Cx<T> *>(feh_dyn_lds);
+    Cx<T> *twl = GEN ? buf + a.lbuf : reinterpret_cast<Cx<T> *>(feh_dyn_lds);
     stage(twl, a.tw, n1);
     Cx<T> v[PPT];
     #pragma unroll
@@ -1032,6 +1045,24 @@ FK<T> base_args(const feh_plan &p, const FftArgs &fa) {
 template <typename T>
 constexpr int ppt() { return sizeof(T) == 4 ? 24 : 16; }
 
+// LDS of a last- or middle-axis pass whose tile holds `cnt` points, in
+// bytes (static tile plus dynamic part).  Power-of-two lengths keep a static
+// tile of the largest size (its address and the twiddle table's are then
+// compile-time constants, which the radix-2/4/8 passes are measurably faster
+// with); general lengths take a dynamic tile sized to the pass and rounded
+// up to 16 bytes, with the twiddle table after it, so that their long rows
+// leave room for a second resident workgroup.  *lbuf receives the dynamic
+// tile's entries (0 for power-of-two lengths), *dyn the dynamic bytes.
+template <typename T>
+size_t lds_of_pass(bool gen, int cnt, int table, int *lbuf, size_t *dyn) {
+    constexpr int PPT = sizeof(T) == 4 ? 24 : 16;
+    constexpr int q = 16 / (int)sizeof(Cx<T>);
+    *lbuf = gen ? (cnt + q - 1) / q * q : 0;
+    *dyn = ((size_t)*lbuf + table) * sizeof(Cx<T>);
+    const size_t stat = (gen ? 1 : (size_t)PPT * kFftThreads) * sizeof(Cx<T>);
+    return stat + *dyn;
+}
+
 template <typename T>
 int last_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     constexpr int PPT = ppt<T>();
@@ -1054,8 +1085,8 @@ int last_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     a.use_axpy = (!inverse && fa.q != nullptr && fa.state != nullptr) ? 1 : 0;
     const dim3 g(a.total), b(kFftThreads);
     const bool gen = !pow2_len(a.ax.n);
-    const size_t dyn = (size_t)a.nlast * sizeof(Cx<T>);
-    if (PPT * kFftThreads * sizeof(Cx<T>) + dyn > kLdsPerWorkgroup)
+    size_t dyn;
+    if (lds_of_pass<T>(gen, a.D * RR * nc, a.nlast, &a.lbuf, &dyn) > kLdsPerWorkgroup)
         return set_error(FEH_ENOTSUP, "last axis too long for the LDS transform");
     if (inverse) {
         const bool upd = fa.p_upd != nullptr;
@@ -1099,14 +1130,15 @@ int middle_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     a.inner_total = inner;
     a.nblk = (int)((inner + PB - 1) / PB);
     a.total = a.nblk * a.n0 * p.L;
-    if (PPT * kFftThreads * sizeof(Cx<T>) + (size_t)a.n1 * sizeof(Cx<T>) > kLdsPerWorkgroup)
+    size_t dyn;
+    if (lds_of_pass<T>(!pow2_len(a.ax.n), PB * a.n1, a.n1, &a.lbuf, &dyn) > kLdsPerWorkgroup)
         return set_error(FEH_ENOTSUP, "middle axis too long for the LDS transform");
     if (pow2_len(a.ax.n))
-        hipLaunchKernelGGL((k_middle<T, PPT, false>), dim3(a.total), dim3(kFftThreads), (size_t)a.n1 * sizeof(Cx<T>),
-                           p.stream, a, inverse ? 1 : 0);
+        hipLaunchKernelGGL((k_middle<T, PPT, false>), dim3(a.total), dim3(kFftThreads), dyn, p.stream, a,
+                           inverse ? 1 : 0);
     else
-        hipLaunchKernelGGL((k_middle<T, PPT, true>), dim3(a.total), dim3(kFftThreads), (size_t)a.n1 * sizeof(Cx<T>),
-                           p.stream, a, inverse ? 1 : 0);
+        hipLaunchKernelGGL((k_middle<T, PPT, true>), dim3(a.total), dim3(kFftThreads), dyn, p.stream, a,
+                           inverse ? 1 : 0);
     return hip_check(hipGetLastError(), "middle-axis fft launch");
 }
 
@@ -1133,14 +1165,15 @@ int first_plain_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     a.n0 = 1;     // one outer slice per load case
     a.nblk = (int)((inner + PB - 1) / PB);
     a.total = a.nblk * p.L;
-    if (PPT * kFftThreads * sizeof(Cx<T>) + (size_t)len * sizeof(Cx<T>) > kLdsPerWorkgroup)
+    size_t dyn;
+    if (lds_of_pass<T>(!pow2_len(a.ax.n), PB * len, len, &a.lbuf, &dyn) > kLdsPerWorkgroup)
         return set_error(FEH_ENOTSUP, "first axis too long for the LDS transform");
     if (pow2_len(a.ax.n))
-        hipLaunchKernelGGL((k_middle<T, PPT, false>), dim3(a.total), dim3(kFftThreads), (size_t)len * sizeof(Cx<T>),
-                           p.stream, a, inverse ? 1 : 0);
+        hipLaunchKernelGGL((k_middle<T, PPT, false>), dim3(a.total), dim3(kFftThreads), dyn, p.stream, a,
+                           inverse ? 1 : 0);
     else
-        hipLaunchKernelGGL((k_middle<T, PPT, true>), dim3(a.total), dim3(kFftThreads), (size_t)len * sizeof(Cx<T>),
-                           p.stream, a, inverse ? 1 : 0);
+        hipLaunchKernelGGL((k_middle<T, PPT, true>), dim3(a.total), dim3(kFftThreads), dyn, p.stream, a,
+                           inverse ? 1 : 0);
     return hip_check(hipGetLastError(), "first-axis fft launch");
 }
 
