@@ -14,7 +14,7 @@ namespace feh {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kVecBlocks = 512;  // blocks per load case of the vector kernels
+constexpr int kVecBlocks = 2048;  // blocks per load case of the vector kernels
 constexpr int kPostBlocks = 256;
 
 enum Kind { K_FE = FEH_DERIV_FE, K_FD = FEH_DERIV_FD, K_CD = FEH_DERIV_CD, K_LS = FEH_DERIV_LS,
