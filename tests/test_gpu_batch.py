@@ -170,9 +170,10 @@ def test_autotuned_plan_matches_default(shape, prec):
 @pytest.mark.parametrize("shape,prec", [((24, 20, 18), "fp64"), ((40, 36, 34), "fp32"), ((33, 17, 20), "fp64")])
 def test_explicit_schedules_match_default(shape, prec):
     """Every schedule feh_plan_set_tuning accepts gives the default plan's
-    solution to rounding: 16-row stencil tiles (ragged tiles included), one
-    first-axis workgroup per load case, other radix orders and smaller
-    workgroups; the CG iteration counts agree."""
+    solution to rounding: 16-row stencil tiles (ragged tiles included), the
+    first-axis layout the default does not use (one workgroup per load case,
+    or every load case in one workgroup with the inverses in registers), other
+    radix orders and smaller workgroups; the CG iteration counts agree."""
     import paper_2105_03297_amd as feh
     say("explicit schedules", shape, prec)
     dim = len(shape)
@@ -185,8 +186,9 @@ def test_explicit_schedules_match_default(shape, prec):
     base = feh.feh_plan_tuning(h.plan)
     PPT = 16 if prec == "fp64" else 24
     first_default = min(32, max(1, PPT * 256 // (shape[0] * dim)))
-    variants = [dict(base, stencil_rows=16), dict(base, first_per_load_case=1),
-                dict(base, stencil_rows=16, first_per_load_case=1, rows_last=2, pencils_mid=2,
+    other = 1 - base["first_per_load_case"]  # the first-axis layout the default does not use
+    variants = [dict(base, stencil_rows=16), dict(base, first_per_load_case=other),
+                dict(base, stencil_rows=16, first_per_load_case=other, rows_last=2, pencils_mid=2,
                      pencils_first=max(1, first_default // 4), radices=[list(reversed(r)) for r in base["radices"]])]
     for v in variants:
         feh.feh_plan_set_tuning(h.plan, v)
