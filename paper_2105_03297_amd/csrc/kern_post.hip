@@ -77,36 +77,49 @@ struct PK {
     int grad_only;      // projection test: write sym(grad u) only (no Ebar, no sums)
 };
 
-template <typename T, int DIM>
-__device__ __forceinline__ void load_corners(const PK<T> &a, int l, long long v, T (&P)[1 << DIM][DIM]) {
-    const int k2 = (int)(v % a.n2);
-    const long long r = v / a.n2;
-    const int k1 = (int)(r % a.n1);
-    const int k0 = (int)(r / a.n1);
-    const T *ub = a.u + (long long)l * DIM * a.N;
+// Node offsets of the corners of voxel v (corner c = c0 + 2 c1 (+ 4 c2)),
+// periodic.  Voxel indices fit 32 bits (N <= 2^31), so the coordinates come
+// from 32-bit divisions; the offsets serve every load case of the voxel.
+template <int DIM>
+__device__ __forceinline__ void corner_offsets(int n0, int n1, int n2, long long v, uint32_t (&idx)[1 << DIM]) {
+    const uint32_t vv = (uint32_t)v;
+    const uint32_t r = vv / (uint32_t)n2;
+    const int k2 = (int)(vv - r * (uint32_t)n2);
+    const int k1 = (int)(r % (uint32_t)n1);
+    const int k0 = (int)(r / (uint32_t)n1);
+    const int j0 = k0 + 1 == n0 ? 0 : k0 + 1, j1 = k1 + 1 == n1 ? 0 : k1 + 1, j2 = k2 + 1 == n2 ? 0 : k2 + 1;
     #pragma unroll
     for (int c = 0; c < (1 << DIM); ++c) {
         int i0, i1, i2;
         if (DIM == 3) {
-            i0 = wrap(k0 + (c & 1), a.n0);
-            i1 = wrap(k1 + ((c >> 1) & 1), a.n1);
-            i2 = wrap(k2 + ((c >> 2) & 1), a.n2);
+            i0 = (c & 1) ? j0 : k0;
+            i1 = ((c >> 1) & 1) ? j1 : k1;
+            i2 = ((c >> 2) & 1) ? j2 : k2;
         } else {
-            i0 = wrap(k0 + (c & 1), a.n0);
+            i0 = (c & 1) ? j0 : k0;
             i1 = 0;
-            i2 = wrap(k2 + ((c >> 1) & 1), a.n2);
+            i2 = ((c >> 1) & 1) ? j2 : k2;
         }
-        const long long idx = ((long long)i0 * a.n1 + i1) * a.n2 + i2;
-        #pragma unroll
-        for (int i = 0; i < DIM; ++i) P[c][i] = a.u ? ub[i * a.N + idx] : T(0);
+        idx[c] = ((uint32_t)i0 * (uint32_t)n1 + (uint32_t)i1) * (uint32_t)n2 + (uint32_t)i2;
     }
 }
 
 template <typename T, int DIM>
-__device__ __forceinline__ void voxel_strains(const PK<T> &a, int l, long long v, bool add_ebar,
+__device__ __forceinline__ void load_corners(const PK<T> &a, int l, const uint32_t (&idx)[1 << DIM],
+                                             T (&P)[1 << DIM][DIM]) {
+    const T *ub = a.u + (long long)l * DIM * a.N;
+    #pragma unroll
+    for (int c = 0; c < (1 << DIM); ++c) {
+        #pragma unroll
+        for (int i = 0; i < DIM; ++i) P[c][i] = a.u ? ub[i * a.N + idx[c]] : T(0);
+    }
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ void voxel_strains(const PK<T> &a, int l, const uint32_t (&cidx)[1 << DIM], bool add_ebar,
                                               double (&e)[DIM == 3 ? 6 : 2][DIM == 3 ? 6 : 3]) {
     T P[1 << DIM][DIM];
-    load_corners<T, DIM>(a, l, v, P);
+    load_corners<T, DIM>(a, l, cidx, P);
     if constexpr (DIM == 3) {
         strains3<T>(P, a.ih, e);
         if (add_ebar) {
@@ -196,8 +209,10 @@ __global__ __launch_bounds__(kThreads) void k_post(PK<T> a) {
     const long long mo = (long long)(l / a.G) * a.N;
     for (long long v = blk * (long long)kThreads + threadIdx.x; v < a.N; v += (long long)a.nblk * kThreads) {
         const double lam = double(a.lam[mo + v]), mu = double(a.mu[mo + v]);
+        uint32_t cidx[1 << DIM];
+        corner_offsets<DIM>(a.n0, a.n1, a.n2, v, cidx);
         double e[NE][NS];
-        voxel_strains<T, DIM>(a, l, v, true, e);
+        voxel_strains<T, DIM>(a, l, cidx, true, e);
         if (m < 0) {
             #pragma unroll
             for (int t = 0; t < NE; ++t) {
@@ -211,7 +226,7 @@ __global__ __launch_bounds__(kThreads) void k_post(PK<T> a) {
             }
         } else {
             double f[NE][NS];
-            voxel_strains<T, DIM>(a, m, v, true, f);
+            voxel_strains<T, DIM>(a, m, cidx, true, f);
             #pragma unroll
             for (int t = 0; t < NE; ++t) {
                 double s[NS];
@@ -237,7 +252,9 @@ __global__ __launch_bounds__(kThreads) void k_grad(PK<T> a) {
     const int l = blockIdx.y;
     for (long long v = blockIdx.x * (long long)kThreads + threadIdx.x; v < a.N; v += (long long)gridDim.x * kThreads) {
         double e[NE][NS];
-        voxel_strains<T, DIM>(a, l, v, false, e);
+        uint32_t cidx[1 << DIM];
+        corner_offsets<DIM>(a.n0, a.n1, a.n2, v, cidx);
+        voxel_strains<T, DIM>(a, l, cidx, false, e);
         #pragma unroll
         for (int t = 0; t < NE; ++t) put_full<T, DIM>(a.strain + (((long long)l * a.N + v) * NE + t) * DIM * DIM, e[t]);
     }
@@ -257,15 +274,17 @@ __global__ __launch_bounds__(kThreads) void k_sens(PK<T> a, const int *pl, const
     constexpr int NE = DIM == 3 ? 6 : 2;
     constexpr int NS = DIM == 3 ? 6 : 3;
     for (long long v = blockIdx.x * (long long)kThreads + threadIdx.x; v < a.N; v += (long long)gridDim.x * kThreads) {
+      uint32_t cidx[1 << DIM];
+      corner_offsets<DIM>(a.n0, a.n1, a.n2, v, cidx);
       for (int bb = 0; bb < a.nbatch; ++bb) {
         double gl = 0.0, gm = 0.0;
         for (int q = gofs[bb]; q < gofs[bb + 1]; ++q) {
             const int l = pl[q], m = pm[q];
             const double w = pw[q];
             double e[NE][NS], f[NE][NS];
-            voxel_strains<T, DIM>(a, l, v, true, e);
+            voxel_strains<T, DIM>(a, l, cidx, true, e);
             if (m != l) {
-                voxel_strains<T, DIM>(a, m, v, true, f);
+                voxel_strains<T, DIM>(a, m, cidx, true, f);
             } else {
                 #pragma unroll
                 for (int t = 0; t < NE; ++t)
