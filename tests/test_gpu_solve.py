@@ -94,6 +94,24 @@ def test_longest_first_axis_matches_oracle(shape, prec):
     assert rel(out["C_eff"], ref["C_eff"]) < (1e-10 if prec == "fp64" else 1e-5)
 
 
+@pytest.mark.parametrize("shape", [(2, 2), (2, 3), (3, 2), (2, 2, 2), (3, 2, 2), (2, 5, 2), (2, 2, 3)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_smallest_grids_match_oracle(shape, prec):
+    """Grids with axes of 2 or 3 voxels: every periodic neighbour wraps, the
+    stencil tiles and halos cover the cell several times over and the FFTs are
+    a single butterfly.  The solve matches the direct solve."""
+    say("smallest grid", shape, prec)
+    from oracle import fe
+    dim = len(shape)
+    lam, mu = random_material(shape, 21, prec)
+    Eb = ms.unit_loads(dim)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    out = _solve(shape, lam, mu, Eb, prec, tol, max_iter=500)
+    assert out["status"] == 0
+    ref = fe.homogenize(None, None, Eb, lam_mu=(lam, mu))
+    assert rel(out["C_eff"], ref["C_eff"]) < (1e-10 if prec == "fp64" else 1e-5)
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_laminate_exact(dim):
     """Laminate with interfaces on voxel faces: FE exact, C_eff equals the
