@@ -144,14 +144,18 @@ def apply_gradient_projection(g, X):
 # ---------------------------------------------------------------------------
 # Newton + projected CG
 # ---------------------------------------------------------------------------
-def _cg(A, b, tol, maxit):
+def _cg(A, b, tol, maxit, floor=0.0):
+    """CG on A x = b from x = 0, stopped at ||r|| <= tol ||b|| or at
+    ||r|| <= floor, the rounding level of the stress b is projected from:
+    below it the residual is noise, and iterating on it lets the zero-energy
+    modes of a vacuum drift without bound."""
     x = np.zeros_like(b)
     r = b.copy()
     p = r.copy()
     rr = np.sum(r * r)
     rr0 = rr
     it = 0
-    if rr0 == 0.0:
+    if rr0 == 0.0 or rr0 <= floor * floor:
         return x, 0
     while it < maxit:
         q = A(p)
@@ -163,7 +167,7 @@ def _cg(A, b, tol, maxit):
         r -= alpha * q
         it += 1
         rr_new = np.sum(r * r)
-        if np.sqrt(rr_new / rr0) <= tol:
+        if np.sqrt(rr_new / rr0) <= tol or rr_new <= floor * floor:
             break
         p = r + (rr_new / rr) * p
         rr = rr_new
@@ -203,7 +207,7 @@ def solve(lam, mu, Fbar, kind="fe", h=None, n_steps=1, newton_tol=1e-10, equil_t
             def A(x, Fc=Fc):
                 return apply_gradient_projection(g, tangent_apply(lam, mu, Fc, x))
 
-            dF, it = _cg(A, b, cg_tol, maxit)
+            dF, it = _cg(A, b, cg_tol, maxit, floor=64.0 * np.finfo(float).eps * nP)
             F += dF
             newton_its += 1
             cg_its += it

@@ -52,7 +52,12 @@ def solve(lam, mu, Ebar, kind="fe", h=None, tol=1e-12, maxit=5000):
     rr0 = rr
     hist = [1.0]
     it = 0
-    if rr0 == 0.0:
+    # The projected right-hand side -G sigma(Ebar) is computed from sigma(Ebar);
+    # at or below that evaluation's rounding level (64 eps |sigma(Ebar)|) it is
+    # zero, and so is the fluctuation.  The relative stop alone would iterate
+    # on rounding noise, whose CG recurrences lose all accuracy.
+    floor2 = (64.0 * np.finfo(float).eps) ** 2 * np.sum(_stress(lam, mu, Eb) ** 2)
+    if rr0 <= floor2:
         return Eb + x, 0, hist
     while it < maxit:
         Ap = A(p)
@@ -62,7 +67,7 @@ def solve(lam, mu, Ebar, kind="fe", h=None, tol=1e-12, maxit=5000):
         it += 1
         rr_new = np.sum(r * r)
         hist.append(float(np.sqrt(rr_new / rr0)))
-        if np.sqrt(rr_new / rr0) <= tol:
+        if np.sqrt(rr_new / rr0) <= tol or rr_new <= floor2:
             break
         p = r + (rr_new / rr) * p
         rr = rr_new

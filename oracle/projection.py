@@ -41,15 +41,37 @@ def _kgrid(shape, h):
     return np.meshgrid(*ks, indexing="ij")
 
 
+def _axis_phase(m, r, n):
+    """exp(2 pi i m r / n) for the integer wave indices m of an axis of n
+    points and an integer node offset r, exact (1, i, -1, -i) where m r / n
+    is a whole number of quarter turns."""
+    t = np.mod(m * r, n)
+    quarter = (4 * t) % n == 0
+    exact = np.array([1.0 + 0j, 1j, -1.0 + 0j, -1j])
+    return np.where(quarter, exact[((4 * t) // n) % 4], np.exp(2j * np.pi * (t / n)))
+
+
 def stencil_symbol(offsets, coeffs, shape, h):
     """Eq. genfourderiv: (1/h_a) sum_j s_j exp(i k . r_j) for a stencil with
     node offsets r_j (voxel units) and coefficients s_j (already divided by
-    h_a here)."""
-    K = _kgrid(shape, h)
+    h_a here).
+
+    exp(i k . r_j) is the product over the axes of exp(i k_a r_a h_a) =
+    exp(2 pi i m_a r_a / n_a), each factor exact at whole quarter turns.  A
+    symbol that vanishes mathematically is then exactly zero instead of a
+    rounding residue that the projection would treat as a derivative
+    direction: a central difference at the Nyquist wavevector
+    (i sin(pi) / h), or the least-squares x-derivative, whose factor
+    (1 + exp(i k_y)) vanishes at the y-Nyquist wavevector."""
+    ms = [np.round(np.fft.fftfreq(n, d=1.0 / n)).astype(np.int64) for n in shape]
+    M = np.meshgrid(*ms, indexing="ij")
     out = np.zeros(shape, dtype=np.complex128)
     for off, c in zip(offsets, coeffs):
-        phase = sum(K[a] * off[a] * h[a] for a in range(len(shape)))
-        out = out + c * np.exp(1j * phase)
+        e = np.ones(shape, dtype=np.complex128)
+        for a in range(len(shape)):
+            if int(off[a]) != 0:
+                e = e * _axis_phase(M[a], int(off[a]), shape[a])
+        out = out + c * e
     return out
 
 

@@ -42,7 +42,9 @@ def _oracle(lam, mu, Fbar, kind, **kw):
 
 
 CASES = [("fe", (8, 6)), ("fd", (8, 6)), ("cd", (9, 7)), ("ls", (9, 7)), ("fourier", (9, 7)), ("fourier2", (7, 9)),
-         ("fe", (4, 3, 5)), ("fd", (5, 4, 3)), ("fourier", (5, 3, 5))]
+         ("fe", (4, 3, 5)), ("fd", (5, 4, 3)), ("fourier", (5, 3, 5)),
+         # smallest grids (axes of 2 and 3 points)
+         ("fe", (2, 3)), ("fd", (2, 2)), ("cd", (3, 3)), ("fourier", (3, 3)), ("fe", (2, 2, 2)), ("fd", (3, 2, 2))]
 
 
 @pytest.mark.parametrize("kind,shape", CASES)

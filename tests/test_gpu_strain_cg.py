@@ -57,6 +57,11 @@ CASES = [
     ("fourier2", (16, 12), None), ("fourier2", (9, 13), None),
     ("fe", (8, 6, 10), None), ("fd", (10, 8, 6), None), ("cd", (7, 9, 5), None), ("fourier", (8, 8, 6), None),
     ("fourier", (7, 5, 9), (1.0, 1.2, 0.9)),
+    # smallest grids: axes of 2 and 3 points (single-butterfly transforms,
+    # symbols that vanish on whole axes)
+    ("fe", (2, 3), None), ("fd", (2, 2), None), ("cd", (2, 3), None), ("ls", (3, 2), None),
+    ("fourier", (3, 3), None), ("fourier2", (3, 3), None), ("fe", (2, 2, 2), None), ("fd", (3, 2, 2), None),
+    ("cd", (3, 3, 3), None),
 ]
 
 

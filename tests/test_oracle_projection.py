@@ -125,3 +125,34 @@ def test_gradient_projection_fe_idempotent_hermitian():
     np.testing.assert_allclose(g, np.conj(np.swapaxes(g, 0, 1)), atol=1e-15)
     tr = np.einsum("aa...->...", g).real
     assert np.allclose(tr.ravel()[1:], 1.0) and tr[0, 0] == 0
+
+
+def test_difference_symbols_vanish_exactly_at_nyquist():
+    """The central difference i sin(k h) / h (Sec. "Finite differences") is
+    exactly zero at the Nyquist wavevector of an even axis, and the
+    least-squares x-derivative carries the factor (1 + exp(i k_y)), exactly
+    zero at the y-Nyquist wavevector (Sec. "Least squares").  Elsewhere the
+    symbols equal their closed forms to rounding."""
+    shape, h = (4, 6), (1.0, 0.7)
+    cd = pj.symbols("cd", shape, h)[0]
+    assert np.all(cd[0][2, :] == 0) and np.all(cd[1][:, 3] == 0)
+    K = np.meshgrid(*[pj.wave_numbers(n, hh) for n, hh in zip(shape, h)], indexing="ij")
+    for a in range(2):
+        np.testing.assert_allclose(cd[a], 1j * np.sin(K[a] * h[a]) / h[a], rtol=0, atol=1e-15)
+    ls = pj.symbols("ls", shape, h)[0]
+    assert np.all(ls[0][:, 3] == 0) and np.all(ls[1][2, :] == 0)
+    ex = (np.exp(1j * K[0] * h[0]) - 1) * (1 + np.exp(1j * K[1] * h[1])) / (2 * h[0])
+    np.testing.assert_allclose(ls[0], ex, rtol=0, atol=1e-15)
+
+
+def test_modes_without_derivative_are_projected_out():
+    """On a 2 x 3 grid the central difference along the 2-point axis vanishes
+    at every wavevector (sin(0) = sin(pi) = 0): the projection then maps every
+    field onto gradients along the other axis only, and the wavevectors whose
+    whole symbol vanishes (m_y = 0) are projected to zero."""
+    D = pj.symbols("cd", (2, 3))
+    assert np.all(D[0, 0] == 0)
+    G = pj.small_strain_operator(D)
+    assert np.all(G[..., :, 0] == 0)
+    # the xx strain component never survives: no x-derivative exists
+    assert np.all(G[0, 0, 0, 0] == 0)
