@@ -62,6 +62,9 @@ CASES = [
     ("fe", (2, 3), None), ("fd", (2, 2), None), ("cd", (2, 3), None), ("ls", (3, 2), None),
     ("fourier", (3, 3), None), ("fourier2", (3, 3), None), ("fe", (2, 2, 2), None), ("fd", (3, 2, 2), None),
     ("cd", (3, 3, 3), None),
+    # even grids: central-difference and least-squares symbols vanish exactly
+    # at Nyquist wavevectors
+    ("cd", (8, 6), None), ("ls", (8, 6), None), ("cd", (6, 4, 8), None),
 ]
 
 
@@ -213,4 +216,41 @@ def test_spheres128_bench_configuration_equals_factored_solver():
     np.testing.assert_allclose(W, W.T, rtol=0, atol=1e-5 * np.abs(W).max())
     HM = np.einsum("lij,mij->lm", b["stress_mean"], Eb)
     np.testing.assert_allclose(HM, W, rtol=0, atol=2e-4 * np.abs(W).max())
+    hz.close()
+
+
+@pytest.mark.parametrize("kind,shape,axis", [
+    ("fd", (8, 6), 0), ("fd", (6, 4, 5), 2), ("cd", (9, 7), 0), ("cd", (5, 7, 3), 1),
+    ("ls", (8, 6), 0), ("ls", (6, 8), 1), ("fourier", (7, 8), 1), ("fourier", (4, 5, 6), 0), ("fe", (8, 6), 0),
+    ("fe", (4, 6, 5), 1),
+])
+@pytest.mark.parametrize("nus", [(0.3, 0.2), (0.0, 0.0)])
+def test_laminate_closed_form(kind, shape, axis, nus):
+    """Laminates (layers normal to `axis`) have the exact effective stiffness
+    of the layered closed form with every discrete derivative (central
+    differences on odd grids only: on an even axis their symbol vanishes at
+    the Nyquist wavevector, which a layering of that axis needs); with nu = 0
+    the loads along the layers have a zero right-hand side (the uniform
+    strain is the solution), which must stop at once rather than iterate on
+    rounding noise."""
+    import torch
+    from test_oracle_fe import _laminate_closed_form
+    from test_oracle_pcg_kinds import _voigt_C
+    from oracle import fe
+    from paper_2105_03297_amd import Homogenizer
+    say("strain_cg laminate", kind, shape, axis, nus)
+    dim = len(shape)
+    nl = 3 if shape[axis] > 5 else 2
+    m = ms.laminate(shape, axis, nl, E=(1.0, 7.0), nu=nus)
+    lam, mu = fe.lame(m.E, m.nu)
+    Eb = ms.unit_loads(dim)
+    hz = Homogenizer(shape, n_load=len(Eb), precision="fp64")
+    hz.set_material(lam=lam, mu=mu)
+    out = hz.strain_cg_solve(Eb, kind=kind, tol=1e-12, max_iter=2000)
+    torch.cuda.synchronize()
+    assert out["status"] == 0, [r for r in out["report"]]
+    frac1 = nl / shape[axis]
+    ref = _laminate_closed_form(_voigt_C(*fe.lame(7.0, nus[1]), dim), _voigt_C(*fe.lame(1.0, nus[0]), dim),
+                                frac1, dim, axis)
+    np.testing.assert_allclose(out["C_eff"], ref, rtol=0, atol=1e-9 * np.abs(ref).max())
     hz.close()
