@@ -112,6 +112,33 @@ def test_smallest_grids_match_oracle(shape, prec):
     assert rel(out["C_eff"], ref["C_eff"]) < (1e-10 if prec == "fp64" else 1e-5)
 
 
+@pytest.mark.parametrize("shape,L", [((20, 16), 64), ((6, 5, 4), 13)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_many_load_cases_match_oracle(shape, L, prec):
+    """Up to the plan's maximum of 64 load cases in one batched solve: every
+    load case's <sigma> and the full energy matrix W_lm = <e_l : C : e_m>
+    (L (L + 1) / 2 pair quantities in the post pass) against the direct
+    solve."""
+    say("many load cases", shape, L, prec)
+    from oracle import fe
+    dim = len(shape)
+    lam, mu = random_material(shape, 33, prec)
+    rng = np.random.default_rng(L)
+    A = rng.standard_normal((L, dim, dim)) * 0.01
+    Eb = 0.5 * (A + np.swapaxes(A, 1, 2))
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    out = _solve(shape, lam, mu, Eb, prec, tol, max_iter=2000)
+    assert out["status"] == 0 and len(out["report"]) == L
+    ref = fe.homogenize(None, None, Eb, lam_mu=(lam, mu))
+    lim = 1e-10 if prec == "fp64" else 1e-4
+    for l in range(L):
+        assert rel(out["stress_mean"][l], ref["sig_mean"][l]) < lim, l
+    W = out["energy"]
+    Wr = ref["W"]
+    np.testing.assert_allclose(W, W.T, rtol=0, atol=1e-12 * np.abs(W).max())
+    np.testing.assert_allclose(W, Wr, rtol=0, atol=(1e-9 if prec == "fp64" else 1e-4) * np.abs(Wr).max())
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_laminate_exact(dim):
     """Laminate with interfaces on voxel faces: FE exact, C_eff equals the
