@@ -254,3 +254,26 @@ def test_laminate_closed_form(kind, shape, axis, nus):
                                 frac1, dim, axis)
     np.testing.assert_allclose(out["C_eff"], ref, rtol=0, atol=1e-9 * np.abs(ref).max())
     hz.close()
+
+
+@pytest.mark.parametrize("kind,shape,L", [("fe", (12, 10), 20), ("fd", (5, 4, 3), 9)])
+def test_many_load_cases_match_oracle(kind, shape, L):
+    """Many load cases in one strain-space solve: every strain field and the
+    full energy matrix (L (L + 1) / 2 pair quantities) against the oracle."""
+    import torch
+    from paper_2105_03297_amd import Homogenizer
+    say("strain_cg many load cases", kind, shape, L)
+    dim = len(shape)
+    lam, mu = random_material(shape, seed=44)
+    Eb = _ebars(dim, L, 8)
+    hz = Homogenizer(shape, n_load=L, precision="fp64")
+    hz.set_material(lam=lam, mu=mu)
+    out = hz.strain_cg_solve(Eb, kind=kind, tol=1e-12, max_iter=2000, fields=True)
+    torch.cuda.synchronize()
+    ref, its = _oracle(lam, mu, Eb, kind)
+    got = out["strain"].cpu().numpy()
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-8 * np.abs(ref).max())
+    W = _energy(lam, mu, ref)
+    np.testing.assert_allclose(out["energy"], W, rtol=0, atol=1e-9 * np.abs(W).max())
+    assert all(r["status"] == 0 for r in out["report"])
+    hz.close()
