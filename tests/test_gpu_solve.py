@@ -197,6 +197,33 @@ def test_identity_material_one_iteration(dim):
     assert umax < 1e-12, umax
 
 
+@pytest.mark.parametrize("shape", [(16, 12), (6, 5, 7)])
+def test_warm_starts(shape):
+    """Warm starts (u0): from the converged u shifted by a constant (the mean
+    is removed) the solve stops at once with the same fields; from a
+    perturbed u it converges to the same C_eff; with Ebar = 0 and a random u0
+    the solution is the zero fluctuation."""
+    say("warm starts", shape)
+    dim = len(shape)
+    lam, mu = random_material(shape, 19, "fp64")
+    Eb = ms.unit_loads(dim)
+    cold = _solve(shape, lam, mu, Eb, "fp64", 1e-12, return_u=True)
+    u = cold["u"]
+    again = _solve(shape, lam, mu, Eb, "fp64", 1e-12, return_u=True, u0=u + 0.3)
+    assert max(r["iterations"] for r in again["report"]) <= 1
+    np.testing.assert_allclose(again["u"], u, rtol=0, atol=1e-9 * np.abs(u).max())
+    assert rel(again["C_eff"], cold["C_eff"]) < 1e-12
+    rng = np.random.default_rng(3)
+    pert = _solve(shape, lam, mu, Eb, "fp64", 1e-12, return_u=True, u0=u + 1e-3 * rng.standard_normal(u.shape))
+    assert pert["status"] == 0 and rel(pert["C_eff"], cold["C_eff"]) < 1e-10
+    np.testing.assert_allclose(pert["u"], u, rtol=0, atol=1e-8 * np.abs(u).max())
+    u0 = rng.standard_normal(u.shape[1:])[None]
+    zero = _solve(shape, lam, mu, np.zeros((1, dim, dim)), "fp64", 1e-12, return_u=True, u0=u0)
+    assert zero["status"] == 0
+    assert np.abs(zero["u"]).max() < 1e-10 * np.abs(u0).max()
+    assert np.abs(zero["stress_mean"]).max() < 1e-10
+
+
 def test_max_iter_reports_noconv_and_keeps_last_iterate():
     say("max_iter")
     from oracle import fe
