@@ -18,10 +18,10 @@ pytestmark = pytest.mark.gpu
 KINDS = ["fe", "fd", "cd", "ls", "fourier", "fourier2"]
 
 
-def _gpu(shape, lam, mu, Fbar, kind, prec="fp64", **kw):
+def _gpu(shape, lam, mu, Fbar, kind, prec="fp64", h=None, **kw):
     import torch
     from paper_2105_03297_amd import Homogenizer
-    hz = Homogenizer(shape, n_load=len(Fbar), precision=prec)
+    hz = Homogenizer(shape, n_load=len(Fbar), precision=prec, h=h)
     hz.set_material(lam=lam, mu=mu)
     out = hz.finite_strain_solve(Fbar, kind=kind, fields=True, **kw)
     torch.cuda.synchronize()
@@ -66,6 +66,25 @@ def test_finite_strain_matches_oracle(kind, shape):
         np.testing.assert_allclose(P[l], Pr, rtol=0, atol=1e-9 * np.abs(Pr).max())
         np.testing.assert_allclose(out["P_mean"][l], Pr.mean(axis=(0, 1)), rtol=0, atol=1e-10)
         np.testing.assert_allclose(F[l].mean(axis=(0, 1)), Fbar[l], atol=1e-12)
+
+
+@pytest.mark.parametrize("kind,shape,h", [("fe", (8, 6), (1.0, 0.7)), ("fd", (7, 9), (0.8, 1.3)),
+                                          ("fourier", (9, 7), (1.2, 0.9)), ("fe", (4, 5, 3), (1.0, 1.4, 0.8))])
+def test_finite_strain_voxel_sizes_match_oracle(kind, shape, h):
+    """Non-cubic voxels (the symbols carry 1/h_a; element volumes and the
+    FE gradients scale with h) against the oracle."""
+    from oracle import finite
+    say("finite strain voxel sizes", kind, shape, h)
+    dim = len(shape)
+    lam, mu = random_material(shape, seed=29, emin=1.0, emax=5.0)
+    rng = np.random.default_rng(4)
+    Fbar = np.array([np.eye(dim) + 0.05 * rng.standard_normal((dim, dim))])
+    out, F, P = _gpu(shape, lam, mu, Fbar, kind, h=h, newton_tol=1e-12, equil_tol=1e-12, cg_tol=1e-10)
+    Fr, nit, _ = finite.solve(lam, mu, Fbar[0], kind, h=h, newton_tol=1e-12, equil_tol=1e-12, cg_tol=1e-10)
+    ref = Fr.reshape((-1,) + Fr.shape[-3:])
+    assert out["report"][0]["status"] == 0
+    np.testing.assert_allclose(F[0], ref, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(F[0].mean(axis=(0, 1)), Fbar[0], atol=1e-12)
 
 
 @pytest.mark.parametrize("kind", KINDS)
