@@ -135,6 +135,25 @@ def test_two_pillars_with_vacuum(kind):
         assert right > 1e-4
 
 
+@pytest.mark.parametrize("kind", KINDS)
+def test_two_pillars_fp32(kind):
+    """The two-pillar vacuum setup in FP32 (FP32 fields, FP64 scalars; Newton
+    and CG tolerances 1e-6): converges for every kind, the vacuum carries no
+    stress, and the stress matches the FP64 oracle to FP32 accuracy."""
+    from oracle import fe, finite
+    say("two pillars fp32", kind)
+    m = ms.two_pillars()
+    lam, mu = fe.lame(m.E, m.nu)
+    Fbar = np.diag([1.0, 1.1])[None]
+    out, F, P = _gpu(m.shape, lam, mu, Fbar, kind, prec="fp32", newton_tol=1e-6, equil_tol=1e-6, cg_tol=1e-6)
+    assert out["report"][0]["status"] == 0, out["report"]
+    ref, _ = _oracle(lam, mu, Fbar, kind, equil_tol=1e-8)
+    Pr = finite.pk1(lam.reshape(-1), mu.reshape(-1), ref[0])
+    Pg = P[0].reshape(17, 17, -1, 2, 2)
+    assert np.abs(Pg[0]).max() == 0.0 and np.abs(Pg[8]).max() == 0.0
+    np.testing.assert_allclose(P[0], Pr, rtol=0, atol=1e-4 * np.abs(Pr).max())
+
+
 def test_load_steps_and_fp32():
     """Four load steps reach the one-step solution; FP32 fields against the
     FP64 solve; objectivity F(R Fbar) = R F(Fbar) on the GPU."""
