@@ -224,6 +224,43 @@ def test_warm_starts(shape):
     assert np.abs(zero["stress_mean"]).max() < 1e-10
 
 
+def test_two_plans_two_streams_two_threads():
+    """Plans share no device or host state (the error message is per thread):
+    two plans on their own streams, solved at the same time from two host
+    threads, give bitwise the results of the same solves run one after the
+    other."""
+    import threading
+    import torch
+    from paper_2105_03297_amd import Homogenizer
+    say("two plans, two streams, two threads")
+    cases = [((16, 12), 5, "fp64"), ((6, 5, 7), 6, "fp32")]
+    mats = [random_material(s, seed, prec) for s, seed, prec in cases]
+    loads = [ms.unit_loads(len(s)) for s, _, _ in cases]
+
+    def run(i, stream, out):
+        shape, _, prec = cases[i]
+        h = Homogenizer(shape, n_load=len(loads[i]), precision=prec, stream=stream)
+        h.set_material(lam=mats[i][0], mu=mats[i][1])
+        r = h.solve(loads[i], tol=1e-10 if prec == "fp64" else 1e-6, max_iter=3000)
+        out[i] = (r["C_eff"], [x["iterations"] for x in r["report"]])
+        h.close()
+
+    seq = [None, None]
+    for i in range(2):
+        run(i, None, seq)
+    conc = [None, None]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    threads = [threading.Thread(target=run, args=(i, streams[i], conc)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    for i in range(2):
+        assert conc[i] is not None, i
+        assert np.array_equal(conc[i][0], seq[i][0]) and conc[i][1] == seq[i][1], i
+
+
 def test_max_iter_reports_noconv_and_keeps_last_iterate():
     say("max_iter")
     from oracle import fe
