@@ -302,7 +302,10 @@ int feh_strain_cg_workspace_bytes(const feh_plan *plan, int kind, size_t *bytes)
  * modes where the symbol vanishes (k = 0; on even grids also the central
  * difference and least-squares modes where every D_T is zero) are projected
  * out.  The Fourier kinds apply the Hermitian part of G at Nyquist indices
- * (real fields).  Inner product: Frobenius, equal weights per point.
+ * (real fields); it is not a projection there, since the Fourier-derivative
+ * projection is exact on odd grids only, so on even grids CG can stall near
+ * 1e-11 relative and report FEH_ENOCONV at tighter tolerances.  Inner
+ * product: Frobenius, equal weights per point.
  * Uses the plan's material, grid and FFT tables (plans of one
  * microstructure: FEH_EINVAL for a batched plan) and leaves the plan's own
  * workspace vectors untouched.
@@ -358,7 +361,9 @@ int feh_finite_strain_workspace_bytes(const feh_plan *plan, int kind, size_t *by
  *   P_mean_host     nullable [n_load][D][D], average of P over the points
  *   report_host     nullable [n_load]
  * Returns FEH_OK, or FEH_ENOCONV if a load case did not converge (outputs
- * filled from the last iterate). */
+ * filled from the last iterate); FEH_ENOTSUP for the Fourier derivatives on a
+ * grid with an even axis (their projection is exact on odd grids only, Sec.
+ * "Even vs. odd number of grid points", and Newton on it need not converge). */
 int feh_finite_strain_solve(feh_plan *plan, int kind, const double *Fbar_host, int n_steps, double newton_tol,
                             double equil_tol, double cg_tol, int max_newton, int max_cg, void *work_dev,
                             size_t work_bytes, void *F_dev, void *P_dev, double *P_mean_host,

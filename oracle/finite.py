@@ -176,11 +176,19 @@ def _cg(A, b, tol, maxit, floor=0.0):
 
 def solve(lam, mu, Fbar, kind="fe", h=None, n_steps=1, newton_tol=1e-10, equil_tol=1e-11, cg_tol=1e-10,
           max_newton=50, maxit=5000, history=None):
-    """Returns (F[grid..., n_e, D, D], newton iterations, total CG iterations)."""
+    """Returns (F[grid..., n_e, D, D], newton iterations, total CG iterations).
+
+    The Fourier derivatives ('fourier', 'fourier2') need odd grid sizes: the
+    paper's Sec. "Even vs. odd number of grid points" shows that their
+    projection is exact only there (the derivative is ambiguous at the Nyquist
+    wavevector of an even axis), and Newton on the inexact one need not
+    converge."""
     lam = np.asarray(lam, float)
     mu = np.asarray(mu, float)
     shape = lam.shape
     dim = len(shape)
+    if kind in ("fourier", "fourier2") and any(n % 2 == 0 for n in shape):
+        raise ValueError("finite strain with a Fourier derivative needs odd grid sizes")
     g = projector(kind, shape, h)
     ne = g.shape[0] // dim
     I = np.eye(dim)

@@ -624,6 +624,14 @@ int feh_finite_strain_solve(feh_plan *plan, int kind, const double *Fbar_host, i
         feh_plan &p = *plan;
         const int ne = points_of(kind, p.dim);
         if (ne < 1) return set_error(FEH_ENOTSUP, "derivative kind not defined in this dimension");
+        if (kind == K_FOURIER || kind == K_FOURIER2) {
+            // the Fourier derivative is ambiguous at the Nyquist wavevector of
+            // an even axis, and its projection is exact on odd grids only; the
+            // Newton iteration on the inexact one need not converge
+            for (int a = 0; a < p.dim; ++a)
+                if (p.n[a] % 2 == 0)
+                    return set_error(FEH_ENOTSUP, "finite strain with a Fourier derivative needs odd grid sizes");
+        }
         if (!p.ws) return set_error(FEH_ENOMEM, "workspace not set (feh_plan_set_workspace)");
         if (!p.material_set) return set_error(FEH_EINVAL, "material not set");
         if (p.nbatch != 1) return set_error(FEH_EINVAL, "finite strain takes plans of one microstructure");

@@ -198,6 +198,11 @@ def test_finite_strain_errors_and_uniform():
         m.feh_finite_strain_solve(hz.plan, m.FEH_DERIV_FE, Fb, 1, 1e-10, 1e-10, 1e-10, 10, 100, work.data_ptr(),
                                   nbytes - 256)
     assert ei.value.status == m.FEH_ENOMEM
+    # the Fourier-derivative projection is exact on odd grids only (10 x 8)
+    for kind in ("fourier", "fourier2"):
+        with pytest.raises(m.FehError) as ei:
+            hz.finite_strain_solve(Fb, kind=kind)
+        assert ei.value.status == m.FEH_ENOTSUP
     lam, mu = random_material(shape, seed=5)
     hz.set_material(lam=lam, mu=mu)
     out = hz.finite_strain_solve(Fb, kind="fe", max_newton=1, equil_tol=1e-14, newton_tol=1e-14)
