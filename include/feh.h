@@ -194,8 +194,11 @@ int feh_plan_tuning(const feh_plan *plan, int *values, int n_values);
  * rounding. */
 int feh_plan_set_tuning(feh_plan *plan, const int *values, int n_values);
 
-/* Uneven batches: plans of different grids (each possibly a batched plan)
- * that share one created HIP stream, solved together.  After each plan's
+/* Uneven batches: plans of different grids (each possibly a batched plan),
+ * each on a created HIP stream (plans may share one), solved together.
+ * Plans on different streams run concurrently: eagerly each plan's kernels
+ * go to its own stream, and a captured graph forks one branch per stream
+ * from the first plan's stream and joins them at its end.  After each plan's
  * set-up, the CG iterations of all plans run in chunks of 4, 8, then 16
  * iterations per plan; with use_graph != 0 each chunk is one hipGraphLaunch
  * of a graph captured once per (chunk, tol, max_iter) and replayed, so a
@@ -204,8 +207,7 @@ int feh_plan_set_tuning(feh_plan *plan, const int *values, int n_values);
  * at once from every kernel).  The batch keeps pointers to the plans (the
  * caller keeps them, their workspaces and materials alive and unchanged
  * while the batch exists; otherwise destroy and re-create the batch).
- * FEH_EINVAL for null or repeated plans, plans on different streams or on
- * the null stream. */
+ * FEH_EINVAL for null or repeated plans or plans on the null stream. */
 int feh_batch_create(feh_batch **batch, feh_plan *const *plans, int n_plans);
 int feh_batch_destroy(feh_batch *batch);
 

@@ -601,15 +601,17 @@ class Homogenizer:
 
 
 class UnevenBatch:
-    """Microstructures of uneven sizes solved together on one dedicated stream.
+    """Microstructures of uneven sizes solved together.
 
     maps: list of (lam, mu) per-voxel arrays (any grid shapes, one dimension);
     maps of the same shape share a batched plan (at most 64 load cases per
     plan), and all plans form one ``feh_batch`` whose CG chunks run as
-    captured HIP graphs.  n_load load cases per map (default: the nv unit
-    Voigt loads)."""
+    captured HIP graphs.  The plans take up to ``n_streams`` dedicated streams
+    in turn (default 4, the hardware queues a process gets by default), so
+    the short kernels of different grids overlap.  n_load load cases per map
+    (default: the nv unit Voigt loads)."""
 
-    def __init__(self, maps, n_load=None, precision="fp32", device="cuda"):
+    def __init__(self, maps, n_load=None, precision="fp32", device="cuda", n_streams=4):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -621,6 +623,9 @@ class UnevenBatch:
         groups = {}
         for i, (lam, mu) in enumerate(maps):
             groups.setdefault(tuple(np.shape(lam)), []).append(i)
+        n_plans = sum((len(idx) + cap - 1) // cap for idx in groups.values())
+        self.streams = [self.stream] + [torch.cuda.Stream(device=self.device)  # default priority
+                                        for _ in range(max(1, min(int(n_streams), n_plans)) - 1)]
         self.plans = []   # (Homogenizer, [map indices])
         self.where = {}   # map index -> (plan number, slot)
         with torch.cuda.stream(self.stream):
@@ -628,7 +633,8 @@ class UnevenBatch:
                 for k in range(0, len(idx), cap):
                     part = idx[k:k + cap]
                     hz = Homogenizer(shape, n_load=self.n_load, precision=precision, device=self.device,
-                                     stream=self.stream, n_batch=len(part))
+                                     stream=self.streams[len(self.plans) % len(self.streams)],
+                                     n_batch=len(part))
                     lam = np.stack([np.asarray(maps[i][0], dtype=np.float64) for i in part])
                     mu = np.stack([np.asarray(maps[i][1], dtype=np.float64) for i in part])
                     hz.set_material(lam=lam, mu=mu)
@@ -646,7 +652,8 @@ class UnevenBatch:
         for (hz, _), e in zip(self.plans, Ebs):
             hz._last_Ebar = e
         rc, sm, W, rep = feh_batch_solve(self.batch, Ebs, tol, max_iter, use_graph)
-        self.stream.synchronize()
+        for s in self.streams:
+            s.synchronize()
         G = self.n_load
         nv = 3 if self.dim == 2 else 6
         out = [None] * self.n_maps

@@ -725,7 +725,10 @@ int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
 
 struct feh_batch {
     std::vector<feh_plan *> plans;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;        // the first plan's stream: graph capture and launch
+    std::vector<hipStream_t> others;     // the other plans' distinct streams
+    hipEvent_t fork = nullptr;           // capture fork (recorded on stream)
+    std::vector<hipEvent_t> joins;       // capture joins, one per other stream
     // instantiated graphs, keyed by (chunk length, tol, max_iter): the CG
     // kernels read their state from device memory, so a graph replays for as
     // long as the plans, their workspaces and the stopping rule are unchanged
@@ -742,6 +745,10 @@ struct feh_batch {
 static void batch_clear(feh_batch &b) {
     for (auto &e : b.graphs) (void)hipGraphExecDestroy(e.exec);
     b.graphs.clear();
+    for (hipEvent_t e : b.joins) (void)hipEventDestroy(e);
+    b.joins.clear();
+    if (b.fork) (void)hipEventDestroy(b.fork);
+    b.fork = nullptr;
 }
 
 static int batch_graph(feh_batch &b, int chunk, double tol, int max_iter, hipGraphExec_t &exec) {
@@ -751,12 +758,26 @@ static int batch_graph(feh_batch &b, int chunk, double tol, int max_iter, hipGra
             return FEH_OK;
         }
     CK(hip_check(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal), "begin capture"));
+    // plans on other streams join the capture through the fork event and
+    // rejoin the capturing stream at the end: the graph holds one branch per
+    // stream, and the branches run concurrently
     int rc = FEH_OK;
+    if (!b.others.empty()) {
+        rc = hip_check(hipEventRecord(b.fork, b.stream), "capture fork");
+        for (size_t k = 0; k < b.others.size() && rc == FEH_OK; ++k)
+            rc = hip_check(hipStreamWaitEvent(b.others[k], b.fork, 0), "capture fork");
+    }
     for (int i = 0; i < chunk && rc == FEH_OK; ++i)
         for (feh_plan *p : b.plans) {
             rc = cg_iteration(*p, p->ptr<LcState>(p->off_state), tol, max_iter);
             if (rc != FEH_OK) break;
         }
+    for (size_t k = 0; k < b.others.size(); ++k) {
+        // always rejoin, also after an error, so that the capture can end
+        const int r1 = hip_check(hipEventRecord(b.joins[k], b.others[k]), "capture join");
+        const int r2 = hip_check(hipStreamWaitEvent(b.stream, b.joins[k], 0), "capture join");
+        if (rc == FEH_OK) rc = r1 ? r1 : r2;
+    }
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(b.stream, &g);
     if (rc != FEH_OK) {
@@ -778,14 +799,28 @@ int feh_batch_create(feh_batch **out, feh_plan *const *plans, int n_plans) {
         if (!plans || n_plans < 1) return set_error(FEH_EINVAL, "need at least one plan");
         for (int i = 0; i < n_plans; ++i) {
             if (!plans[i]) return set_error(FEH_EINVAL, "null plan");
-            if (plans[i]->stream != plans[0]->stream) return set_error(FEH_EINVAL, "plans must share one stream");
+            if (plans[i]->stream == nullptr) return set_error(FEH_EINVAL, "a batch needs created (non-null) streams");
             for (int j = 0; j < i; ++j)
                 if (plans[j] == plans[i]) return set_error(FEH_EINVAL, "a plan appears twice");
         }
-        if (plans[0]->stream == nullptr) return set_error(FEH_EINVAL, "a batch needs a created (non-null) stream");
         auto b = new feh_batch();
         b->plans.assign(plans, plans + n_plans);
         b->stream = plans[0]->stream;
+        for (int i = 1; i < n_plans; ++i)
+            if (plans[i]->stream != b->stream &&
+                std::find(b->others.begin(), b->others.end(), plans[i]->stream) == b->others.end())
+                b->others.push_back(plans[i]->stream);
+        if (!b->others.empty()) {
+            int rc = hip_check(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming), "batch events");
+            b->joins.assign(b->others.size(), nullptr);
+            for (size_t k = 0; k < b->others.size() && rc == FEH_OK; ++k)
+                rc = hip_check(hipEventCreateWithFlags(&b->joins[k], hipEventDisableTiming), "batch events");
+            if (rc != FEH_OK) {
+                batch_clear(*b);
+                delete b;
+                return rc;
+            }
+        }
         *out = b;
         return FEH_OK;
     } catch (const std::bad_alloc &) {
