@@ -199,3 +199,26 @@ def test_explicit_schedules_match_default(shape, prec):
         its_ref = [r["iterations"] for r in ref["report"]]
         assert max(abs(x - y) for x, y in zip(its, its_ref)) <= (1 if prec == "fp64" else 2), (v, its, its_ref)
     h.close()
+
+
+def test_uneven_batch_streams_do_not_change_results():
+    """The plans of an uneven batch on one shared stream or on separate
+    streams (concurrent kernels, forked graph branches) give bitwise the same
+    results, with graph replay and with eager launches."""
+    import paper_2105_03297_amd as feh
+    say("uneven batch one vs several streams")
+    rng = np.random.default_rng(12)
+    shapes = [(24, 20), (9, 31), (16, 16), (24, 20), (9, 31), (40, 8)]
+    maps = [random_material(s, int(rng.integers(1000)), "fp32") for s in shapes]
+    res = {}
+    for ns in (1, 4):
+        for graph in (True, False):
+            ub = feh.UnevenBatch(maps, precision="fp32", n_streams=ns)
+            assert len(ub.streams) == min(ns, 4)
+            out = ub.solve(ms.unit_loads(2), tol=1e-6, max_iter=3000, use_graph=graph)
+            res[(ns, graph)] = [(o["C_eff"], [r["iterations"] for r in o["report"]]) for o in out]
+            ub.close()
+    ref = res[(1, False)]
+    for key, val in res.items():
+        for (c, it), (cr, itr) in zip(val, ref):
+            assert np.array_equal(c, cr) and it == itr, key
