@@ -391,6 +391,7 @@ struct FK {
     int last_even;
     int use_axpy;             // selects the AXPY instantiation on the host
     double out_scale, invN, chalf;  // chalf = element volume / 2
+    float near0;              // FP32 plans: sum_a |aa_a|^2 below which M^-1 is formed in FP64
 };
 
 // ---------------------------------------------------------------------------
@@ -721,30 +722,33 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kGe
 // inverse (mode 0); forward only (mode 1); inverse only (mode 2)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ Cx<double> ld2(const double *p, int i) { return Cx<double>{p[2 * i], p[2 * i + 1]}; }
-__device__ __forceinline__ double nrm(Cx<double> a) { return a.x * a.x + a.y * a.y; }
+template <typename R>
+__device__ __forceinline__ R nrm(Cx<R> a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 // Inverse of the Hermitian positive definite M (diagonal Md, upper triangle
-// Mo = (M01, M02, M12)) by the adjugate: Mi = (real diagonal, M01', M02', M12').
-template <int D>
-__device__ __forceinline__ void herm_inverse(const double (&Md)[D], const Cx<double> (&Mo)[3], double (&Id)[D],
-                                             Cx<double> (&Io)[3]) {
+// Mo = (M01, M02, M12)) by the adjugate in the scalar type R: Id = real
+// diagonal, Io = upper triangle of M^-1.
+template <typename R, int D>
+__device__ __forceinline__ void herm_inverse(const R (&Md)[D], const Cx<R> (&Mo)[3], R (&Id)[D], Cx<R> (&Io)[3]) {
     if constexpr (D == 2) {
-        const double id = 1.0 / (Md[0] * Md[1] - nrm(Mo[0]));
+        const R id = recip(Md[0] * Md[1] - nrm(Mo[0]));
         Id[0] = Md[1] * id;
         Id[1] = Md[0] * id;
         Io[0] = cscale(Mo[0], -id);
-        Io[1] = Io[2] = Cx<double>{0.0, 0.0};
+        Io[1] = Io[2] = Cx<R>{R(0), R(0)};
     } else {
-        const Cx<double> a = Mo[0], b = Mo[1], c = Mo[2];
-        const double C0 = Md[1] * Md[2] - nrm(c);
-        const double C1 = Md[0] * Md[2] - nrm(b);
-        const double C2 = Md[0] * Md[1] - nrm(a);
-        const Cx<double> A01 = csub(cmulc(b, c), cscale(a, Md[2]));  // b conj(c) - a d2
-        const Cx<double> A02 = csub(cmul(a, c), cscale(b, Md[1]));   // a c - b d1
-        const Cx<double> A12 = csub(cmulc(b, a), cscale(c, Md[0]));  // b conj(a) - c d0
+        const Cx<R> a = Mo[0], b = Mo[1], c = Mo[2];
+        const R C0 = Md[1] * Md[2] - nrm(c);
+        const R C1 = Md[0] * Md[2] - nrm(b);
+        const R C2 = Md[0] * Md[1] - nrm(a);
+        const Cx<R> A01 = csub(cmulc(b, c), cscale(a, Md[2]));  // b conj(c) - a d2
+        const Cx<R> A02 = csub(cmul(a, c), cscale(b, Md[1]));   // a c - b d1
+        const Cx<R> A12 = csub(cmulc(b, a), cscale(c, Md[0]));  // b conj(a) - c d0
         // det = d0 C00 + Re(a conj(A01)) + Re(b conj(A02))
-        const double det = Md[0] * C0 + (a.x * A01.x + a.y * A01.y) + (b.x * A02.x + b.y * A02.y);
-        const double id = 1.0 / det;
+        const R det = Md[0] * C0 + (a.x * A01.x + a.y * A01.y) + (b.x * A02.x + b.y * A02.y);
+        const R id = recip(det);
         Id[0] = C0 * id;
         Id[1] = C1 * id;
         Id[2] = C2 * id;
@@ -754,26 +758,58 @@ __device__ __forceinline__ void herm_inverse(const double (&Md)[D], const Cx<dou
     }
 }
 
-// First axis, one workgroup per block of PB pencils for every load case in
-// turn: forward transform, per-wavevector z^ = M(k)^-1 r^ with the Parseval
-// partial of r.z (mode 0), inverse transform.  Mode 1: forward only; mode 2:
-// inverse only.  In mode 0 the inverses of the workgroup's wavevectors are
-// formed once (FP64, adjugate) and kept in registers in the plan precision for
-// all load cases.
-// Inverse of the projection core at wavevector slot e of the workgroup (FP64):
-// Id = real diagonal, Io = upper triangle of M(k)^-1 (zero at k = 0 and for
-// slots past the block's pencils); the Parseval weight bit of the slot.
+// M(k) = B^*B(k) of the linear elements of one voxel (six Kuhn tetrahedra in
+// 3D, two triangles in 2D) from the per-axis factors aa_a = (w_a - 1) / h_a
+// and w_a = e^{2 pi i m_a / n_a}, in the scalar type R; ch = element volume / 2.
+template <typename R, int DIM>
+__device__ __forceinline__ void core_matrix(const Cx<R> (&aa)[3], const Cx<R> (&w)[3], R ch, R (&Md)[DIM],
+                                            Cx<R> (&Mo)[3]) {
+    if constexpr (DIM == 3) {
+        const Cx<R> a0 = aa[0], a1 = aa[1], a2 = aa[2];
+        const Cx<R> w0 = w[0], w1 = w[1], w2 = w[2];
+        const R n0s = nrm(a0), n1s = nrm(a1), n2s = nrm(a2);
+        const R S = R(6) * (n0s + n1s + n2s);
+        Md[0] = ch * (S + R(6) * n0s);
+        Md[1] = ch * (S + R(6) * n1s);
+        Md[2] = ch * (S + R(6) * n2s);
+        const Cx<R> two = {R(2), R(0)};
+        // M_ab = ch a_a conj(a_b) [conj(w_a)(2 + conj(w_c)) + w_b (2 + w_c)]
+        Mo[0] = cscale(cmul(cmulc(a0, a1), cadd(cmulc(cadd(two, cconj(w2)), w0), cmul(w1, cadd(two, w2)))), ch);
+        Mo[1] = cscale(cmul(cmulc(a0, a2), cadd(cmulc(cadd(two, cconj(w1)), w0), cmul(w2, cadd(two, w1)))), ch);
+        Mo[2] = cscale(cmul(cmulc(a1, a2), cadd(cmulc(cadd(two, cconj(w0)), w1), cmul(w2, cadd(two, w0)))), ch);
+    } else {
+        const Cx<R> a0 = aa[0], a1 = aa[1];
+        const Cx<R> w0 = w[0], w1 = w[1];
+        const R n0s = nrm(a0), n1s = nrm(a1);
+        const R S = R(2) * (n0s + n1s);
+        Md[0] = ch * (S + R(2) * n0s);
+        Md[1] = ch * (S + R(2) * n1s);
+        // M_01 = ch a0 conj(a1) (1 + w1 conj(w0))
+        const Cx<R> f = {R(1) + (w1.x * w0.x + w1.y * w0.y), w1.y * w0.x - w1.x * w0.y};
+        Mo[0] = cscale(cmul(cmulc(a0, a1), f), ch);
+        Mo[1] = Mo[2] = Cx<R>{R(0), R(0)};
+    }
+}
+
+// Inverse of the projection core at wavevector slot e of the workgroup, in
+// the plan precision: md = real diagonal, mo = upper triangle of M(k)^-1 (zero
+// at k = 0 and for slots past the block's pencils); the Parseval weight bit of
+// the slot.  The per-axis factors come from FP64 tables.  FP64 plans form the
+// inverse in FP64.  FP32 plans form it in FP32 where sum_a |aa_a|^2 >= near0
+// and in FP64 (rounded once) at the long-wavelength wavevectors below it,
+// whose entries are O(|k|^2) and whose inverse is O(|k|^-2).  Either way the
+// result is Hermitian positive definite, so its rounding moves the CG's
+// convergence rate, not the solution it converges to.
 template <typename T, int DIM>
 __device__ __forceinline__ void slot_inverse(const FK<T> &a, int e, int PB, long long in0, int lim,
-                                             const Cx<double> *pin, double (&Id)[DIM], Cx<double> (&Io)[3],
-                                             bool &half) {
+                                             const Cx<double> *pin, T (&md)[DIM], Cx<T> (&mo)[3], bool &half) {
     constexpr int D = DIM;
     const int j = (int)a.d_PB.div((uint32_t)e);
     const int b = e - j * PB;
     const long long inn = in0 + b;
     #pragma unroll
-    for (int c = 0; c < D; ++c) Id[c] = 0.0;
-    Io[0] = Io[1] = Io[2] = Cx<double>{0.0, 0.0};
+    for (int c = 0; c < D; ++c) md[c] = T(0);
+    mo[0] = mo[1] = mo[2] = Cx<T>{T(0), T(0)};
     half = false;
     if (!(e < PB * a.n0 && b * D < lim && !(j == 0 && inn == 0))) return;
     int m1 = 0, kh;
@@ -784,42 +820,45 @@ __device__ __forceinline__ void slot_inverse(const FK<T> &a, int e, int PB, long
         kh = (int)inn;
     }
     half = kh == 0 || (a.last_even && kh == a.nh - 1);
-    const double ch = a.chalf;
+    Cx<double> A[3], W[3];
+    A[0] = ld2(a.aa[0], j);
+    W[0] = ld2(a.om[0], j);
+    A[1] = pin[4 * b + 0];
+    W[1] = pin[4 * b + 1];
+    A[2] = DIM == 3 ? pin[4 * b + 2] : Cx<double>{0.0, 0.0};
+    W[2] = DIM == 3 ? pin[4 * b + 3] : Cx<double>{1.0, 0.0};
+    if constexpr (sizeof(T) == 4) {
+        Cx<float> Af[3], Wf[3];
+        #pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Af[c] = Cx<float>{float(A[c].x), float(A[c].y)};
+            Wf[c] = Cx<float>{float(W[c].x), float(W[c].y)};
+        }
+        if (nrm(Af[0]) + nrm(Af[1]) + nrm(Af[2]) >= a.near0) {
+            float Md[D];
+            Cx<float> Mo[3];
+            core_matrix<float, DIM>(Af, Wf, float(a.chalf), Md, Mo);
+            herm_inverse<float, D>(Md, Mo, md, mo);
+            return;
+        }
+    }
     double Md[D];
     Cx<double> Mo[3];
-    if constexpr (DIM == 3) {
-        const Cx<double> a0 = ld2(a.aa[0], j), a1 = pin[4 * b + 0], a2 = pin[4 * b + 2];
-        const Cx<double> w0 = ld2(a.om[0], j), w1 = pin[4 * b + 1], w2 = pin[4 * b + 3];
-        const double n0s = nrm(a0), n1s = nrm(a1), n2s = nrm(a2);
-        const double S = 6.0 * (n0s + n1s + n2s);
-        Md[0] = ch * (S + 6.0 * n0s);
-        Md[1] = ch * (S + 6.0 * n1s);
-        Md[2] = ch * (S + 6.0 * n2s);
-        const Cx<double> two = {2.0, 0.0};
-        // M_ab = ch a_a conj(a_b) [conj(w_a)(2 + conj(w_c)) + w_b (2 + w_c)]
-        Mo[0] = cscale(cmul(cmulc(a0, a1), cadd(cmulc(cadd(two, cconj(w2)), w0), cmul(w1, cadd(two, w2)))), ch);
-        Mo[1] = cscale(cmul(cmulc(a0, a2), cadd(cmulc(cadd(two, cconj(w1)), w0), cmul(w2, cadd(two, w1)))), ch);
-        Mo[2] = cscale(cmul(cmulc(a1, a2), cadd(cmulc(cadd(two, cconj(w0)), w1), cmul(w2, cadd(two, w0)))), ch);
-    } else {
-        const Cx<double> a0 = ld2(a.aa[0], j), a1 = pin[4 * b + 0];
-        const Cx<double> w0 = ld2(a.om[0], j), w1 = pin[4 * b + 1];
-        const double n0s = nrm(a0), n1s = nrm(a1);
-        const double S = 2.0 * (n0s + n1s);
-        Md[0] = ch * (S + 2.0 * n0s);
-        Md[1] = ch * (S + 2.0 * n1s);
-        // M_01 = ch a0 conj(a1) (1 + w1 conj(w0))
-        const Cx<double> f = {1.0 + (w1.x * w0.x + w1.y * w0.y), w1.y * w0.x - w1.x * w0.y};
-        Mo[0] = cscale(cmul(cmulc(a0, a1), f), ch);
-        Mo[1] = Mo[2] = Cx<double>{0.0, 0.0};
-    }
-    herm_inverse<D>(Md, Mo, Id, Io);
+    core_matrix<double, DIM>(A, W, a.chalf, Md, Mo);
+    double Id[D];
+    Cx<double> Io[3];
+    herm_inverse<double, D>(Md, Mo, Id, Io);
+    #pragma unroll
+    for (int c = 0; c < D; ++c) md[c] = T(Id[c]);
+    #pragma unroll
+    for (int c = 0; c < 3; ++c) mo[c] = Cx<T>{T(Io[c].x), T(Io[c].y)};
 }
 
 // First axis: forward transform, per-wavevector z^ = M(k)^-1 r^ with the
 // Parseval partial of r.z (mode 0), inverse transform.  Mode 1: forward only;
 // mode 2: inverse only.  PERLC = false: one workgroup per block of PB pencils
 // runs through every load case, forming the inverses of its wavevectors once
-// (FP64, adjugate) and keeping them in registers in the plan precision.
+// (adjugate, see slot_inverse) and keeping them in registers.
 // PERLC = true: one workgroup per (load case, pencil block), the inverses
 // formed again per load case just in time (no register cache, more resident
 // workgroups to overlap memory and compute).  The power-of-two PERLC
@@ -883,15 +922,15 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu((PE
         if constexpr (!PERLC) {
             #pragma unroll
             for (int kw = 0; kw < KW; ++kw) {
-                double Id[D];
-                Cx<double> Io[3];
+                T md[D];
+                Cx<T> mo[3];
                 bool half;
-                slot_inverse<T, DIM>(a, threadIdx.x + kw * NT, PB, in0, lim, pin, Id, Io, half);
+                slot_inverse<T, DIM>(a, threadIdx.x + kw * NT, PB, in0, lim, pin, md, mo, half);
                 if (half) half_w |= 1u << kw;
                 #pragma unroll
-                for (int c = 0; c < D; ++c) Mid[kw][c] = T(Id[c]);
+                for (int c = 0; c < D; ++c) Mid[kw][c] = md[c];
                 #pragma unroll
-                for (int c = 0; c < (DIM == 3 ? 3 : 1); ++c) Mio[kw][c] = Cx<T>{T(Io[c].x), T(Io[c].y)};
+                for (int c = 0; c < (DIM == 3 ? 3 : 1); ++c) Mio[kw][c] = mo[c];
             }
         }
     }
@@ -935,13 +974,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu((PE
                     Cx<T> mo[3];
                     bool half;
                     if constexpr (PERLC) {
-                        double Id[D];
-                        Cx<double> Io[3];
-                        slot_inverse<T, DIM>(a, e, PB, in0, lim, pin, Id, Io, half);
-                        #pragma unroll
-                        for (int c = 0; c < D; ++c) md[c] = T(Id[c]);
-                        #pragma unroll
-                        for (int c = 0; c < 3; ++c) mo[c] = Cx<T>{T(Io[c].x), T(Io[c].y)};
+                        slot_inverse<T, DIM>(a, e, PB, in0, lim, pin, md, mo, half);
                     } else {
                         #pragma unroll
                         for (int c = 0; c < D; ++c) md[c] = Mid[kw][c];
@@ -1031,6 +1064,9 @@ FK<T> base_args(const feh_plan &p, const FftArgs &fa) {
     a.invN = 1.0 / (double)p.N;
     const double vol = p.dim == 3 ? p.h[0] * p.h[1] * p.h[2] / 6.0 : p.h[0] * p.h[1] / 2.0;
     a.chalf = 0.5 * vol;
+    double hmax = 0.0;
+    for (int ax = 0; ax < p.dim; ++ax) hmax = std::max(hmax, p.h[ax]);
+    a.near0 = (float)(0.0625 / (hmax * hmax));  // |k| h_max < 1/4
     a.tw_last = p.ptr<const Cx<T>>(p.off_tw[p.dim - 1]);
     for (int ax = 0; ax < 3; ++ax) {
         a.om[ax] = p.ptr<const double>(p.off_om[ax]);
