@@ -550,7 +550,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": list(shape), "elements_per_voxel": 6 if dim == 3 else 2,
                    "load_cases": L, "tol": tol, "recipe": m.recipe,
-                   "precision": "fp32 fields/FFT/stencil and M(k)^-1 application, fp64 CG scalars and M(k)^-1 formation" if precname == "fp32" else "fp64"},
+                   "precision": "fp32 fields/FFT/stencil, M(k)^-1 formed in fp32 away from k=0 (fp64 near it) and applied in fp32, fp64 CG scalars" if precname == "fp32" else "fp64"},
         "s_per_C_eff": t / args.steps,
         "cg_iterations_per_load_case": iters_all[-1],
         "ms_per_cg_iteration": 1e3 * t / max(1, sum(max(x) for x in iters_all)),
