@@ -311,3 +311,28 @@ def test_fp32_vs_fp64_circle32():
                  Eb, "fp32", 1e-5)
     ref = fe.homogenize(m.E, m.nu, Eb)
     assert rel(o32["C_eff"], ref["C_eff"]) < 1e-5
+
+
+@pytest.mark.parametrize("shape", [(48, 24), (8, 5, 48)])
+@pytest.mark.parametrize("scale", [1e-3, 1e3])
+def test_fp32_voxel_scale_invariance(shape, scale):
+    """C_eff does not depend on a uniform scaling of the voxel (the element
+    stiffness and the load both scale out of the energy balance).  FP32 plans
+    form M(k)^-1 in FP32 away from k = 0, with entries of order h and a
+    determinant of order h^3 in 3D: scaled voxels move them by 1e+-9 and must
+    leave C_eff, and the iteration count to within a few, unchanged.  The grids
+    hold wavevectors on both sides of the FP64 long-wavelength shell."""
+    say("fp32 voxel scale", shape, scale)
+    from oracle import fe
+    dim = len(shape)
+    lam, mu = random_material(shape, 5, "fp32")
+    Eb = ms.unit_loads(dim)
+    hvox = np.array((1.0, 1.3, 0.8)[:dim])
+    base = _solve(shape, lam, mu, Eb, "fp32", 1e-6, h=tuple(hvox))
+    out = _solve(shape, lam, mu, Eb, "fp32", 1e-6, h=tuple(scale * hvox))
+    ref = fe.homogenize(None, None, Eb, h=tuple(hvox), lam_mu=(lam, mu))
+    assert out["status"] == 0 and base["status"] == 0
+    assert rel(out["C_eff"], ref["C_eff"]) < 1e-5
+    assert rel(base["C_eff"], ref["C_eff"]) < 1e-5
+    for l in range(len(Eb)):
+        assert abs(out["report"][l]["iterations"] - base["report"][l]["iterations"]) <= 3
