@@ -392,6 +392,7 @@ struct FK {
     int use_axpy;             // selects the AXPY instantiation on the host
     double out_scale, invN, chalf;  // chalf = element volume / 2
     float near0;              // FP32 plans: sum_a |aa_a|^2 below which M^-1 is formed in FP64
+    float hmax_f, post_f;     // FP32 plans: h_max and h_max^2 / chalf (scale-free FP32 inverse)
 };
 
 // ---------------------------------------------------------------------------
@@ -729,11 +730,12 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 // Inverse of the Hermitian positive definite M (diagonal Md, upper triangle
 // Mo = (M01, M02, M12)) by the adjugate in the scalar type R: Id = real
-// diagonal, Io = upper triangle of M^-1.
+// diagonal, Io = upper triangle of post M^-1.
 template <typename R, int D>
-__device__ __forceinline__ void herm_inverse(const R (&Md)[D], const Cx<R> (&Mo)[3], R (&Id)[D], Cx<R> (&Io)[3]) {
+__device__ __forceinline__ void herm_inverse(const R (&Md)[D], const Cx<R> (&Mo)[3], R (&Id)[D], Cx<R> (&Io)[3],
+                                             R post = R(1)) {
     if constexpr (D == 2) {
-        const R id = recip(Md[0] * Md[1] - nrm(Mo[0]));
+        const R id = post * recip(Md[0] * Md[1] - nrm(Mo[0]));
         Id[0] = Md[1] * id;
         Id[1] = Md[0] * id;
         Io[0] = cscale(Mo[0], -id);
@@ -748,7 +750,7 @@ __device__ __forceinline__ void herm_inverse(const R (&Md)[D], const Cx<R> (&Mo)
         const Cx<R> A12 = csub(cmulc(b, a), cscale(c, Md[0]));  // b conj(a) - c d0
         // det = d0 C00 + Re(a conj(A01)) + Re(b conj(A02))
         const R det = Md[0] * C0 + (a.x * A01.x + a.y * A01.y) + (b.x * A02.x + b.y * A02.y);
-        const R id = recip(det);
+        const R id = post * recip(det);
         Id[0] = C0 * id;
         Id[1] = C1 * id;
         Id[2] = C2 * id;
@@ -835,10 +837,16 @@ __device__ __forceinline__ void slot_inverse(const FK<T> &a, int e, int PB, long
             Wf[c] = Cx<float>{float(W[c].x), float(W[c].y)};
         }
         if (nrm(Af[0]) + nrm(Af[1]) + nrm(Af[2]) >= a.near0) {
+            // dimensionless factors aa_a h_max: M~ = M h_max^2 / ch has entries
+            // of order |k h_max|^2 whatever the voxel size, so the adjugate
+            // neither underflows nor overflows; M^-1 = M~^-1 h_max^2 / ch
+            const float hm = a.hmax_f;
+            #pragma unroll
+            for (int c = 0; c < 3; ++c) Af[c] = Cx<float>{Af[c].x * hm, Af[c].y * hm};
             float Md[D];
             Cx<float> Mo[3];
-            core_matrix<float, DIM>(Af, Wf, float(a.chalf), Md, Mo);
-            herm_inverse<float, D>(Md, Mo, md, mo);
+            core_matrix<float, DIM>(Af, Wf, 1.0f, Md, Mo);
+            herm_inverse<float, D>(Md, Mo, md, mo, a.post_f);
             return;
         }
     }
@@ -1067,6 +1075,8 @@ FK<T> base_args(const feh_plan &p, const FftArgs &fa) {
     double hmax = 0.0;
     for (int ax = 0; ax < p.dim; ++ax) hmax = std::max(hmax, p.h[ax]);
     a.near0 = (float)(0.0625 / (hmax * hmax));  // |k| h_max < 1/4
+    a.hmax_f = (float)hmax;
+    a.post_f = (float)(hmax * hmax / a.chalf);
     a.tw_last = p.ptr<const Cx<T>>(p.off_tw[p.dim - 1]);
     for (int ax = 0; ax < 3; ++ax) {
         a.om[ax] = p.ptr<const double>(p.off_om[ax]);
