@@ -91,7 +91,10 @@ typedef struct {
  * to 13 run as radix butterflies, larger primes (e.g. 17, 151) as direct-DFT
  * passes (O(p) work per output of that pass).  An axis whose points times
  * the components of a transform exceed the LDS tile (4096 points in FP64,
- * 6144 in FP32) gives FEH_ENOTSUP; n_load in [1, 64]; N <= 2^31.  Host-side only: computes the
+ * 6144 in FP32) gives FEH_ENOTSUP; n_load in [1, 64]; N <= 2^31.  FP32 plans
+ * carry the element volume (h^3 / 6 in 3D) in the FP32 stencil: keep 3D voxel
+ * sizes within about 1e-12 .. 1e12 in the chosen length unit (C_eff does not
+ * depend on the unit).  Host-side only: computes the
  * FFT factorisations, twiddle and phase tables (Discrete Fourier transform
  * appendix: k_a = 2 pi m / (n_a h_a)). */
 int feh_plan_create(feh_plan **plan, int dim, const int64_t n[], const double h[],
