@@ -93,6 +93,21 @@ def traffic_from_profiles(kernel, workload):
     return tj.get("bytes_per_launch")
 
 
+def set_material(hz, m):
+    """Hand a generated microstructure to the library's own material setters
+    (phase map + (E, nu) table, or E field + uniform nu): the Lame constants
+    are formed inside the library."""
+    import torch
+    if m.phase is not None:
+        k = int(m.phase.max()) + 1
+        table = [(float(m.E[m.phase == i].flat[0]), float(m.nu[m.phase == i].flat[0])) for i in range(k)]
+        hz.set_material(phases=m.phase, table=table)
+    else:
+        nu = float(m.nu.flat[0])
+        assert np.all(m.nu == nu), "an E field needs a uniform Poisson ratio"
+        hz.set_material(E=torch.as_tensor(m.E, dtype=hz.dtype), nu=nu)
+
+
 def uneven_batch_measure(log):
     """The uneven-batch workload: 48 two-phase 2D maps of sizes 64^2 .. 512^2
     (laminates and circular inclusions, contrast log-uniform in [2, 1000]),
@@ -105,10 +120,10 @@ def uneven_batch_measure(log):
     import microstructures as ms
     import paper_2105_03297_amd as feh
     maps = ms.uneven_batch()
-    # plane-strain Lame constants of each map
-    lm = [(m.E * m.nu / ((1 + m.nu) * (1 - 2 * m.nu)), m.E / (2 * (1 + m.nu))) for m in maps]
+    # each map as (E field, uniform nu): the library forms the Lame constants
+    en = [(m.E, float(m.nu.flat[0])) for m in maps]
     Eb = ms.unit_loads(2)
-    ub = feh.UnevenBatch(lm, precision="fp32")
+    ub = feh.UnevenBatch(en, precision="fp32")
     res = {}
     # alternate the two modes and keep each one's fastest of three timed runs
     # (after one untimed run each, which also captures the graphs)
@@ -127,9 +142,9 @@ def uneven_batch_measure(log):
     for rep in range(2):
         seq = []
         t_seq = 0.0
-        for (lam, mu), m in zip(lm, maps):
-            h = feh.Homogenizer(m.shape, n_load=3, precision="fp32")
-            h.set_material(lam=lam, mu=mu)
+        for E, nu in en:
+            h = feh.Homogenizer(E.shape, n_load=3, precision="fp32")
+            h.set_material(E=torch.as_tensor(E, dtype=torch.float32), nu=nu)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             seq.append(h.solve(Eb, tol=1e-5, max_iter=5000))
@@ -187,13 +202,11 @@ def strain_space_measure(log):
     hz = None
     for wl, kind, prec, tol in cases:
         m, Eb, _, _ = ms.workload(wl)
-        lam = m.E * m.nu / ((1 + m.nu) * (1 - 2 * m.nu))
-        mu = m.E / (2 * (1 + m.nu))
         if hz is None or hz.shape != m.shape or hz.precision != prec or hz.n_load != len(Eb):
             if hz is not None:
                 hz.close()
             hz = feh.Homogenizer(m.shape, n_load=len(Eb), precision=prec)
-            hz.set_material(lam=lam, mu=mu)
+            set_material(hz, m)
         for rep in range(2):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -240,10 +253,8 @@ def finite_strain_measure(log):
     import microstructures as ms
     import paper_2105_03297_amd as feh
     m, _, _, _ = ms.workload("spheres128")
-    lam = m.E * m.nu / ((1 + m.nu) * (1 - 2 * m.nu))
-    mu = m.E / (2 * (1 + m.nu))
     hz = feh.Homogenizer(m.shape, n_load=1, precision="fp32")
-    hz.set_material(lam=lam, mu=mu)
+    set_material(hz, m)
     Fbar = np.diag([1.05, 0.98, 0.98])[None]
     for rep in range(2):
         torch.cuda.synchronize()
@@ -345,13 +356,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     hz = feh.Homogenizer(shape, n_load=L, precision=precname, device=dev)
-    dt = torch.float32 if precname == "fp32" else torch.float64
-    if m.phase is not None and args.workload != "grf256" and not args.workload.startswith("grf"):
-        table = np.stack([np.unique(m.E[m.phase == k])[:1] for k in range(m.phase.max() + 1)])
-        nus = np.stack([np.unique(m.nu[m.phase == k])[:1] for k in range(m.phase.max() + 1)])
-        hz.set_material(phases=m.phase, table=np.concatenate([table, nus], axis=1))
-    else:
-        hz.set_material(E=torch.as_tensor(m.E, dtype=dt), nu=float(m.nu.flat[0]))
+    set_material(hz, m)
     torch.cuda.synchronize()
     tuning = None
     if args.autotune:

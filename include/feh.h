@@ -37,8 +37,12 @@
  *   - Material: isotropic, per voxel Lame constants (lambda, mu); 2D is
  *     plane strain when set from (E, nu).  E = 0 (vacuum) is accepted.
  *   - Precision: FEH_FP64 runs everything in double.  FEH_FP32 stores and
- *     streams fields, stencils and FFTs in float and keeps the CG dot
- *     products, alpha/beta and the per-wavevector (B^*B)^-1 solve in double.
+ *     streams fields, stencils and FFTs in float and applies the
+ *     per-wavevector inverse (B^*B)^-1 in float; that inverse is formed in
+ *     float from dimensionless phase factors, except at long wavelengths
+ *     (|k| h_max below about 1/4), where it is formed in double and rounded
+ *     once.  The CG dot products and alpha/beta stay in double (fixed-order
+ *     sums), and so do the post-processing sums (<sigma>, W, sensitivities).
  *   - Nodal vector fields at the ABI are [n_load][N][D] and element fields
  *     [n_load][N][n_e][D][D], in the plan's precision (float or double).
  *   - All device pointers are caller-owned device memory (e.g. torch
@@ -82,6 +86,9 @@ typedef struct {
     int32_t status;       /* FEH_OK, FEH_ENOCONV or FEH_EBREAKDOWN                */
     double rel_residual;  /* sqrt(r.z / f.M^+f): relative residual in the strain
                              space norm (Euclidean over all elements)            */
+    double seconds;       /* host wall time of the whole call that filled the
+                             report (set-up, CG, post-processing; the same for
+                             every load case of the call)                        */
 } feh_report;
 
 /* Create a plan for a dim-dimensional periodic grid n[] with voxel sizes h[]
@@ -91,10 +98,13 @@ typedef struct {
  * to 13 run as radix butterflies, larger primes (e.g. 17, 151) as direct-DFT
  * passes (O(p) work per output of that pass).  An axis whose points times
  * the components of a transform exceed the LDS tile (4096 points in FP64,
- * 6144 in FP32) gives FEH_ENOTSUP; n_load in [1, 64]; N <= 2^31.  FP32 plans
- * carry the element volume (h^3 / 6 in 3D) in the FP32 stencil: keep 3D voxel
- * sizes within about 1e-12 .. 1e12 in the chosen length unit (C_eff does not
- * depend on the unit).  Host-side only: computes the
+ * 6144 in FP32) gives FEH_ENOTSUP; n_load in [1, 64]; N <= 2^31.  The CG
+ * applies K, f and (B^*B)^-1 with the element volume divided by the voxel
+ * volume (1/6 in 3D, 1/2 in 2D; one common factor, which leaves every iterate
+ * unchanged), and FP32 plans form (B^*B)^-1 from dimensionless phase factors,
+ * so no power of the voxel size enters the FP32 arithmetic; FP32 solves are
+ * tested at voxel sizes 1e-12 .. 1e12 (the fluctuations, of order
+ * |Ebar| n h, must stay inside the FP32 range).  Host-side only: computes the
  * FFT factorisations, twiddle and phase tables (Discrete Fourier transform
  * appendix: k_a = 2 pi m / (n_a h_a)). */
 int feh_plan_create(feh_plan **plan, int dim, const int64_t n[], const double h[],
@@ -126,25 +136,47 @@ int feh_plan_workspace_bytes(const feh_plan *plan, size_t *bytes);
 int feh_plan_set_workspace(feh_plan *plan, void *dev_ptr, size_t bytes);
 
 /* Material from per-voxel Lame constants (device arrays of N values, or
- * [n_batch][N] for a batched plan, in the plan precision).  lambda and mu must be finite with mu >= 0 and
- * lambda + 2 mu / dim >= 0 (checked on the device; FEH_EINVAL otherwise). */
+ * [n_batch][N] for a batched plan, in the plan precision; caller-owned, read
+ * once and copied into the workspace).  The isotropic law
+ * sigma = lambda tr(e) I + 2 mu e per element is the constitutive map of the
+ * paper's small-strain examples (Sec. "Eshelby inhomogeneity": isotropic
+ * linear elasticity given by Young's modulus and Poisson's ratio; small-strain
+ * appendix for the strain measure).  lambda and mu must be finite with
+ * mu >= 0 and lambda + 2 mu / dim >= 0 (checked on the device; FEH_EINVAL
+ * otherwise, and the plan keeps no material).  Blocking. */
 int feh_set_material_lame(feh_plan *plan, const void *lambda_dev, const void *mu_dev);
 
 /* Material from a phase map (device int32[N] or [n_batch][N], values in
- * [0, n_phase)) and a
- * host table E_nu[n_phase][2] = (E, nu) with E >= 0 and -1 < nu < 0.5.
- * Plane strain in 2D: lambda = E nu/((1+nu)(1-2nu)), mu = E/(2(1+nu)). */
+ * [0, n_phase), caller-owned) and a host table E_nu[n_phase][2] = (E, nu)
+ * with E >= 0 (E = 0 is vacuum, as in the paper's two-pillar example) and
+ * -1 < nu < 0.5, n_phase in [1, 4096].  The paper fixes isotropic linear
+ * elasticity by (E, nu) (Sec. "Eshelby inhomogeneity") but does not say which
+ * 2D reduction; this library reads it as plane strain:
+ * lambda = E nu/((1+nu)(1-2nu)), mu = E/(2(1+nu)) in 2D and 3D.  A phase id
+ * outside the table gives FEH_EINVAL (checked on the device).  Blocking. */
 int feh_set_material_phases(feh_plan *plan, const int32_t *phase_dev,
                             const double *E_nu_host, int n_phase);
 
 /* Material from a per-voxel Young's modulus field (device, N or [n_batch][N]
- * values in the plan precision, E >= 0) and a uniform Poisson ratio
- * (-1 < nu < 0.5). */
+ * values in the plan precision, E >= 0 and finite, caller-owned) and a
+ * uniform Poisson ratio (-1 < nu < 0.5); the Lame constants follow with the
+ * plane-strain reading of feh_set_material_phases.  The plan remembers nu for
+ * feh_energy_sensitivity_E.  FEH_EINVAL for a negative or non-finite E
+ * (checked on the device).  Blocking. */
 int feh_set_material_field(feh_plan *plan, const void *E_dev, double nu);
 
 /* Solve all load cases: find the periodic fluctuation u with zero mean such
  * that the element strains e = Ebar_l + B u satisfy the discrete equilibrium
- * B^T C e = 0 (equivalently G(C e) = 0 with compatible e - Ebar).
+ * B^T C e = 0 (equivalently G(C e) = 0 with compatible e - Ebar).  This is the
+ * weak form of Sec. "Compatibility projection" (test strains projected onto
+ * compatible fields, the mean strain Ebar as the macroscopic boundary
+ * condition at k = 0), discretised by the linear elements of Sec. "Linear
+ * finite elements", with the projection of the small-strain appendix applied
+ * in factored form by projected CG (every iterate stays compatible).  Inputs
+ * are read, outputs written in caller-owned memory; blocking (host outputs
+ * valid on return).  FEH_EINVAL for a non-finite or non-symmetric Ebar, a
+ * negative or non-finite tol, max_iter < 1, or no material; FEH_ENOMEM
+ * without a workspace.
  *   Ebar_host         [n_load][D][D] symmetric macroscopic strains (host)
  *   tol               stop a load case when sqrt(r.z / f.M^+f) <= tol
  *   max_iter          per load case, >= 1
@@ -265,6 +297,18 @@ int feh_effective_stiffness_weights(int dim, int n_load, const double *Ebar_host
  * breakdown, or the material or workspace changed since).  Blocking. */
 int feh_energy_sensitivity(feh_plan *plan, const double *weight_host, void *grad_lam_dev, void *grad_mu_dev);
 
+/* The same objective differentiated with respect to a per-voxel Young's
+ * modulus field at a uniform Poisson ratio (the material of
+ * feh_set_material_field; the derivative of the same weak-form energy as
+ * feh_energy_sensitivity, through the plane-strain Lame maps of that setter):
+ *   grad_E[v] = grad_lam[v] nu / ((1+nu)(1-2nu)) + grad_mu[v] / (2 (1+nu)),
+ * written in one pass by the sensitivity kernel (the two Lame fields are not
+ * formed).  weight_host as above; grad_E_dev output [N] ([n_batch][N]) in the
+ * plan precision, caller-owned.  FEH_EINVAL if the plan's material was not
+ * set by feh_set_material_field, and in the cases of feh_energy_sensitivity.
+ * Blocking. */
+int feh_energy_sensitivity_E(feh_plan *plan, const double *weight_host, void *grad_E_dev);
+
 /* Discrete derivatives of the strain-space solver (Sec. "Discrete
  * projection": the projection is built from the Fourier symbol D(k) of a
  * discrete derivative, one symbol per evaluation point T of a voxel):
@@ -374,16 +418,27 @@ int feh_finite_strain_solve(feh_plan *plan, int kind, const double *Fbar_host, i
                             size_t work_bytes, void *F_dev, void *P_dev, double *P_mean_host,
                             feh_finite_report *report_host);
 
-/* Test export: q = K p with K = sum_e |e| B_e^T C_e B_e, p and q
- * [n_load][N][D] in the plan precision. */
+/* Test export: q = K p with K = sum_e |e| B_e^T C_e B_e, the stiffness of the
+ * linear elements of Sec. "Linear finite elements" (element gradients from the
+ * shape functions of its element stencils, one constant strain per element,
+ * the plan's isotropic material), p and q [n_load][N][D] in the plan
+ * precision, caller-owned.  Overwrites the plan's CG vectors p and q (a
+ * following feh_energy_sensitivity still sees the last solve).  FEH_EINVAL
+ * without material or for null pointers.  Blocking. */
 int feh_apply_operator(feh_plan *plan, const void *p_dev, void *q_dev);
 
 /* Test export: z = M^+ r with M = sum_e |e| B_e^T B_e (K for lambda = 0,
- * mu = 1/2), applied per wavevector; z has zero mean. [n_load][N][D]. */
+ * mu = 1/2), applied per wavevector as (B^*B)(k)^-1 with z(k = 0) = 0 (Sec.
+ * "Discrete projection": the operator is block diagonal in Fourier space and
+ * k = 0 carries the mean); z has zero mean.  r, z [n_load][N][D] in the plan
+ * precision, caller-owned.  Blocking. */
 int feh_apply_preconditioner(feh_plan *plan, const void *r_dev, void *z_dev);
 
-/* Test export: the small-strain projection G = B (B^T B)^+ B^T on element
- * fields e [n_load][N][n_e][D][D] (only the symmetric part of e enters). */
+/* Test export: the small-strain projection of the paper's small-strain
+ * appendix, G = B (B^*B)^+ B^* (the operator G_ThetaLambda,ijlm there, written
+ * for the linear-element derivative), on element fields
+ * e [n_load][N][n_e][D][D] in the plan precision (only the symmetric part of e
+ * enters; G e is symmetric and compatible), caller-owned.  Blocking. */
 int feh_apply_projection(feh_plan *plan, const void *e_dev, void *Ge_dev);
 
 /* Test export: unnormalised forward real-to-half-complex DFT over the grid

@@ -43,11 +43,13 @@ def _weights(dim, ne, N, h=None):
     return w / (w.sum() * N)
 
 
-def energy_sensitivity(eps_list, h=None):
-    """dW/dlambda and dW/dmu per voxel: arrays (L, L, N) each."""
+def energy_sensitivity(eps_list, h=None, n_voxels=None):
+    """dW/dlambda and dW/dmu per voxel: arrays (L, L, N) each.  With n_voxels,
+    eps_list holds the strains of a subset of the voxels of a grid of
+    n_voxels (fe.element_strains_at) and the result covers that subset."""
     L = len(eps_list)
     N, ne, dim, _ = eps_list[0].shape
-    w = _weights(dim, ne, N, h)
+    w = _weights(dim, ne, N if n_voxels is None else n_voxels, h)
     tr = [np.trace(e, axis1=2, axis2=3) for e in eps_list]  # (N, ne)
     dl = np.zeros((L, L, N))
     dm = np.zeros((L, L, N))
@@ -65,10 +67,11 @@ def objective_weights(Ebars, G):
     return Einv @ np.asarray(G, float) @ Einv.T
 
 
-def objective_gradient(eps_list, Ebars, G, h=None):
-    """dJ/dlambda_v and dJ/dmu_v (each (N,)) for J = sum G_IJ C_eff_IJ."""
+def objective_gradient(eps_list, Ebars, G, h=None, n_voxels=None):
+    """dJ/dlambda_v and dJ/dmu_v (each (N,)) for J = sum G_IJ C_eff_IJ
+    (n_voxels: as in energy_sensitivity)."""
     Wt = objective_weights(Ebars, G)
-    dl, dm = energy_sensitivity(eps_list, h)
+    dl, dm = energy_sensitivity(eps_list, h, n_voxels)
     return np.einsum("lm,lmn->n", Wt, dl), np.einsum("lm,lmn->n", Wt, dm)
 
 

@@ -390,6 +390,27 @@ def apply_K_at_nodes(lam, mu, p, nodes, h=None):
     return out
 
 
+def element_strains_at(u, shape, voxels, Ebar, h=None):
+    """Element strains eps = Ebar + sym(grad u) of selected voxels only (local
+    evaluation of `fields` for grids too large to post-process whole).
+
+    u: nodal field (N, D); voxels: flat voxel indices.  Returns
+    (len(voxels), n_e, D, D); element e of voxel v uses the nodes v + verts[c]
+    with the shape-function gradients g[c], as in `element_gradients`."""
+    dim = len(shape)
+    h = _default_h(dim, h)
+    u = np.asarray(u, dtype=np.float64).reshape(-1, dim)
+    voxels = np.asarray(voxels, dtype=np.int64)
+    pos = np.stack(np.unravel_index(voxels, shape), axis=1)
+    els = elements(dim, h)
+    G = np.zeros((len(voxels), len(els), dim, dim))
+    for e, (verts, g, vol) in enumerate(els):
+        for c in range(dim + 1):
+            node = np.ravel_multi_index(((pos + verts[c]) % np.asarray(shape)).T, shape)
+            G[:, e] += u[node][:, :, None] * g[c][None, None, :]
+    return np.asarray(Ebar, float)[None, None] + 0.5 * (G + np.swapaxes(G, -1, -2))
+
+
 def load_at_nodes(lam, mu, Ebar, nodes, h=None):
     """f at selected nodes (local evaluation of load_vector)."""
     lam = np.asarray(lam)

@@ -21,7 +21,8 @@ __all__ = [
     "FEH_FP64", "FEH_FP32", "FehError", "feh_report", "library_path", "load",
     "feh_plan_create", "feh_plan_create_batch", "feh_plan_destroy", "feh_plan_workspace_bytes", "feh_plan_set_workspace",
     "feh_set_material_lame", "feh_set_material_phases", "feh_set_material_field", "feh_solve",
-    "feh_effective_stiffness", "feh_effective_stiffness_weights", "feh_energy_sensitivity",
+    "feh_effective_stiffness", "feh_effective_stiffness_weights", "feh_energy_sensitivity", "feh_energy_sensitivity_E",
+    "unit_loads", "UNIT_STRAIN",
     "feh_apply_operator", "feh_apply_preconditioner", "feh_apply_projection",
     "feh_fft_forward", "feh_fft_inverse", "feh_profile_enable", "feh_profile_read", "feh_stream_copy", "PROFILE_KINDS",
     "feh_batch_create", "feh_batch_destroy", "feh_batch_solve", "feh_batch_graph_launches",
@@ -38,6 +39,21 @@ FEH_DERIV_FE, FEH_DERIV_FD, FEH_DERIV_CD, FEH_DERIV_LS, FEH_DERIV_FOURIER, FEH_D
 DERIV_KINDS = {"fe": FEH_DERIV_FE, "fd": FEH_DERIV_FD, "cd": FEH_DERIV_CD, "ls": FEH_DERIV_LS,
                "fourier": FEH_DERIV_FOURIER, "fourier2": FEH_DERIV_FOURIER2}
 
+# The unit load set whose energy matrix gives C_eff: tensor strain 0.01 per
+# normal component and per shear pair (engineering shear 0.02), in Voigt
+# order (xx, yy, xy) / (xx, yy, zz, yz, xz, xy).
+UNIT_STRAIN = 0.01
+
+
+def unit_loads(dim):
+    """[nv][D][D] unit macroscopic strains (the load cases C_eff is defined on)."""
+    pairs = [(0, 0), (1, 1), (0, 1)] if dim == 2 else [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+    Eb = np.zeros((len(pairs), dim, dim))
+    for k, (a, b) in enumerate(pairs):
+        Eb[k, a, b] = Eb[k, b, a] = UNIT_STRAIN
+    return Eb
+
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libfeh.so")
 
@@ -50,7 +66,12 @@ class FehError(RuntimeError):
 
 
 class feh_report(ctypes.Structure):
-    _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32), ("rel_residual", ctypes.c_double)]
+    _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+def _report_dict(r):
+    return dict(iterations=r.iterations, status=r.status, rel_residual=r.rel_residual, seconds=r.seconds)
 
 
 class feh_finite_report(ctypes.Structure):
@@ -79,6 +100,7 @@ _SIGS = {
     "feh_effective_stiffness": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]),
     "feh_effective_stiffness_weights": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]),
     "feh_energy_sensitivity": (ctypes.c_int, [_vp, _dp, _vp, _vp]),
+    "feh_energy_sensitivity_E": (ctypes.c_int, [_vp, _dp, _vp]),
     "feh_apply_operator": (ctypes.c_int, [_vp, _vp, _vp]),
     "feh_apply_preconditioner": (ctypes.c_int, [_vp, _vp, _vp]),
     "feh_apply_projection": (ctypes.c_int, [_vp, _vp, _vp]),
@@ -213,7 +235,7 @@ def feh_solve(plan, Ebar, tol, max_iter, u0_ptr=0, u_ptr=0, strain_ptr=0, stress
                           _vp(strain_ptr or 0), _vp(stress_ptr or 0), smean.ctypes.data_as(_dp),
                           W.ctypes.data_as(_dp), rep)
     _check(rc, allow=(FEH_ENOCONV,) if allow_noconv else ())
-    return rc, smean, W, [dict(iterations=r.iterations, status=r.status, rel_residual=r.rel_residual) for r in rep]
+    return rc, smean, W, [_report_dict(r) for r in rep]
 
 
 def feh_strain_cg_points(kind, dim):
@@ -239,7 +261,7 @@ def feh_strain_cg_solve(plan, kind, Ebar, tol, max_iter, work_ptr, work_bytes, s
                                     ctypes.c_size_t(int(work_bytes)), _vp(strain_ptr or 0),
                                     smean.ctypes.data_as(_dp), W.ctypes.data_as(_dp), rep)
     _check(rc, allow=(FEH_ENOCONV,) if allow_noconv else ())
-    return rc, smean, W, [dict(iterations=r.iterations, status=r.status, rel_residual=r.rel_residual) for r in rep]
+    return rc, smean, W, [_report_dict(r) for r in rep]
 
 
 def feh_finite_strain_workspace_bytes(plan, kind):
@@ -297,7 +319,7 @@ def feh_batch_solve(batch, Ebars, tol, max_iter, use_graph=True, allow_noconv=Tr
     rp = (ctypes.POINTER(feh_report) * n)(*[ctypes.cast(r, ctypes.POINTER(feh_report)) for r in reps])
     rc = load().feh_batch_solve(batch, eb, float(tol), int(max_iter), 1 if use_graph else 0, smp, Wp, rp)
     _check(rc, allow=(FEH_ENOCONV,) if allow_noconv else ())
-    out_rep = [[dict(iterations=r.iterations, status=r.status, rel_residual=r.rel_residual) for r in rr] for rr in reps]
+    out_rep = [[_report_dict(r) for r in rr] for rr in reps]
     return rc, sm, W, out_rep
 
 
@@ -372,6 +394,11 @@ def feh_effective_stiffness_weights(dim, Ebar, G):
 def feh_energy_sensitivity(plan, weight, glam_ptr, gmu_ptr):
     w = np.ascontiguousarray(weight, dtype=np.float64)
     return _check(load().feh_energy_sensitivity(plan, w.ctypes.data_as(_dp), _vp(glam_ptr), _vp(gmu_ptr)))
+
+
+def feh_energy_sensitivity_E(plan, weight, gE_ptr):
+    w = np.ascontiguousarray(weight, dtype=np.float64)
+    return _check(load().feh_energy_sensitivity_E(plan, w.ctypes.data_as(_dp), _vp(gE_ptr)))
 
 
 def feh_apply_operator(plan, p_ptr, q_ptr):
@@ -540,6 +567,15 @@ class Homogenizer:
                                g_lam.data_ptr(), g_mu.data_ptr())
         return g_lam, g_mu
 
+    def energy_sensitivity_E(self, weight):
+        """Per-voxel dJ/dE for J = sum weight_lm W_lm of the last solve (material
+        set from an E field with a uniform nu)."""
+        gshape = self.shape if self.n_batch == 1 else (self.n_batch,) + self.shape
+        g_E = self.torch.empty(gshape, dtype=self.dtype, device=self.device)
+        feh_energy_sensitivity_E(self.plan, np.asarray(weight, dtype=np.float64).reshape(self.n_load, self.n_load),
+                                 g_E.data_ptr())
+        return g_E
+
     def c_eff_sensitivity(self, G):
         """Per-voxel (dJ/dlambda, dJ/dmu) for J = sum G_IJ C_eff_IJ of the last solve
         (nv load cases per microstructure); G one nv x nv matrix, or one per
@@ -603,7 +639,11 @@ class Homogenizer:
 class UnevenBatch:
     """Microstructures of uneven sizes solved together.
 
-    maps: list of (lam, mu) per-voxel arrays (any grid shapes, one dimension);
+    maps: list of per-map materials (any grid shapes, one dimension), each
+    either (E, nu) with a per-voxel Young's modulus array and a uniform
+    Poisson ratio (set through feh_set_material_field), or (lam, mu) per-voxel
+    Lame arrays (feh_set_material_lame); maps of one group must use one kind,
+    and (E, nu) maps of a group one nu;
     maps of the same shape share a batched plan (at most 64 load cases per
     plan), and all plans form one ``feh_batch`` whose CG chunks run as
     captured HIP graphs.  The plans take up to ``n_streams`` dedicated streams
@@ -635,9 +675,15 @@ class UnevenBatch:
                     hz = Homogenizer(shape, n_load=self.n_load, precision=precision, device=self.device,
                                      stream=self.streams[len(self.plans) % len(self.streams)],
                                      n_batch=len(part))
-                    lam = np.stack([np.asarray(maps[i][0], dtype=np.float64) for i in part])
-                    mu = np.stack([np.asarray(maps[i][1], dtype=np.float64) for i in part])
-                    hz.set_material(lam=lam, mu=mu)
+                    a = np.stack([np.asarray(maps[i][0], dtype=np.float64) for i in part])
+                    if np.ndim(maps[part[0]][1]) == 0:
+                        nus = {float(maps[i][1]) for i in part}
+                        if len(nus) != 1:
+                            raise ValueError("(E, nu) maps of one shape group need one nu")
+                        hz.set_material(E=a, nu=nus.pop())
+                    else:
+                        b = np.stack([np.asarray(maps[i][1], dtype=np.float64) for i in part])
+                        hz.set_material(lam=a, mu=b)
                     for s_, i in enumerate(part):
                         self.where[i] = (len(self.plans), s_)
                     self.plans.append((hz, part))
@@ -668,6 +714,15 @@ class UnevenBatch:
 
     def graph_launches(self):
         return feh_batch_graph_launches(self.batch)
+
+    def energy_sensitivity_E(self, weight):
+        """Per-voxel dJ/dE for J = sum weight_lm W_lm of the last solve (material
+        set from an E field with a uniform nu)."""
+        gshape = self.shape if self.n_batch == 1 else (self.n_batch,) + self.shape
+        g_E = self.torch.empty(gshape, dtype=self.dtype, device=self.device)
+        feh_energy_sensitivity_E(self.plan, np.asarray(weight, dtype=np.float64).reshape(self.n_load, self.n_load),
+                                 g_E.data_ptr())
+        return g_E
 
     def c_eff_sensitivity(self, G):
         """Per map (dJ/dlambda, dJ/dmu) for J = sum G_IJ C_eff_IJ (one nv x nv G

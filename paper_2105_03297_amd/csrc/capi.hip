@@ -257,8 +257,10 @@ static int read_flag(feh_plan &p, int *flag_dev, const char *what) {
 
 // z = M^+ r on SoA fields (spectrum buffer as scratch); Parseval r.z partials.
 // r is consumed by the first pass, so z may be the same buffer.
-static int precondition(const feh_plan &p, const void *r, void *z, double *partial, const LcState *st) {
+static int precondition(const feh_plan &p, const void *r, void *z, double *partial, const LcState *st,
+                        bool unit_volume) {
     FftArgs fa;
+    fa.unit_volume = unit_volume;
     fa.r = r;
     fa.spec = p.ws + p.off_spec;
     fa.z = z;
@@ -320,6 +322,7 @@ static int cg_iteration(const feh_plan &p, LcState *st, double tol, int max_iter
     sa.out0 = p.ws + p.off_q;
     sa.partial = part;
     sa.state = st;
+    sa.unit_volume = true;
     {
         ProfScope ps(p, 0);
         CK(launch_stencil(p, ST_CG, sa));
@@ -338,6 +341,7 @@ static int cg_iteration(const feh_plan &p, LcState *st, double tol, int max_iter
     fa.partial = part;
     fa.state = st;
     fa.out_scale = 1.0 / (double)p.N;
+    fa.unit_volume = true;
     {
         ProfScope ps(p, 2);
         CK(launch_forward_last(p, fa));
@@ -506,6 +510,7 @@ int feh_plan_set_workspace(feh_plan *plan, void *dev_ptr, size_t bytes) {
         plan->ws_bytes = bytes;
         plan->material_set = false;
         plan->solved = false;
+        plan->field_nu = -2.0;
         return upload_tables(*plan);
     } catch (...) {
         return set_error(FEH_EINVAL, "unexpected host exception");
@@ -517,6 +522,9 @@ int feh_set_material_lame(feh_plan *plan, const void *lambda_dev, const void *mu
     if (!lambda_dev || !mu_dev) return set_error(FEH_EINVAL, "null material pointer");
     int *flag = plan->ptr<int>(plan->off_flag);
     CK(hip_check(hipMemsetAsync(flag, 0, sizeof(int), plan->stream), "material"));
+    plan->material_set = false;
+    plan->solved = false;
+    plan->field_nu = -2.0;
     CK(launch_material_lame(*plan, lambda_dev, mu_dev, flag));
     CK(read_flag(*plan, flag, "feh_set_material_lame"));
     plan->material_set = true;
@@ -541,6 +549,9 @@ int feh_set_material_phases(feh_plan *plan, const int32_t *phase_dev, const doub
                  "phase table"));
     int *flag = plan->ptr<int>(plan->off_flag);
     CK(hip_check(hipMemsetAsync(flag, 0, sizeof(int), plan->stream), "material"));
+    plan->material_set = false;
+    plan->solved = false;
+    plan->field_nu = -2.0;
     CK(launch_material_phases(*plan, phase_dev, dtab, n_phase, flag));
     CK(read_flag(*plan, flag, "feh_set_material_phases"));
     plan->material_set = true;
@@ -554,9 +565,13 @@ int feh_set_material_field(feh_plan *plan, const void *E_dev, double nu) {
     if (!(nu > -1.0 && nu < 0.5)) return set_error(FEH_EINVAL, "nu must lie in (-1, 0.5)");
     int *flag = plan->ptr<int>(plan->off_flag);
     CK(hip_check(hipMemsetAsync(flag, 0, sizeof(int), plan->stream), "material"));
+    plan->material_set = false;
+    plan->solved = false;
+    plan->field_nu = -2.0;
     CK(launch_material_field(*plan, E_dev, nu, flag));
     CK(read_flag(*plan, flag, "feh_set_material_field"));
     plan->material_set = true;
+    plan->field_nu = nu;
     plan->solved = false;
     return FEH_OK;
 }
@@ -592,6 +607,7 @@ static int solve_begin(feh_plan &p, const double *Ebar_host, double tol, int max
     CK(launch_init_state(p, st, p.L));
     StencilArgs sa;
     sa.Ebar = ebar_dev;
+    sa.unit_volume = true;
     if (u0_dev) {
         CK(launch_aos_to_soa(p, u0_dev, p.ws + p.off_u));
         // the fluctuation is fixed up to a rigid translation: start from zero mean
@@ -600,7 +616,7 @@ static int solve_begin(feh_plan &p, const double *Ebar_host, double tol, int max
         sa.in0 = nullptr;
         sa.out0 = p.ws + p.off_q;
         CK(launch_stencil(p, ST_RESID, sa));
-        CK(precondition(p, p.ws + p.off_q, p.ws + p.off_q, part, nullptr));
+        CK(precondition(p, p.ws + p.off_q, p.ws + p.off_q, part, nullptr, true));
         CK(launch_finish_rho(p, st, part, first_num_parts(p), 0, tol, max_iter));
         sa.in0 = p.ws + p.off_u;
     } else {
@@ -610,7 +626,7 @@ static int solve_begin(feh_plan &p, const double *Ebar_host, double tol, int max
     // r = f - K u0, first search direction p = M^+ r
     sa.out0 = p.ws + p.off_r;
     CK(launch_stencil(p, ST_RESID, sa));
-    CK(precondition(p, p.ws + p.off_r, p.ws + p.off_p, part, nullptr));
+    CK(precondition(p, p.ws + p.off_r, p.ws + p.off_p, part, nullptr, true));
     return launch_finish_rho(p, st, part, first_num_parts(p), u0_dev ? 1 : 11, tol, max_iter);
 }
 
@@ -695,6 +711,7 @@ int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
               void *strain_dev, void *stress_dev, double *stress_mean_host, double *energy_host,
               feh_report *report_host) {
     try {
+        const double t0 = wall_seconds();
         CK(check_plan(plan, true));
         feh_plan &p = *plan;
         CK(solve_begin(p, Ebar_host, tol, max_iter, u0_dev));
@@ -711,7 +728,9 @@ int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
             done += c;
             if (chunk < 16) chunk *= 2;
         }
-        return solve_end(p, u_dev, strain_dev, stress_dev, stress_mean_host, energy_host, report_host);
+        const int rc = solve_end(p, u_dev, strain_dev, stress_dev, stress_mean_host, energy_host, report_host);
+        if (rc == FEH_OK || rc == FEH_ENOCONV || rc == FEH_EBREAKDOWN) stamp_reports(report_host, p.L, t0);
+        return rc;
     } catch (const std::bad_alloc &) {
         return set_error(FEH_ENOMEM, "host allocation failed");
     } catch (...) {
@@ -838,6 +857,7 @@ int feh_batch_destroy(feh_batch *b) {
 int feh_batch_solve(feh_batch *b, const double *const *Ebar_host, double tol, int max_iter, int use_graph,
                     double *const *stress_mean_host, double *const *energy_host, feh_report *const *report_host) {
     try {
+        const double t0 = wall_seconds();
         if (!b) return set_error(FEH_EINVAL, "null batch");
         if (!Ebar_host) return set_error(FEH_EINVAL, "null Ebar table");
         const int n = (int)b->plans.size();
@@ -872,6 +892,8 @@ int feh_batch_solve(feh_batch *b, const double *const *Ebar_host, double tol, in
                                     energy_host ? energy_host[i] : nullptr, report_host ? report_host[i] : nullptr);
             if (r == FEH_EBREAKDOWN || (r != FEH_OK && rc == FEH_OK)) rc = r;
         }
+        if (report_host)
+            for (int i = 0; i < n; ++i) stamp_reports(report_host[i], b->plans[i]->L, t0);
         if (rc == FEH_ENOCONV) return set_error(rc, "max_iter reached before the tolerance (some plan)");
         if (rc == FEH_EBREAKDOWN) return set_error(rc, "CG breakdown (some plan)");
         return rc;
@@ -1174,11 +1196,24 @@ int feh_profile_read(const feh_plan *plan, double *ms_total, int64_t *launches, 
     return FEH_OK;
 }
 
-int feh_energy_sensitivity(feh_plan *plan, const double *weight_host, void *grad_lam_dev, void *grad_mu_dev) {
+// Sensitivity pass shared by feh_energy_sensitivity (grad_E_dev null: the
+// two Lame fields) and feh_energy_sensitivity_E (grad_lam_dev, grad_mu_dev
+// null: the Young's modulus field through the plane-strain Lame maps at the
+// nu the material was set with).
+static int sensitivity(feh_plan *plan, const double *weight_host, void *grad_lam_dev, void *grad_mu_dev,
+                       void *grad_E_dev) {
     try {
         CK(check_plan(plan, true));
         feh_plan &p = *plan;
-        if (!weight_host || !grad_lam_dev || !grad_mu_dev) return set_error(FEH_EINVAL, "null argument");
+        if (!weight_host || (!grad_E_dev && (!grad_lam_dev || !grad_mu_dev))) return set_error(FEH_EINVAL, "null argument");
+        double aE = 0.0, bE = 0.0;
+        if (grad_E_dev) {
+            if (!(p.field_nu > -1.0 && p.field_nu < 0.5))
+                return set_error(FEH_EINVAL, "the material was not set by feh_set_material_field");
+            const double nu = p.field_nu;
+            aE = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));  // d lambda / d E
+            bE = 1.0 / (2.0 * (1.0 + nu));             // d mu / d E
+        }
         if (!p.solved) return set_error(FEH_EINVAL, "no solution in the plan (call feh_solve first)");
         for (int i = 0; i < p.L * p.L; ++i)
             if (!std::isfinite(weight_host[i])) return set_error(FEH_EINVAL, "weights must be finite");
@@ -1212,13 +1247,23 @@ int feh_energy_sensitivity(feh_plan *plan, const double *weight_host, void *grad
         }
         CK(hip_check(hipMemcpyAsync(dgo, gofs.data(), gofs.size() * sizeof(int), hipMemcpyHostToDevice, p.stream), "pairs"));
         CK(launch_sensitivity(p, p.ws + p.off_u, p.ptr<double>(p.off_ebar), dpl, dpm, dpw, dgo, grad_lam_dev,
-                              grad_mu_dev));
+                              grad_mu_dev, grad_E_dev, aE, bE));
         return hip_check(hipStreamSynchronize(p.stream), "sensitivity");
     } catch (const std::bad_alloc &) {
         return set_error(FEH_ENOMEM, "host allocation failed");
     } catch (...) {
         return set_error(FEH_EINVAL, "unexpected host exception");
     }
+}
+
+int feh_energy_sensitivity(feh_plan *plan, const double *weight_host, void *grad_lam_dev, void *grad_mu_dev) {
+    if (!grad_lam_dev || !grad_mu_dev) return set_error(FEH_EINVAL, "null argument");
+    return sensitivity(plan, weight_host, grad_lam_dev, grad_mu_dev, nullptr);
+}
+
+int feh_energy_sensitivity_E(feh_plan *plan, const double *weight_host, void *grad_E_dev) {
+    if (!grad_E_dev) return set_error(FEH_EINVAL, "null argument");
+    return sensitivity(plan, weight_host, nullptr, nullptr, grad_E_dev);
 }
 
 int feh_apply_operator(feh_plan *plan, const void *p_dev, void *q_dev) {
@@ -1239,7 +1284,7 @@ int feh_apply_preconditioner(feh_plan *plan, const void *r_dev, void *z_dev) {
     if (!r_dev || !z_dev) return set_error(FEH_EINVAL, "null argument");
     feh_plan &p = *plan;
     CK(launch_aos_to_soa(p, r_dev, p.ws + p.off_r));
-    CK(precondition(p, p.ws + p.off_r, p.ws + p.off_q, nullptr, nullptr));
+    CK(precondition(p, p.ws + p.off_r, p.ws + p.off_q, nullptr, nullptr, false));
     CK(launch_soa_to_aos(p, p.ws + p.off_q, z_dev));
     return hip_check(hipStreamSynchronize(p.stream), "apply preconditioner");
 }
@@ -1253,7 +1298,7 @@ int feh_apply_projection(feh_plan *plan, const void *e_dev, void *Ge_dev) {
     sa.out0 = p.ws + p.off_q;
     sa.identity_material = true;
     CK(launch_stencil(p, ST_DIV, sa));
-    CK(precondition(p, p.ws + p.off_q, p.ws + p.off_q, nullptr, nullptr));
+    CK(precondition(p, p.ws + p.off_q, p.ws + p.off_q, nullptr, nullptr, false));
     CK(launch_grad(p, p.ws + p.off_q, Ge_dev));
     return hip_check(hipStreamSynchronize(p.stream), "apply projection");
 }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -139,6 +140,7 @@ struct feh_plan {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     bool material_set = false;
+    double field_nu = -2.0;             // nu of feh_set_material_field (outside (-1, 0.5): other setter)
     // launch geometry chosen by feh_plan_autotune (0: the default heuristic);
     // the radix orders are the pass lists of fft[]
     int tune_rr_last = 0;               // rows per workgroup, last axis
@@ -172,6 +174,17 @@ namespace feh {
 int set_error(int code, const std::string &msg);
 int hip_check(hipError_t e, const char *what);
 
+// Host wall clock (seconds) and the stamp of a call's duration into its
+// reports (every load case of one call gets the same value).
+inline double wall_seconds() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+inline void stamp_reports(feh_report *rep, int n, double t0) {
+    if (!rep) return;
+    const double dt = wall_seconds() - t0;
+    for (int i = 0; i < n; ++i) rep[i].seconds = dt;
+}
+
 // return the error code of a failing call
 #define CK(...)                          \
     do {                                 \
@@ -197,6 +210,11 @@ struct StencilArgs {
     double *partial = nullptr;   // [L][part_stride] (CG)
     const LcState *state = nullptr;
     bool identity_material = false;  // lambda = 0, mu = 1/2 (preconditioner tests)
+    // element volume divided by the voxel volume (1/6, 1/2) instead of the
+    // true volume: the CG paths scale K, f and M by the same constant, which
+    // leaves every iterate unchanged and keeps FP32 stencils in range at any
+    // voxel size; the test exports use the true volume
+    bool unit_volume = false;
 };
 
 int launch_stencil(const feh_plan &p, int mode, const StencilArgs &a);
@@ -216,6 +234,7 @@ struct FftArgs {
     int ksolve = 1;              // apply (B^*B)^-1 between forward and inverse first axis
     bool identity_test = false;  // forward/inverse only (no k-solve)
     int comps = 0;               // components per point (0: the dimension)
+    bool unit_volume = false;    // M formed with the element volume over the voxel volume (CG paths)
 };
 
 int launch_forward_last(const feh_plan &p, const FftArgs &a);   // r2c along the last axis
@@ -254,8 +273,10 @@ int launch_post_sums(const feh_plan &p, const void *u, const double *Ebar_dev, v
 int launch_grad(const feh_plan &p, const void *u, void *e);   // e = sym(B u) element field
 // g_lam, g_mu [nbatch][N] = sum over the pairs of each microstructure (l <= m,
 // weight w; pairs gofs[b] .. gofs[b+1] - 1) of the voxel's share of dW_lm/dlambda, dW_lm/dmu
+// g_E non-null: write g_E = aE g_lam + bE g_mu instead of the two fields
 int launch_sensitivity(const feh_plan &p, const void *u, const double *Ebar_dev, const int *pl, const int *pm,
-                       const double *pw, const int *gofs, void *g_lam, void *g_mu);
+                       const double *pw, const int *gofs, void *g_lam, void *g_mu, void *g_E, double aE,
+                       double bE);
 int post_num_slots(const feh_plan &p);
 
 // partial-sum sizes

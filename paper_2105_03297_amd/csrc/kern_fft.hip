@@ -1070,7 +1070,8 @@ FK<T> base_args(const feh_plan &p, const FftArgs &fa) {
     a.part_stride = (int)p.part_stride;
     a.out_scale = fa.out_scale;
     a.invN = 1.0 / (double)p.N;
-    const double vol = p.dim == 3 ? p.h[0] * p.h[1] * p.h[2] / 6.0 : p.h[0] * p.h[1] / 2.0;
+    const double vol = p.dim == 3 ? (fa.unit_volume ? 1.0 : p.h[0] * p.h[1] * p.h[2]) / 6.0
+                                  : (fa.unit_volume ? 1.0 : p.h[0] * p.h[1]) / 2.0;
     a.chalf = 0.5 * vol;
     double hmax = 0.0;
     for (int ax = 0; ax < p.dim; ++ax) hmax = std::max(hmax, p.h[ax]);

@@ -268,9 +268,12 @@ __global__ __launch_bounds__(kThreads) void k_grad(PK<T> a) {
 // (scale = 1 / (N n_e)).  The pair list holds l <= m within one
 // microstructure, grouped by microstructure (pairs gofs[b] .. gofs[b+1] - 1
 // write field b); an off-diagonal pair's weight already carries w_lm + w_ml.
+// g_E non-null: one field g_E = aE g_lam + bE g_mu (the Young's modulus
+// sensitivity through the Lame maps at a uniform nu) instead of the two.
 template <typename T, int DIM>
 __global__ __launch_bounds__(kThreads) void k_sens(PK<T> a, const int *pl, const int *pm, const double *pw,
-                                                   const int *gofs, double scale, T *g_lam, T *g_mu) {
+                                                   const int *gofs, double scale, T *g_lam, T *g_mu, T *g_E,
+                                                   double aE, double bE) {
     constexpr int NE = DIM == 3 ? 6 : 2;
     constexpr int NS = DIM == 3 ? 6 : 3;
     for (long long v = blockIdx.x * (long long)kThreads + threadIdx.x; v < a.N; v += (long long)gridDim.x * kThreads) {
@@ -311,8 +314,12 @@ __global__ __launch_bounds__(kThreads) void k_sens(PK<T> a, const int *pl, const
             gl += w * sl;
             gm += w * sm;
         }
-        g_lam[(long long)bb * a.N + v] = T(gl * scale);
-        g_mu[(long long)bb * a.N + v] = T(gm * scale);
+        if (g_E) {
+            g_E[(long long)bb * a.N + v] = T((aE * gl + bE * gm) * scale);
+        } else {
+            g_lam[(long long)bb * a.N + v] = T(gl * scale);
+            g_mu[(long long)bb * a.N + v] = T(gm * scale);
+        }
       }
     }
 }
@@ -414,7 +421,7 @@ int launch_grad(const feh_plan &p, const void *u, void *e) {
 
 template <typename T>
 static int sens_t(const feh_plan &p, const void *u, const double *Ebar, const int *pl, const int *pm, const double *pw,
-                  const int *gofs, void *g_lam, void *g_mu) {
+                  const int *gofs, void *g_lam, void *g_mu, void *g_E, double aE, double bE) {
     PK<T> a = post_args<T>(p);
     a.u = static_cast<const T *>(u);
     a.Ebar = Ebar;
@@ -424,17 +431,17 @@ static int sens_t(const feh_plan &p, const void *u, const double *Ebar, const in
     const double scale = 1.0 / ((double)p.N * ne);
     if (p.dim == 3)
         hipLaunchKernelGGL((k_sens<T, 3>), dim3((unsigned)g), dim3(kThreads), 0, p.stream, a, pl, pm, pw, gofs, scale,
-                           static_cast<T *>(g_lam), static_cast<T *>(g_mu));
+                           static_cast<T *>(g_lam), static_cast<T *>(g_mu), static_cast<T *>(g_E), aE, bE);
     else
         hipLaunchKernelGGL((k_sens<T, 2>), dim3((unsigned)g), dim3(kThreads), 0, p.stream, a, pl, pm, pw, gofs, scale,
-                           static_cast<T *>(g_lam), static_cast<T *>(g_mu));
+                           static_cast<T *>(g_lam), static_cast<T *>(g_mu), static_cast<T *>(g_E), aE, bE);
     return hip_check(hipGetLastError(), "sensitivity launch");
 }
 
 int launch_sensitivity(const feh_plan &p, const void *u, const double *Ebar_dev, const int *pl, const int *pm,
-                       const double *pw, const int *gofs, void *g_lam, void *g_mu) {
-    return p.prec == FEH_FP64 ? sens_t<double>(p, u, Ebar_dev, pl, pm, pw, gofs, g_lam, g_mu)
-                              : sens_t<float>(p, u, Ebar_dev, pl, pm, pw, gofs, g_lam, g_mu);
+                       const double *pw, const int *gofs, void *g_lam, void *g_mu, void *g_E, double aE, double bE) {
+    return p.prec == FEH_FP64 ? sens_t<double>(p, u, Ebar_dev, pl, pm, pw, gofs, g_lam, g_mu, g_E, aE, bE)
+                              : sens_t<float>(p, u, Ebar_dev, pl, pm, pw, gofs, g_lam, g_mu, g_E, aE, bE);
 }
 
 }  // namespace feh

@@ -600,7 +600,7 @@ int launch_t(const feh_plan &p, int mode, const StencilArgs &sa) {
         a.ih[0] = T(1.0 / p.h[0]);
         a.ih[1] = T(1.0 / p.h[1]);
         a.ih[2] = T(1.0 / p.h[2]);
-        a.vol = T(p.h[0] * p.h[1] * p.h[2] / 6.0);
+        a.vol = T(sa.unit_volume ? 1.0 / 6.0 : p.h[0] * p.h[1] * p.h[2] / 6.0);
     } else {
         a.n0 = (int)p.n[0];
         a.n1 = 1;
@@ -608,7 +608,7 @@ int launch_t(const feh_plan &p, int mode, const StencilArgs &sa) {
         a.ih[0] = T(1.0 / p.h[0]);
         a.ih[1] = T(1.0 / p.h[1]);
         a.ih[2] = T(1);
-        a.vol = T(p.h[0] * p.h[1] / 2.0);
+        a.vol = T(sa.unit_volume ? 0.5 : p.h[0] * p.h[1] / 2.0);
     }
     a.N = p.N;
     a.xc = xchunk(a.n0);

@@ -509,6 +509,7 @@ int feh_strain_cg_solve(feh_plan *plan, int kind, const double *Ebar_host, doubl
                         size_t work_bytes, void *strain_dev, double *stress_mean_host, double *energy_host,
                         feh_report *report_host) {
     try {
+        const double t0 = wall_seconds();
         int ne = 0;
         CK(check_kind(plan, kind, ne));
         feh_plan &p = *plan;
@@ -571,6 +572,7 @@ int feh_strain_cg_solve(feh_plan *plan, int kind, const double *Ebar_host, doubl
                 }
         }
         rc = FEH_OK;
+        stamp_reports(report_host, p.L, t0);
         for (int l = 0; l < p.L; ++l) {
             if (report_host) {
                 report_host[l].iterations = hs[l].iters;

@@ -12,7 +12,15 @@ one by one or what holds at any size:
   * the solve: C_eff symmetric positive definite inside the Voigt and Reuss
     bounds, energy and stress-average forms consistent, FP32 within 1e-5 of
     the FP64 solve of the same input;
-and the same recipe at 32^3 is compared with the full oracle solve."""
+  * the FE equilibrium f - K u = 0 of the returned 256^3 fluctuations (FP32 and
+    FP64) at sampled nodes, f and K u evaluated element by element by the
+    oracle;
+and the same recipe at 64^3 (two 32-plane chunks of the stencil march) is
+compared with the oracle's solve stored in tests/golden/grf64_oracle.json,
+and at 32^3 with a full oracle solve in the test."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -179,3 +187,86 @@ def test_grf_recipe_32_matches_oracle(prec):
     err = rel(out["C_eff"], ref["C_eff"])
     print("C_eff rel err vs oracle", err)
     assert err < (1e-5 if prec == "fp32" else 1e-10)
+
+
+def _steep_nodes(E, n_random, n_steep, seed):
+    """Seeded random nodes plus the nodes next to the steepest changes of E
+    (where the right-hand side f is largest), and the first and last node."""
+    N = E.size
+    steep = np.zeros(E.shape)
+    for ax in range(E.ndim):
+        steep = np.maximum(steep, np.abs(np.roll(E, -1, axis=ax) - E))
+    top = np.argpartition(steep.ravel(), -n_steep)[-n_steep:]
+    rnd = np.random.default_rng(seed).choice(N, n_random, replace=False)
+    return np.unique(np.concatenate([rnd, top, [0, N - 1]]))
+
+
+# bounds on max_nodes |f - K u| / (max(lambda + 2 mu) max|Ebar|): the FP64
+# solve stops at a relative residual of 1e-10 in the M^-1 norm, the FP32 one
+# at 1e-5 with its u rounded to FP32
+EQUIL_BOUND = {"fp64": 1e-8, "fp32": 1e-4}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_fullsize_equilibrium_sampled(grf, prec):
+    """The benchmark configuration's own solution is the canonical FE solution:
+    f - K u at 66 sampled nodes (32 seeded, 32 at the steepest changes of E,
+    the first and last), with f and K u formed element by element by the
+    oracle from the GPU's u and the plan's material, for every load case."""
+    import torch
+    from oracle import fe
+    say("fullsize equilibrium 256^3 x 6", prec)
+    m, E32 = grf
+    E = E32.astype(np.float64) if prec == "fp32" else m.E
+    h = _plan(prec)
+    h.set_material(E=torch.as_tensor(E32 if prec == "fp32" else m.E), nu=0.3)
+    Eb = ms.unit_loads(3)
+    out = h.solve(Eb, tol=1e-5 if prec == "fp32" else 1e-10, max_iter=5000, return_u=True)
+    assert out["status"] == 0
+    lam, mu = fe.lame(E, np.full(SHAPE, 0.3))
+    if prec == "fp32":
+        lam = lam.astype(np.float32).astype(np.float64)
+        mu = mu.astype(np.float32).astype(np.float64)
+    nodes = _steep_nodes(E, 32, 32, 77)
+    scale = float((lam + 2 * mu).max() * np.abs(Eb).max())
+    worst = 0.0
+    for l in range(6):
+        ul = out["u"][l].double().cpu().numpy()
+        f = fe.load_at_nodes(lam, mu, Eb[l], nodes)
+        Ku = fe.apply_K_at_nodes(lam, mu, ul, nodes)
+        assert np.abs(f).max() > 1e-3 * scale  # the steep sample carries load
+        worst = max(worst, float(np.abs(f - Ku).max() / scale))
+    h.close()
+    print("256^3 %s equilibrium residual at sampled nodes: %.3e (iterations %s)"
+          % (prec, worst, [r["iterations"] for r in out["report"]]))
+    assert worst < EQUIL_BOUND[prec]
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "grf64_oracle.json")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_grf_recipe_64_matches_oracle_golden(prec):
+    """The benchmark recipe at 64^3 (correlation length 4 voxels, seed 1004)
+    against the oracle's plain-CG solve to 1e-13 stored by
+    tests/golden/make_grf64.py: C_eff (energy form) and the stress means."""
+    import torch
+    import paper_2105_03297_amd as feh
+    say("grf recipe 64^3 vs stored oracle solve", prec)
+    ref = json.load(open(GOLDEN))
+    n = ref["n"]
+    m = ms.grf_modulus((n, n, n), ref["ell"], ref["seed"], ref["nu"])
+    assert m.recipe == ref["recipe"]
+    Eb = np.array(ref["load_cases"])
+    h = feh.Homogenizer((n, n, n), n_load=6, precision=prec)
+    E = m.E.astype(np.float32) if prec == "fp32" else m.E
+    h.set_material(E=torch.as_tensor(E), nu=ref["nu"])
+    out = h.solve(Eb, tol=1e-5 if prec == "fp32" else 1e-12, max_iter=5000)
+    h.close()
+    err = rel(out["C_eff"], np.array(ref["C_eff"]))
+    serr = rel(out["stress_mean"], np.array(ref["stress_mean"]))
+    print("64^3 %s: C_eff rel err %.3e, <sigma> rel err %.3e, iterations %s"
+          % (prec, err, serr, [r["iterations"] for r in out["report"]]))
+    # FP32: the material itself is rounded to FP32 (relative 6e-8)
+    assert err < (1e-5 if prec == "fp32" else 1e-10)
+    assert serr < (1e-5 if prec == "fp32" else 1e-10)

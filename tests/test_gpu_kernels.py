@@ -2,9 +2,10 @@
 definition (numpy.fft), q = K p vs the oracle's assembled stiffness, z = M^+ r
 vs a direct solve of the assembled M (lambda = 0, mu = 1/2), and the
 projection G vs the small-strain appendix operator and dense brute force.
-Shapes span several tiles with ragged tails (stencil tiles 4 x 64 in 3D and
-256 in 2D, 16-plane chunks along axis 0) and odd sizes (Nyquist-free axes,
-general radices)."""
+Shapes span several tiles with ragged tails (3D stencil tiles of 8 x 32 voxels
+updating 7 x 31 nodes, 2D rows of 256 voxels updating 255 nodes, marches of
+32-plane chunks along axis 0: operator shapes with n0 > 32 cross chunk
+boundaries) and odd sizes (Nyquist-free axes, general radices)."""
 import numpy as np
 import pytest
 
@@ -42,7 +43,8 @@ def test_fft_roundtrip_matches_dft(shape, prec):
     h.close()
 
 
-OP_SHAPES = [(6, 5), (7, 300), (40, 20), (3, 4, 5), (5, 9, 70), (18, 6, 5), (2, 2, 2), (9, 7, 130)]
+OP_SHAPES = [(6, 5), (7, 300), (40, 20), (3, 4, 5), (5, 9, 70), (18, 6, 5), (2, 2, 2), (9, 7, 130),
+             (70, 9, 40), (65, 17, 33)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

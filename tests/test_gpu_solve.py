@@ -314,17 +314,18 @@ def test_fp32_vs_fp64_circle32():
 
 
 @pytest.mark.parametrize("shape", [(48, 24), (8, 5, 48)])
-@pytest.mark.parametrize("scale", [1e-3, 1e3, 1e12])
+@pytest.mark.parametrize("scale", [1e-12, 1e-3, 1e3, 1e12])
 def test_fp32_voxel_scale_invariance(shape, scale):
     """C_eff does not depend on a uniform scaling of the voxel (the element
     stiffness and the load both scale out of the energy balance).  FP32 plans
     form M(k)^-1 in FP32 away from k = 0; M itself has entries of order h and
     a determinant of order h^3 in 3D (up to about 1.7e39 at h = 1e12, beyond
     the FP32 range), so the kernel forms it from the dimensionless factors
-    a_a h_max.  Scaled voxels must leave C_eff, and the iteration count to
-    within a few, unchanged.  The grids hold wavevectors on both sides of the
-    FP64 long-wavelength shell.  (At h = 1e-13 the FP32 stencil's element
-    volume, h^3 / 6, is itself below the FP32 normal range.)"""
+    a_a h_max, and the CG paths scale K, f and M by the voxel volume (element
+    volume 1/6 of the voxel), whose h^3 / 6 would leave the FP32 normal range
+    below h = 1e-12 (sigma |e| of order 1e-39).  Scaled voxels must leave
+    C_eff, and the iteration count to within a few, unchanged.  The grids hold
+    wavevectors on both sides of the FP64 long-wavelength shell."""
     say("fp32 voxel scale", shape, scale)
     from oracle import fe
     dim = len(shape)

@@ -115,3 +115,22 @@ def test_objective_weights_diagonal_loads():
     expect[0, 0] = 1.0 / 0.01 ** 2
     expect[4, 4] = 2.0 / 0.02 ** 2
     np.testing.assert_allclose(Wt, expect, rtol=1e-13)
+
+
+def test_gradient_on_voxel_subset_equals_full():
+    """The sensitivity formula evaluated from locally computed strains of a
+    voxel subset (grids too large for whole fields) equals the full-field
+    result at those voxels."""
+    shape = (5, 4, 3)
+    lam, mu = _material(shape, 8)
+    Eb = ms.unit_loads(3)
+    out = fe.homogenize(None, None, Eb, lam_mu=(lam, mu))
+    G = np.random.default_rng(4).standard_normal((6, 6))
+    gl, gm = adjoint.objective_gradient(out["eps"], Eb, G)
+    N = lam.size
+    vox = np.array([0, 7, 31, N - 1])
+    u = [x.reshape(-1) for x in out["u"]]
+    eps_sub = [fe.element_strains_at(u[l], shape, vox, Eb[l]) for l in range(6)]
+    sl, sm = adjoint.objective_gradient(eps_sub, Eb, G, n_voxels=N)
+    np.testing.assert_allclose(sl, gl[vox], rtol=1e-13, atol=1e-16)
+    np.testing.assert_allclose(sm, gm[vox], rtol=1e-13, atol=1e-16)

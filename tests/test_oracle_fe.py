@@ -292,3 +292,21 @@ def test_local_evaluation_matches_assembly(shape):
     Eb[0, 1] = Eb[1, 0] = 0.004
     f = fe.load_vector(lam, mu, Eb).reshape(-1, dim)
     np.testing.assert_allclose(fe.load_at_nodes(lam, mu, Eb, nodes), f[nodes], atol=1e-15)
+
+
+@pytest.mark.parametrize("shape,h", [((5, 4), (1.0, 1.0)), ((6, 3), (0.7, 1.9)), ((3, 4, 5), (1.0, 1.0, 1.0)),
+                                     ((4, 3, 5), (1.3, 0.6, 2.1))])
+def test_element_strains_at_matches_fields(shape, h):
+    """Local strain evaluation at selected voxels equals the full-field
+    post-processing there (ragged and non-unit grids; first and last voxels)."""
+    dim = len(shape)
+    N = int(np.prod(shape))
+    rng = np.random.default_rng(11)
+    u = rng.standard_normal((N, dim))
+    Eb = rng.standard_normal((dim, dim))
+    Eb = 0.5 * (Eb + Eb.T)
+    lam = np.ones(shape)
+    eps, _ = fe.fields(u, lam, lam, Eb, h)
+    vox = np.array([0, N - 1, N // 2, 1, N - 2])
+    loc = fe.element_strains_at(u, shape, vox, Eb, h)
+    np.testing.assert_allclose(loc, eps[vox], rtol=0, atol=1e-14)
