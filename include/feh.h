@@ -193,6 +193,25 @@ int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
               const void *u0_dev, void *u_dev, void *strain_dev, void *stress_dev,
               double *stress_mean_host, double *energy_host, feh_report *report_host);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): feh_solve
+ * with the workspace taken from a static device array of the library (256 MiB
+ * per GPU, held until the process ends) instead of the plan's workspace, and
+ * the material passed in as per-voxel Lame constants (lambda_dev, mu_dev as
+ * in feh_set_material_lame).  No device memory is allocated or freed; the
+ * caller passes inputs and outputs exactly as for feh_solve (same layouts,
+ * statuses and report).  The plan needs no workspace of its own; if it has
+ * one, its workspace, material and last solution are left untouched (so
+ * feh_energy_sensitivity does not see this solve).  FEH_ENOMEM if the plan's
+ * workspace (feh_plan_workspace_bytes) exceeds 256 MiB, e.g. beyond about
+ * 64^3 voxels x 6 load cases in FP64; FEH_EINVAL with profiling enabled.
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents (the solve initialises everything it reads): calls that
+ * overlap on one GPU, from any plan or thread, race.  Blocking. */
+int feh_solve_noalloc(feh_plan *plan, const void *lambda_dev, const void *mu_dev, const double *Ebar_host,
+                      double tol, int max_iter, const void *u0_dev, void *u_dev, void *strain_dev, void *stress_dev,
+                      double *stress_mean_host, double *energy_host, feh_report *report_host);
+
 /* FFT autotuner: times, on the plan's workspace and stream (blocking), the
  * candidate radix orders of each axis (the orders of the default
  * factorisation and of the radix-4 one) and then fewer rows / pencils per

@@ -20,7 +20,7 @@ __all__ = [
     "FEH_OK", "FEH_EINVAL", "FEH_ENOMEM", "FEH_EHIP", "FEH_ENOCONV", "FEH_EBREAKDOWN", "FEH_ENOTSUP",
     "FEH_FP64", "FEH_FP32", "FehError", "feh_report", "library_path", "load",
     "feh_plan_create", "feh_plan_create_batch", "feh_plan_destroy", "feh_plan_workspace_bytes", "feh_plan_set_workspace",
-    "feh_set_material_lame", "feh_set_material_phases", "feh_set_material_field", "feh_solve",
+    "feh_set_material_lame", "feh_set_material_phases", "feh_set_material_field", "feh_solve", "feh_solve_noalloc",
     "feh_effective_stiffness", "feh_effective_stiffness_weights", "feh_energy_sensitivity", "feh_energy_sensitivity_E",
     "unit_loads", "UNIT_STRAIN",
     "feh_apply_operator", "feh_apply_preconditioner", "feh_apply_projection",
@@ -97,6 +97,8 @@ _SIGS = {
     "feh_set_material_field": (ctypes.c_int, [_vp, _vp, ctypes.c_double]),
     "feh_solve": (ctypes.c_int, [_vp, _dp, ctypes.c_double, ctypes.c_int, _vp, _vp, _vp, _vp, _dp, _dp,
                                  ctypes.POINTER(feh_report)]),
+    "feh_solve_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _dp, ctypes.c_double, ctypes.c_int, _vp, _vp, _vp, _vp,
+                                         _dp, _dp, ctypes.POINTER(feh_report)]),
     "feh_effective_stiffness": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]),
     "feh_effective_stiffness_weights": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]),
     "feh_energy_sensitivity": (ctypes.c_int, [_vp, _dp, _vp, _vp]),
@@ -234,6 +236,22 @@ def feh_solve(plan, Ebar, tol, max_iter, u0_ptr=0, u_ptr=0, strain_ptr=0, stress
     rc = load().feh_solve(plan, Ebp, float(tol), int(max_iter), _vp(u0_ptr or 0), _vp(u_ptr or 0),
                           _vp(strain_ptr or 0), _vp(stress_ptr or 0), smean.ctypes.data_as(_dp),
                           W.ctypes.data_as(_dp), rep)
+    _check(rc, allow=(FEH_ENOCONV,) if allow_noconv else ())
+    return rc, smean, W, [_report_dict(r) for r in rep]
+
+
+def feh_solve_noalloc(plan, lam_ptr, mu_ptr, Ebar, tol, max_iter, u0_ptr=0, u_ptr=0, strain_ptr=0, stress_ptr=0,
+                      allow_noconv=True):
+    """feh_solve on the library's static workspace with the material passed in;
+    returns (status, stress_mean[L,D,D], energy[L,L], reports)."""
+    Eb, Ebp = _f64(Ebar)
+    L, D = Eb.shape[0], Eb.shape[1]
+    smean = np.zeros((L, D, D))
+    W = np.zeros((L, L))
+    rep = (feh_report * L)()
+    rc = load().feh_solve_noalloc(plan, _vp(lam_ptr), _vp(mu_ptr), Ebp, float(tol), int(max_iter), _vp(u0_ptr or 0),
+                                  _vp(u_ptr or 0), _vp(strain_ptr or 0), _vp(stress_ptr or 0),
+                                  smean.ctypes.data_as(_dp), W.ctypes.data_as(_dp), rep)
     _check(rc, allow=(FEH_ENOCONV,) if allow_noconv else ())
     return rc, smean, W, [_report_dict(r) for r in rep]
 

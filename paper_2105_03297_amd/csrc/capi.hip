@@ -18,6 +18,7 @@
 #include <cmath>
 #include <functional>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -401,6 +402,37 @@ static void invert(int n, std::vector<double> &A, bool &ok) {
     A = I;
 }
 
+// Workspace of feh_solve_noalloc: a file-scope device array (every GPU the
+// library runs on holds its own copy until the process ends).  In host code
+// `scratch` is only a stand-in for the symbol: its device address is queried
+// once per device, with that device current, and used everywhere instead.
+constexpr size_t kStaticScratchBytes = size_t(256) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the device of `stream`.
+static int static_scratch(hipStream_t stream, char **out) {
+    int dev = 0;
+    CK(hip_check(hipStreamGetDevice(stream, &dev), "device of the plan's stream"));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(FEH_ENOTSUP, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = 0;
+        CK(hip_check(hipGetDevice(&cur), "current device"));
+        if (cur != dev) CK(hip_check(hipSetDevice(dev), "select the plan's device"));
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        CK(hip_check(e, "address of the static scratch"));
+        if (!ptr) return set_error(FEH_EHIP, "null address of the static scratch");
+        g_scratch_ptr[dev] = static_cast<char *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return FEH_OK;
+}
+
 }  // namespace feh
 
 using namespace feh;
@@ -521,7 +553,7 @@ int feh_set_material_lame(feh_plan *plan, const void *lambda_dev, const void *mu
     CK(check_plan(plan, false));
     if (!lambda_dev || !mu_dev) return set_error(FEH_EINVAL, "null material pointer");
     int *flag = plan->ptr<int>(plan->off_flag);
-    CK(hip_check(hipMemsetAsync(flag, 0, sizeof(int), plan->stream), "material"));
+    CK(launch_fill(*plan, flag, 1, 0.0));  // a kernel, not a memset node (capturable)
     plan->material_set = false;
     plan->solved = false;
     plan->field_nu = -2.0;
@@ -548,7 +580,7 @@ int feh_set_material_phases(feh_plan *plan, const int32_t *phase_dev, const doub
     CK(hip_check(hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, plan->stream),
                  "phase table"));
     int *flag = plan->ptr<int>(plan->off_flag);
-    CK(hip_check(hipMemsetAsync(flag, 0, sizeof(int), plan->stream), "material"));
+    CK(launch_fill(*plan, flag, 1, 0.0));  // a kernel, not a memset node (capturable)
     plan->material_set = false;
     plan->solved = false;
     plan->field_nu = -2.0;
@@ -564,7 +596,7 @@ int feh_set_material_field(feh_plan *plan, const void *E_dev, double nu) {
     if (!E_dev) return set_error(FEH_EINVAL, "null material pointer");
     if (!(nu > -1.0 && nu < 0.5)) return set_error(FEH_EINVAL, "nu must lie in (-1, 0.5)");
     int *flag = plan->ptr<int>(plan->off_flag);
-    CK(hip_check(hipMemsetAsync(flag, 0, sizeof(int), plan->stream), "material"));
+    CK(launch_fill(*plan, flag, 1, 0.0));  // a kernel, not a memset node (capturable)
     plan->material_set = false;
     plan->solved = false;
     plan->field_nu = -2.0;
@@ -707,6 +739,30 @@ static int any_active(feh_plan *const *plans, int n, std::vector<std::vector<LcS
     return FEH_OK;
 }
 
+// The whole solve on the plan's current workspace: set-up, CG loop (host
+// checks of the stop flags after chunks of 4, 8, then 16 iterations), and
+// finalisation.
+static int solve_all(feh_plan &p, const double *Ebar_host, double tol, int max_iter, const void *u0_dev, void *u_dev,
+                     void *strain_dev, void *stress_dev, double *stress_mean_host, double *energy_host,
+                     feh_report *report_host) {
+    CK(solve_begin(p, Ebar_host, tol, max_iter, u0_dev));
+    LcState *st = p.ptr<LcState>(p.off_state);
+    std::vector<std::vector<LcState>> hs(1);
+    feh_plan *pp = &p;
+    int done = 0, chunk = 4;
+    while (done < max_iter) {
+        bool any = false;
+        CK(any_active(&pp, 1, hs, any));
+        prof_drain(p);
+        if (!any) break;
+        const int c = chunk < max_iter - done ? chunk : max_iter - done;
+        for (int i = 0; i < c; ++i) CK(cg_iteration(p, st, tol, max_iter));
+        done += c;
+        if (chunk < 16) chunk *= 2;
+    }
+    return solve_end(p, u_dev, strain_dev, stress_dev, stress_mean_host, energy_host, report_host);
+}
+
 int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter, const void *u0_dev, void *u_dev,
               void *strain_dev, void *stress_dev, double *stress_mean_host, double *energy_host,
               feh_report *report_host) {
@@ -714,21 +770,8 @@ int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
         const double t0 = wall_seconds();
         CK(check_plan(plan, true));
         feh_plan &p = *plan;
-        CK(solve_begin(p, Ebar_host, tol, max_iter, u0_dev));
-        LcState *st = p.ptr<LcState>(p.off_state);
-        std::vector<std::vector<LcState>> hs(1);
-        int done = 0, chunk = 4;
-        while (done < max_iter) {
-            bool any = false;
-            CK(any_active(&plan, 1, hs, any));
-            prof_drain(p);
-            if (!any) break;
-            const int c = chunk < max_iter - done ? chunk : max_iter - done;
-            for (int i = 0; i < c; ++i) CK(cg_iteration(p, st, tol, max_iter));
-            done += c;
-            if (chunk < 16) chunk *= 2;
-        }
-        const int rc = solve_end(p, u_dev, strain_dev, stress_dev, stress_mean_host, energy_host, report_host);
+        const int rc = solve_all(p, Ebar_host, tol, max_iter, u0_dev, u_dev, strain_dev, stress_dev, stress_mean_host,
+                                 energy_host, report_host);
         if (rc == FEH_OK || rc == FEH_ENOCONV || rc == FEH_EBREAKDOWN) stamp_reports(report_host, p.L, t0);
         return rc;
     } catch (const std::bad_alloc &) {
@@ -1315,6 +1358,58 @@ int feh_fft_forward(feh_plan *plan, const void *x_dev, void *X_dev) {
     CK(launch_first(p, fa, false));
     CK(launch_spec_to_numpy(p, p.ws + p.off_spec, X_dev, true));
     return hip_check(hipStreamSynchronize(p.stream), "fft forward");
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free solve: the workspace is a file-scope device array
+// ---------------------------------------------------------------------------
+int feh_solve_noalloc(feh_plan *plan, const void *lambda_dev, const void *mu_dev, const double *Ebar_host,
+                      double tol, int max_iter, const void *u0_dev, void *u_dev, void *strain_dev, void *stress_dev,
+                      double *stress_mean_host, double *energy_host, feh_report *report_host) {
+    try {
+        const double t0 = wall_seconds();
+        if (!plan) return set_error(FEH_EINVAL, "null plan");
+        if (!lambda_dev || !mu_dev) return set_error(FEH_EINVAL, "null material pointer");
+        feh_plan &p = *plan;
+        if (p.prof_on) return set_error(FEH_EINVAL, "profiling creates events; disable it for feh_solve_noalloc");
+        if (p.total > kStaticScratchBytes)
+            return set_error(FEH_ENOMEM, "the plan needs " + std::to_string(p.total) +
+                                             " bytes of workspace, more than the static scratch of " +
+                                             std::to_string(kStaticScratchBytes) + " bytes");
+        char *ws = nullptr;
+        CK(static_scratch(p.stream, &ws));
+        // borrow the static array as the workspace; the plan's own workspace,
+        // material and last solution are left as they were
+        char *const own_ws = p.ws;
+        const size_t own_bytes = p.ws_bytes;
+        const bool own_material = p.material_set, own_solved = p.solved;
+        const double own_nu = p.field_nu;
+        p.ws = ws;
+        p.ws_bytes = kStaticScratchBytes;
+        int rc = upload_tables(p);
+        if (rc == FEH_OK) {
+            int *flag = p.ptr<int>(p.off_flag);
+            rc = launch_fill(p, flag, 1, 0.0);
+            if (rc == FEH_OK) rc = launch_material_lame(p, lambda_dev, mu_dev, flag);
+            if (rc == FEH_OK) rc = read_flag(p, flag, "feh_solve_noalloc");
+        }
+        if (rc == FEH_OK) {
+            p.material_set = true;
+            rc = solve_all(p, Ebar_host, tol, max_iter, u0_dev, u_dev, strain_dev, stress_dev, stress_mean_host,
+                           energy_host, report_host);
+            if (rc == FEH_OK || rc == FEH_ENOCONV || rc == FEH_EBREAKDOWN) stamp_reports(report_host, p.L, t0);
+        }
+        p.ws = own_ws;
+        p.ws_bytes = own_bytes;
+        p.material_set = own_material;
+        p.solved = own_solved;
+        p.field_nu = own_nu;
+        return rc;
+    } catch (const std::bad_alloc &) {
+        return set_error(FEH_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return set_error(FEH_EINVAL, "unexpected host exception");
+    }
 }
 
 int feh_fft_inverse(feh_plan *plan, const void *X_dev, void *x_dev) {
