@@ -79,18 +79,21 @@ def source_sha1(name):
 def traffic_from_profiles(kernel, workload):
     """HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
     (scaled by the counters of a plain copy of known size), as committed
-    under profiles/; None when absent or when the kernel source has changed
-    since the counters were taken."""
-    tf = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    under profiles/, and a note on where the figure comes from: the counters
+    are taken in a separate profiled run, not in this one.  None when absent
+    or when the kernel source has changed since the counters were taken."""
+    rel_path = f"profiles/traffic_{kernel}_{workload}.json"
+    tf = os.path.join(ROOT, rel_path)
     if not os.path.exists(tf):
-        return None
+        return None, f"no counters committed ({rel_path} absent)"
     try:
         tj = json.load(open(tf))
     except ValueError:
-        return None
+        return None, f"{rel_path} unreadable"
     if tj.get("source_sha1") != source_sha1(kernel):
-        return None
-    return tj.get("bytes_per_launch")
+        return None, f"{rel_path} was measured on another version of the kernel source"
+    return tj.get("bytes_per_launch"), (f"{rel_path}: rocprofv3 FETCH_SIZE and WRITE_SIZE runs of this workload "
+                                        f"on kernel source sha1 {tj.get('source_sha1')} (committed, not this run)")
 
 
 def set_material(hz, m):
@@ -275,24 +278,40 @@ def finite_strain_measure(log):
     return res
 
 
-def cpu_baseline(n=40, iters=6000):
-    """Oracle timing on the host: the same random-field recipe on an n^3 grid
-    (correlation length scaled to the same fraction of the cell), one load
-    case, sparse assembly then a fixed number of plain CG iterations of the
-    oracle's C CSR solver (OpenMP)."""
+def cpu_baseline(n=128, iters=10):
+    """The oracle on the host: plain CG (C CSR, OpenMP, FP64) on the canonical
+    FE stiffness of the same random-field recipe at n^3 (correlation length
+    scaled with the cell).  The stiffness (283 M nonzeros, 3.4 GB at 128^3)
+    is far beyond any host cache, so the per-iteration time scales with the
+    nonzeros and the DOF-iterations/s carry over to 256^3 (labelled
+    extrapolated).  Median of `iters` timed iterations after 2 warm-up ones.
+    Time to solution at 256^3: plain CG iterations to ||r|| <= 1e-5 ||f||
+    measured for the xx load case at 24^3 and 48^3, extrapolated as a power
+    law in n to 256, times 6 load cases times the 256^3 iteration time (8x
+    the 128^3 one); assembly excluded."""
     import microstructures as ms
     from oracle import cg as ocg
     from oracle import fe
     m = ms.grf_modulus((n, n, n), 16.0 * n / 256.0, 1004)
     lam, mu = fe.lame(m.E, m.nu)
     t0 = time.perf_counter()
-    K = fe.assemble(lam, mu)
-    f = fe.load_vector(lam, mu, ms.unit_loads(3)[0])
+    K = fe.assemble_structured(lam, mu)
     t_asm = time.perf_counter() - t0
-    ocg.run_fixed(K, f, 5)  # warm-up (loads the library, touches memory)
-    t0 = time.perf_counter()
-    ocg.run_fixed(K, f, iters)
-    t_cg = time.perf_counter() - t0
+    f = K @ np.random.default_rng(7).standard_normal(K.shape[0])  # any vector in the range of K
+    t_it = ocg.run_timed(K, f, iters + 2)[2:]
+    t_med = float(np.median(t_it))
+    nnz = int(K.nnz)
+    del K
+    its = {}
+    for ns in (24, 48):
+        ms_ = ms.grf_modulus((ns, ns, ns), 16.0 * ns / 256.0, 1004)
+        ls, us = fe.lame(ms_.E, ms_.nu)
+        Ks = fe.assemble_structured(ls, us)
+        _, it, _ = ocg.solve(Ks, fe.load_vector(ls, us, ms.unit_loads(3)[0]), 1e-5, 10 ** 6)
+        its[ns] = int(it)
+    expo = float(np.log(its[48] / its[24]) / np.log(2.0))
+    it256 = its[48] * (256.0 / 48.0) ** expo
+    t_sol = 6 * it256 * 8.0 * t_med
     dof = 3 * n ** 3
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     model = ""
@@ -304,14 +323,21 @@ def cpu_baseline(n=40, iters=6000):
     except OSError:
         pass
     return {
-        "value": dof * iters / t_cg,
+        "value": dof / t_med,
         "unit": "DOF-CG-iterations/s",
         "cores": cores,
         "kind": "oracle",
+        "label": f"{n}^3, extrapolated to 256^3 (same DOF-iterations/s: CSR far beyond cache)",
         "host": {"cpu_model": model, "nproc": os.cpu_count(), "omp_num_threads": os.environ.get("OMP_NUM_THREADS")},
-        "sample": (f"oracle plain CG (C CSR, OpenMP) on the same E=exp(GRF) recipe at {n}^3 "
-                   f"(ell={16.0 * n / 256.0:g}), 1 load case, {iters} iterations in {t_cg:.2f} s; "
-                   f"sparse assembly {t_asm:.2f} s excluded; nnz={K.nnz}"),
+        "s_per_iteration_128": round(t_med, 5),
+        "s_per_iteration_256_extrapolated": round(8.0 * t_med, 4),
+        "time_to_C_eff_256_s_extrapolated": round(t_sol, 1),
+        "time_to_solution_basis": (f"plain CG to ||r||/||f|| <= 1e-5, xx load case: {its[24]} iterations at 24^3, "
+                                   f"{its[48]} at 48^3 (power {expo:.2f} in n), so {it256:.0f} at 256^3; "
+                                   f"x 6 load cases x {8.0 * t_med:.3f} s per 256^3 iteration (extrapolated)"),
+        "sample": (f"oracle plain CG (C CSR, OpenMP, FP64) on the E=exp(GRF) recipe at {n}^3 "
+                   f"(ell={16.0 * n / 256.0:g}), nnz={nnz}, median of {iters} iterations after 2 warm-up; "
+                   f"node-neighbour CSR assembly {t_asm:.2f} s excluded"),
     }
 
 
@@ -442,16 +468,18 @@ def main():
             # bound by FP32 vector arithmetic, not by HBM: priced in flops
             fl = STENCIL_FLOPS[dim] * N * lc_iters  # one apply per active load case and iteration
             tf = fl / (k_ms / 1e3) / 1e12
+            traffic, tsrc = traffic_from_profiles(k, args.workload)
             return {"bound": "alu", "kernel": k, "achieved": round(tf, 2), "peak": PEAK_FP32_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(tf / PEAK_FP32_TFLOPS, 4),
-                    "traffic": traffic_from_profiles(k, args.workload),
+                    "traffic": traffic, "traffic_source": tsrc,
                     "avg_launch_ms": round(k_ms / max(k_n, 1), 4),
                     "algorithmic_flops_per_launch": round(fl / max(k_n, 1)),
                     "peak_without_packed_fp32": PEAK_FP32_NOPACK_TFLOPS,
                     "frac_without_packed_fp32": round(tf / PEAK_FP32_NOPACK_TFLOPS, 4),
                     "GBps_algorithmic": round(gbs, 1)}
+        traffic, tsrc = traffic_from_profiles(k, args.workload)
         return {"bound": "hbm", "kernel": k, "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic_from_profiles(k, args.workload),
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic, "traffic_source": tsrc,
                 "avg_launch_ms": round(k_ms / max(k_n, 1), 4),
                 "algorithmic_bytes_per_launch": round(kb[k] / max(k_n, 1)),
                 "copy_ceiling_GBps": round(copy_gbs, 1), "frac_of_copy": round(gbs / copy_gbs, 4),

@@ -37,6 +37,10 @@ def _load():
         lib.oracle_csr_cg.argtypes = head + [ctypes.c_double, ctypes.c_int64, dp]
         lib.oracle_csr_cg_fixed.restype = ctypes.c_int64
         lib.oracle_csr_cg_fixed.argtypes = head + [ctypes.c_int64, dp]
+        lib.oracle_csr_cg_timed.restype = ctypes.c_int64
+        lib.oracle_csr_cg_timed.argtypes = head + [ctypes.c_int64, dp]
+        lib.oracle_structured_csr.restype = None
+        lib.oracle_structured_csr.argtypes = [ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int] + [vp] * 8
         _lib = lib
     return _lib
 
@@ -77,3 +81,32 @@ def run_fixed(K, f, iters):
     lib.oracle_csr_cg_fixed(n, _ptr(ip), _ptr(ix), _ptr(a), _ptr(f), _ptr(u), _ptr(r), _ptr(p),
                             _ptr(q), int(iters), ctypes.byref(rel))
     return u
+
+
+def run_timed(K, f, iters):
+    """Run exactly ``iters`` CG iterations and return the wall time of each
+    iteration (seconds, host clock around every iteration)."""
+    lib = _load()
+    ip, ix, a = _prep(K)
+    n = K.shape[0]
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    u, r, p, q = (np.empty(n) for _ in range(4))
+    t = np.zeros(int(iters))
+    lib.oracle_csr_cg_timed(n, _ptr(ip), _ptr(ix), _ptr(a), _ptr(f), _ptr(u), _ptr(r), _ptr(p),
+                            _ptr(q), int(iters), t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return t
+
+
+def structured_csr(shape, slot_off, t_slot, t_vc, t_A, t_B, lam, mu):
+    """Indices and values of the node-neighbour CSR (see fe.assemble_structured)."""
+    lib = _load()
+    dim = len(shape)
+    N = int(np.prod(shape))
+    nb = len(slot_off)
+    shp = np.ascontiguousarray(list(shape) + [1] * (3 - dim), dtype=np.int64)
+    indices = np.empty(N * dim * nb * dim, dtype=np.int32)
+    data = np.empty(N * dim * nb * dim)
+    lib.oracle_structured_csr(dim, _ptr(shp), nb, _ptr(np.ascontiguousarray(slot_off)), len(t_slot),
+                              _ptr(np.ascontiguousarray(t_slot)), _ptr(np.ascontiguousarray(t_vc)),
+                              _ptr(t_A), _ptr(t_B), _ptr(lam), _ptr(mu), _ptr(indices), _ptr(data))
+    return indices, data

@@ -157,6 +157,51 @@ def assemble(lam, mu, h=None):
     return K
 
 
+def assemble_structured(lam, mu, h=None):
+    """The same periodic stiffness as `assemble`, built per node from
+    node-neighbour coefficient blocks instead of a per-element triplet list
+    (far less memory and time, for grids such as 128^3).
+
+    Node n couples to node n + o for the vertex offsets o = v_d - v_c of every
+    element; the block of K[n, n + o] sums, over the elements and vertex pairs
+    (c, d) with that offset, lambda A_cd + mu B_cd of the element's voxel
+    n - v_c (element_block).  Terms with the same offset and the same vertex
+    v_c share the voxel, so their coefficient blocks are added here; the C
+    routine of the oracle (csr_cg.c) evaluates them per node.  On grids with
+    an axis of length 1 or 2, two offsets can reach the same neighbour; their
+    entries stay separate (duplicate column indices, which a product with K
+    sums)."""
+    from . import cg as ccg
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    shape = lam.shape
+    dim = len(shape)
+    h = _default_h(dim, h)
+    N = lam.size
+    coef = {}
+    for verts, g, vol in elements(dim, h):
+        for c in range(dim + 1):
+            for d in range(dim + 1):
+                key = (tuple(int(x) for x in verts[d] - verts[c]), tuple(int(x) for x in verts[c]))
+                A, B = element_block(g, vol, c, d)
+                a0, b0 = coef.get(key, (0.0, 0.0))
+                coef[key] = (a0 + A, b0 + B)
+    offs = sorted({o for o, _ in coef})
+    slot = {o: k for k, o in enumerate(offs)}
+    terms = sorted(coef)
+    pad = lambda v: list(v) + [0] * (3 - len(v))
+    slot_off = np.array([pad(o) for o in offs], dtype=np.int32)
+    t_slot = np.array([slot[o] for o, _ in terms], dtype=np.int32)
+    t_vc = np.array([pad(vc) for _, vc in terms], dtype=np.int32)
+    t_A = np.ascontiguousarray([coef[t][0] for t in terms], dtype=np.float64)
+    t_B = np.ascontiguousarray([coef[t][1] for t in terms], dtype=np.float64)
+    nb = len(offs)
+    indices, data = ccg.structured_csr(shape, slot_off, t_slot, t_vc, t_A, t_B, lam, mu)
+    idx_t = np.int32 if N * dim * nb * dim < 2 ** 31 else np.int64
+    indptr = np.arange(0, N * dim * nb * dim + 1, nb * dim, dtype=idx_t)
+    return sp.csr_matrix((data, indices, indptr), shape=(N * dim, N * dim))
+
+
 def stress_of(lam, mu, eps):
     """sigma = lambda tr(eps) I + 2 mu eps for eps[..., D, D]."""
     D = eps.shape[-1]

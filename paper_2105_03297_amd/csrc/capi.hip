@@ -162,6 +162,12 @@ static void layout(feh_plan &p) {
     // weights 8-byte aligned), weights (double)
     p.off_pairs = take((size_t)kMaxLoad * (kMaxLoad + 1) / 2 * (2 * sizeof(int) + sizeof(double)) +
                        2 * kMaxLoad * sizeof(int));
+    // (B^*B)^-1 per wavevector: D real diagonal + 3 (2D: 1) complex upper
+    // entries, for whole pencil blocks (any block size up to 32)
+    {
+        const size_t ncomp = p.dim == 3 ? 9 : 4;
+        p.off_minv = take(ncomp * (size_t)(inner0 + 32) * (size_t)p.n[0] * p.rsize);
+    }
     p.total = o;
 }
 

@@ -134,6 +134,7 @@ struct feh_plan {
     size_t off_tab = 0, off_ebar = 0, off_sums = 0;
     size_t off_part = 0, off_state = 0, off_flag = 0;
     size_t off_pairs = 0;               // load-case pair list of the sensitivity pass
+    size_t off_minv = 0;                // per-wavevector (B^*B)^-1 table of the CG's first-axis pass
     size_t part_stride = 0;             // doubles per load case in the partials
     size_t total = 0;
 
@@ -149,6 +150,10 @@ struct feh_plan {
     int tune_stencil_vy = 0;            // 3D stencil tile rows (8 or 16; 0: default)
     int tune_first_perlc = 0;           // axis-0 pass: 1 one workgroup per load case, -1 all load cases, 0 default
     bool solved = false;                // off_u holds the fluctuations of the last feh_solve
+    // the (B^*B)^-1 table at off_minv: built for this workspace and pencil
+    // block size (0: not built); rebuilt by the first-axis launcher on change
+    mutable const char *minv_ws = nullptr;
+    mutable int minv_pb = 0;
 
     // optional per-kernel event timing of the CG loop
     static constexpr int kProfKinds = 8;

@@ -393,6 +393,7 @@ struct FK {
     double out_scale, invN, chalf;  // chalf = element volume / 2
     float near0;              // FP32 plans: sum_a |aa_a|^2 below which M^-1 is formed in FP64
     float hmax_f, post_f;     // FP32 plans: h_max and h_max^2 / chalf (scale-free FP32 inverse)
+    T *minv;                  // (B^*B)^-1 table [block][component][slot] (first-axis pass)
 };
 
 // ---------------------------------------------------------------------------
@@ -862,16 +863,79 @@ __device__ __forceinline__ void slot_inverse(const FK<T> &a, int e, int PB, long
     for (int c = 0; c < 3; ++c) mo[c] = Cx<T>{T(Io[c].x), T(Io[c].y)};
 }
 
+// Components of one table entry: the D real diagonal entries of M^-1, then
+// the real and imaginary parts of its upper triangle (3 entries in 3D, 1 in 2D).
+template <int DIM>
+constexpr int kMinvComps = DIM == 3 ? 9 : 4;
+
+// Stage the per-axis phase factors of a block's PB inner wavevector indices
+// in LDS: pin[4 b + 0..3] = aa_1, om_1, aa_2, om_2 (2D: aa_1, om_1).
+template <typename T, int DIM>
+__device__ __forceinline__ void stage_inner_phases(const FK<T> &a, long long in0, int PB, Cx<double> *pin) {
+    const long long inner = a.inner_total;
+    for (int b = threadIdx.x; b < PB; b += kFftThreads) {
+        const long long inn = in0 + b;
+        if (inn < inner) {
+            if constexpr (DIM == 3) {
+                const int m1 = (int)a.d_nh.div((uint32_t)inn);
+                const int kh = (int)(inn - (long long)m1 * a.nh);
+                pin[4 * b + 0] = ld2(a.aa[1], m1);
+                pin[4 * b + 1] = ld2(a.om[1], m1);
+                pin[4 * b + 2] = ld2(a.aa[2], kh);
+                pin[4 * b + 3] = ld2(a.om[2], kh);
+            } else {
+                pin[4 * b + 0] = ld2(a.aa[1], (int)inn);
+                pin[4 * b + 1] = ld2(a.om[1], (int)inn);
+            }
+        }
+    }
+}
+
+// The (B^*B)^-1 table of the first-axis pass: one workgroup per pencil block
+// writes slot_inverse of its PB n0 wavevector slots (zeros at k = 0 and past
+// the last pencil), component-major within the block so that the pass reads
+// each component with consecutive threads on consecutive words.  Built once
+// per workspace and block size; every load case and iteration then reads the
+// inverse instead of forming it again.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kFftThreads) void k_first_table(FK<T> a) {
+    constexpr int D = DIM;
+    constexpr int NC = kMinvComps<DIM>;
+    const int blk = blockIdx.x;
+    const int PB = a.PB;
+    const long long in0 = (long long)blk * PB;
+    const int lim = (int)min((long long)PB, a.inner_total - in0) * D;
+    const int cntk = PB * a.n0;
+    __shared__ Cx<double> pin[4 * 32];
+    stage_inner_phases<T, DIM>(a, in0, PB, pin);
+    __syncthreads();
+    T *tb = a.minv + (long long)blk * NC * cntk;
+    for (int e = threadIdx.x; e < cntk; e += kFftThreads) {
+        T md[D];
+        Cx<T> mo[3];
+        bool half;
+        slot_inverse<T, DIM>(a, e, PB, in0, lim, pin, md, mo, half);
+        #pragma unroll
+        for (int c = 0; c < D; ++c) tb[c * cntk + e] = md[c];
+        #pragma unroll
+        for (int c = 0; c < (DIM == 3 ? 3 : 1); ++c) {
+            tb[(D + 2 * c) * cntk + e] = mo[c].x;
+            tb[(D + 2 * c + 1) * cntk + e] = mo[c].y;
+        }
+    }
+}
+
 // First axis: forward transform, per-wavevector z^ = M(k)^-1 r^ with the
 // Parseval partial of r.z (mode 0), inverse transform.  Mode 1: forward only;
 // mode 2: inverse only.  PERLC = false: one workgroup per block of PB pencils
 // runs through every load case, forming the inverses of its wavevectors once
 // (adjugate, see slot_inverse) and keeping them in registers.
-// PERLC = true: one workgroup per (load case, pencil block), the inverses
-// formed again per load case just in time (no register cache, more resident
-// workgroups to overlap memory and compute).  The power-of-two PERLC
+// PERLC = true: one workgroup per (load case, pencil block), load cases
+// fastest in the workgroup order (the L workgroups of a block run side by
+// side on one XCD); the inverses are read from the table of k_first_table
+// (TAB) or formed again per load case just in time.  The power-of-two PERLC
 // instantiations are held to 3 waves per SIMD (at most 168 VGPRs, no spills).
-template <typename T, int PPT, int DIM, int MODE, bool GEN, bool PERLC>
+template <typename T, int PPT, int DIM, int MODE, bool GEN, bool PERLC, bool TAB>
 __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu((PERLC && !GEN) ? 3 : 1))) void k_first(FK<T> a) {
     constexpr int NT = kFftThreads;
     constexpr int D = DIM;
@@ -882,8 +946,8 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu((PE
     int blk, lc0, lc1;
     if constexpr (PERLC) {
         const int t = xcd_remap(blockIdx.x, a.total);
-        lc0 = t / a.nblk;
-        blk = t - lc0 * a.nblk;
+        blk = t / a.L;
+        lc0 = t - blk * a.L;
         lc1 = lc0 + 1;
         if (a.st && !a.st[lc0].active) return;
     } else {
@@ -909,23 +973,8 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu((PE
     T Mid[KC][D];
     Cx<T> Mio[KC][DIM == 3 ? 3 : 1];
     unsigned half_w = 0;  // bit kw: wavevector counted once in the half-spectrum Parseval sum
-    if constexpr (MODE == 0) {
-        for (int b = threadIdx.x; b < PB; b += NT) {
-            const long long inn = in0 + b;
-            if (inn < inner) {
-                if constexpr (DIM == 3) {
-                    const int m1 = (int)a.d_nh.div((uint32_t)inn);
-                    const int kh = (int)(inn - (long long)m1 * a.nh);
-                    pin[4 * b + 0] = ld2(a.aa[1], m1);
-                    pin[4 * b + 1] = ld2(a.om[1], m1);
-                    pin[4 * b + 2] = ld2(a.aa[2], kh);
-                    pin[4 * b + 3] = ld2(a.om[2], kh);
-                } else {
-                    pin[4 * b + 0] = ld2(a.aa[1], (int)inn);
-                    pin[4 * b + 1] = ld2(a.om[1], (int)inn);
-                }
-            }
-        }
+    if constexpr (MODE == 0 && !TAB) {
+        stage_inner_phases<T, DIM>(a, in0, PB, pin);
         __syncthreads();
         if constexpr (!PERLC) {
             #pragma unroll
@@ -981,7 +1030,20 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu((PE
                     T md[D];
                     Cx<T> mo[3];
                     bool half;
-                    if constexpr (PERLC) {
+                    if constexpr (TAB) {
+                        const int cntk = PB * n0;
+                        const T *tb = a.minv + (long long)blk * kMinvComps<DIM> * cntk + e;
+                        #pragma unroll
+                        for (int c = 0; c < D; ++c) md[c] = tb[c * cntk];
+                        #pragma unroll
+                        for (int c = 0; c < (DIM == 3 ? 3 : 1); ++c)
+                            mo[c] = Cx<T>{tb[(D + 2 * c) * cntk], tb[(D + 2 * c + 1) * cntk]};
+                        // counted once in the half-spectrum Parseval sum: the
+                        // last-axis index 0 and (even length) n/2
+                        const long long inn = in0 + b;
+                        const int kh = DIM == 3 ? (int)(inn - (long long)a.d_nh.div((uint32_t)inn) * a.nh) : (int)inn;
+                        half = kh == 0 || (a.last_even && kh == a.nh - 1);
+                    } else if constexpr (PERLC) {
                         slot_inverse<T, DIM>(a, e, PB, in0, lim, pin, md, mo, half);
                     } else {
                         #pragma unroll
@@ -1249,14 +1311,34 @@ int first_t(const feh_plan &p, const FftArgs &fa, int mode) {
     const size_t dyn = ((a.n0 * sizeof(Cx<T>) + 15) / 16) * 16 + (mode == 0 ? 4 * (size_t)PB * sizeof(Cx<double>) : 0);
     if (PPT * kFftThreads * sizeof(Cx<T>) + (kFftThreads / 64) * sizeof(double) + dyn > kLdsPerWorkgroup)
         return set_error(FEH_ENOTSUP, "first axis too long for the LDS transform");
+    // the CG's fused pass (element volume relative to the voxel) reads the
+    // (B^*B)^-1 table, built here on the first use for this workspace and
+    // block size; the test exports (true volume) form the inverses in place
+    const bool tab = mode == 0 && perlc && fa.unit_volume;
+    if (tab) {
+        a.minv = p.ptr<T>(p.off_minv);
+        if (p.minv_ws != p.ws || p.minv_pb != PB) {
+            hipLaunchKernelGGL((k_first_table<T, DIM>), dim3(a.nblk), b, 0, p.stream, a);
+            const int rc = hip_check(hipGetLastError(), "inverse table launch");
+            if (rc != FEH_OK) return rc;
+            p.minv_ws = p.ws;
+            p.minv_pb = PB;
+        }
+    }
 #define FEH_FIRST(M, G)                                                                                   \
     do {                                                                                                  \
-        if (perlc) hipLaunchKernelGGL((k_first<T, PPT, DIM, M, G, true>), g, b, dyn, p.stream, a);       \
-        else hipLaunchKernelGGL((k_first<T, PPT, DIM, M, G, false>), g, b, dyn, p.stream, a);            \
+        if (perlc) hipLaunchKernelGGL((k_first<T, PPT, DIM, M, G, true, false>), g, b, dyn, p.stream, a); \
+        else hipLaunchKernelGGL((k_first<T, PPT, DIM, M, G, false, false>), g, b, dyn, p.stream, a);      \
     } while (0)
     switch (mode * 2 + (gen ? 1 : 0)) {
-    case 0: FEH_FIRST(0, false); break;
-    case 1: FEH_FIRST(0, true); break;
+    case 0:
+        if (tab) hipLaunchKernelGGL((k_first<T, PPT, DIM, 0, false, true, true>), g, b, dyn, p.stream, a);
+        else FEH_FIRST(0, false);
+        break;
+    case 1:
+        if (tab) hipLaunchKernelGGL((k_first<T, PPT, DIM, 0, true, true, true>), g, b, dyn, p.stream, a);
+        else FEH_FIRST(0, true);
+        break;
     case 2: FEH_FIRST(1, false); break;
     case 3: FEH_FIRST(1, true); break;
     case 4: FEH_FIRST(2, false); break;

@@ -310,3 +310,17 @@ def test_element_strains_at_matches_fields(shape, h):
     vox = np.array([0, N - 1, N // 2, 1, N - 2])
     loc = fe.element_strains_at(u, shape, vox, Eb, h)
     np.testing.assert_allclose(loc, eps[vox], rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("shape,h", [((5, 4), (1.0, 1.0)), ((6, 3), (0.7, 1.9)), ((3, 4, 5), (1.0, 1.0, 1.0)),
+                                     ((4, 4, 4), (1.3, 0.6, 2.1)), ((2, 3, 2), (1.0, 1.0, 1.0))])
+def test_structured_assembly_equals_triplet_assembly(shape, h):
+    """The node-neighbour assembly used for large grids gives the triplet
+    assembly's matrix entry by entry (axes of length 2 included, where two
+    neighbour offsets reach the same node)."""
+    rng = np.random.default_rng(13)
+    lam = rng.uniform(0.5, 3.0, shape)
+    mu = rng.uniform(0.5, 3.0, shape)
+    K = fe.assemble(lam, mu, h).toarray()
+    Ks = fe.assemble_structured(lam, mu, h).toarray()
+    np.testing.assert_allclose(Ks, K, rtol=0, atol=1e-13 * np.abs(K).max())
