@@ -233,8 +233,12 @@ int feh_plan_autotune(feh_plan *plan, int reps);
  * case, the default for a power-of-two axis 0; 0: every load case in one
  * workgroup, the default otherwise), stencil tile rows (3D: 8 or
  * 16 rows of 32 voxels; 2D: 1)], then for each axis 0..2 the
- * number of passes followed by the radices in pass order.  Writes at most
- * n_values entries and returns the full length. */
+ * number of passes followed by the radices in pass order, then 1 if passes
+ * whose shape has a compile-time transform may use it (power-of-two axes of
+ * 64, 128 or 256 points in the default radix order; the same butterflies and
+ * twiddles, with the index arithmetic resolved at compile time) or 0 for
+ * the run-time passes throughout (default 1).  Writes at most n_values
+ * entries and returns the full length. */
 int feh_plan_tuning(const feh_plan *plan, int *values, int n_values);
 
 /* Set the FFT schedule and stencil tile explicitly (e.g. one saved from
@@ -243,7 +247,8 @@ int feh_plan_tuning(const feh_plan *plan, int *values, int n_values);
  * quarter of the default, which sizes the partial sums), axis-0 layout 0 or 1,
  * stencil rows 8 or 16 in 3D (1 in 2D), and per axis radices from
  * {2, 3, 4, 5, 7, 8, 11, 13} or primes above 13 whose product is the
- * transformed length (n_a, n_last/2 for an even last axis).
+ * transformed length (n_a, n_last/2 for an even last axis), and optionally
+ * the trailing compile-time transform flag (0 or 1; kept if absent).
  * FEH_EINVAL leaves the plan unchanged.  Any valid schedule is exact to
  * rounding. */
 int feh_plan_set_tuning(feh_plan *plan, const int *values, int n_values);

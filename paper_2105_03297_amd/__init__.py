@@ -362,7 +362,7 @@ def feh_plan_tuning(plan):
         rad.append(v[i + 1:i + 1 + k])
         i += 1 + k
     return {"rows_last": v[0], "pencils_mid": v[1], "pencils_first": v[2], "first_per_load_case": v[3],
-            "stencil_rows": v[4], "radices": rad}
+            "stencil_rows": v[4], "radices": rad, "compile_time_transforms": v[i]}
 
 
 def feh_plan_set_tuning(plan, tuning):
@@ -372,6 +372,8 @@ def feh_plan_set_tuning(plan, tuning):
     for r in list(tuning["radices"]) + [[]] * (3 - len(tuning["radices"])):
         v.append(len(r))
         v.extend(int(x) for x in r)
+    if "compile_time_transforms" in tuning:
+        v.append(int(tuning["compile_time_transforms"]))
     buf = (ctypes.c_int * len(v))(*v)
     return _check(load().feh_plan_set_tuning(plan, buf, len(v)))
 

@@ -1189,7 +1189,14 @@ int feh_plan_set_tuning(feh_plan *plan, const int *values, int n_values) {
             }
             if (!make_axis(len, rad, ax[a])) return set_error(FEH_EINVAL, "radices do not multiply to the axis length");
         }
+        // optional trailing value: compile-time transforms allowed (1) or not (0)
+        int ct = p.tune_ct;
+        if (i < n_values) {
+            ct = values[i++];
+            if (ct != 0 && ct != 1) return set_error(FEH_EINVAL, "compile-time transform flag must be 0 or 1");
+        }
         for (int a = 0; a < 3; ++a) p.fft[a] = ax[a];
+        p.tune_ct = ct;
         p.tune_rr_last = rr;
         p.tune_pb_mid = pbm;
         p.tune_pb_first = pbf;
@@ -1210,6 +1217,7 @@ int feh_plan_tuning(const feh_plan *plan, int *values, int n_values) {
         v.push_back(np);
         for (int s = 0; s < np; ++s) v.push_back(plan->fft[a].pass[s].R);
     }
+    v.push_back(plan->tune_ct);
     for (int i = 0; i < n_values; ++i) values[i] = i < (int)v.size() ? v[i] : 0;
     return (int)v.size();
 }

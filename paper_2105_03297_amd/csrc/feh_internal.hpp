@@ -149,6 +149,7 @@ struct feh_plan {
     int tune_pb_first = 0;              // pencils per workgroup, axis 0
     int tune_stencil_vy = 0;            // 3D stencil tile rows (8 or 16; 0: default)
     int tune_first_perlc = 0;           // axis-0 pass: 1 one workgroup per load case, -1 all load cases, 0 default
+    int tune_ct = 1;                    // 1: compile-time transforms where the shape has one, 0: run-time passes only
     bool solved = false;                // off_u holds the fluctuations of the last feh_solve
     // the (B^*B)^-1 table at off_minv: built for this workspace and pencil
     // block size (0: not built); rebuilt by the first-axis launcher on change
@@ -289,6 +290,7 @@ int stencil_num_parts(const feh_plan &p);
 int stencil_rows(const feh_plan &p);           // 3D stencil tile rows in use
 int first_num_parts(const feh_plan &p);
 int first_pencils_default(const feh_plan &p);  // before tuning
+int first_ct_pencils(const feh_plan &p);       // compile-time CG pass block size (0: none)
 bool first_per_load_case(const feh_plan &p);   // axis-0 pass layout (workgroup per load case)
 int post_num_parts(const feh_plan &p);
 

@@ -397,6 +397,118 @@ struct FK {
 };
 
 // ---------------------------------------------------------------------------
+// Transforms with the shape fixed at compile time: power-of-two length N in
+// the plan's default radix order (8 while it divides, then 4 or 2), DS
+// sub-problems of NB batches each (NB a power of two), element j of batch b
+// of sub-problem s at buf[(s N + j) NB + b].  Every thread index splits into
+// (sub-problem, butterfly, batch) by shifts and masks, the LDS offsets of a
+// butterfly are compile-time strides and the passes unroll, so the index
+// arithmetic that the run-time passes spend in integer multiplies and
+// divisions (quarter-rate on this chip) and in bounds branches disappears.
+// The butterflies and twiddles are those of stockham_pass, in the same
+// order, so the results are the same numbers.
+// ---------------------------------------------------------------------------
+constexpr int ct_radix_at(int n, int s) {
+    int m = n, r = 1;
+    for (int i = 0; i <= s; ++i) {
+        r = (m % 8 == 0) ? 8 : (m % 4 == 0) ? 4 : 2;
+        m /= r;
+    }
+    return r;
+}
+constexpr int ct_npass(int n) {
+    int k = 0;
+    for (int m = n; m > 1; ++k) m /= (m % 8 == 0) ? 8 : (m % 4 == 0) ? 4 : 2;
+    return k;
+}
+constexpr int ct_lstar(int n, int s) {
+    int L = 1;
+    for (int i = 0; i < s; ++i) L *= ct_radix_at(n, i);
+    return L;
+}
+constexpr int ct_log2(int x) {
+    int l = 0;
+    while ((1 << l) < x) ++l;
+    return l;
+}
+
+// Does the run-time schedule of an axis equal the compile-time one of length n?
+__host__ inline bool ct_schedule_matches(const AxisFFT &ax, int n) {
+    if (ax.n != n || ax.npass != ct_npass(n)) return false;
+    for (int s = 0; s < ax.npass; ++s)
+        if (ax.pass[s].R != ct_radix_at(n, s)) return false;
+    return true;
+}
+
+template <typename T, int N, int NB, int DS, int S, bool INV>
+__device__ __forceinline__ void ct_pass(Cx<T> *buf, const Cx<T> *tw) {
+    constexpr int NT = kFftThreads;
+    constexpr int R = ct_radix_at(N, S), LS = ct_lstar(N, S);
+    constexpr int M = N / (LS * R), BF = N / R;
+    constexpr int ITEMS = DS * BF * NB;
+    constexpr int K = (ITEMS + NT - 1) / NT;
+    constexpr bool EXACT = ITEMS % NT == 0;  // else the last round has idle threads
+    constexpr int LNB = ct_log2(NB), LBF = ct_log2(BF), LM = ct_log2(M);
+    Cx<T> y[K][R];
+    int ob[K];
+    #pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i0 = threadIdx.x + k * NT;
+        const bool on = EXACT || i0 < ITEMS;
+        const int i = on ? i0 : 0;
+        const int b = i & (NB - 1);
+        const int w = (i >> LNB) & (BF - 1);
+        const int sb = (i >> (LNB + LBF)) * (N * NB) + b;
+        const int p = w >> LM, q = w & (M - 1);
+        const int ib = sb + (q + ((p * R) << LM)) * NB;
+        Cx<T> x[R];
+        #pragma unroll
+        for (int c = 0; c < R; ++c) x[c] = buf[ib + c * M * NB];
+        if constexpr (LS > 1) {
+            if (p != 0) {
+                const int pm = p << LM;
+                #pragma unroll
+                for (int c = 1; c < R; ++c) x[c] = cmul(x[c], twid(tw, 1, c * pm, INV));
+            }
+        }
+        Dft<T, R>::run(x, INV, tw, 1, N);
+        #pragma unroll
+        for (int d = 0; d < R; ++d) y[k][d] = x[d];
+        ob[k] = sb + (q + (p << LM)) * NB;
+        if (!on) ob[k] = -1;
+    }
+    __syncthreads();
+    #pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (EXACT || ob[k] >= 0) {
+            #pragma unroll
+            for (int d = 0; d < R; ++d) buf[ob[k] + d * (M * LS * NB)] = y[k][d];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int N, int NB, int DS, int S, bool INV>
+__device__ __forceinline__ void ct_passes(Cx<T> *buf, const Cx<T> *tw) {
+    if constexpr (S < ct_npass(N)) {
+        ct_pass<T, N, NB, DS, S, INV>(buf, tw);
+        ct_passes<T, N, NB, DS, S + 1, INV>(buf, tw);
+    }
+}
+
+// The whole transform (the buffer already staged and synchronised).
+template <typename T, int N, int NB, int DS, bool INV>
+__device__ __forceinline__ void ct_fft(Cx<T> *buf, const Cx<T> *tw) {
+    ct_passes<T, N, NB, DS, 0, INV>(buf, tw);
+}
+
+// Pencils of a compile-time pass per workgroup: N NB points, 16 per thread in
+// FP32 (32 KiB of LDS) and 8 in FP64, so that four (FP32) or two (FP64)
+// workgroups share a CU.
+template <typename T, int N>
+constexpr int ct_batches() { return (sizeof(T) == 4 ? 16 : 8) * kFftThreads / N; }
+
+// ---------------------------------------------------------------------------
 // last axis, real -> half spectrum (AXPY: fused r -= alpha q, r written back)
 //
 // Global memory is touched in two phases per kernel: every load of a thread
@@ -719,6 +831,52 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kGe
     }
 }
 
+// Middle axis with the compile-time transform of length N (= n1): the
+// workgroup takes NB consecutive (kh, component) pencils of one (load case,
+// axis-0 index), as k_middle does with its run-time pencil count.
+template <typename T, int N, bool INV>
+__global__ __launch_bounds__(kFftThreads) void k_middle_ct(FK<T> a) {
+    constexpr int NT = kFftThreads;
+    constexpr int NB = ct_batches<T, N>();
+    constexpr int PPT = N * NB / NT;
+    constexpr int LNB = ct_log2(NB);
+    __shared__ Cx<T> buf[N * NB];
+    __shared__ Cx<T> twl[N];
+    int t = xcd_remap(blockIdx.x, a.total);
+    const int ib = t % a.nblk;
+    t /= a.nblk;
+    const int i0 = t % a.n0;
+    const int lc = t / a.n0;
+    if (a.st && !a.st[lc].active) return;
+    const unsigned inner = (unsigned)a.inner_total;
+    const unsigned in0 = (unsigned)ib * NB;
+    Cx<T> *base = a.spec + ((long long)lc * a.n0 + i0) * (long long)N * inner + in0;
+    const int lim = min(NB, (int)(inner - in0));
+    for (int i = threadIdx.x; i < N; i += NT) twl[i] = a.tw[i];
+    Cx<T> v[PPT];
+    #pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int e = threadIdx.x + k * NT;
+        const int j = e >> LNB, b = e & (NB - 1);
+        v[k] = base[__umul24((unsigned)j, inner) + (unsigned)(b < lim ? b : lim - 1)];
+    }
+    #pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int e = threadIdx.x + k * NT;
+        buf[e] = ((e & (NB - 1)) < lim) ? v[k] : Cx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    ct_fft<T, N, NB, 1, INV>(buf, twl);
+    #pragma unroll
+    for (int k = 0; k < PPT; ++k) v[k] = buf[threadIdx.x + k * NT];
+    #pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int e = threadIdx.x + k * NT;
+        const int j = e >> LNB, b = e & (NB - 1);
+        if (b < lim) base[__umul24((unsigned)j, inner) + (unsigned)b] = v[k];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // first axis: forward, per-wavevector (B^*B)^-1 solve with Parseval r.z,
 // inverse (mode 0); forward only (mode 1); inverse only (mode 2)
@@ -861,6 +1019,27 @@ __device__ __forceinline__ void slot_inverse(const FK<T> &a, int e, int PB, long
     for (int c = 0; c < D; ++c) md[c] = T(Id[c]);
     #pragma unroll
     for (int c = 0; c < 3; ++c) mo[c] = Cx<T>{T(Io[c].x), T(Io[c].y)};
+}
+
+// z = M^-1 r at one wavevector (md: real diagonal, mo: upper triangle of
+// M^-1) and the Parseval term Re(r . conj z) in FP64.
+template <typename T, int DIM>
+__device__ __forceinline__ double apply_minv(const T (&md)[DIM], const Cx<T> (&mo)[3], const Cx<T> (&r)[DIM],
+                                             Cx<T> (&z)[DIM]) {
+    if constexpr (DIM == 3) {
+        const Cx<T> o01 = mo[0], o02 = mo[1], o12 = mo[2];
+        z[0] = cadd(cadd(cscale(r[0], md[0]), cmul(o01, r[1])), cmul(o02, r[2]));
+        z[1] = cadd(cadd(cmulc(r[0], o01), cscale(r[1], md[1])), cmul(o12, r[2]));
+        z[2] = cadd(cadd(cmulc(r[0], o02), cmulc(r[1], o12)), cscale(r[2], md[2]));
+    } else {
+        const Cx<T> o01 = mo[0];
+        z[0] = cadd(cscale(r[0], md[0]), cmul(o01, r[1]));
+        z[1] = cadd(cmulc(r[0], o01), cscale(r[1], md[1]));
+    }
+    double dot = 0.0;
+    #pragma unroll
+    for (int c = 0; c < DIM; ++c) dot += double(r[c].x) * double(z[c].x) + double(r[c].y) * double(z[c].y);
+    return dot;
 }
 
 // Components of one table entry: the D real diagonal entries of M^-1, then
@@ -1056,22 +1235,9 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu((PE
                     Cx<T> r[D], z[D];
                     #pragma unroll
                     for (int c = 0; c < D; ++c) r[c] = pt[c];
-                    if constexpr (DIM == 3) {
-                        const Cx<T> o01 = mo[0], o02 = mo[1], o12 = mo[2];
-                        z[0] = cadd(cadd(cscale(r[0], md[0]), cmul(o01, r[1])), cmul(o02, r[2]));
-                        z[1] = cadd(cadd(cmulc(r[0], o01), cscale(r[1], md[1])), cmul(o12, r[2]));
-                        z[2] = cadd(cadd(cmulc(r[0], o02), cmulc(r[1], o12)), cscale(r[2], md[2]));
-                    } else {
-                        const Cx<T> o01 = mo[0];
-                        z[0] = cadd(cscale(r[0], md[0]), cmul(o01, r[1]));
-                        z[1] = cadd(cmulc(r[0], o01), cscale(r[1], md[1]));
-                    }
-                    double dot = 0.0;
+                    const double dot = apply_minv<T, DIM>(md, mo, r, z);
                     #pragma unroll
-                    for (int c = 0; c < D; ++c) {
-                        dot += double(r[c].x) * double(z[c].x) + double(r[c].y) * double(z[c].y);
-                        pt[c] = z[c];
-                    }
+                    for (int c = 0; c < D; ++c) pt[c] = z[c];
                     acc += half ? dot : 2.0 * dot;
                 }
             }
@@ -1098,6 +1264,123 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu((PE
             if (threadIdx.x == 0) a.partial[(long long)lc * a.part_stride + blk] = s * a.invN;
         }
         __syncthreads();  // the next load case reuses buf
+    }
+}
+
+// Pencils per block of the compile-time first-axis pass (N = n0): N PB D
+// points per workgroup, 24 per thread in FP32 3D.
+template <typename T, int N>
+constexpr int ct_first_pencils() { return (sizeof(T) == 4 ? 2048 : 1024) / N; }
+
+// First axis with the compile-time transform, the CG's fused pass only
+// (forward, z = M^-1 r with the inverse table and the Parseval partial,
+// inverse): one workgroup per (pencil block, load case), load cases fastest,
+// as k_first with PERLC and TAB.  LDS holds component c of the block at
+// [c][m0][pencil] (D sub-problems of PB batches); the global spectrum keeps
+// the D components of a wavevector together, so the staging maps the row's
+// PB D contiguous values (pencil-major) onto the components.
+template <typename T, int N, int DIM>
+__global__ __launch_bounds__(kFftThreads) void k_first_ct(FK<T> a) {
+    constexpr int NT = kFftThreads, D = DIM;
+    constexpr int PB = ct_first_pencils<T, N>();
+    constexpr int LPB = ct_log2(PB);
+    constexpr int RS = NT / PB;           // rows per staging sweep
+    constexpr int NC = kMinvComps<DIM>;
+    constexpr int CNTK = PB * N;          // wavevector slots of the block
+    static_assert(NT % PB == 0 && N % RS == 0, "staging covers whole rows");
+    __shared__ Cx<T> buf[D * N * PB];
+    __shared__ Cx<T> twl[N];
+    __shared__ double red[NT / 64];
+    const int t = xcd_remap(blockIdx.x, a.total);
+    const int blk = t / a.L;
+    const int lc = t - blk * a.L;
+    if (a.st && !a.st[lc].active) return;
+    const unsigned inner = (unsigned)a.inner_total;
+    const unsigned in0 = (unsigned)blk * PB;
+    const int lim = min(PB, (int)(inner - in0));
+    const unsigned rowD = inner * D;      // complex values between consecutive m0
+    Cx<T> *base = a.spec + ((long long)lc * N * inner + in0) * D;
+    for (int i = threadIdx.x; i < N; i += NT) twl[i] = a.tw[i];
+    const int lane = threadIdx.x & (PB - 1), g = threadIdx.x >> LPB;
+    // staging slot (i, j): row m0 = g + RS i, value r = lane + PB j of the row,
+    // pencil r / D, component r % D
+    auto pencil_of = [](int r) { return D == 3 ? (r * 43) >> 7 : r >> 1; };  // r < 3 * 32
+    {
+        Cx<T> v[N / RS][D];
+        #pragma unroll
+        for (int i = 0; i < N / RS; ++i) {
+            #pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const int r = lane + PB * j;
+                const int rc = r < lim * D ? r : lim * D - 1;
+                v[i][j] = base[__umul24((unsigned)(g + RS * i), rowD) + (unsigned)rc];
+            }
+        }
+        #pragma unroll
+        for (int i = 0; i < N / RS; ++i) {
+            #pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const int r = lane + PB * j;
+                const int b = pencil_of(r), c = r - D * b;
+                buf[(c * N + g + RS * i) * PB + b] = b < lim ? v[i][j] : Cx<T>{T(0), T(0)};
+            }
+        }
+    }
+    __syncthreads();
+    ct_fft<T, N, PB, D, false>(buf, twl);
+    double acc = 0.0;
+    {
+        const T *tb0 = a.minv + (long long)blk * NC * CNTK;
+        #pragma unroll
+        for (int k = 0; k < CNTK / NT; ++k) {
+            const int e = threadIdx.x + k * NT;
+            const int m0 = e >> LPB, b = e & (PB - 1);
+            if (b < lim) {
+                T md[D];
+                Cx<T> mo[3];
+                #pragma unroll
+                for (int c = 0; c < D; ++c) md[c] = tb0[c * CNTK + e];
+                #pragma unroll
+                for (int c = 0; c < (DIM == 3 ? 3 : 1); ++c)
+                    mo[c] = Cx<T>{tb0[(D + 2 * c) * CNTK + e], tb0[(D + 2 * c + 1) * CNTK + e]};
+                const unsigned inn = in0 + b;
+                const int kh = DIM == 3 ? (int)(inn - a.d_nh.div(inn) * (unsigned)a.nh) : (int)inn;
+                const bool half = kh == 0 || (a.last_even && kh == a.nh - 1);
+                Cx<T> r[D], z[D];
+                #pragma unroll
+                for (int c = 0; c < D; ++c) r[c] = buf[(c * N + m0) * PB + b];
+                const double dot = apply_minv<T, DIM>(md, mo, r, z);
+                #pragma unroll
+                for (int c = 0; c < D; ++c) buf[(c * N + m0) * PB + b] = z[c];
+                acc += half ? dot : 2.0 * dot;
+            }
+        }
+    }
+    __syncthreads();
+    ct_fft<T, N, PB, D, true>(buf, twl);
+    {
+        Cx<T> v[N / RS][D];
+        #pragma unroll
+        for (int i = 0; i < N / RS; ++i) {
+            #pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const int r = lane + PB * j;
+                const int b = pencil_of(r), c = r - D * b;
+                v[i][j] = buf[(c * N + g + RS * i) * PB + b];
+            }
+        }
+        #pragma unroll
+        for (int i = 0; i < N / RS; ++i) {
+            #pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const int r = lane + PB * j;
+                if (r < lim * D) base[__umul24((unsigned)(g + RS * i), rowD) + (unsigned)r] = v[i][j];
+            }
+        }
+    }
+    if (a.partial) {
+        const double s = block_sum<NT>(acc, red);
+        if (threadIdx.x == 0) a.partial[(long long)lc * a.part_stride + blk] = s * a.invN;
     }
 }
 
@@ -1239,6 +1522,25 @@ int middle_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     a.inner_total = inner;
     a.nblk = (int)((inner + PB - 1) / PB);
     a.total = a.nblk * a.n0 * p.L;
+    // compile-time transform: the default schedule of n1 = 64, 128 or 256 and
+    // the default pencil count
+    if (p.tune_ct && p.tune_pb_mid == 0 && ct_schedule_matches(a.ax, a.n1) &&
+        (a.n1 == 64 || a.n1 == 128 || a.n1 == 256)) {
+        auto go = [&](auto kern, int nb) {
+            a.nblk = (int)((inner + nb - 1) / nb);
+            a.total = a.nblk * a.n0 * p.L;
+            hipLaunchKernelGGL(kern, dim3(a.total), dim3(kFftThreads), 0, p.stream, a);
+        };
+        switch (a.n1 * 2 + (inverse ? 1 : 0)) {
+        case 128: go(k_middle_ct<T, 64, false>, ct_batches<T, 64>()); break;
+        case 129: go(k_middle_ct<T, 64, true>, ct_batches<T, 64>()); break;
+        case 256: go(k_middle_ct<T, 128, false>, ct_batches<T, 128>()); break;
+        case 257: go(k_middle_ct<T, 128, true>, ct_batches<T, 128>()); break;
+        case 512: go(k_middle_ct<T, 256, false>, ct_batches<T, 256>()); break;
+        default: go(k_middle_ct<T, 256, true>, ct_batches<T, 256>()); break;
+        }
+        return hip_check(hipGetLastError(), "middle-axis fft launch");
+    }
     size_t dyn;
     if (lds_of_pass<T>(!pow2_len(a.ax.n), PB * a.n1, a.n1, &a.lbuf, &dyn) > kLdsPerWorkgroup)
         return set_error(FEH_ENOTSUP, "middle axis too long for the LDS transform");
@@ -1293,12 +1595,14 @@ int first_t(const feh_plan &p, const FftArgs &fa, int mode) {
     a.ax = p.fft[0];
     a.tw = p.ptr<const Cx<T>>(p.off_tw[0]);
     a.tws = 1;
+    const int ctpb = mode == 0 && fa.unit_volume ? first_ct_pencils(p) : 0;
     int PB = (PPT * kFftThreads) / (a.n0 * DIM);
     if (PB < 1) return set_error(FEH_ENOTSUP, "first axis too long for the LDS transform");
     if (PB > 32) PB = 32;
     // tuned value, never below a quarter of the default: the partial-sum
     // buffer holds one slot per pencil block for that size
     if (p.tune_pb_first > 0 && p.tune_pb_first < PB) PB = std::max(p.tune_pb_first, std::max(1, PB / 4));
+    if (ctpb > 0) PB = ctpb;
     if (PB > a.inner_total) PB = (int)a.inner_total;
     a.PB = PB;
     a.d_PB = FastDiv::make((uint32_t)PB);
@@ -1324,6 +1628,14 @@ int first_t(const feh_plan &p, const FftArgs &fa, int mode) {
             p.minv_ws = p.ws;
             p.minv_pb = PB;
         }
+    }
+    if (ctpb > 0) {
+        switch (a.n0) {
+        case 64: hipLaunchKernelGGL((k_first_ct<T, 64, DIM>), g, b, 0, p.stream, a); break;
+        case 128: hipLaunchKernelGGL((k_first_ct<T, 128, DIM>), g, b, 0, p.stream, a); break;
+        default: hipLaunchKernelGGL((k_first_ct<T, 256, DIM>), g, b, 0, p.stream, a); break;
+        }
+        return hip_check(hipGetLastError(), "first-axis fft launch");
     }
 #define FEH_FIRST(M, G)                                                                                   \
     do {                                                                                                  \
@@ -1366,6 +1678,21 @@ bool first_per_load_case(const feh_plan &p) {
     return pow2_len((int)p.n[0]);
 }
 
+// Pencils per block of the compile-time first-axis pass of the CG, or 0 when
+// the plan's shape or schedule has none: a power-of-two axis 0 of 64, 128 or
+// 256 points in the default radix order, the default layout (one workgroup
+// per load case) and block size, and offsets that fit the 24-bit products
+// of the staging.
+int first_ct_pencils(const feh_plan &p) {
+    const int n0 = (int)p.n[0];
+    if (!p.tune_ct || p.tune_pb_first != 0 || !first_per_load_case(p)) return 0;
+    if (!(n0 == 64 || n0 == 128 || n0 == 256) || !ct_schedule_matches(p.fft[0], n0)) return 0;
+    const long long inner = p.dim == 3 ? p.n[1] * p.nh : p.nh;
+    const long long rowD = inner * p.dim;
+    if (rowD >= (1 << 24) || rowD * n0 >= (1ll << 31)) return 0;
+    return (p.prec == FEH_FP32 ? 2048 : 1024) / n0;
+}
+
 int first_pencils_default(const feh_plan &p) {
     const int PPT = p.prec == FEH_FP32 ? 24 : 16;
     int PB = (PPT * kFftThreads) / (int)(p.n[0] * p.dim);
@@ -1379,6 +1706,7 @@ int first_num_parts(const feh_plan &p) {
     // tuned value, never below a quarter of the default: the partial-sum
     // buffer holds one slot per pencil block for that size
     if (p.tune_pb_first > 0 && p.tune_pb_first < PB) PB = std::max(p.tune_pb_first, std::max(1, PB / 4));
+    if (const int ct = first_ct_pencils(p)) PB = ct;  // the CG's fused pass
     const long long inner = p.dim == 3 ? p.n[1] * p.nh : p.nh;
     if (PB > inner) PB = (int)inner;
     return (int)((inner + PB - 1) / PB);

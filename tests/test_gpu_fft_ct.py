@@ -1,0 +1,66 @@
+"""The compile-time transforms (power-of-two axes of 64, 128 or 256 points in
+the default radix order: the middle-axis pass and the CG's fused first-axis
+pass) against the run-time passes they replace, on the same plan: the CG
+solution, its iteration counts and C_eff, and the FFT export against the DFT
+definition.  Both use the same butterflies and twiddles in the same order,
+so they agree to rounding (the compiler may contract multiply-adds
+differently in the two instruction streams)."""
+import numpy as np
+import pytest
+
+import microstructures as ms
+from gpu_util import random_material, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve(shape, lam, mu, prec, ct):
+    import paper_2105_03297_amd as feh
+    dim = len(shape)
+    h = feh.Homogenizer(shape, n_load=3 if dim == 2 else 6, precision=prec)
+    t = feh.feh_plan_tuning(h.plan)
+    t["compile_time_transforms"] = ct
+    feh.feh_plan_set_tuning(h.plan, t)
+    assert feh.feh_plan_tuning(h.plan)["compile_time_transforms"] == ct
+    h.set_material(lam=lam, mu=mu)
+    out = h.solve(ms.unit_loads(dim), tol=1e-10 if prec == "fp64" else 1e-5, max_iter=3000, return_u=True)
+    out["u"] = out["u"].double().cpu().numpy()
+    h.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("shape", [(64, 64, 64), (128, 64, 20), (256, 128, 12), (40, 256, 18), (64, 12, 64),
+                                   (256, 90), (64, 128)])
+def test_compile_time_transforms_match_runtime_passes(shape, prec):
+    say("compile-time vs run-time transforms", shape, prec)
+    lam, mu = random_material(shape, 17, prec)
+    a = _solve(shape, lam, mu, prec, 1)
+    b = _solve(shape, lam, mu, prec, 0)
+    ia = [r["iterations"] for r in a["report"]]
+    ib = [r["iterations"] for r in b["report"]]
+    eu = max(rel(a["u"][l], b["u"][l]) for l in range(len(ia)))
+    ec = rel(a["C_eff"], b["C_eff"])
+    print(shape, prec, "iterations", ia, ib, "u rel diff %.3e, C_eff rel diff %.3e, bitwise %s"
+          % (eu, ec, bool(np.array_equal(a["u"], b["u"]))))
+    assert all(abs(x - y) <= 1 for x, y in zip(ia, ib))
+    bar = 1e-12 if prec == "fp64" else 1e-5
+    assert ec < bar and eu < (1e-10 if prec == "fp64" else 1e-3)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(8, 64, 16), (4, 128, 8), (3, 256, 10), (5, 64, 9)])
+def test_fft_with_compile_time_middle_pass_matches_dft(shape, prec):
+    import paper_2105_03297_amd as feh
+    say("fft compile-time middle", shape, prec)
+    L = 2
+    h = feh.Homogenizer(shape, n_load=L, precision=prec)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((L * 3,) + shape)
+    X = h.fft_forward(x.reshape(L * 3, -1)).cpu().numpy()
+    ref = np.fft.rfftn(x, axes=(1, 2, 3))
+    tol = 1e-13 if prec == "fp64" else 3e-6
+    assert np.abs(X - ref).max() / np.abs(ref).max() < tol
+    back = h.fft_inverse(ref.astype(np.complex128 if prec == "fp64" else np.complex64))
+    np.testing.assert_allclose(back.cpu().numpy().reshape(x.shape), x, atol=tol * np.abs(x).max() * 10)
+    h.close()
