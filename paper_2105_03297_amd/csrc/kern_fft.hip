@@ -440,7 +440,35 @@ __host__ inline bool ct_schedule_matches(const AxisFFT &ax, int n) {
     return true;
 }
 
-template <typename T, int N, int NB, int DS, int S, bool INV>
+// floor(x / DV) for 0 <= x < RANGE: a shift for powers of two, otherwise
+// one full-rate 24-bit multiply by a magic constant and a shift, the
+// constant searched and checked over the whole range at compile time.
+template <int DV, int RANGE>
+struct CtDiv {
+    static constexpr bool pow2 = (DV & (DV - 1)) == 0;
+    static constexpr bool exact(int sh, unsigned long long m) {
+        for (int x = 0; x < RANGE; ++x)
+            if ((unsigned long long)x * m >> sh != (unsigned long long)(x / DV)) return false;
+        return true;
+    }
+    static constexpr int find() {
+        if (pow2) return ct_log2(DV);
+        for (int sh = 0; sh < 32; ++sh) {
+            const unsigned long long m = (1ull << sh) / DV + 1;
+            if (m < (1ull << 24) && (unsigned long long)(RANGE - 1) * m < (1ull << 32) && exact(sh, m)) return sh;
+        }
+        return -1;
+    }
+    static constexpr int SH = find();
+    static constexpr unsigned MG = pow2 ? 1u : (unsigned)((1ull << (SH < 0 ? 0 : SH)) / DV + 1);
+    static_assert(SH >= 0, "no 24-bit magic divisor for this range");
+    static __device__ __forceinline__ int div(int x) {
+        if constexpr (pow2) return x >> SH;
+        else return (int)(__umul24((unsigned)x, MG) >> SH);
+    }
+};
+
+template <typename T, int N, int NB, int DS, int S, bool INV, int TWS = 1>
 __device__ __forceinline__ void ct_pass(Cx<T> *buf, const Cx<T> *tw) {
     constexpr int NT = kFftThreads;
     constexpr int R = ct_radix_at(N, S), LS = ct_lstar(N, S);
@@ -448,7 +476,7 @@ __device__ __forceinline__ void ct_pass(Cx<T> *buf, const Cx<T> *tw) {
     constexpr int ITEMS = DS * BF * NB;
     constexpr int K = (ITEMS + NT - 1) / NT;
     constexpr bool EXACT = ITEMS % NT == 0;  // else the last round has idle threads
-    constexpr int LNB = ct_log2(NB), LBF = ct_log2(BF), LM = ct_log2(M);
+    constexpr int LBF = ct_log2(BF), LM = ct_log2(M);
     Cx<T> y[K][R];
     int ob[K];
     #pragma unroll
@@ -456,20 +484,21 @@ __device__ __forceinline__ void ct_pass(Cx<T> *buf, const Cx<T> *tw) {
         const int i0 = threadIdx.x + k * NT;
         const bool on = EXACT || i0 < ITEMS;
         const int i = on ? i0 : 0;
-        const int b = i & (NB - 1);
-        const int w = (i >> LNB) & (BF - 1);
-        const int sb = (i >> (LNB + LBF)) * (N * NB) + b;
+        const int wq = CtDiv<NB, ITEMS>::div(i);  // butterfly index over all sub-problems
+        const int b = i - wq * NB;
+        const int w = wq & (BF - 1);
+        const int sb = (wq >> LBF) * (N * NB) + b;
         const int p = w >> LM, q = w & (M - 1);
         const int ib = sb + (q + ((p * R) << LM)) * NB;
         Cx<T> x[R];
         #pragma unroll
         for (int c = 0; c < R; ++c) x[c] = buf[ib + c * M * NB];
         if constexpr (LS > 1) {
-            if (p != 0) {
-                const int pm = p << LM;
-                #pragma unroll
-                for (int c = 1; c < R; ++c) x[c] = cmul(x[c], twid(tw, 1, c * pm, INV));
-            }
+            // butterflies with p = 0 multiply by the twiddle 1 (exact), so
+            // the lanes of a wave take no divergent branch
+            const int pm = p << LM;
+            #pragma unroll
+            for (int c = 1; c < R; ++c) x[c] = cmul(x[c], twid(tw, TWS, c * pm, INV));
         }
         Dft<T, R>::run(x, INV, tw, 1, N);
         #pragma unroll
@@ -488,18 +517,20 @@ __device__ __forceinline__ void ct_pass(Cx<T> *buf, const Cx<T> *tw) {
     __syncthreads();
 }
 
-template <typename T, int N, int NB, int DS, int S, bool INV>
+template <typename T, int N, int NB, int DS, int S, bool INV, int TWS>
 __device__ __forceinline__ void ct_passes(Cx<T> *buf, const Cx<T> *tw) {
     if constexpr (S < ct_npass(N)) {
-        ct_pass<T, N, NB, DS, S, INV>(buf, tw);
-        ct_passes<T, N, NB, DS, S + 1, INV>(buf, tw);
+        ct_pass<T, N, NB, DS, S, INV, TWS>(buf, tw);
+        ct_passes<T, N, NB, DS, S + 1, INV, TWS>(buf, tw);
     }
 }
 
-// The whole transform (the buffer already staged and synchronised).
-template <typename T, int N, int NB, int DS, bool INV>
+// The whole transform (the buffer already staged and synchronised); the
+// twiddle table holds e^{-2 pi i j / (N TWS)} at j (TWS = 2: the table of the
+// unpacked length of a packed real transform).
+template <typename T, int N, int NB, int DS, bool INV, int TWS = 1>
 __device__ __forceinline__ void ct_fft(Cx<T> *buf, const Cx<T> *tw) {
-    ct_passes<T, N, NB, DS, 0, INV>(buf, tw);
+    ct_passes<T, N, NB, DS, 0, INV, TWS>(buf, tw);
 }
 
 // Pencils of a compile-time pass per workgroup: N NB points, 16 per thread in
@@ -774,6 +805,253 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kGe
             }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Last-axis passes with the compile-time transform: even length NL (packed
+// into NC = NL / 2 complex points) in the default radix order, RR rows of D
+// components per workgroup (24 points per thread in FP32), the LDS tile and
+// the global layouts of k_last_fwd / k_last_inv (batch b = row D + component,
+// element j at buf[j NB + b]).  Same arithmetic in the same order.
+// ---------------------------------------------------------------------------
+template <int NL, int D>
+constexpr int ct_last_rows() { return 24 * kFftThreads / (NL / 2 * D); }
+
+// Element at a 32-bit byte offset from a base pointer: with the base uniform
+// the load or store takes the scalar-base form (no 64-bit address arithmetic
+// per access); the launchers check that the offsets fit.
+template <typename P>
+__device__ __forceinline__ P *at_byte(P *base, unsigned off) {
+    return reinterpret_cast<P *>(reinterpret_cast<char *>(base) + off);
+}
+template <typename P>
+__device__ __forceinline__ const P *at_byte(const P *base, unsigned off) {
+    return reinterpret_cast<const P *>(reinterpret_cast<const char *>(base) + off);
+}
+
+// Byte offset of packed pair j of row sl (of the block) and component c in
+// the load case's real SoA field [D][N].
+template <typename T, int NL, int D>
+__device__ __forceinline__ unsigned last_pair_offset(int c, int sl, int j, unsigned N32, unsigned row0) {
+    // c N: N is a multiple of NL >= 128, so one 24-bit multiply of N / 128
+    static_assert(NL % 128 == 0, "component stride from N / 128");
+    const unsigned cb = __umul24((unsigned)c, N32 >> 7) << 7;
+    return (cb + row0 + (unsigned)(sl * NL + 2 * j)) * (unsigned)sizeof(T);
+}
+
+template <typename T, int NL, int D, bool AXPY, bool FULL>
+__device__ __forceinline__ void last_fwd_ct_body(const FK<T> &a, int lc, long long s0, int nrows, T alpha,
+                                                 Cx<T> *buf, const Cx<T> *twl) {
+    constexpr int NT = kFftThreads, NC = NL / 2, NH = NC + 1;
+    constexpr int RR = ct_last_rows<NL, D>(), NB = D * RR;
+    constexpr int CNT = NB * NC, PPT = CNT / NT;
+    constexpr int OCNT = RR * NH * D;                  // half-spectrum values of the block
+    constexpr int KO = (OCNT + NT - 1) / NT;
+    constexpr int LNC = ct_log2(NC);
+    const long long lbase = (long long)lc * D * a.N;
+    const T *rl = a.r + lbase;
+    const T *ql = AXPY ? a.q + lbase : nullptr;
+    T *rol = AXPY ? a.r_out + lbase : nullptr;
+    const unsigned N32 = (unsigned)a.N, row0 = (unsigned)(s0 * NL);
+    // slot e -> batch b = e / NC (row sl = b / D, component c), packed pair j
+    constexpr int CH = AXPY ? 8 : PPT;
+    #pragma unroll
+    for (int h = 0; h < PPT; h += CH) {
+        Cx<T> v[CH];
+        Cx<T> w[AXPY ? CH : 1];
+        #pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int e = threadIdx.x + (h + k) * NT;
+            const int b = e >> LNC, j = e & (NC - 1);
+            const int sl0 = CtDiv<D, NB>::div(b), c = b - sl0 * D;
+            const int sl = (FULL || sl0 < nrows) ? sl0 : nrows - 1;
+            const unsigned off = last_pair_offset<T, NL, D>(c, sl, j, N32, row0);
+            v[k] = *at_byte(reinterpret_cast<const Cx<T> *>(rl), off);
+            if (AXPY) w[k] = *at_byte(reinterpret_cast<const Cx<T> *>(ql), off);
+        }
+        #pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int e = threadIdx.x + (h + k) * NT;
+            const int b = e >> LNC, j = e & (NC - 1);
+            const int sl = CtDiv<D, NB>::div(b), c = b - sl * D;
+            const bool ok = FULL || sl < nrows;
+            if (AXPY) {
+                v[k].x -= alpha * w[k].x;
+                v[k].y -= alpha * w[k].y;
+                if (ok) *at_byte(reinterpret_cast<Cx<T> *>(rol), last_pair_offset<T, NL, D>(c, sl, j, N32, row0)) = v[k];
+            }
+            buf[j * NB + b] = ok ? v[k] : Cx<T>{T(0), T(0)};
+        }
+    }
+    __syncthreads();
+    ct_fft<T, NC, NB, 1, false, 2>(buf, twl);
+    // untangle the packed transform; half spectrum out, components fastest
+    Cx<T> X[KO];
+    #pragma unroll
+    for (int k = 0; k < KO; ++k) {
+        const int e0 = threadIdx.x + k * NT;
+        const int e = (OCNT % NT == 0 || e0 < OCNT) ? e0 : 0;
+        const int kk = CtDiv<D, OCNT>::div(e);
+        const int c = e - kk * D;
+        const int sl = CtDiv<NH, OCNT / D>::div(kk);
+        const int kx = kk - sl * NH;
+        const int b = sl * D + c;
+        const int ka = (kx == NC) ? 0 : kx;
+        const int kb = (kx == 0) ? 0 : NC - kx;
+        const Cx<T> Zk = buf[ka * NB + b], Zm = cconj(buf[kb * NB + b]);
+        const Cx<T> A = {T(0.5) * (Zk.x + Zm.x), T(0.5) * (Zk.y + Zm.y)};
+        const Cx<T> dZ = csub(Zk, Zm);
+        const Cx<T> B = {T(0.5) * dZ.y, -T(0.5) * dZ.x};  // -i/2 (Zk - conj Z(nc-k))
+        X[k] = cadd(A, cmul(twl[kx], B));
+    }
+    Cx<T> *dst = a.spec + ((long long)lc * a.rows + s0) * (long long)NH * D;
+    const int ocnt = FULL ? OCNT : nrows * NH * D;
+    #pragma unroll
+    for (int k = 0; k < KO; ++k) {
+        const int e0 = threadIdx.x + k * NT;
+        if ((FULL && (OCNT % NT == 0 || k + 1 < KO)) || e0 < ocnt) *at_byte(dst, (unsigned)e0 * (unsigned)sizeof(Cx<T>)) = X[k];
+    }
+}
+
+template <typename T, int NL, int D, bool AXPY>
+__global__ __launch_bounds__(kFftThreads) void k_last_fwd_ct(FK<T> a) {
+    constexpr int NT = kFftThreads, NC = NL / 2;
+    constexpr int RR = ct_last_rows<NL, D>(), NB = D * RR;
+    static_assert((NB * NC) % NT == 0, "whole slots per thread");
+    __shared__ Cx<T> buf[NB * NC];
+    __shared__ Cx<T> twl[NL];
+    const int t = xcd_remap(blockIdx.x, a.total);
+    const int lc = t / a.nblk;
+    const int blk = t - lc * a.nblk;
+    T alpha = T(0);
+    if (a.st) {
+        if (!a.st[lc].active) return;
+        if (AXPY) alpha = T(a.st[lc].alpha);
+    }
+    const long long s0 = (long long)blk * RR;
+    const int nrows = (int)min((long long)RR, a.rows - s0);
+    for (int i = threadIdx.x; i < NL; i += NT) twl[i] = a.tw_last[i];
+    if (nrows == RR) last_fwd_ct_body<T, NL, D, AXPY, true>(a, lc, s0, nrows, alpha, buf, twl);
+    else last_fwd_ct_body<T, NL, D, AXPY, false>(a, lc, s0, nrows, alpha, buf, twl);
+}
+
+template <typename T, int NL, int D, bool UPD, bool FULL>
+__device__ __forceinline__ void last_inv_ct_body(const FK<T> &a, int lc, long long s0, int nrows, Cx<T> *buf,
+                                                 const Cx<T> *twl) {
+    constexpr int NT = kFftThreads, NC = NL / 2, NH = NC + 1;
+    constexpr int RR = ct_last_rows<NL, D>(), NB = D * RR;
+    constexpr int CNT = NB * NC, PPT = CNT / NT;
+    constexpr int LNC = ct_log2(NC);
+    // gather e -> (row sl, k, component c), components fastest; the packed
+    // input Z(k) needs X(k) and X(nc - k)
+    const Cx<T> *src = a.spec + ((long long)lc * a.rows + s0) * (long long)NH * D;
+    constexpr int CH = PPT / 2;
+    #pragma unroll
+    for (int h = 0; h < PPT; h += CH) {
+        Cx<T> Xa[CH], Xb[CH];
+        #pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int e = threadIdx.x + (h + k) * NT;
+            const int kk = CtDiv<D, CNT>::div(e);
+            const int c = e - kk * D;
+            const int sl0 = kk >> LNC, kx = kk & (NC - 1);
+            const int sl = (FULL || sl0 < nrows) ? sl0 : nrows - 1;
+            const unsigned row = (unsigned)(sl * (NH * D) + c);
+            Xa[k] = *at_byte(src, (row + (unsigned)(kx * D)) * (unsigned)sizeof(Cx<T>));
+            Xb[k] = *at_byte(src, (row + (unsigned)((NC - kx) * D)) * (unsigned)sizeof(Cx<T>));
+        }
+        #pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int e = threadIdx.x + (h + k) * NT;
+            const int kk = CtDiv<D, CNT>::div(e);
+            const int c = e - kk * D;
+            const int sl = kk >> LNC, kx = kk & (NC - 1);
+            // the DC and Nyquist samples of a real signal's spectrum are real:
+            // their imaginary parts (rounding residue) are dropped
+            const Cx<T> xa = {Xa[k].x, kx == 0 ? T(0) : Xa[k].y};
+            const Cx<T> Xm = {Xb[k].x, kx == 0 ? T(0) : -Xb[k].y};
+            const Cx<T> A = cadd(xa, Xm);
+            const Cx<T> B = cmulc(csub(xa, Xm), twl[kx]);  // exp(+2 pi i k / n) (Xk - conj X(nc-k))
+            Cx<T> Z = cadd(A, mul_pi(B));
+            if (!FULL && sl >= nrows) Z = Cx<T>{T(0), T(0)};
+            buf[kx * NB + sl * D + c] = Z;
+        }
+    }
+    __syncthreads();
+    ct_fft<T, NC, NB, 1, true, 2>(buf, twl);
+    const T sc = T(a.out_scale);
+    Cx<T> y[PPT];
+    #pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int e = threadIdx.x + k * NT;
+        const int b = e >> LNC, j = e & (NC - 1);
+        y[k] = buf[j * NB + b];
+    }
+    const long long lbase = (long long)lc * D * a.N;
+    const unsigned N32 = (unsigned)a.N, row0 = (unsigned)(s0 * NL);
+    if constexpr (UPD) {
+        Cx<T> *pl = reinterpret_cast<Cx<T> *>(a.p_upd + lbase);
+        Cx<T> *ul = reinterpret_cast<Cx<T> *>(a.u_upd + lbase);
+        const T beta = T(a.st[lc].beta), ap = T(a.st[lc].alpha_pend);
+        constexpr int CH2 = 8;  // slots per round: two loads each in flight
+        #pragma unroll
+        for (int h = 0; h < PPT; h += CH2) {
+            Cx<T> pv[CH2], uv[CH2];
+            #pragma unroll
+            for (int k = 0; k < CH2; ++k) {
+                const int e = threadIdx.x + (h + k) * NT;
+                const int b = e >> LNC, j = e & (NC - 1);
+                const int sl0 = CtDiv<D, NB>::div(b), c = b - sl0 * D;
+                const int sl = (FULL || sl0 < nrows) ? sl0 : nrows - 1;
+                const unsigned o = last_pair_offset<T, NL, D>(c, sl, j, N32, row0);
+                pv[k] = ldc_nt(at_byte(pl, o));
+                uv[k] = ldc_nt(at_byte(ul, o));
+            }
+            #pragma unroll
+            for (int k = 0; k < CH2; ++k) {
+                const int e = threadIdx.x + (h + k) * NT;
+                const int b = e >> LNC, j = e & (NC - 1);
+                const int sl = CtDiv<D, NB>::div(b), c = b - sl * D;
+                if (FULL || sl < nrows) {
+                    const unsigned o = last_pair_offset<T, NL, D>(c, sl, j, N32, row0);
+                    const Cx<T> z = {y[h + k].x * sc, y[h + k].y * sc};
+                    const Cx<T> un = {uv[k].x + ap * pv[k].x, uv[k].y + ap * pv[k].y};
+                    const Cx<T> pn = {z.x + beta * pv[k].x, z.y + beta * pv[k].y};
+                    stc_nt(at_byte(ul, o), un);
+                    stc_nt(at_byte(pl, o), pn);
+                }
+            }
+        }
+    } else {
+        Cx<T> *zl = reinterpret_cast<Cx<T> *>(a.z + lbase);
+        #pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int e = threadIdx.x + k * NT;
+            const int b = e >> LNC, j = e & (NC - 1);
+            const int sl = CtDiv<D, NB>::div(b), c = b - sl * D;
+            if (FULL || sl < nrows)
+                stc_nt(at_byte(zl, last_pair_offset<T, NL, D>(c, sl, j, N32, row0)), Cx<T>{y[k].x * sc, y[k].y * sc});
+        }
+    }
+}
+
+template <typename T, int NL, int D, bool UPD>
+__global__ __launch_bounds__(kFftThreads) void k_last_inv_ct(FK<T> a) {
+    constexpr int NT = kFftThreads, NC = NL / 2;
+    constexpr int RR = ct_last_rows<NL, D>(), NB = D * RR;
+    static_assert((NB * NC) % NT == 0, "whole slots per thread");
+    __shared__ Cx<T> buf[NB * NC];
+    __shared__ Cx<T> twl[NL];
+    const int t = xcd_remap(blockIdx.x, a.total);
+    const int lc = t / a.nblk;
+    const int blk = t - lc * a.nblk;
+    if (a.st && !a.st[lc].active) return;
+    const long long s0 = (long long)blk * RR;
+    const int nrows = (int)min((long long)RR, a.rows - s0);
+    for (int i = threadIdx.x; i < NL; i += NT) twl[i] = a.tw_last[i];
+    __syncthreads();
+    if (nrows == RR) last_inv_ct_body<T, NL, D, UPD, true>(a, lc, s0, nrows, buf, twl);
+    else last_inv_ct_body<T, NL, D, UPD, false>(a, lc, s0, nrows, buf, twl);
 }
 
 // ---------------------------------------------------------------------------
@@ -1330,29 +1608,39 @@ __global__ __launch_bounds__(kFftThreads) void k_first_ct(FK<T> a) {
     ct_fft<T, N, PB, D, false>(buf, twl);
     double acc = 0.0;
     {
+        // Q consecutive wavevector slots per thread and round, so that each
+        // table component arrives in one 16-byte load per round
+        constexpr int Q = 16 / (int)sizeof(T) < PB ? 16 / (int)sizeof(T) : PB;
+        typedef T TV __attribute__((ext_vector_type(Q)));
         const T *tb0 = a.minv + (long long)blk * NC * CNTK;
         #pragma unroll
-        for (int k = 0; k < CNTK / NT; ++k) {
-            const int e = threadIdx.x + k * NT;
-            const int m0 = e >> LPB, b = e & (PB - 1);
-            if (b < lim) {
-                T md[D];
-                Cx<T> mo[3];
-                #pragma unroll
-                for (int c = 0; c < D; ++c) md[c] = tb0[c * CNTK + e];
-                #pragma unroll
-                for (int c = 0; c < (DIM == 3 ? 3 : 1); ++c)
-                    mo[c] = Cx<T>{tb0[(D + 2 * c) * CNTK + e], tb0[(D + 2 * c + 1) * CNTK + e]};
-                const unsigned inn = in0 + b;
-                const int kh = DIM == 3 ? (int)(inn - a.d_nh.div(inn) * (unsigned)a.nh) : (int)inn;
-                const bool half = kh == 0 || (a.last_even && kh == a.nh - 1);
-                Cx<T> r[D], z[D];
-                #pragma unroll
-                for (int c = 0; c < D; ++c) r[c] = buf[(c * N + m0) * PB + b];
-                const double dot = apply_minv<T, DIM>(md, mo, r, z);
-                #pragma unroll
-                for (int c = 0; c < D; ++c) buf[(c * N + m0) * PB + b] = z[c];
-                acc += half ? dot : 2.0 * dot;
+        for (int k = 0; k < CNTK / (NT * Q); ++k) {
+            const int e0 = (threadIdx.x + k * NT) * Q;
+            TV tv[NC];
+            #pragma unroll
+            for (int c = 0; c < NC; ++c) tv[c] = *reinterpret_cast<const TV *>(tb0 + c * CNTK + e0);
+            #pragma unroll
+            for (int qq = 0; qq < Q; ++qq) {
+                const int e = e0 + qq;
+                const int m0 = e >> LPB, b = e & (PB - 1);
+                if (b < lim) {
+                    T md[D];
+                    Cx<T> mo[3];
+                    #pragma unroll
+                    for (int c = 0; c < D; ++c) md[c] = tv[c][qq];
+                    #pragma unroll
+                    for (int c = 0; c < (DIM == 3 ? 3 : 1); ++c) mo[c] = Cx<T>{tv[D + 2 * c][qq], tv[D + 2 * c + 1][qq]};
+                    const unsigned inn = in0 + b;
+                    const int kh = DIM == 3 ? (int)(inn - a.d_nh.div(inn) * (unsigned)a.nh) : (int)inn;
+                    const bool half = kh == 0 || (a.last_even && kh == a.nh - 1);
+                    Cx<T> r[D], z[D];
+                    #pragma unroll
+                    for (int c = 0; c < D; ++c) r[c] = buf[(c * N + m0) * PB + b];
+                    const double dot = apply_minv<T, DIM>(md, mo, r, z);
+                    #pragma unroll
+                    for (int c = 0; c < D; ++c) buf[(c * N + m0) * PB + b] = z[c];
+                    acc += half ? dot : 2.0 * dot;
+                }
             }
         }
     }
@@ -1475,6 +1763,40 @@ int last_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     a.nblk = (int)((a.rows + RR - 1) / RR);
     a.total = a.nblk * p.L;
     a.use_axpy = (!inverse && fa.q != nullptr && fa.state != nullptr) ? 1 : 0;
+    // compile-time transform: FP32, 3D (or 2D) with an even last axis of 128
+    // or 256 points in the default radix order and the default row count
+    if (sizeof(T) == 4 && p.tune_ct && p.tune_rr_last == 0 && p.last_even && (a.D == 3 || a.D == 2) &&
+        (a.nlast == 128 || a.nlast == 256) && ct_schedule_matches(a.ax, a.nlast / 2) &&
+        (double)a.D * (double)a.N * sizeof(T) < 4294967296.0) {
+        const int rr = (a.D == 3 ? (a.nlast == 256 ? ct_last_rows<256, 3>() : ct_last_rows<128, 3>())
+                                 : (a.nlast == 256 ? ct_last_rows<256, 2>() : ct_last_rows<128, 2>()));
+        a.RR = rr;
+        a.nblk = (int)((a.rows + rr - 1) / rr);
+        a.total = a.nblk * p.L;
+        const dim3 g(a.total), b(kFftThreads);
+        const bool upd = inverse && fa.p_upd != nullptr;
+        if (upd && (fa.u_upd == nullptr || fa.state == nullptr))
+            return set_error(FEH_EINVAL, "fused CG update needs p, u and the CG state");
+#define FEH_LAST_CT(NLv, Dv)                                                                                    \
+        do {                                                                                                      \
+            if (inverse) {                                                                                        \
+                if (upd) hipLaunchKernelGGL((k_last_inv_ct<T, NLv, Dv, true>), g, b, 0, p.stream, a);             \
+                else hipLaunchKernelGGL((k_last_inv_ct<T, NLv, Dv, false>), g, b, 0, p.stream, a);                \
+            } else {                                                                                              \
+                if (a.use_axpy) hipLaunchKernelGGL((k_last_fwd_ct<T, NLv, Dv, true>), g, b, 0, p.stream, a);      \
+                else hipLaunchKernelGGL((k_last_fwd_ct<T, NLv, Dv, false>), g, b, 0, p.stream, a);                \
+            }                                                                                                     \
+        } while (0)
+        if (a.D == 3) {
+            if (a.nlast == 256) FEH_LAST_CT(256, 3);
+            else FEH_LAST_CT(128, 3);
+        } else {
+            if (a.nlast == 256) FEH_LAST_CT(256, 2);
+            else FEH_LAST_CT(128, 2);
+        }
+#undef FEH_LAST_CT
+        return hip_check(hipGetLastError(), "last-axis fft launch");
+    }
     const dim3 g(a.total), b(kFftThreads);
     const bool gen = !pow2_len(a.ax.n);
     size_t dyn;
