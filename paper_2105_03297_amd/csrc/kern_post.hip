@@ -7,6 +7,8 @@
 // CG error.  One grid axis enumerates the scalar quantities (stress means of
 // each load case, and each load-case pair of W); partial sums per block are
 // combined in a fixed order by k_reduce_slots.
+#include <algorithm>
+
 #include "device_common.hpp"
 
 namespace feh {
@@ -324,6 +326,313 @@ __global__ __launch_bounds__(kThreads) void k_sens(PK<T> a, const int *pl, const
     }
 }
 
+// ---------------------------------------------------------------------------
+// Plane-marching variants (microstructures of at most kMarchG load cases):
+// a workgroup of VY x VZ voxels (3D 8 x 32, 2D one row of 256) marches
+// along axis 0 over a chunk of kMarchChunk planes, each thread reading the
+// corner nodes of its voxel column straight from memory.  Consecutive
+// workgroups (the same XCD after xcd_remap) cover the load cases of one tile
+// and neighbouring tiles, so a node plane is fetched from HBM about once and
+// served from L2 to the other corners, quantities and load cases that use it.
+// ---------------------------------------------------------------------------
+constexpr int kMarchG = 6;
+constexpr int kMarchChunk = 16;
+
+template <int DIM>
+struct MTile;
+template <>
+struct MTile<3> {
+    static constexpr int VY = 8, VZ = 32, EY = 9, EZ = 33;
+};
+template <>
+struct MTile<2> {
+    static constexpr int VY = 1, VZ = 256, EY = 1, EZ = 257;
+};
+
+struct MarchGeom {
+    int nty, ntz, nchunk;
+};
+
+template <int DIM>
+MarchGeom march_geom(const feh_plan &p) {
+    using TL = MTile<DIM>;
+    const int n0 = (int)p.n[0], n1 = DIM == 3 ? (int)p.n[1] : 1, n2 = (int)p.n[DIM - 1];
+    return MarchGeom{(n1 + TL::VY - 1) / TL::VY, (n2 + TL::VZ - 1) / TL::VZ, (n0 + kMarchChunk - 1) / kMarchChunk};
+}
+
+// In-plane offsets of the corner nodes of a voxel column (corner
+// c = cx + 2 cy (+ 4 cz) with cx the axis-0 bit, periodic).
+template <int DIM>
+struct ColumnCorners {
+    uint32_t o[4];  // in-plane offsets of the corners (cy, cz) = 00, 10, 01, 11 (3D); 2D cz = 0, 1
+    __device__ __forceinline__ void init(int n1, int n2, int y, int z) {
+        const int z1 = z + 1 == n2 ? 0 : z + 1;
+        if constexpr (DIM == 3) {
+            const int y1 = y + 1 == n1 ? 0 : y + 1;
+            o[0] = (uint32_t)y * n2 + z;
+            o[1] = (uint32_t)y1 * n2 + z;
+            o[2] = (uint32_t)y * n2 + z1;
+            o[3] = (uint32_t)y1 * n2 + z1;
+        } else {
+            o[0] = (uint32_t)z;
+            o[1] = (uint32_t)z1;
+            o[2] = o[3] = 0;
+        }
+    }
+};
+
+// Corner values of load case l of the voxel between node planes at offsets
+// xa (cx = 0) and xb (cx = 1).
+template <typename T, int DIM>
+__device__ __forceinline__ void column_corners(const PK<T> &a, int l, uint32_t xa, uint32_t xb,
+                                               const ColumnCorners<DIM> &cc, T (&P)[1 << DIM][DIM]) {
+    #pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        const T *ui = a.u + ((long long)l * DIM + i) * a.N;
+        #pragma unroll
+        for (int c = 0; c < (1 << DIM); ++c) P[c][i] = ui[((c & 1) ? xb : xa) + cc.o[c >> 1]];
+    }
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ void for_corners_zero(T (&P)[1 << DIM][DIM]) {
+    #pragma unroll
+    for (int c = 0; c < (1 << DIM); ++c)
+        #pragma unroll
+        for (int i = 0; i < DIM; ++i) P[c][i] = T(0);
+}
+
+template <typename T, int DIM, int TT>
+__device__ __forceinline__ void element_strain(const T (&P)[1 << DIM][DIM], const T (&ih)[3], const double *eb,
+                                               double (&e)[DIM == 3 ? 6 : 3]) {
+    if constexpr (DIM == 3) {
+        constexpr int KP[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+        constexpr int a0 = KP[TT][0], a1 = KP[TT][1], a2 = KP[TT][2];
+        constexpr int v1 = 1 << a0, v2 = v1 | (1 << a1);
+        double G[3][3];
+        #pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            G[i][a0] = double(P[v1][i] - P[0][i]) * double(ih[a0]);
+            G[i][a1] = double(P[v2][i] - P[v1][i]) * double(ih[a1]);
+            G[i][a2] = double(P[7][i] - P[v2][i]) * double(ih[a2]);
+        }
+        e[0] = G[0][0] + eb[0];
+        e[1] = G[1][1] + eb[1];
+        e[2] = G[2][2] + eb[2];
+        e[3] = 0.5 * (G[1][2] + G[2][1]) + eb[3];
+        e[4] = 0.5 * (G[0][2] + G[2][0]) + eb[4];
+        e[5] = 0.5 * (G[0][1] + G[1][0]) + eb[5];
+    } else {
+        const double hx = ih[0], hy = ih[1];
+        double G[2][2];
+        if constexpr (TT == 0) {  // nodes 00, 10, 01
+            G[0][0] = double(P[1][0] - P[0][0]) * hx;
+            G[0][1] = double(P[2][0] - P[0][0]) * hy;
+            G[1][0] = double(P[1][1] - P[0][1]) * hx;
+            G[1][1] = double(P[2][1] - P[0][1]) * hy;
+        } else {                  // nodes 11, 01, 10
+            G[0][0] = double(P[3][0] - P[2][0]) * hx;
+            G[0][1] = double(P[3][0] - P[1][0]) * hy;
+            G[1][0] = double(P[3][1] - P[2][1]) * hx;
+            G[1][1] = double(P[3][1] - P[1][1]) * hy;
+        }
+        e[0] = G[0][0] + eb[0];
+        e[1] = G[1][1] + eb[1];
+        e[2] = 0.5 * (G[0][1] + G[1][0]) + eb[2];
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ void ebar_sym(const double *Ebar, int l, double (&eb)[DIM == 3 ? 6 : 3]) {
+    if constexpr (DIM == 3) {
+        const double *E = Ebar + l * 9;
+        eb[0] = E[0]; eb[1] = E[4]; eb[2] = E[8]; eb[3] = E[5]; eb[4] = E[2]; eb[5] = E[1];
+    } else {
+        const double *E = Ebar + l * 4;
+        eb[0] = E[0]; eb[1] = E[3]; eb[2] = E[1];
+    }
+}
+
+// Per element of the voxel: strain of load case li, its stress, and
+// f(r, e, s) for element r (unrolled over the elements).
+template <typename T, int DIM, int TT = 0, typename F>
+__device__ __forceinline__ void for_elements(const T (&P)[1 << DIM][DIM], const T (&ih)[3], const double *eb, F &&f) {
+    constexpr int NEL = DIM == 3 ? 6 : 2;
+    if constexpr (TT < NEL) {
+        double e[DIM == 3 ? 6 : 3];
+        element_strain<T, DIM, TT>(P, ih, eb, e);
+        f(TT, e);
+        for_elements<T, DIM, TT + 1>(P, ih, eb, f);
+    }
+}
+
+// Workgroup (load case li of microstructure b, voxel tile, chunk):
+// <sigma_l> partials, W_lm partials for m >= l, and the strain and stress
+// fields of load case l when requested.  The stresses of the voxel's elements
+// under load case l stay in registers while the later load cases' strains
+// are formed against them.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kThreads) void k_post_march(PK<T> a, MarchGeom geo) {
+    using TL = MTile<DIM>;
+    constexpr int NEL = DIM == 3 ? 6 : 2;
+    constexpr int NS = DIM == 3 ? 6 : 3;
+    __shared__ double red[kThreads / 64];
+    const int G = a.G;
+    int t = xcd_remap(blockIdx.x, (int)gridDim.x);
+    const int li = t % G;
+    t /= G;
+    const int tz_t = t % geo.ntz;
+    t /= geo.ntz;
+    const int ty_t = t % geo.nty;
+    const int ch = t / geo.nty;
+    const int b = blockIdx.y;
+    const int l = b * G + li;
+    const int nl = G - li;  // pairs (l, l + k), k < nl
+    const int y = ty_t * TL::VY + (DIM == 3 ? (int)threadIdx.x / TL::VZ : 0);
+    const int z = tz_t * TL::VZ + (int)threadIdx.x % TL::VZ;
+    const bool inside = (DIM == 2 || y < a.n1) && z < a.n2;
+    const int x0 = ch * kMarchChunk, x1 = min(x0 + kMarchChunk, a.n0);
+    const uint32_t plane = (uint32_t)a.n1 * (uint32_t)a.n2;
+    const long long mo = (long long)b * a.N;
+    double ebl[NS];
+    ebar_sym<DIM>(a.Ebar, l, ebl);
+    double sig[NS], w[kMarchG];
+    #pragma unroll
+    for (int k = 0; k < NS; ++k) sig[k] = 0.0;
+    #pragma unroll
+    for (int k = 0; k < kMarchG; ++k) w[k] = 0.0;
+    if (inside) {
+        ColumnCorners<DIM> cc;
+        cc.init(a.n1, a.n2, DIM == 3 ? y : 0, z);
+        const uint32_t vin = cc.o[0];
+        for (int X = x0; X < x1; ++X) {
+            const uint32_t xa = (uint32_t)X * plane, xb = (uint32_t)(X + 1 == a.n0 ? 0 : X + 1) * plane;
+            const uint32_t v = xa + vin;
+            const double lam = double(a.lam[mo + v]), mu = double(a.mu[mo + v]);
+            T P[1 << DIM][DIM];
+            if (a.u)
+                column_corners<T, DIM>(a, l, xa, xb, cc, P);
+            else
+                for_corners_zero<T, DIM>(P);
+            double s[NEL][NS];
+            for_elements<T, DIM>(P, a.ih, ebl, [&](int r, const double (&e)[NS]) {
+                stress_of<DIM>(e, lam, mu, s[r]);
+                #pragma unroll
+                for (int k = 0; k < NS; ++k) sig[k] += s[r][k];
+                w[0] += ddot<DIM>(e, s[r]);
+                const long long off = (((long long)l * a.N + v) * NEL + r) * DIM * DIM;
+                if (a.strain) put_full<T, DIM>(a.strain + off, e);
+                if (a.stress) put_full<T, DIM>(a.stress + off, s[r]);
+            });
+            // one pair at a time (not unrolled, so that the corner loads of
+            // later load cases are not all hoisted into registers)
+            #pragma unroll 1
+            for (int k = 1; k < nl; ++k) {
+                double ebm[NS];
+                ebar_sym<DIM>(a.Ebar, l + k, ebm);
+                if (a.u)
+                    column_corners<T, DIM>(a, l + k, xa, xb, cc, P);
+                double acc = 0.0;
+                for_elements<T, DIM>(P, a.ih, ebm, [&](int r, const double (&f)[NS]) { acc += ddot<DIM>(f, s[r]); });
+                #pragma unroll
+                for (int j = 1; j < kMarchG; ++j) w[j] += j == k ? acc : 0.0;
+            }
+        }
+    }
+    const int blk = (ch * geo.nty + ty_t) * geo.ntz + tz_t;
+    for (int k = 0; k < NS; ++k) {
+        const double sm = block_sum<kThreads>(sig[k], red);
+        if (threadIdx.x == 0) a.partial[((long long)l * NS + k) * a.nblk + blk] = sm;
+    }
+    // pair (l, l + k) of microstructure b: pairs ordered l outer, m >= l inner
+    const int pbase = a.L * NS + b * (G * (G + 1) / 2) + li * G - li * (li - 1) / 2;
+    #pragma unroll
+    for (int k = 0; k < kMarchG; ++k) {
+        if (k < nl) {
+            const double sm = block_sum<kThreads>(w[k], red);
+            if (threadIdx.x == 0) a.partial[(long long)(pbase + k) * a.nblk + blk] = sm;
+        }
+    }
+}
+
+// Workgroup (voxel tile, chunk, microstructure b): the sensitivity pairs of
+// b (see k_sens), each load case's corners read per pair from L1/L2.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kThreads) void k_sens_march(PK<T> a, MarchGeom geo, const int *pl, const int *pm,
+                                                         const double *pw, const int *gofs, double scale, T *g_lam,
+                                                         T *g_mu, T *g_E, double aE, double bE) {
+    using TL = MTile<DIM>;
+    constexpr int NS = DIM == 3 ? 6 : 3;
+    constexpr int NEL = DIM == 3 ? 6 : 2;
+    int t = xcd_remap(blockIdx.x, (int)gridDim.x);
+    const int tz_t = t % geo.ntz;
+    t /= geo.ntz;
+    const int ty_t = t % geo.nty;
+    const int ch = t / geo.nty;
+    const int b = blockIdx.y;
+    const int y = ty_t * TL::VY + (DIM == 3 ? (int)threadIdx.x / TL::VZ : 0);
+    const int z = tz_t * TL::VZ + (int)threadIdx.x % TL::VZ;
+    if (!((DIM == 2 || y < a.n1) && z < a.n2)) return;
+    const int x0 = ch * kMarchChunk, x1 = min(x0 + kMarchChunk, a.n0);
+    const uint32_t plane = (uint32_t)a.n1 * (uint32_t)a.n2;
+    const int q0 = gofs[b], q1 = gofs[b + 1];
+    ColumnCorners<DIM> cc;
+    cc.init(a.n1, a.n2, DIM == 3 ? y : 0, z);
+    for (int X = x0; X < x1; ++X) {
+        const uint32_t xa = (uint32_t)X * plane, xb = (uint32_t)(X + 1 == a.n0 ? 0 : X + 1) * plane;
+        double gl = 0.0, gm = 0.0;
+        for (int q = q0; q < q1; ++q) {
+            const int l = pl[q], m = pm[q];
+            const double wq = pw[q];
+            double ebl[NS];
+            ebar_sym<DIM>(a.Ebar, l, ebl);
+            T Pl[1 << DIM][DIM];
+            if (a.u)
+                column_corners<T, DIM>(a, l, xa, xb, cc, Pl);
+            else
+                for_corners_zero<T, DIM>(Pl);
+            double sl = 0.0, sm = 0.0;
+            if (m == l) {
+                // element r: (tr e)^2 and 2 e : e
+                for_elements<T, DIM>(Pl, a.ih, ebl, [&](int, const double (&e)[NS]) {
+                    const double te = DIM == 3 ? e[0] + e[1] + e[2] : e[0] + e[1];
+                    sl += te * te;
+                    sm += 2.0 * ddot<DIM>(e, e);
+                });
+            } else {
+                double ebm[NS];
+                ebar_sym<DIM>(a.Ebar, m, ebm);
+                T Pm[1 << DIM][DIM];
+                if (a.u)
+                    column_corners<T, DIM>(a, m, xa, xb, cc, Pm);
+                else
+                    for_corners_zero<T, DIM>(Pm);
+                // element r of both load cases: tr e tr f and 2 e : f
+                double te[NEL], el[NEL][NS];
+                for_elements<T, DIM>(Pl, a.ih, ebl, [&](int r, const double (&e)[NS]) {
+                    te[r] = DIM == 3 ? e[0] + e[1] + e[2] : e[0] + e[1];
+                    #pragma unroll
+                    for (int k = 0; k < NS; ++k) el[r][k] = e[k];
+                });
+                for_elements<T, DIM>(Pm, a.ih, ebm, [&](int r, const double (&f)[NS]) {
+                    const double tf = DIM == 3 ? f[0] + f[1] + f[2] : f[0] + f[1];
+                    sl += te[r] * tf;
+                    sm += 2.0 * ddot<DIM>(el[r], f);
+                });
+            }
+            gl += wq * sl;
+            gm += wq * sm;
+        }
+        const long long v = (long long)b * a.N + xa + cc.o[0];
+        if (g_E) {
+            g_E[v] = T((aE * gl + bE * gm) * scale);
+        } else {
+            g_lam[v] = T(gl * scale);
+            g_mu[v] = T(gm * scale);
+        }
+    }
+}
+
 __global__ void k_reduce_slots(const double *part, int nblk, double *out, double scale) {
     __shared__ double red[kThreads / 64];
     const int slot = blockIdx.x;
@@ -358,9 +667,16 @@ PK<T> post_args(const feh_plan &p) {
 
 }  // namespace
 
+// Does the plan take the plane-marching post-processing?
+static bool march_ok(const feh_plan &p) { return p.G <= kMarchG; }
+
 int post_num_parts(const feh_plan &p) {
     long long b = (p.N + kThreads - 1) / kThreads;
     if (b > 512) b = 512;
+    if (march_ok(p)) {
+        const MarchGeom g = p.dim == 3 ? march_geom<3>(p) : march_geom<2>(p);
+        b = std::max(b, (long long)g.nty * g.ntz * g.nchunk);
+    }
     return (int)b;
 }
 
@@ -378,13 +694,24 @@ static int post_t(const feh_plan &p, const void *u, const double *Ebar, void *st
     a.strain = static_cast<T *>(strain);
     a.stress = static_cast<T *>(stress);
     a.partial = partial;
-    a.nblk = post_num_parts(p);
-    const int nq = p.L + p.nbatch * (p.G * (p.G + 1) / 2);
-    dim3 g(a.nblk, nq);
-    if (p.dim == 3)
-        hipLaunchKernelGGL((k_post<T, 3>), g, dim3(kThreads), 0, p.stream, a);
-    else
-        hipLaunchKernelGGL((k_post<T, 2>), g, dim3(kThreads), 0, p.stream, a);
+    if (march_ok(p)) {
+        const MarchGeom geo = p.dim == 3 ? march_geom<3>(p) : march_geom<2>(p);
+        a.nblk = geo.nty * geo.ntz * geo.nchunk;
+        dim3 g(a.nblk * p.G, p.nbatch);
+        if (p.dim == 3)
+            hipLaunchKernelGGL((k_post_march<T, 3>), g, dim3(kThreads), 0, p.stream, a, geo);
+        else
+            hipLaunchKernelGGL((k_post_march<T, 2>), g, dim3(kThreads), 0, p.stream, a, geo);
+    } else {
+        const long long nb = (p.N + kThreads - 1) / kThreads;
+        a.nblk = (int)(nb > 512 ? 512 : nb);
+        const int nq = p.L + p.nbatch * (p.G * (p.G + 1) / 2);
+        dim3 g(a.nblk, nq);
+        if (p.dim == 3)
+            hipLaunchKernelGGL((k_post<T, 3>), g, dim3(kThreads), 0, p.stream, a);
+        else
+            hipLaunchKernelGGL((k_post<T, 2>), g, dim3(kThreads), 0, p.stream, a);
+    }
     int rc = hip_check(hipGetLastError(), "post launch");
     if (rc) return rc;
     const int ne = p.dim == 3 ? 6 : 2;
@@ -429,6 +756,17 @@ static int sens_t(const feh_plan &p, const void *u, const double *Ebar, const in
     if (g > 4096) g = 4096;
     const int ne = p.dim == 3 ? 6 : 2;
     const double scale = 1.0 / ((double)p.N * ne);
+    if (march_ok(p)) {
+        const MarchGeom geo = p.dim == 3 ? march_geom<3>(p) : march_geom<2>(p);
+        dim3 grid(geo.nty * geo.ntz * geo.nchunk, p.nbatch);
+        if (p.dim == 3)
+            hipLaunchKernelGGL((k_sens_march<T, 3>), grid, dim3(kThreads), 0, p.stream, a, geo, pl, pm, pw, gofs,
+                               scale, static_cast<T *>(g_lam), static_cast<T *>(g_mu), static_cast<T *>(g_E), aE, bE);
+        else
+            hipLaunchKernelGGL((k_sens_march<T, 2>), grid, dim3(kThreads), 0, p.stream, a, geo, pl, pm, pw, gofs,
+                               scale, static_cast<T *>(g_lam), static_cast<T *>(g_mu), static_cast<T *>(g_E), aE, bE);
+        return hip_check(hipGetLastError(), "sensitivity launch");
+    }
     if (p.dim == 3)
         hipLaunchKernelGGL((k_sens<T, 3>), dim3((unsigned)g), dim3(kThreads), 0, p.stream, a, pl, pm, pw, gofs, scale,
                            static_cast<T *>(g_lam), static_cast<T *>(g_mu), static_cast<T *>(g_E), aE, bE);
