@@ -402,67 +402,163 @@ __device__ __forceinline__ void for_corners_zero(T (&P)[1 << DIM][DIM]) {
         for (int i = 0; i < DIM; ++i) P[c][i] = T(0);
 }
 
-template <typename T, int DIM, int TT>
-__device__ __forceinline__ void element_strain(const T (&P)[1 << DIM][DIM], const T (&ih)[3], const double *eb,
-                                               double (&e)[DIM == 3 ? 6 : 3]) {
-    if constexpr (DIM == 3) {
-        constexpr int KP[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
-        constexpr int a0 = KP[TT][0], a1 = KP[TT][1], a2 = KP[TT][2];
-        constexpr int v1 = 1 << a0, v2 = v1 | (1 << a1);
-        double G[3][3];
+// Displacement gradient of element TT of the voxel plus Ebar (full D x D,
+// g[i][a] = d u_i / d x_a + Ebar_ia), one FMA per entry: the element's edge
+// along axis a starts at corner BASE[TT][a] (3D: tetrahedron with axis path
+// (a0, a1, a2) walks corners 0, 1<<a0, 1<<a0 | 1<<a1, 7; 2D: triangle 0 is
+// nodes 00, 10, 01, triangle 1 nodes 11, 01, 10).  The symmetric part of g is
+// the element strain e; the unrolled callers share the twelve (3D) edge
+// differences between elements.
+template <typename R, typename T, int DIM, int TT>
+__device__ __forceinline__ void element_grad(const T (&P)[1 << DIM][DIM], const T (&ih)[3], const R (&Eb)[DIM][DIM],
+                                             R (&g)[DIM][DIM]) {
+    constexpr int BASE3[6][3] = {{0, 1, 3}, {0, 5, 1}, {2, 0, 3}, {6, 0, 2}, {4, 5, 0}, {6, 4, 0}};
+    constexpr int BASE2[2][2] = {{0, 0}, {2, 1}};
+    #pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+        const int c0 = DIM == 3 ? BASE3[TT][ax] : BASE2[TT][ax];
+        const int c1 = c0 | (DIM == 3 ? 1 << ax : 1 << ax);
         #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            G[i][a0] = double(P[v1][i] - P[0][i]) * double(ih[a0]);
-            G[i][a1] = double(P[v2][i] - P[v1][i]) * double(ih[a1]);
-            G[i][a2] = double(P[7][i] - P[v2][i]) * double(ih[a2]);
-        }
-        e[0] = G[0][0] + eb[0];
-        e[1] = G[1][1] + eb[1];
-        e[2] = G[2][2] + eb[2];
-        e[3] = 0.5 * (G[1][2] + G[2][1]) + eb[3];
-        e[4] = 0.5 * (G[0][2] + G[2][0]) + eb[4];
-        e[5] = 0.5 * (G[0][1] + G[1][0]) + eb[5];
-    } else {
-        const double hx = ih[0], hy = ih[1];
-        double G[2][2];
-        if constexpr (TT == 0) {  // nodes 00, 10, 01
-            G[0][0] = double(P[1][0] - P[0][0]) * hx;
-            G[0][1] = double(P[2][0] - P[0][0]) * hy;
-            G[1][0] = double(P[1][1] - P[0][1]) * hx;
-            G[1][1] = double(P[2][1] - P[0][1]) * hy;
-        } else {                  // nodes 11, 01, 10
-            G[0][0] = double(P[3][0] - P[2][0]) * hx;
-            G[0][1] = double(P[3][0] - P[1][0]) * hy;
-            G[1][0] = double(P[3][1] - P[2][1]) * hx;
-            G[1][1] = double(P[3][1] - P[1][1]) * hy;
-        }
-        e[0] = G[0][0] + eb[0];
-        e[1] = G[1][1] + eb[1];
-        e[2] = 0.5 * (G[0][1] + G[1][0]) + eb[2];
+        for (int i = 0; i < DIM; ++i) g[i][ax] = fma(R(P[c1][i] - P[c0][i]), R(ih[ax]), Eb[i][ax]);
     }
 }
 
-template <int DIM>
-__device__ __forceinline__ void ebar_sym(const double *Ebar, int l, double (&eb)[DIM == 3 ? 6 : 3]) {
-    if constexpr (DIM == 3) {
-        const double *E = Ebar + l * 9;
-        eb[0] = E[0]; eb[1] = E[4]; eb[2] = E[8]; eb[3] = E[5]; eb[4] = E[2]; eb[5] = E[1];
-    } else {
-        const double *E = Ebar + l * 4;
-        eb[0] = E[0]; eb[1] = E[3]; eb[2] = E[1];
-    }
+template <int DIM, typename R>
+__device__ __forceinline__ void ebar_full(const double *Ebar, int l, R (&Eb)[DIM][DIM]) {
+    #pragma unroll
+    for (int i = 0; i < DIM; ++i)
+        #pragma unroll
+        for (int j = 0; j < DIM; ++j) Eb[i][j] = R(Ebar[(l * DIM + i) * DIM + j]);
 }
 
-// Per element of the voxel: strain of load case li, its stress, and
-// f(r, e, s) for element r (unrolled over the elements).
-template <typename T, int DIM, int TT = 0, typename F>
-__device__ __forceinline__ void for_elements(const T (&P)[1 << DIM][DIM], const T (&ih)[3], const double *eb, F &&f) {
+// Sums over the voxel's elements of (tr e)^2 and e : e for corner values P,
+// in arithmetic R.
+template <typename R, typename T, int DIM, int TT = 0>
+__device__ __forceinline__ void self_sums(const T (&P)[1 << DIM][DIM], const T (&ih)[3], const R (&Eb)[DIM][DIM], R &st,
+                                          R &se) {
     constexpr int NEL = DIM == 3 ? 6 : 2;
     if constexpr (TT < NEL) {
-        double e[DIM == 3 ? 6 : 3];
-        element_strain<T, DIM, TT>(P, ih, eb, e);
-        f(TT, e);
-        for_elements<T, DIM, TT + 1>(P, ih, eb, f);
+        R g[DIM][DIM];
+        element_grad<R, T, DIM, TT>(P, ih, Eb, g);
+        R tr = g[0][0], dg = g[0][0] * g[0][0], off = R(0);
+        #pragma unroll
+        for (int i = 1; i < DIM; ++i) {
+            tr += g[i][i];
+            dg = fma(g[i][i], g[i][i], dg);
+        }
+        #pragma unroll
+        for (int i = 0; i < DIM; ++i)
+            #pragma unroll
+            for (int j = i + 1; j < DIM; ++j) {
+                const R o = g[i][j] + g[j][i];  // 2 e_ij
+                off = fma(o, o, off);
+            }
+        st = fma(tr, tr, st);
+        se += fma(R(0.5), off, dg);
+        self_sums<R, T, DIM, TT + 1>(P, ih, Eb, st, se);
+    }
+}
+
+// Sums over the voxel's elements of tr e tr f and e : f for the corner values
+// Pe, Pf of two load cases, in arithmetic R.
+template <typename R, typename T, int DIM, int TT = 0>
+__device__ __forceinline__ void pair_sums(const T (&Pe)[1 << DIM][DIM], const T (&Pf)[1 << DIM][DIM], const T (&ih)[3],
+                                          const R (&Ebe)[DIM][DIM], const R (&Ebf)[DIM][DIM], R &st, R &se) {
+    constexpr int NEL = DIM == 3 ? 6 : 2;
+    if constexpr (TT < NEL) {
+        R ge[DIM][DIM], gf[DIM][DIM];
+        element_grad<R, T, DIM, TT>(Pe, ih, Ebe, ge);
+        element_grad<R, T, DIM, TT>(Pf, ih, Ebf, gf);
+        R te = ge[0][0], tf = gf[0][0], dg = ge[0][0] * gf[0][0], off = R(0);
+        #pragma unroll
+        for (int i = 1; i < DIM; ++i) {
+            te += ge[i][i];
+            tf += gf[i][i];
+            dg = fma(ge[i][i], gf[i][i], dg);
+        }
+        #pragma unroll
+        for (int i = 0; i < DIM; ++i)
+            #pragma unroll
+            for (int j = i + 1; j < DIM; ++j) off = fma(ge[i][j] + ge[j][i], gf[i][j] + gf[j][i], off);
+        st = fma(te, tf, st);
+        se += fma(R(0.5), off, dg);
+        pair_sums<R, T, DIM, TT + 1>(Pe, Pf, ih, Ebe, Ebf, st, se);
+    }
+}
+
+// Stresses s = C e of the voxel's elements for corner values P: their sum
+// over the elements into ss (symmetric storage as stress_of), the sum of
+// e : s into w, the nodal forces F = B^T s of the voxel (so that
+// sum_elements f : s = sum_c P'[c] . F[c] + Ebar' : ss for the strains f of
+// any other corner values P' and mean strain Ebar'), and, when FIELDS, the
+// full strain and stress blocks of element TT at fe + TT D^2, fs + TT D^2.
+template <typename T, int DIM, bool FIELDS, int TT = 0>
+__device__ __forceinline__ void element_forces(const T (&P)[1 << DIM][DIM], const T (&ih)[3],
+                                               const double (&Eb)[DIM][DIM], double lam, double mu,
+                                               double (&F)[1 << DIM][DIM], double (&ss)[DIM == 3 ? 6 : 3], double &w,
+                                               T *fe, T *fs) {
+    constexpr int NEL = DIM == 3 ? 6 : 2;
+    constexpr int NS = DIM == 3 ? 6 : 3;
+    if constexpr (TT < NEL) {
+        double g[DIM][DIM];
+        element_grad<double, T, DIM, TT>(P, ih, Eb, g);
+        double sr[NS];
+        const double m2 = 2.0 * mu;
+        if constexpr (DIM == 3) {
+            const double lt = lam * (g[0][0] + g[1][1] + g[2][2]);
+            const double o0 = g[1][2] + g[2][1], o1 = g[0][2] + g[2][0], o2 = g[0][1] + g[1][0];  // 2 e_ij
+            sr[0] = fma(m2, g[0][0], lt);
+            sr[1] = fma(m2, g[1][1], lt);
+            sr[2] = fma(m2, g[2][2], lt);
+            sr[3] = mu * o0;
+            sr[4] = mu * o1;
+            sr[5] = mu * o2;
+            w = fma(g[0][0], sr[0], w);
+            w = fma(g[1][1], sr[1], w);
+            w = fma(g[2][2], sr[2], w);
+            w = fma(o0, sr[3], w);
+            w = fma(o1, sr[4], w);
+            w = fma(o2, sr[5], w);
+            if constexpr (FIELDS) {
+                const double e[6] = {g[0][0], g[1][1], g[2][2], 0.5 * o0, 0.5 * o1, 0.5 * o2};
+                if (fe) put_full<T, DIM>(fe + TT * 9, e);
+                if (fs) put_full<T, DIM>(fs + TT * 9, sr);
+            }
+        } else {
+            const double lt = lam * (g[0][0] + g[1][1]);
+            const double o2 = g[0][1] + g[1][0];
+            sr[0] = fma(m2, g[0][0], lt);
+            sr[1] = fma(m2, g[1][1], lt);
+            sr[2] = mu * o2;
+            w = fma(g[0][0], sr[0], w);
+            w = fma(g[1][1], sr[1], w);
+            w = fma(o2, sr[2], w);
+            if constexpr (FIELDS) {
+                const double e[3] = {g[0][0], g[1][1], 0.5 * o2};
+                if (fe) put_full<T, DIM>(fe + TT * 4, e);
+                if (fs) put_full<T, DIM>(fs + TT * 4, sr);
+            }
+        }
+        #pragma unroll
+        for (int k = 0; k < NS; ++k) ss[k] += sr[k];
+        // F: the element's edge along axis a (corners c0 -> c1) carries the
+        // gradient (P[c1] - P[c0]) / h_a, so s_ia / h_a goes to c1 and back from c0
+        constexpr int BASE3[6][3] = {{0, 1, 3}, {0, 5, 1}, {2, 0, 3}, {6, 0, 2}, {4, 5, 0}, {6, 4, 0}};
+        constexpr int BASE2[2][2] = {{0, 0}, {2, 1}};
+        constexpr int SYM3[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
+        constexpr int SYM2[2][2] = {{0, 2}, {2, 1}};
+        #pragma unroll
+        for (int ax = 0; ax < DIM; ++ax) {
+            const int c0 = DIM == 3 ? BASE3[TT][ax] : BASE2[TT][ax];
+            const int c1 = c0 | (1 << ax);
+            #pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+                const double f = sr[DIM == 3 ? SYM3[i][ax] : SYM2[i][ax]] * double(ih[ax]);
+                F[c1][i] += f;
+                F[c0][i] -= f;
+            }
+        }
+        element_forces<T, DIM, FIELDS, TT + 1>(P, ih, Eb, lam, mu, F, ss, w, fe, fs);
     }
 }
 
@@ -471,7 +567,7 @@ __device__ __forceinline__ void for_elements(const T (&P)[1 << DIM][DIM], const 
 // fields of load case l when requested.  The stresses of the voxel's elements
 // under load case l stay in registers while the later load cases' strains
 // are formed against them.
-template <typename T, int DIM>
+template <typename T, int DIM, bool FIELDS>
 __global__ __launch_bounds__(kThreads) void k_post_march(PK<T> a, MarchGeom geo) {
     using TL = MTile<DIM>;
     constexpr int NEL = DIM == 3 ? 6 : 2;
@@ -494,8 +590,8 @@ __global__ __launch_bounds__(kThreads) void k_post_march(PK<T> a, MarchGeom geo)
     const int x0 = ch * kMarchChunk, x1 = min(x0 + kMarchChunk, a.n0);
     const uint32_t plane = (uint32_t)a.n1 * (uint32_t)a.n2;
     const long long mo = (long long)b * a.N;
-    double ebl[NS];
-    ebar_sym<DIM>(a.Ebar, l, ebl);
+    double Ebl[DIM][DIM];
+    ebar_full<DIM>(a.Ebar, l, Ebl);
     double sig[NS], w[kMarchG];
     #pragma unroll
     for (int k = 0; k < NS; ++k) sig[k] = 0.0;
@@ -514,26 +610,41 @@ __global__ __launch_bounds__(kThreads) void k_post_march(PK<T> a, MarchGeom geo)
                 column_corners<T, DIM>(a, l, xa, xb, cc, P);
             else
                 for_corners_zero<T, DIM>(P);
-            double s[NEL][NS];
-            for_elements<T, DIM>(P, a.ih, ebl, [&](int r, const double (&e)[NS]) {
-                stress_of<DIM>(e, lam, mu, s[r]);
+            double F[1 << DIM][DIM], ss[NS];
+            #pragma unroll
+            for (int c = 0; c < (1 << DIM); ++c)
                 #pragma unroll
-                for (int k = 0; k < NS; ++k) sig[k] += s[r][k];
-                w[0] += ddot<DIM>(e, s[r]);
-                const long long off = (((long long)l * a.N + v) * NEL + r) * DIM * DIM;
-                if (a.strain) put_full<T, DIM>(a.strain + off, e);
-                if (a.stress) put_full<T, DIM>(a.stress + off, s[r]);
-            });
-            // one pair at a time (not unrolled, so that the corner loads of
+                for (int i = 0; i < DIM; ++i) F[c][i] = 0.0;
+            #pragma unroll
+            for (int k = 0; k < NS; ++k) ss[k] = 0.0;
+            if constexpr (FIELDS) {
+                const long long off = ((long long)l * a.N + v) * NEL * DIM * DIM;
+                element_forces<T, DIM, true>(P, a.ih, Ebl, lam, mu, F, ss, w[0], a.strain ? a.strain + off : nullptr,
+                                             a.stress ? a.stress + off : nullptr);
+            } else {
+                element_forces<T, DIM, false>(P, a.ih, Ebl, lam, mu, F, ss, w[0], nullptr, nullptr);
+            }
+            #pragma unroll
+            for (int k = 0; k < NS; ++k) sig[k] += ss[k];
+            // W_lm for the later load cases m = l + k of the microstructure:
+            // sum_elements e_m : s = sum_c u_m[c] . F[c] + Ebar_m : ss (one
+            // pair at a time: not unrolled, so that the corner loads of the
             // later load cases are not all hoisted into registers)
             #pragma unroll 1
             for (int k = 1; k < nl; ++k) {
-                double ebm[NS];
-                ebar_sym<DIM>(a.Ebar, l + k, ebm);
-                if (a.u)
+                const double *Em = a.Ebar + (l + k) * DIM * DIM;
+                double acc;
+                if constexpr (DIM == 3)
+                    acc = Em[0] * ss[0] + Em[4] * ss[1] + Em[8] * ss[2] + 2.0 * (Em[5] * ss[3] + Em[2] * ss[4] + Em[1] * ss[5]);
+                else
+                    acc = Em[0] * ss[0] + Em[3] * ss[1] + 2.0 * Em[1] * ss[2];
+                if (a.u) {
                     column_corners<T, DIM>(a, l + k, xa, xb, cc, P);
-                double acc = 0.0;
-                for_elements<T, DIM>(P, a.ih, ebm, [&](int r, const double (&f)[NS]) { acc += ddot<DIM>(f, s[r]); });
+                    #pragma unroll
+                    for (int c = 0; c < (1 << DIM); ++c)
+                        #pragma unroll
+                        for (int i = 0; i < DIM; ++i) acc = fma(double(P[c][i]), F[c][i], acc);
+                }
                 #pragma unroll
                 for (int j = 1; j < kMarchG; ++j) w[j] += j == k ? acc : 0.0;
             }
@@ -584,44 +695,32 @@ __global__ __launch_bounds__(kThreads) void k_sens_march(PK<T> a, MarchGeom geo,
         for (int q = q0; q < q1; ++q) {
             const int l = pl[q], m = pm[q];
             const double wq = pw[q];
-            double ebl[NS];
-            ebar_sym<DIM>(a.Ebar, l, ebl);
             T Pl[1 << DIM][DIM];
             if (a.u)
                 column_corners<T, DIM>(a, l, xa, xb, cc, Pl);
             else
                 for_corners_zero<T, DIM>(Pl);
-            double sl = 0.0, sm = 0.0;
+            // the voxel's element sums in the plan precision T, the pairs in FP64
+            T sl = T(0), se = T(0);
             if (m == l) {
-                // element r: (tr e)^2 and 2 e : e
-                for_elements<T, DIM>(Pl, a.ih, ebl, [&](int, const double (&e)[NS]) {
-                    const double te = DIM == 3 ? e[0] + e[1] + e[2] : e[0] + e[1];
-                    sl += te * te;
-                    sm += 2.0 * ddot<DIM>(e, e);
-                });
+                // (tr e)^2 and e : e over the elements
+                T Ebl[DIM][DIM];
+                ebar_full<DIM>(a.Ebar, l, Ebl);
+                self_sums<T, T, DIM>(Pl, a.ih, Ebl, sl, se);
             } else {
-                double ebm[NS];
-                ebar_sym<DIM>(a.Ebar, m, ebm);
+                T Ebl[DIM][DIM], Ebm[DIM][DIM];
+                ebar_full<DIM>(a.Ebar, l, Ebl);
+                ebar_full<DIM>(a.Ebar, m, Ebm);
                 T Pm[1 << DIM][DIM];
                 if (a.u)
                     column_corners<T, DIM>(a, m, xa, xb, cc, Pm);
                 else
                     for_corners_zero<T, DIM>(Pm);
-                // element r of both load cases: tr e tr f and 2 e : f
-                double te[NEL], el[NEL][NS];
-                for_elements<T, DIM>(Pl, a.ih, ebl, [&](int r, const double (&e)[NS]) {
-                    te[r] = DIM == 3 ? e[0] + e[1] + e[2] : e[0] + e[1];
-                    #pragma unroll
-                    for (int k = 0; k < NS; ++k) el[r][k] = e[k];
-                });
-                for_elements<T, DIM>(Pm, a.ih, ebm, [&](int r, const double (&f)[NS]) {
-                    const double tf = DIM == 3 ? f[0] + f[1] + f[2] : f[0] + f[1];
-                    sl += te[r] * tf;
-                    sm += 2.0 * ddot<DIM>(el[r], f);
-                });
+                // tr e tr f and e : f over the elements of both load cases
+                pair_sums<T, T, DIM>(Pl, Pm, a.ih, Ebl, Ebm, sl, se);
             }
-            gl += wq * sl;
-            gm += wq * sm;
+            gl += wq * double(sl);
+            gm += 2.0 * wq * double(se);
         }
         const long long v = (long long)b * a.N + xa + cc.o[0];
         if (g_E) {
@@ -698,10 +797,15 @@ static int post_t(const feh_plan &p, const void *u, const double *Ebar, void *st
         const MarchGeom geo = p.dim == 3 ? march_geom<3>(p) : march_geom<2>(p);
         a.nblk = geo.nty * geo.ntz * geo.nchunk;
         dim3 g(a.nblk * p.G, p.nbatch);
-        if (p.dim == 3)
-            hipLaunchKernelGGL((k_post_march<T, 3>), g, dim3(kThreads), 0, p.stream, a, geo);
+        const bool fields = a.strain || a.stress;
+        if (p.dim == 3 && fields)
+            hipLaunchKernelGGL((k_post_march<T, 3, true>), g, dim3(kThreads), 0, p.stream, a, geo);
+        else if (p.dim == 3)
+            hipLaunchKernelGGL((k_post_march<T, 3, false>), g, dim3(kThreads), 0, p.stream, a, geo);
+        else if (fields)
+            hipLaunchKernelGGL((k_post_march<T, 2, true>), g, dim3(kThreads), 0, p.stream, a, geo);
         else
-            hipLaunchKernelGGL((k_post_march<T, 2>), g, dim3(kThreads), 0, p.stream, a, geo);
+            hipLaunchKernelGGL((k_post_march<T, 2, false>), g, dim3(kThreads), 0, p.stream, a, geo);
     } else {
         const long long nb = (p.N + kThreads - 1) / kThreads;
         a.nblk = (int)(nb > 512 ? 512 : nb);
