@@ -162,6 +162,7 @@ def uneven_batch_measure(log):
          "s_graph": round(res["graph"][0], 4), "s_eager": round(res["eager"][0], 4), "s_one_plan_per_map": round(t_seq, 4),
          "graph_launches": res["graph"][2],
          "DOF_CG_iterations_per_s_graph": dof_it / res["graph"][0],
+         "DOF_CG_iterations_per_s_eager": dof_it / res["eager"][0],
          "max_cg_iterations": max(max(r["iterations"] for r in o["report"]) for o in res["graph"][1]),
          "C_eff_graph_vs_one_plan_per_map": worst}
     log("uneven batch", u)
@@ -355,6 +356,8 @@ def main():
     ap.add_argument("--no-finite-strain", action="store_true", help="skip the finite-strain measurement")
     ap.add_argument("--strain-space-only", action="store_true",
                     help="run only the strain-space and finite-strain measurements and print them as the JSON line")
+    ap.add_argument("--uneven-only", action="store_true",
+                    help="run only the uneven-batch measurement and print it as the JSON line")
     ap.add_argument("--copy-ref", action="store_true",
                     help="after the steps, copy a 1 GiB buffer once (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -369,6 +372,9 @@ def main():
     import paper_2105_03297_amd as feh
 
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
+    if args.uneven_only:
+        print(json.dumps({"uneven_batch": uneven_batch_measure(log)}), flush=True)
+        return
     if args.strain_space_only:
         print(json.dumps({"strain_space": strain_space_measure(log),
                           "finite_strain": finite_strain_measure(log)}), flush=True)

@@ -235,7 +235,8 @@ int feh_plan_autotune(feh_plan *plan, int reps);
  * 16 rows of 32 voxels; 2D: 1)], then for each axis 0..2 the
  * number of passes followed by the radices in pass order, then 1 if passes
  * whose shape has a compile-time transform may use it (power-of-two axes of
- * 64, 128 or 256 points in the default radix order; the same butterflies and
+ * 64 to 512 points in the default radix order, the last axis in FP32 from
+ * 128 points; the same butterflies and
  * twiddles, with the index arithmetic resolved at compile time) or 0 for
  * the run-time passes throughout (default 1).  Writes at most n_values
  * entries and returns the full length. */

@@ -1763,13 +1763,13 @@ int last_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     a.nblk = (int)((a.rows + RR - 1) / RR);
     a.total = a.nblk * p.L;
     a.use_axpy = (!inverse && fa.q != nullptr && fa.state != nullptr) ? 1 : 0;
-    // compile-time transform: FP32, 3D (or 2D) with an even last axis of 128
-    // or 256 points in the default radix order and the default row count
-    if (sizeof(T) == 4 && p.tune_ct && p.tune_rr_last == 0 && p.last_even && (a.D == 3 || a.D == 2) &&
-        (a.nlast == 128 || a.nlast == 256) && ct_schedule_matches(a.ax, a.nlast / 2) &&
-        (double)a.D * (double)a.N * sizeof(T) < 4294967296.0) {
-        const int rr = (a.D == 3 ? (a.nlast == 256 ? ct_last_rows<256, 3>() : ct_last_rows<128, 3>())
-                                 : (a.nlast == 256 ? ct_last_rows<256, 2>() : ct_last_rows<128, 2>()));
+    // compile-time transform: FP32, 3D (or 2D) with an even last axis of 128,
+    // 256 or 512 points in the default radix order and the default row count
+    if constexpr (sizeof(T) == 4) {
+      if (p.tune_ct && p.tune_rr_last == 0 && p.last_even && (a.D == 3 || a.D == 2) &&
+          (a.nlast == 128 || a.nlast == 256 || a.nlast == 512) && ct_schedule_matches(a.ax, a.nlast / 2) &&
+          (double)a.D * (double)a.N * sizeof(T) < 4294967296.0) {
+        const int rr = 24 * kFftThreads / (a.nlast / 2 * a.D);  // ct_last_rows<nlast, D>()
         a.RR = rr;
         a.nblk = (int)((a.rows + rr - 1) / rr);
         a.total = a.nblk * p.L;
@@ -1788,14 +1788,17 @@ int last_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
             }                                                                                                     \
         } while (0)
         if (a.D == 3) {
-            if (a.nlast == 256) FEH_LAST_CT(256, 3);
+            if (a.nlast == 512) FEH_LAST_CT(512, 3);
+            else if (a.nlast == 256) FEH_LAST_CT(256, 3);
             else FEH_LAST_CT(128, 3);
         } else {
-            if (a.nlast == 256) FEH_LAST_CT(256, 2);
+            if (a.nlast == 512) FEH_LAST_CT(512, 2);
+            else if (a.nlast == 256) FEH_LAST_CT(256, 2);
             else FEH_LAST_CT(128, 2);
         }
 #undef FEH_LAST_CT
         return hip_check(hipGetLastError(), "last-axis fft launch");
+      }
     }
     const dim3 g(a.total), b(kFftThreads);
     const bool gen = !pow2_len(a.ax.n);
@@ -1844,10 +1847,10 @@ int middle_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     a.inner_total = inner;
     a.nblk = (int)((inner + PB - 1) / PB);
     a.total = a.nblk * a.n0 * p.L;
-    // compile-time transform: the default schedule of n1 = 64, 128 or 256 and
-    // the default pencil count
+    // compile-time transform: the default schedule of n1 = 64 .. 512 (a power
+    // of two) and the default pencil count
     if (p.tune_ct && p.tune_pb_mid == 0 && ct_schedule_matches(a.ax, a.n1) &&
-        (a.n1 == 64 || a.n1 == 128 || a.n1 == 256)) {
+        (a.n1 == 64 || a.n1 == 128 || a.n1 == 256 || a.n1 == 512)) {
         auto go = [&](auto kern, int nb) {
             a.nblk = (int)((inner + nb - 1) / nb);
             a.total = a.nblk * a.n0 * p.L;
@@ -1859,7 +1862,9 @@ int middle_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
         case 256: go(k_middle_ct<T, 128, false>, ct_batches<T, 128>()); break;
         case 257: go(k_middle_ct<T, 128, true>, ct_batches<T, 128>()); break;
         case 512: go(k_middle_ct<T, 256, false>, ct_batches<T, 256>()); break;
-        default: go(k_middle_ct<T, 256, true>, ct_batches<T, 256>()); break;
+        case 513: go(k_middle_ct<T, 256, true>, ct_batches<T, 256>()); break;
+        case 1024: go(k_middle_ct<T, 512, false>, ct_batches<T, 512>()); break;
+        default: go(k_middle_ct<T, 512, true>, ct_batches<T, 512>()); break;
         }
         return hip_check(hipGetLastError(), "middle-axis fft launch");
     }
@@ -1955,7 +1960,8 @@ int first_t(const feh_plan &p, const FftArgs &fa, int mode) {
         switch (a.n0) {
         case 64: hipLaunchKernelGGL((k_first_ct<T, 64, DIM>), g, b, 0, p.stream, a); break;
         case 128: hipLaunchKernelGGL((k_first_ct<T, 128, DIM>), g, b, 0, p.stream, a); break;
-        default: hipLaunchKernelGGL((k_first_ct<T, 256, DIM>), g, b, 0, p.stream, a); break;
+        case 256: hipLaunchKernelGGL((k_first_ct<T, 256, DIM>), g, b, 0, p.stream, a); break;
+        default: hipLaunchKernelGGL((k_first_ct<T, 512, DIM>), g, b, 0, p.stream, a); break;
         }
         return hip_check(hipGetLastError(), "first-axis fft launch");
     }
@@ -2001,14 +2007,14 @@ bool first_per_load_case(const feh_plan &p) {
 }
 
 // Pencils per block of the compile-time first-axis pass of the CG, or 0 when
-// the plan's shape or schedule has none: a power-of-two axis 0 of 64, 128 or
-// 256 points in the default radix order, the default layout (one workgroup
+// the plan's shape or schedule has none: a power-of-two axis 0 of 64 to 512
+// points in the default radix order, the default layout (one workgroup
 // per load case) and block size, and offsets that fit the 24-bit products
 // of the staging.
 int first_ct_pencils(const feh_plan &p) {
     const int n0 = (int)p.n[0];
     if (!p.tune_ct || p.tune_pb_first != 0 || !first_per_load_case(p)) return 0;
-    if (!(n0 == 64 || n0 == 128 || n0 == 256) || !ct_schedule_matches(p.fft[0], n0)) return 0;
+    if (!(n0 == 64 || n0 == 128 || n0 == 256 || n0 == 512) || !ct_schedule_matches(p.fft[0], n0)) return 0;
     const long long inner = p.dim == 3 ? p.n[1] * p.nh : p.nh;
     const long long rowD = inner * p.dim;
     if (rowD >= (1 << 24) || rowD * n0 >= (1ll << 31)) return 0;

@@ -578,7 +578,13 @@ __global__ __launch_bounds__((Tile<DIM, VYT>::NT)) void k_stencil(SK<T> a) {
     }
 }
 
-int xchunk(int n0) { return n0 < 32 ? n0 : 32; }
+// Planes per workgroup march: 32 in 3D; 8 in 2D, whose grids are small enough
+// that the march length (not HBM) bounds a launch once most load cases of a
+// batch have converged.
+int xchunk(int n0, int dim) {
+    const int c = dim == 3 ? 32 : 8;
+    return n0 < c ? n0 : c;
+}
 
 template <typename T, int DIM, int VYT>
 int launch_t(const feh_plan &p, int mode, const StencilArgs &sa) {
@@ -611,7 +617,7 @@ int launch_t(const feh_plan &p, int mode, const StencilArgs &sa) {
         a.vol = T(sa.unit_volume ? 0.5 : p.h[0] * p.h[1] / 2.0);
     }
     a.N = p.N;
-    a.xc = xchunk(a.n0);
+    a.xc = xchunk(a.n0, DIM);
     a.nchunk = (a.n0 + a.xc - 1) / a.xc;
     a.nty = (a.n1 + TL::SY - 1) / TL::SY;
     a.ntz = (a.n2 + TL::SZ - 1) / TL::SZ;
@@ -645,7 +651,7 @@ int stencil_rows(const feh_plan &p) {
 
 int stencil_num_parts(const feh_plan &p) {
     const int n0 = (int)p.n[0];
-    const int xc = xchunk(n0);
+    const int xc = xchunk(n0, p.dim);
     const int nchunk = (n0 + xc - 1) / xc;
     if (p.dim == 3) {
         const int sy = stencil_rows(p) - 1, sz = 31;

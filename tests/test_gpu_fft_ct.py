@@ -1,6 +1,6 @@
-"""The compile-time transforms (power-of-two axes of 64, 128 or 256 points in
-the default radix order: the middle-axis pass, the CG's fused first-axis pass
-and, in FP32, the last-axis passes of 128 or 256 points with their fused CG
+"""The compile-time transforms (power-of-two axes of 64 to 512 points in the
+default radix order: the middle-axis pass, the CG's fused first-axis pass
+and, in FP32, the last-axis passes of 128 to 512 points with their fused CG
 updates) against the run-time passes they replace, on the same plan: the CG
 solution, its iteration counts and C_eff, and the FFT export against the DFT
 definition.  Both use the same butterflies and twiddles in the same order,
@@ -34,7 +34,9 @@ def _solve(shape, lam, mu, prec, ct):
 @pytest.mark.parametrize("shape", [(64, 64, 64), (128, 64, 20), (256, 128, 12), (40, 256, 18), (64, 12, 64),
                                    (256, 90), (64, 128),
                                    # last axis of 128 / 256 points, with a partial row block (rows % 16 != 0)
-                                   (9, 7, 256), (24, 10, 128), (33, 128), (40, 256)])
+                                   (9, 7, 256), (24, 10, 128), (33, 128), (40, 256),
+                                   # 512-point axes: first, middle, last (3D and 2D)
+                                   (512, 6, 10), (5, 512, 12), (6, 9, 512), (512, 40), (21, 512), (512, 512)])
 def test_compile_time_transforms_match_runtime_passes(shape, prec):
     say("compile-time vs run-time transforms", shape, prec)
     lam, mu = random_material(shape, 17, prec)
@@ -52,7 +54,8 @@ def test_compile_time_transforms_match_runtime_passes(shape, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("shape", [(8, 64, 16), (4, 128, 8), (3, 256, 10), (5, 64, 9), (3, 5, 256), (2, 6, 128)])
+@pytest.mark.parametrize("shape", [(8, 64, 16), (4, 128, 8), (3, 256, 10), (5, 64, 9), (3, 5, 256), (2, 6, 128),
+                                   (3, 512, 6), (2, 5, 512)])
 def test_fft_with_compile_time_passes_matches_dft(shape, prec):
     import paper_2105_03297_amd as feh
     say("fft compile-time middle", shape, prec)
