@@ -468,7 +468,10 @@ struct CtDiv {
     }
 };
 
-template <typename T, int N, int NB, int DS, int S, bool INV, int TWS = 1>
+// Element j of batch b of sub-problem s sits at buf[(s N + j) NBS + b]; a
+// row stride NBS > NB (odd) spreads the lanes of a stride-NBS access over the
+// LDS banks.
+template <typename T, int N, int NB, int DS, int S, bool INV, int TWS = 1, int NBS = NB>
 __device__ __forceinline__ void ct_pass(Cx<T> *buf, const Cx<T> *tw) {
     constexpr int NT = kFftThreads;
     constexpr int R = ct_radix_at(N, S), LS = ct_lstar(N, S);
@@ -487,12 +490,12 @@ __device__ __forceinline__ void ct_pass(Cx<T> *buf, const Cx<T> *tw) {
         const int wq = CtDiv<NB, ITEMS>::div(i);  // butterfly index over all sub-problems
         const int b = i - wq * NB;
         const int w = wq & (BF - 1);
-        const int sb = (wq >> LBF) * (N * NB) + b;
+        const int sb = (wq >> LBF) * (N * NBS) + b;
         const int p = w >> LM, q = w & (M - 1);
-        const int ib = sb + (q + ((p * R) << LM)) * NB;
+        const int ib = sb + (q + ((p * R) << LM)) * NBS;
         Cx<T> x[R];
         #pragma unroll
-        for (int c = 0; c < R; ++c) x[c] = buf[ib + c * M * NB];
+        for (int c = 0; c < R; ++c) x[c] = buf[ib + c * M * NBS];
         if constexpr (LS > 1) {
             // butterflies with p = 0 multiply by the twiddle 1 (exact), so
             // the lanes of a wave take no divergent branch
@@ -503,7 +506,7 @@ __device__ __forceinline__ void ct_pass(Cx<T> *buf, const Cx<T> *tw) {
         Dft<T, R>::run(x, INV, tw, 1, N);
         #pragma unroll
         for (int d = 0; d < R; ++d) y[k][d] = x[d];
-        ob[k] = sb + (q + (p << LM)) * NB;
+        ob[k] = sb + (q + (p << LM)) * NBS;
         if (!on) ob[k] = -1;
     }
     __syncthreads();
@@ -511,26 +514,26 @@ __device__ __forceinline__ void ct_pass(Cx<T> *buf, const Cx<T> *tw) {
     for (int k = 0; k < K; ++k) {
         if (EXACT || ob[k] >= 0) {
             #pragma unroll
-            for (int d = 0; d < R; ++d) buf[ob[k] + d * (M * LS * NB)] = y[k][d];
+            for (int d = 0; d < R; ++d) buf[ob[k] + d * (M * LS * NBS)] = y[k][d];
         }
     }
     __syncthreads();
 }
 
-template <typename T, int N, int NB, int DS, int S, bool INV, int TWS>
+template <typename T, int N, int NB, int DS, int S, bool INV, int TWS, int NBS>
 __device__ __forceinline__ void ct_passes(Cx<T> *buf, const Cx<T> *tw) {
     if constexpr (S < ct_npass(N)) {
-        ct_pass<T, N, NB, DS, S, INV, TWS>(buf, tw);
-        ct_passes<T, N, NB, DS, S + 1, INV, TWS>(buf, tw);
+        ct_pass<T, N, NB, DS, S, INV, TWS, NBS>(buf, tw);
+        ct_passes<T, N, NB, DS, S + 1, INV, TWS, NBS>(buf, tw);
     }
 }
 
 // The whole transform (the buffer already staged and synchronised); the
 // twiddle table holds e^{-2 pi i j / (N TWS)} at j (TWS = 2: the table of the
 // unpacked length of a packed real transform).
-template <typename T, int N, int NB, int DS, bool INV, int TWS = 1>
+template <typename T, int N, int NB, int DS, bool INV, int TWS = 1, int NBS = NB>
 __device__ __forceinline__ void ct_fft(Cx<T> *buf, const Cx<T> *tw) {
-    ct_passes<T, N, NB, DS, 0, INV, TWS>(buf, tw);
+    ct_passes<T, N, NB, DS, 0, INV, TWS, NBS>(buf, tw);
 }
 
 // Pencils of a compile-time pass per workgroup: N NB points, 16 per thread in
@@ -812,10 +815,19 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kGe
 // into NC = NL / 2 complex points) in the default radix order, RR rows of D
 // components per workgroup (24 points per thread in FP32), the LDS tile and
 // the global layouts of k_last_fwd / k_last_inv (batch b = row D + component,
-// element j at buf[j NB + b]).  Same arithmetic in the same order.
+// element j at buf[j NBS + b], NBS = ct_last_stride).  Same arithmetic in the
+// same order.
 // ---------------------------------------------------------------------------
 template <int NL, int D>
 constexpr int ct_last_rows() { return 24 * kFftThreads / (NL / 2 * D); }
+// LDS row stride of the tile: one past the D RR batches (odd, so that the
+// transposing accesses, consecutive lanes one row apart, hit distinct banks)
+// when three workgroups still fit a CU's LDS with it, else D RR
+template <int NL, int D>
+constexpr int ct_last_stride() {
+    constexpr int NB = D * ct_last_rows<NL, D>();
+    return (NB + 1) * (NL / 2) * 8 + NL * 8 <= 160 * 1024 / 3 ? NB + 1 : NB;
+}
 
 // Element at a 32-bit byte offset from a base pointer: with the base uniform
 // the load or store takes the scalar-base form (no 64-bit address arithmetic
@@ -843,7 +855,7 @@ template <typename T, int NL, int D, bool AXPY, bool FULL>
 __device__ __forceinline__ void last_fwd_ct_body(const FK<T> &a, int lc, long long s0, int nrows, T alpha,
                                                  Cx<T> *buf, const Cx<T> *twl) {
     constexpr int NT = kFftThreads, NC = NL / 2, NH = NC + 1;
-    constexpr int RR = ct_last_rows<NL, D>(), NB = D * RR;
+    constexpr int RR = ct_last_rows<NL, D>(), NB = D * RR, NBS = ct_last_stride<NL, D>();
     constexpr int CNT = NB * NC, PPT = CNT / NT;
     constexpr int OCNT = RR * NH * D;                  // half-spectrum values of the block
     constexpr int KO = (OCNT + NT - 1) / NT;
@@ -880,11 +892,11 @@ __device__ __forceinline__ void last_fwd_ct_body(const FK<T> &a, int lc, long lo
                 v[k].y -= alpha * w[k].y;
                 if (ok) *at_byte(reinterpret_cast<Cx<T> *>(rol), last_pair_offset<T, NL, D>(c, sl, j, N32, row0)) = v[k];
             }
-            buf[j * NB + b] = ok ? v[k] : Cx<T>{T(0), T(0)};
+            buf[j * NBS + b] = ok ? v[k] : Cx<T>{T(0), T(0)};
         }
     }
     __syncthreads();
-    ct_fft<T, NC, NB, 1, false, 2>(buf, twl);
+    ct_fft<T, NC, NB, 1, false, 2, NBS>(buf, twl);
     // untangle the packed transform; half spectrum out, components fastest
     Cx<T> X[KO];
     #pragma unroll
@@ -898,7 +910,7 @@ __device__ __forceinline__ void last_fwd_ct_body(const FK<T> &a, int lc, long lo
         const int b = sl * D + c;
         const int ka = (kx == NC) ? 0 : kx;
         const int kb = (kx == 0) ? 0 : NC - kx;
-        const Cx<T> Zk = buf[ka * NB + b], Zm = cconj(buf[kb * NB + b]);
+        const Cx<T> Zk = buf[ka * NBS + b], Zm = cconj(buf[kb * NBS + b]);
         const Cx<T> A = {T(0.5) * (Zk.x + Zm.x), T(0.5) * (Zk.y + Zm.y)};
         const Cx<T> dZ = csub(Zk, Zm);
         const Cx<T> B = {T(0.5) * dZ.y, -T(0.5) * dZ.x};  // -i/2 (Zk - conj Z(nc-k))
@@ -918,7 +930,7 @@ __global__ __launch_bounds__(kFftThreads) void k_last_fwd_ct(FK<T> a) {
     constexpr int NT = kFftThreads, NC = NL / 2;
     constexpr int RR = ct_last_rows<NL, D>(), NB = D * RR;
     static_assert((NB * NC) % NT == 0, "whole slots per thread");
-    __shared__ Cx<T> buf[NB * NC];
+    __shared__ Cx<T> buf[ct_last_stride<NL, D>() * NC];
     __shared__ Cx<T> twl[NL];
     const int t = xcd_remap(blockIdx.x, a.total);
     const int lc = t / a.nblk;
@@ -939,7 +951,7 @@ template <typename T, int NL, int D, bool UPD, bool FULL>
 __device__ __forceinline__ void last_inv_ct_body(const FK<T> &a, int lc, long long s0, int nrows, Cx<T> *buf,
                                                  const Cx<T> *twl) {
     constexpr int NT = kFftThreads, NC = NL / 2, NH = NC + 1;
-    constexpr int RR = ct_last_rows<NL, D>(), NB = D * RR;
+    constexpr int RR = ct_last_rows<NL, D>(), NB = D * RR, NBS = ct_last_stride<NL, D>();
     constexpr int CNT = NB * NC, PPT = CNT / NT;
     constexpr int LNC = ct_log2(NC);
     // gather e -> (row sl, k, component c), components fastest; the packed
@@ -974,18 +986,18 @@ __device__ __forceinline__ void last_inv_ct_body(const FK<T> &a, int lc, long lo
             const Cx<T> B = cmulc(csub(xa, Xm), twl[kx]);  // exp(+2 pi i k / n) (Xk - conj X(nc-k))
             Cx<T> Z = cadd(A, mul_pi(B));
             if (!FULL && sl >= nrows) Z = Cx<T>{T(0), T(0)};
-            buf[kx * NB + sl * D + c] = Z;
+            buf[kx * NBS + sl * D + c] = Z;
         }
     }
     __syncthreads();
-    ct_fft<T, NC, NB, 1, true, 2>(buf, twl);
+    ct_fft<T, NC, NB, 1, true, 2, NBS>(buf, twl);
     const T sc = T(a.out_scale);
     Cx<T> y[PPT];
     #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int e = threadIdx.x + k * NT;
         const int b = e >> LNC, j = e & (NC - 1);
-        y[k] = buf[j * NB + b];
+        y[k] = buf[j * NBS + b];
     }
     const long long lbase = (long long)lc * D * a.N;
     const unsigned N32 = (unsigned)a.N, row0 = (unsigned)(s0 * NL);
@@ -1040,7 +1052,7 @@ __global__ __launch_bounds__(kFftThreads) void k_last_inv_ct(FK<T> a) {
     constexpr int NT = kFftThreads, NC = NL / 2;
     constexpr int RR = ct_last_rows<NL, D>(), NB = D * RR;
     static_assert((NB * NC) % NT == 0, "whole slots per thread");
-    __shared__ Cx<T> buf[NB * NC];
+    __shared__ Cx<T> buf[ct_last_stride<NL, D>() * NC];
     __shared__ Cx<T> twl[NL];
     const int t = xcd_remap(blockIdx.x, a.total);
     const int lc = t / a.nblk;
