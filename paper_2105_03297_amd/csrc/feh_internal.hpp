@@ -279,10 +279,11 @@ int launch_post_sums(const feh_plan &p, const void *u, const double *Ebar_dev, v
 int launch_grad(const feh_plan &p, const void *u, void *e);   // e = sym(B u) element field
 // g_lam, g_mu [nbatch][N] = sum over the pairs of each microstructure (l <= m,
 // weight w; pairs gofs[b] .. gofs[b+1] - 1) of the voxel's share of dW_lm/dlambda, dW_lm/dmu
-// g_E non-null: write g_E = aE g_lam + bE g_mu instead of the two fields
+// g_E non-null: write g_E = aE g_lam + bE g_mu instead of the two fields;
+// offdiag: some pair has l != m
 int launch_sensitivity(const feh_plan &p, const void *u, const double *Ebar_dev, const int *pl, const int *pm,
-                       const double *pw, const int *gofs, void *g_lam, void *g_mu, void *g_E, double aE,
-                       double bE);
+                       const double *pw, const int *gofs, bool offdiag, void *g_lam, void *g_mu, void *g_E,
+                       double aE, double bE);
 int post_num_slots(const feh_plan &p);
 
 // partial-sum sizes

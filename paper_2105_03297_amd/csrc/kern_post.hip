@@ -666,15 +666,47 @@ __global__ __launch_bounds__(kThreads) void k_post_march(PK<T> a, MarchGeom geo)
     }
 }
 
-// Workgroup (voxel tile, chunk, microstructure b): the sensitivity pairs of
-// b (see k_sens), each load case's corners read per pair from L1/L2.
+// Corner values of load case l on one node plane (in-plane corners
+// (cy, cz) = 00, 10, 01, 11 in 3D, cz = 0, 1 in 2D) at plane offset xo.
+// The plane's base address is uniform (scalar registers) and the in-plane
+// byte offsets per thread fixed, so no address is formed per plane.
 template <typename T, int DIM>
+__device__ __forceinline__ void plane_corners(const PK<T> &a, int l, uint32_t xo, const uint32_t (&ob)[4],
+                                              T (&C)[DIM == 3 ? 4 : 2][DIM]) {
+    #pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        const T *ui = a.u + ((long long)l * DIM + i) * a.N + xo;
+        #pragma unroll
+        for (int k = 0; k < (DIM == 3 ? 4 : 2); ++k)
+            C[k][i] = a.u ? *reinterpret_cast<const T *>(reinterpret_cast<const char *>(ui) + ob[k]) : T(0);
+    }
+}
+
+// Voxel corners (c = cx + 2 cy (+ 4 cz)) from the planes X (A) and X + 1 (B).
+template <typename T, int DIM>
+__device__ __forceinline__ void join_planes(const T (&A)[DIM == 3 ? 4 : 2][DIM], const T (&B)[DIM == 3 ? 4 : 2][DIM],
+                                            T (&P)[1 << DIM][DIM]) {
+    #pragma unroll
+    for (int c = 0; c < (1 << DIM); ++c)
+        #pragma unroll
+        for (int i = 0; i < DIM; ++i) P[c][i] = (c & 1) ? B[c >> 1][i] : A[c >> 1][i];
+}
+
+// Workgroup (voxel tile, chunk, microstructure b): the sensitivity pairs of
+// b (see k_sens).  Pairs outer, the chunk's planes inner: a load case's node
+// plane X + 1 is carried in registers to the next voxel plane, so each node
+// plane of a pair's load cases is read once per workgroup, and the working
+// set of a workgroup is one or two load cases' planes (L2-resident for the
+// neighbouring tiles that share its edge nodes).  The chunk's per-voxel sums
+// stay in registers (the plane loop is unrolled).  OFFDIAG: the pair list
+// holds pairs l != m (else every pair is diagonal, and the kernel keeps the
+// registers of one load case only).
+template <typename T, int DIM, bool OFFDIAG>
 __global__ __launch_bounds__(kThreads) void k_sens_march(PK<T> a, MarchGeom geo, const int *pl, const int *pm,
                                                          const double *pw, const int *gofs, double scale, T *g_lam,
                                                          T *g_mu, T *g_E, double aE, double bE) {
     using TL = MTile<DIM>;
-    constexpr int NS = DIM == 3 ? 6 : 3;
-    constexpr int NEL = DIM == 3 ? 6 : 2;
+    constexpr int NK = DIM == 3 ? 4 : 2;
     int t = xcd_remap(blockIdx.x, (int)gridDim.x);
     const int tz_t = t % geo.ntz;
     t /= geo.ntz;
@@ -684,50 +716,86 @@ __global__ __launch_bounds__(kThreads) void k_sens_march(PK<T> a, MarchGeom geo,
     const int y = ty_t * TL::VY + (DIM == 3 ? (int)threadIdx.x / TL::VZ : 0);
     const int z = tz_t * TL::VZ + (int)threadIdx.x % TL::VZ;
     if (!((DIM == 2 || y < a.n1) && z < a.n2)) return;
-    const int x0 = ch * kMarchChunk, x1 = min(x0 + kMarchChunk, a.n0);
+    const int x0 = ch * kMarchChunk, nx = min(kMarchChunk, a.n0 - x0);
     const uint32_t plane = (uint32_t)a.n1 * (uint32_t)a.n2;
     const int q0 = gofs[b], q1 = gofs[b + 1];
     ColumnCorners<DIM> cc;
     cc.init(a.n1, a.n2, DIM == 3 ? y : 0, z);
-    for (int X = x0; X < x1; ++X) {
-        const uint32_t xa = (uint32_t)X * plane, xb = (uint32_t)(X + 1 == a.n0 ? 0 : X + 1) * plane;
-        double gl = 0.0, gm = 0.0;
-        for (int q = q0; q < q1; ++q) {
-            const int l = pl[q], m = pm[q];
-            const double wq = pw[q];
-            T Pl[1 << DIM][DIM];
-            if (a.u)
-                column_corners<T, DIM>(a, l, xa, xb, cc, Pl);
-            else
-                for_corners_zero<T, DIM>(Pl);
-            // the voxel's element sums in the plan precision T, the pairs in FP64
-            T sl = T(0), se = T(0);
-            if (m == l) {
-                // (tr e)^2 and e : e over the elements
-                T Ebl[DIM][DIM];
-                ebar_full<DIM>(a.Ebar, l, Ebl);
-                self_sums<T, T, DIM>(Pl, a.ih, Ebl, sl, se);
-            } else {
-                T Ebl[DIM][DIM], Ebm[DIM][DIM];
-                ebar_full<DIM>(a.Ebar, l, Ebl);
-                ebar_full<DIM>(a.Ebar, m, Ebm);
-                T Pm[1 << DIM][DIM];
-                if (a.u)
-                    column_corners<T, DIM>(a, m, xa, xb, cc, Pm);
-                else
-                    for_corners_zero<T, DIM>(Pm);
-                // tr e tr f and e : f over the elements of both load cases
-                pair_sums<T, T, DIM>(Pl, Pm, a.ih, Ebl, Ebm, sl, se);
+    uint32_t ob[4];  // in-plane byte offsets (n1 n2 sizeof(T) < 2^32: checked by the launcher)
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) ob[k] = cc.o[k] * (uint32_t)sizeof(T);
+    double gl[kMarchChunk], gm[kMarchChunk];
+    #pragma unroll
+    for (int k = 0; k < kMarchChunk; ++k) gl[k] = gm[k] = 0.0;
+    // the voxel's element sums in the plan precision T, the pairs in FP64
+    for (int q = q0; q < q1; ++q) {
+        const int l = pl[q], m = pm[q];
+        const double wq = pw[q];
+        T Ebl[DIM][DIM];
+        ebar_full<DIM>(a.Ebar, l, Ebl);
+        T Al[NK][DIM];
+        plane_corners<T, DIM>(a, l, (uint32_t)x0 * plane, ob, Al);
+        if (!OFFDIAG || m == l) {
+            // (tr e)^2 and e : e over the elements
+            #pragma unroll
+            for (int k = 0; k < kMarchChunk; ++k) {
+                if (k < nx) {
+                    const int X1 = x0 + k + 1 == a.n0 ? 0 : x0 + k + 1;
+                    T Bl[NK][DIM], P[1 << DIM][DIM];
+                    plane_corners<T, DIM>(a, l, (uint32_t)X1 * plane, ob, Bl);
+                    join_planes<T, DIM>(Al, Bl, P);
+                    T sl = T(0), se = T(0);
+                    self_sums<T, T, DIM>(P, a.ih, Ebl, sl, se);
+                    gl[k] += wq * double(sl);
+                    gm[k] += 2.0 * wq * double(se);
+                    #pragma unroll
+                    for (int c = 0; c < NK; ++c)
+                        #pragma unroll
+                        for (int i = 0; i < DIM; ++i) Al[c][i] = Bl[c][i];
+                }
+                __builtin_amdgcn_sched_barrier(0);  // keep later planes' loads out of this step (registers)
             }
-            gl += wq * double(sl);
-            gm += 2.0 * wq * double(se);
+        } else if constexpr (OFFDIAG) {
+            // tr e tr f and e : f over the elements of both load cases
+            T Ebm[DIM][DIM];
+            ebar_full<DIM>(a.Ebar, m, Ebm);
+            T Am[NK][DIM];
+            plane_corners<T, DIM>(a, m, (uint32_t)x0 * plane, ob, Am);
+            #pragma unroll
+            for (int k = 0; k < kMarchChunk; ++k) {
+                if (k < nx) {
+                    const int X1 = x0 + k + 1 == a.n0 ? 0 : x0 + k + 1;
+                    T Bl[NK][DIM], Bm[NK][DIM], Pl[1 << DIM][DIM], Pm[1 << DIM][DIM];
+                    plane_corners<T, DIM>(a, l, (uint32_t)X1 * plane, ob, Bl);
+                    plane_corners<T, DIM>(a, m, (uint32_t)X1 * plane, ob, Bm);
+                    join_planes<T, DIM>(Al, Bl, Pl);
+                    join_planes<T, DIM>(Am, Bm, Pm);
+                    T sl = T(0), se = T(0);
+                    pair_sums<T, T, DIM>(Pl, Pm, a.ih, Ebl, Ebm, sl, se);
+                    gl[k] += wq * double(sl);
+                    gm[k] += 2.0 * wq * double(se);
+                    #pragma unroll
+                    for (int c = 0; c < NK; ++c)
+                        #pragma unroll
+                        for (int i = 0; i < DIM; ++i) {
+                            Al[c][i] = Bl[c][i];
+                            Am[c][i] = Bm[c][i];
+                        }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
-        const long long v = (long long)b * a.N + xa + cc.o[0];
-        if (g_E) {
-            g_E[v] = T((aE * gl + bE * gm) * scale);
-        } else {
-            g_lam[v] = T(gl * scale);
-            g_mu[v] = T(gm * scale);
+    }
+    #pragma unroll
+    for (int k = 0; k < kMarchChunk; ++k) {
+        if (k < nx) {
+            const long long v = (long long)b * a.N + (uint32_t)(x0 + k) * plane + cc.o[0];
+            if (g_E) {
+                g_E[v] = T((aE * gl[k] + bE * gm[k]) * scale);
+            } else {
+                g_lam[v] = T(gl[k] * scale);
+                g_mu[v] = T(gm[k] * scale);
+            }
         }
     }
 }
@@ -767,7 +835,11 @@ PK<T> post_args(const feh_plan &p) {
 }  // namespace
 
 // Does the plan take the plane-marching post-processing?
-static bool march_ok(const feh_plan &p) { return p.G <= kMarchG; }
+static bool march_ok(const feh_plan &p) {
+    const double plane_bytes = (p.dim == 3 ? (double)p.n[1] * (double)p.n[2] : (double)p.n[1]) *
+                               (p.prec == FEH_FP64 ? 8.0 : 4.0);
+    return p.G <= kMarchG && plane_bytes < 4294967296.0;
+}
 
 int post_num_parts(const feh_plan &p) {
     long long b = (p.N + kThreads - 1) / kThreads;
@@ -852,7 +924,7 @@ int launch_grad(const feh_plan &p, const void *u, void *e) {
 
 template <typename T>
 static int sens_t(const feh_plan &p, const void *u, const double *Ebar, const int *pl, const int *pm, const double *pw,
-                  const int *gofs, void *g_lam, void *g_mu, void *g_E, double aE, double bE) {
+                  const int *gofs, bool offdiag, void *g_lam, void *g_mu, void *g_E, double aE, double bE) {
     PK<T> a = post_args<T>(p);
     a.u = static_cast<const T *>(u);
     a.Ebar = Ebar;
@@ -863,12 +935,17 @@ static int sens_t(const feh_plan &p, const void *u, const double *Ebar, const in
     if (march_ok(p)) {
         const MarchGeom geo = p.dim == 3 ? march_geom<3>(p) : march_geom<2>(p);
         dim3 grid(geo.nty * geo.ntz * geo.nchunk, p.nbatch);
-        if (p.dim == 3)
-            hipLaunchKernelGGL((k_sens_march<T, 3>), grid, dim3(kThreads), 0, p.stream, a, geo, pl, pm, pw, gofs,
-                               scale, static_cast<T *>(g_lam), static_cast<T *>(g_mu), static_cast<T *>(g_E), aE, bE);
-        else
-            hipLaunchKernelGGL((k_sens_march<T, 2>), grid, dim3(kThreads), 0, p.stream, a, geo, pl, pm, pw, gofs,
-                               scale, static_cast<T *>(g_lam), static_cast<T *>(g_mu), static_cast<T *>(g_E), aE, bE);
+#define FEH_SENS(DV, OD)                                                                                     \
+        hipLaunchKernelGGL((k_sens_march<T, DV, OD>), grid, dim3(kThreads), 0, p.stream, a, geo, pl, pm, pw, gofs, \
+                           scale, static_cast<T *>(g_lam), static_cast<T *>(g_mu), static_cast<T *>(g_E), aE, bE)
+        if (p.dim == 3) {
+            if (offdiag) FEH_SENS(3, true);
+            else FEH_SENS(3, false);
+        } else {
+            if (offdiag) FEH_SENS(2, true);
+            else FEH_SENS(2, false);
+        }
+#undef FEH_SENS
         return hip_check(hipGetLastError(), "sensitivity launch");
     }
     if (p.dim == 3)
@@ -881,9 +958,10 @@ static int sens_t(const feh_plan &p, const void *u, const double *Ebar, const in
 }
 
 int launch_sensitivity(const feh_plan &p, const void *u, const double *Ebar_dev, const int *pl, const int *pm,
-                       const double *pw, const int *gofs, void *g_lam, void *g_mu, void *g_E, double aE, double bE) {
-    return p.prec == FEH_FP64 ? sens_t<double>(p, u, Ebar_dev, pl, pm, pw, gofs, g_lam, g_mu, g_E, aE, bE)
-                              : sens_t<float>(p, u, Ebar_dev, pl, pm, pw, gofs, g_lam, g_mu, g_E, aE, bE);
+                       const double *pw, const int *gofs, bool offdiag, void *g_lam, void *g_mu, void *g_E, double aE,
+                       double bE) {
+    return p.prec == FEH_FP64 ? sens_t<double>(p, u, Ebar_dev, pl, pm, pw, gofs, offdiag, g_lam, g_mu, g_E, aE, bE)
+                              : sens_t<float>(p, u, Ebar_dev, pl, pm, pw, gofs, offdiag, g_lam, g_mu, g_E, aE, bE);
 }
 
 }  // namespace feh

@@ -34,11 +34,11 @@ def test_circle32_fp64_matches_oracle():
     ref = fe.homogenize(m.E, m.nu, Eb)
     assert out["status"] == 0
     assert rel(out["C_eff"], ref["C_eff"]) < 1e-10
-    for l in range(3):
-        assert rel(out["stress_mean"][l], ref["sig_mean"][l]) < 1e-10
-        assert rel(out["strain"][l], ref["eps"][l]) < 1e-9
-        assert rel(out["stress"][l], ref["sig"][l]) < 1e-9
-        assert rel(out["u"][l], ref["u"][l]) < 1e-9
+    errs = {k: max(rel(out[k][l], ref[r][l]) for l in range(3))
+            for k, r in (("stress_mean", "sig_mean"), ("strain", "eps"), ("stress", "sig"), ("u", "u"))}
+    print("circle32 fp64 tol 1e-12, max rel err over the load cases:", errs)
+    for k, e in errs.items():
+        assert e < 1e-10, (k, e)
     np.testing.assert_allclose(out["energy"], out["energy"].T, rtol=0, atol=1e-15)
 
 
@@ -54,7 +54,9 @@ def test_circle32_iterations_at_paper_tolerance():
     assert 30 <= it <= 55, it
     assert out["report"][0]["rel_residual"] <= tol
     ref = fe.homogenize(m.E, m.nu, Eb)
-    assert rel(out["stress_mean"][0], ref["sig_mean"][0]) < 1e-9
+    e = rel(out["stress_mean"][0], ref["sig_mean"][0])
+    print("circle32 fp64 tol 1e-10: <sigma> rel err %.3e" % e)
+    assert e < 1e-10
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
