@@ -36,15 +36,19 @@ PEAK_FP32_NOPACK_TFLOPS = 78.6
 STENCIL_FLOPS = {2: 60.0, 3: 400.0}
 
 
-def kernel_bytes(dim, s, n_last, iters, n_voxels):
+def kernel_bytes(dim, s, n_last, iters, n_voxels, residual_spectral=False):
     """Algorithmic HBM bytes of every CG kernel over one solve.
 
     Per voxel and active load case (V = D s for a nodal vector, Vh = D 2 s
     (n_last/2+1)/n_last for the half spectrum):
       stencil      read p, write q: 2V; plus the (lambda, mu) material once
                    per launch: 2 s per voxel
-      last fwd     read r, q; write r and the half spectrum: 3V + Vh
-      middle       read + write the spectrum: 2 Vh (each direction, 3D)
+      last fwd     read r, q; write r and the half spectrum: 3V + Vh; with the
+                   residual kept as a last-axis half spectrum (the library's
+                   feh_plan_cg_residual_spectral): read q, read and write the
+                   spectral residual: V + 2 Vh
+      middle       read + write the spectrum: 2 Vh (each direction, 3D; the
+                   forward one reads the spectral residual when it is kept)
       first+solve  read + write the spectrum: 2 Vh
       last inv     read the spectrum, p and u; write p and u: Vh + 4V
     The inverse passes do not run in the iteration at which a load case
@@ -57,7 +61,7 @@ def kernel_bytes(dim, s, n_last, iters, n_voxels):
     launches = float(max(iters)) if iters else 0.0
     out = {
         "stencil": lc_it * 2 * V * n_voxels + launches * 2 * s * n_voxels,
-        "fft_last_fwd": lc_it * (3 * V + Vh) * n_voxels,
+        "fft_last_fwd": lc_it * ((V + 2 * Vh) if residual_spectral else (3 * V + Vh)) * n_voxels,
         "fft_first_ksolve": lc_it * 2 * Vh * n_voxels,
         "fft_last_inv": (lc_it - stops) * (Vh + 4 * V) * n_voxels,
     }
@@ -428,8 +432,9 @@ def main():
     # roofline of the dominant kernel (live HIP events around each launch)
     s = 4 if precname == "fp32" else 8
     kb = {k: 0.0 for k in feh.PROFILE_KINDS}
+    rspec = feh.feh_plan_cg_residual_spectral(hz.plan)
     for its in iters_all:
-        for k, v in kernel_bytes(dim, s, shape[-1], its, N).items():
+        for k, v in kernel_bytes(dim, s, shape[-1], its, N, rspec).items():
             kb[k] += v
     if args.copy_ref:
         xs = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -605,6 +610,7 @@ def main():
         "kernels": kernels,
         "sensitivity": sens,
         "fft_schedule": tuning,
+        "cg_residual_spectral": rspec,
         "uneven_batch": uneven,
         "strain_space": strain,
         "finite_strain": finite,

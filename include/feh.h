@@ -254,6 +254,16 @@ int feh_plan_tuning(const feh_plan *plan, int *values, int n_values);
  * rounding. */
 int feh_plan_set_tuning(feh_plan *plan, const int *values, int n_values);
 
+/* Whether the plan's CG, with its current schedule, keeps the residual as its
+ * last-axis half spectrum (1) or as a real field (0); negative on a null
+ * plan.  3D FP32 plans whose last-axis passes take the compile-time
+ * transform keep it as a half spectrum: the forward last-axis pass then
+ * transforms q and updates the spectral residual in place (the transform is
+ * linear), and the forward middle pass reads it into the spectrum, which
+ * saves about one nodal vector of HBM traffic per iteration.  Both forms give
+ * the same iterates up to rounding.  A host-side query for byte accounting. */
+int feh_plan_cg_residual_spectral(const feh_plan *plan);
+
 /* Uneven batches: plans of different grids (each possibly a batched plan),
  * each on a created HIP stream (plans may share one), solved together.
  * Plans on different streams run concurrently: eagerly each plan's kernels

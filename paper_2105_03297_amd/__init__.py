@@ -26,7 +26,7 @@ __all__ = [
     "feh_apply_operator", "feh_apply_preconditioner", "feh_apply_projection",
     "feh_fft_forward", "feh_fft_inverse", "feh_profile_enable", "feh_profile_read", "feh_stream_copy", "PROFILE_KINDS",
     "feh_batch_create", "feh_batch_destroy", "feh_batch_solve", "feh_batch_graph_launches",
-    "feh_plan_autotune", "feh_plan_tuning", "feh_plan_set_tuning",
+    "feh_plan_autotune", "feh_plan_tuning", "feh_plan_set_tuning", "feh_plan_cg_residual_spectral",
     "FEH_DERIV_FE", "FEH_DERIV_FD", "FEH_DERIV_CD", "FEH_DERIV_LS", "FEH_DERIV_FOURIER", "FEH_DERIV_FOURIER2",
     "DERIV_KINDS", "feh_strain_cg_points", "feh_strain_cg_workspace_bytes", "feh_strain_cg_solve",
     "feh_finite_report", "feh_finite_strain_workspace_bytes", "feh_finite_strain_solve",
@@ -117,6 +117,7 @@ _SIGS = {
                                        ctypes.POINTER(_dp), ctypes.POINTER(_dp), ctypes.POINTER(ctypes.POINTER(feh_report))]),
     "feh_batch_graph_launches": (ctypes.c_int, [_vp]),
     "feh_plan_autotune": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "feh_plan_cg_residual_spectral": (ctypes.c_int, [_vp]),
     "feh_plan_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "feh_plan_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "feh_strain_cg_points": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
@@ -347,6 +348,14 @@ def feh_batch_graph_launches(batch):
 
 def feh_plan_autotune(plan, reps=3):
     return _check(load().feh_plan_autotune(plan, int(reps)))
+
+
+def feh_plan_cg_residual_spectral(plan):
+    """True when the plan's CG keeps its residual as a last-axis half spectrum."""
+    rc = load().feh_plan_cg_residual_spectral(plan)
+    if rc < 0:
+        raise FehError(rc, feh_last_error())
+    return bool(rc)
 
 
 def feh_plan_tuning(plan):

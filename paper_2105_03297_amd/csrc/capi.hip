@@ -124,7 +124,8 @@ static void layout(feh_plan &p) {
         return at;
     };
     p.off_u = take(vec);
-    p.off_r = take(vec);
+    // r: a real field, or in the CG of cg_residual_spectral its last-axis half spectrum
+    p.off_r = take(std::max(vec, (size_t)p.L * p.dim * p.Nspec * 2 * p.rsize));
     p.off_p = take(vec);
     p.off_q = take(vec);
     p.off_spec = take((size_t)p.L * p.dim * p.Nspec * 2 * p.rsize);
@@ -264,18 +265,25 @@ static int read_flag(feh_plan &p, int *flag_dev, const char *what) {
 
 // z = M^+ r on SoA fields (spectrum buffer as scratch); Parseval r.z partials.
 // r is consumed by the first pass, so z may be the same buffer.
+// z = M^+ r.  rhat non-null (3D): the last-axis half spectrum of r is written
+// there and kept (the forward middle pass reads it into the spectrum).
 static int precondition(const feh_plan &p, const void *r, void *z, double *partial, const LcState *st,
-                        bool unit_volume) {
+                        bool unit_volume, void *rhat = nullptr) {
     FftArgs fa;
     fa.unit_volume = unit_volume;
     fa.r = r;
-    fa.spec = p.ws + p.off_spec;
+    fa.spec = rhat ? rhat : p.ws + p.off_spec;
     fa.z = z;
     fa.partial = partial;
     fa.state = st;
     fa.out_scale = 1.0 / (double)p.N;
     CK(launch_forward_last(p, fa));
-    if (p.dim == 3) CK(launch_middle(p, fa, false));
+    fa.spec = p.ws + p.off_spec;
+    if (p.dim == 3) {
+        FftArgs fm = fa;
+        fm.spec_in = rhat;
+        CK(launch_middle(p, fm, false));
+    }
     CK(launch_first_fused(p, fa));
     if (p.dim == 3) CK(launch_middle(p, fa, true));
     return launch_inverse_last(p, fa);
@@ -349,13 +357,26 @@ static int cg_iteration(const feh_plan &p, LcState *st, double tol, int max_iter
     fa.state = st;
     fa.out_scale = 1.0 / (double)p.N;
     fa.unit_volume = true;
+    // residual kept as a last-axis half spectrum r^ (3D): the forward last
+    // pass transforms q and updates r^ -= alpha q^ in place (the FFT is
+    // linear), and the forward middle pass reads r^ into the spectrum
+    const bool rs = cg_residual_spectral(p);
     {
         ProfScope ps(p, 2);
-        CK(launch_forward_last(p, fa));
+        FftArgs fl = fa;
+        if (rs) {
+            fl.r = nullptr;
+            fl.r_out = nullptr;
+            fl.spec = p.ws + p.off_r;
+            fl.rspec = true;
+        }
+        CK(launch_forward_last(p, fl));
     }
     if (p.dim == 3) {
         ProfScope ps(p, 3);
-        CK(launch_middle(p, fa, false));
+        FftArgs fm = fa;
+        if (rs) fm.spec_in = p.ws + p.off_r;
+        CK(launch_middle(p, fm, false));
     }
     {
         ProfScope ps(p, 4);
@@ -661,10 +682,12 @@ static int solve_begin(feh_plan &p, const double *Ebar_host, double tol, int max
         CK(launch_fill(p, p.ws + p.off_u, nvec, 0.0));
         sa.in0 = nullptr;
     }
-    // r = f - K u0, first search direction p = M^+ r
-    sa.out0 = p.ws + p.off_r;
+    // r = f - K u0, first search direction p = M^+ r; with the residual kept
+    // as a last-axis half spectrum, r goes through q and its spectrum to r's place
+    const bool rs = cg_residual_spectral(p);
+    sa.out0 = p.ws + (rs ? p.off_q : p.off_r);
     CK(launch_stencil(p, ST_RESID, sa));
-    CK(precondition(p, p.ws + p.off_r, p.ws + p.off_p, part, nullptr, true));
+    CK(precondition(p, sa.out0, p.ws + p.off_p, part, nullptr, true, rs ? p.ws + p.off_r : nullptr));
     return launch_finish_rho(p, st, part, first_num_parts(p), u0_dev ? 1 : 11, tol, max_iter);
 }
 
@@ -1207,6 +1230,11 @@ int feh_plan_set_tuning(feh_plan *plan, const int *values, int n_values) {
     } catch (...) {
         return set_error(FEH_EINVAL, "unexpected host exception");
     }
+}
+
+int feh_plan_cg_residual_spectral(const feh_plan *plan) {
+    if (!plan) return set_error(FEH_EINVAL, "null plan");
+    return cg_residual_spectral(*plan) ? 1 : 0;
 }
 
 int feh_plan_tuning(const feh_plan *plan, int *values, int n_values) {

@@ -364,6 +364,7 @@ struct FK {
     const T *q;
     T *r_out;
     Cx<T> *spec;
+    const Cx<T> *spec_in;     // middle pass: read from here, write spec (null: in place)
     T *z;
     T *p_upd;                 // fused CG update in the last inverse pass
     T *u_upd;
@@ -851,7 +852,10 @@ __device__ __forceinline__ unsigned last_pair_offset(int c, int sl, int j, unsig
     return (cb + row0 + (unsigned)(sl * NL + 2 * j)) * (unsigned)sizeof(T);
 }
 
-template <typename T, int NL, int D, bool AXPY, bool FULL>
+// MODE 0: r -> half spectrum; MODE 1 (AXPY): r -= alpha q, r written back, its
+// half spectrum written; MODE 2 (RSPEC): the half spectrum of q, and the
+// residual kept as a half spectrum updated in place, spec -= alpha q^.
+template <typename T, int NL, int D, int MODE, bool FULL>
 __device__ __forceinline__ void last_fwd_ct_body(const FK<T> &a, int lc, long long s0, int nrows, T alpha,
                                                  Cx<T> *buf, const Cx<T> *twl) {
     constexpr int NT = kFftThreads, NC = NL / 2, NH = NC + 1;
@@ -861,7 +865,8 @@ __device__ __forceinline__ void last_fwd_ct_body(const FK<T> &a, int lc, long lo
     constexpr int KO = (OCNT + NT - 1) / NT;
     constexpr int LNC = ct_log2(NC);
     const long long lbase = (long long)lc * D * a.N;
-    const T *rl = a.r + lbase;
+    constexpr bool AXPY = MODE == 1;
+    const T *rl = MODE == 2 ? a.q + lbase : a.r + lbase;  // the transformed field
     const T *ql = AXPY ? a.q + lbase : nullptr;
     T *rol = AXPY ? a.r_out + lbase : nullptr;
     const unsigned N32 = (unsigned)a.N, row0 = (unsigned)(s0 * NL);
@@ -918,14 +923,32 @@ __device__ __forceinline__ void last_fwd_ct_body(const FK<T> &a, int lc, long lo
     }
     Cx<T> *dst = a.spec + ((long long)lc * a.rows + s0) * (long long)NH * D;
     const int ocnt = FULL ? OCNT : nrows * NH * D;
-    #pragma unroll
-    for (int k = 0; k < KO; ++k) {
-        const int e0 = threadIdx.x + k * NT;
-        if ((FULL && (OCNT % NT == 0 || k + 1 < KO)) || e0 < ocnt) *at_byte(dst, (unsigned)e0 * (unsigned)sizeof(Cx<T>)) = X[k];
+    if constexpr (MODE == 2) {
+        // every load before the first store
+        Cx<T> R[KO];
+        #pragma unroll
+        for (int k = 0; k < KO; ++k) {
+            const int e0 = threadIdx.x + k * NT;
+            const int e = ((FULL && (OCNT % NT == 0 || k + 1 < KO)) || e0 < ocnt) ? e0 : 0;
+            R[k] = *at_byte(dst, (unsigned)e * (unsigned)sizeof(Cx<T>));
+        }
+        #pragma unroll
+        for (int k = 0; k < KO; ++k) {
+            const int e0 = threadIdx.x + k * NT;
+            if ((FULL && (OCNT % NT == 0 || k + 1 < KO)) || e0 < ocnt)
+                *at_byte(dst, (unsigned)e0 * (unsigned)sizeof(Cx<T>)) =
+                    Cx<T>{R[k].x - alpha * X[k].x, R[k].y - alpha * X[k].y};
+        }
+    } else {
+        #pragma unroll
+        for (int k = 0; k < KO; ++k) {
+            const int e0 = threadIdx.x + k * NT;
+            if ((FULL && (OCNT % NT == 0 || k + 1 < KO)) || e0 < ocnt) *at_byte(dst, (unsigned)e0 * (unsigned)sizeof(Cx<T>)) = X[k];
+        }
     }
 }
 
-template <typename T, int NL, int D, bool AXPY>
+template <typename T, int NL, int D, int MODE>
 __global__ __launch_bounds__(kFftThreads) void k_last_fwd_ct(FK<T> a) {
     constexpr int NT = kFftThreads, NC = NL / 2;
     constexpr int RR = ct_last_rows<NL, D>(), NB = D * RR;
@@ -938,13 +961,13 @@ __global__ __launch_bounds__(kFftThreads) void k_last_fwd_ct(FK<T> a) {
     T alpha = T(0);
     if (a.st) {
         if (!a.st[lc].active) return;
-        if (AXPY) alpha = T(a.st[lc].alpha);
+        if (MODE != 0) alpha = T(a.st[lc].alpha);
     }
     const long long s0 = (long long)blk * RR;
     const int nrows = (int)min((long long)RR, a.rows - s0);
     for (int i = threadIdx.x; i < NL; i += NT) twl[i] = a.tw_last[i];
-    if (nrows == RR) last_fwd_ct_body<T, NL, D, AXPY, true>(a, lc, s0, nrows, alpha, buf, twl);
-    else last_fwd_ct_body<T, NL, D, AXPY, false>(a, lc, s0, nrows, alpha, buf, twl);
+    if (nrows == RR) last_fwd_ct_body<T, NL, D, MODE, true>(a, lc, s0, nrows, alpha, buf, twl);
+    else last_fwd_ct_body<T, NL, D, MODE, false>(a, lc, s0, nrows, alpha, buf, twl);
 }
 
 template <typename T, int NL, int D, bool UPD, bool FULL>
@@ -1085,7 +1108,9 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kGe
     const int cnt = PB * n1;
     const long long inner = a.inner_total;
     const long long in0 = (long long)ib * PB;
-    Cx<T> *base = a.spec + ((long long)lc * a.n0 + i0) * n1 * inner + in0;
+    const long long boff = ((long long)lc * a.n0 + i0) * n1 * inner + in0;
+    Cx<T> *base = a.spec + boff;
+    const Cx<T> *src = (a.spec_in ? a.spec_in : a.spec) + boff;
     const int lim = (int)min((long long)PB, inner - in0);
     Cx<T> *twl = GEN ? buf + a.lbuf : reinterpret_cast<Cx<T> *>(feh_dyn_lds);
     stage(twl, a.tw, n1);
@@ -1096,7 +1121,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kGe
         const int e = e0 < cnt ? e0 : 0;
         const int j = (int)a.d_PB.div((uint32_t)e);
         const int b = e - j * PB;
-        v[k] = base[(long long)j * inner + (b < lim ? b : lim - 1)];
+        v[k] = src[(long long)j * inner + (b < lim ? b : lim - 1)];
     }
     #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -1140,7 +1165,9 @@ __global__ __launch_bounds__(kFftThreads) void k_middle_ct(FK<T> a) {
     if (a.st && !a.st[lc].active) return;
     const unsigned inner = (unsigned)a.inner_total;
     const unsigned in0 = (unsigned)ib * NB;
-    Cx<T> *base = a.spec + ((long long)lc * a.n0 + i0) * (long long)N * inner + in0;
+    const long long boff = ((long long)lc * a.n0 + i0) * (long long)N * inner + in0;
+    Cx<T> *base = a.spec + boff;
+    const Cx<T> *src = (a.spec_in ? a.spec_in : a.spec) + boff;
     const int lim = min(NB, (int)(inner - in0));
     for (int i = threadIdx.x; i < N; i += NT) twl[i] = a.tw[i];
     Cx<T> v[PPT];
@@ -1148,7 +1175,7 @@ __global__ __launch_bounds__(kFftThreads) void k_middle_ct(FK<T> a) {
     for (int k = 0; k < PPT; ++k) {
         const int e = threadIdx.x + k * NT;
         const int j = e >> LNB, b = e & (NB - 1);
-        v[k] = base[__umul24((unsigned)j, inner) + (unsigned)(b < lim ? b : lim - 1)];
+        v[k] = src[__umul24((unsigned)j, inner) + (unsigned)(b < lim ? b : lim - 1)];
     }
     #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -1696,6 +1723,7 @@ FK<T> base_args(const feh_plan &p, const FftArgs &fa) {
     a.q = static_cast<const T *>(fa.q);
     a.r_out = static_cast<T *>(fa.r_out);
     a.spec = static_cast<Cx<T> *>(fa.spec);
+    a.spec_in = static_cast<const Cx<T> *>(fa.spec_in);
     a.z = static_cast<T *>(fa.z);
     a.p_upd = static_cast<T *>(fa.p_upd);
     a.u_upd = static_cast<T *>(fa.u_upd);
@@ -1755,6 +1783,22 @@ size_t lds_of_pass(bool gen, int cnt, int table, int *lbuf, size_t *dyn) {
     return stat + *dyn;
 }
 
+}  // namespace
+
+// The last-axis passes of a plan take the compile-time transform: FP32, an
+// even last axis of 128, 256 or 512 points in the default radix order, the
+// default row count, D = 2 or 3 components, 32-bit byte offsets.
+bool last_ct_ok(const feh_plan &p, int D) {
+    const int nlast = (int)p.n[p.dim - 1];
+    return p.prec == FEH_FP32 && p.tune_ct && p.tune_rr_last == 0 && p.last_even && (D == 3 || D == 2) &&
+           (nlast == 128 || nlast == 256 || nlast == 512) && ct_schedule_matches(p.fft[p.dim - 1], nlast / 2) &&
+           (double)D * (double)p.N * 4.0 < 4294967296.0;
+}
+
+bool cg_residual_spectral(const feh_plan &p) { return p.dim == 3 && last_ct_ok(p, 3); }
+
+namespace {
+
 template <typename T>
 int last_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     constexpr int PPT = ppt<T>();
@@ -1774,13 +1818,13 @@ int last_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
     a.d_nc = FastDiv::make((uint32_t)nc);
     a.nblk = (int)((a.rows + RR - 1) / RR);
     a.total = a.nblk * p.L;
-    a.use_axpy = (!inverse && fa.q != nullptr && fa.state != nullptr) ? 1 : 0;
+    a.use_axpy = (!inverse && fa.q != nullptr && fa.state != nullptr) ? (fa.rspec ? 2 : 1) : 0;
+    if (fa.rspec && (inverse || a.use_axpy != 2 || !last_ct_ok(p, a.D)))
+        return set_error(FEH_EINVAL, "the spectral residual update needs the compile-time last-axis pass");
     // compile-time transform: FP32, 3D (or 2D) with an even last axis of 128,
     // 256 or 512 points in the default radix order and the default row count
     if constexpr (sizeof(T) == 4) {
-      if (p.tune_ct && p.tune_rr_last == 0 && p.last_even && (a.D == 3 || a.D == 2) &&
-          (a.nlast == 128 || a.nlast == 256 || a.nlast == 512) && ct_schedule_matches(a.ax, a.nlast / 2) &&
-          (double)a.D * (double)a.N * sizeof(T) < 4294967296.0) {
+      if (last_ct_ok(p, a.D)) {
         const int rr = 24 * kFftThreads / (a.nlast / 2 * a.D);  // ct_last_rows<nlast, D>()
         a.RR = rr;
         a.nblk = (int)((a.rows + rr - 1) / rr);
@@ -1795,8 +1839,9 @@ int last_t(const feh_plan &p, const FftArgs &fa, bool inverse) {
                 if (upd) hipLaunchKernelGGL((k_last_inv_ct<T, NLv, Dv, true>), g, b, 0, p.stream, a);             \
                 else hipLaunchKernelGGL((k_last_inv_ct<T, NLv, Dv, false>), g, b, 0, p.stream, a);                \
             } else {                                                                                              \
-                if (a.use_axpy) hipLaunchKernelGGL((k_last_fwd_ct<T, NLv, Dv, true>), g, b, 0, p.stream, a);      \
-                else hipLaunchKernelGGL((k_last_fwd_ct<T, NLv, Dv, false>), g, b, 0, p.stream, a);                \
+                if (a.use_axpy == 2) hipLaunchKernelGGL((k_last_fwd_ct<T, NLv, Dv, 2>), g, b, 0, p.stream, a);    \
+                else if (a.use_axpy) hipLaunchKernelGGL((k_last_fwd_ct<T, NLv, Dv, 1>), g, b, 0, p.stream, a);    \
+                else hipLaunchKernelGGL((k_last_fwd_ct<T, NLv, Dv, 0>), g, b, 0, p.stream, a);                    \
             }                                                                                                     \
         } while (0)
         if (a.D == 3) {

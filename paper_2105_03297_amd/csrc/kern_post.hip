@@ -342,11 +342,11 @@ template <int DIM>
 struct MTile;
 template <>
 struct MTile<3> {
-    static constexpr int VY = 8, VZ = 32, EY = 9, EZ = 33;
+    static constexpr int VY = 8, VZ = 32;
 };
 template <>
 struct MTile<2> {
-    static constexpr int VY = 1, VZ = 256, EY = 1, EZ = 257;
+    static constexpr int VY = 1, VZ = 256;
 };
 
 struct MarchGeom {
@@ -417,7 +417,7 @@ __device__ __forceinline__ void element_grad(const T (&P)[1 << DIM][DIM], const 
     #pragma unroll
     for (int ax = 0; ax < DIM; ++ax) {
         const int c0 = DIM == 3 ? BASE3[TT][ax] : BASE2[TT][ax];
-        const int c1 = c0 | (DIM == 3 ? 1 << ax : 1 << ax);
+        const int c1 = c0 | (1 << ax);  // corner bit of axis ax: 3D c = cx + 2 cy + 4 cz, 2D c = cx + 2 cz
         #pragma unroll
         for (int i = 0; i < DIM; ++i) g[i][ax] = fma(R(P[c1][i] - P[c0][i]), R(ih[ax]), Eb[i][ax]);
     }

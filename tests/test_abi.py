@@ -63,6 +63,33 @@ def test_prime_sizes_factorise(n, passes):
     feh.feh_plan_destroy(p)
 
 
+def test_cg_residual_form_follows_the_schedule():
+    """The CG keeps its residual as a last-axis half spectrum exactly when the
+    last-axis passes take the compile-time transform in a 3D FP32 plan."""
+    cases = [((64, 32, 256), feh.FEH_FP32, True), ((16, 8, 128), feh.FEH_FP32, True),
+             ((8, 8, 512), feh.FEH_FP32, True), ((64, 64, 64), feh.FEH_FP32, False),
+             ((16, 8, 256), feh.FEH_FP64, False), ((64, 256), feh.FEH_FP32, False),
+             ((16, 8, 250), feh.FEH_FP32, False)]
+    for n, prec, want in cases:
+        p = feh.feh_plan_create(len(n), n, None, 2, prec)
+        assert feh.feh_plan_cg_residual_spectral(p) is want, (n, prec)
+        if want:
+            t = feh.feh_plan_tuning(p)
+            t["compile_time_transforms"] = 0
+            feh.feh_plan_set_tuning(p, t)
+            assert feh.feh_plan_cg_residual_spectral(p) is False
+            t["compile_time_transforms"] = 1
+            t["rows_last"] = 4
+            feh.feh_plan_set_tuning(p, t)
+            assert feh.feh_plan_cg_residual_spectral(p) is False
+        feh.feh_plan_destroy(p)
+    assert load_rc_null() < 0
+
+
+def load_rc_null():
+    return feh.load().feh_plan_cg_residual_spectral(None)
+
+
 def test_bad_voxel_size():
     with pytest.raises(feh.FehError) as ei:
         feh.feh_plan_create(2, (8, 8), (1.0, -1.0), 1, 0)
