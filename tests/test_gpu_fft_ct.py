@@ -70,3 +70,72 @@ def test_fft_with_compile_time_passes_matches_dft(shape, prec):
     back = h.fft_inverse(ref.astype(np.complex128 if prec == "fp64" else np.complex64))
     np.testing.assert_allclose(back.cpu().numpy().reshape(x.shape), x, atol=tol * np.abs(x).max() * 10)
     h.close()
+
+
+def test_spectral_residual_warm_start_batches():
+    """The CG with its residual kept as a last-axis half spectrum (3D FP32,
+    compile-time last-axis passes) against the real-field residual on the same
+    plans: a warm start from a perturbed solution, a batched plan of two
+    microstructures, and an uneven batch of two grids (graph replay)."""
+    import paper_2105_03297_amd as feh
+    say("spectral residual: warm start, batched plan, uneven batch")
+    shape = (10, 12, 128)
+    Eb = ms.unit_loads(3)
+    lam, mu = random_material(shape, 23, "fp32")
+
+    def plan(ct, n_batch=1, shp=shape):
+        h = feh.Homogenizer(shp, n_load=6, precision="fp32", n_batch=n_batch)
+        t = feh.feh_plan_tuning(h.plan)
+        t["compile_time_transforms"] = ct
+        feh.feh_plan_set_tuning(h.plan, t)
+        assert feh.feh_plan_cg_residual_spectral(h.plan) == bool(ct)
+        return h
+
+    cold = {}
+    for ct in (1, 0):
+        h = plan(ct)
+        h.set_material(lam=lam, mu=mu)
+        o = h.solve(Eb, tol=1e-6, max_iter=3000, return_u=True)
+        u = o["u"].double().cpu().numpy()
+        pert = u + 1e-3 * np.abs(u).max() * np.random.default_rng(5).standard_normal(u.shape)
+        w = h.solve(Eb, tol=1e-6, max_iter=3000, return_u=True, u0=pert)
+        h.close()
+        cold[ct] = (o, w)
+    (o1, w1), (o0, w0) = cold[1], cold[0]
+    print("cold C_eff rel diff %.3e, warm %.3e, warm iterations %s / %s" % (
+        rel(o1["C_eff"], o0["C_eff"]), rel(w1["C_eff"], w0["C_eff"]),
+        [r["iterations"] for r in w1["report"]], [r["iterations"] for r in w0["report"]]))
+    assert rel(o1["C_eff"], o0["C_eff"]) < 1e-5
+    assert w1["status"] == 0 and rel(w1["C_eff"], o1["C_eff"]) < 1e-5 and rel(w1["C_eff"], w0["C_eff"]) < 1e-5
+    assert all(abs(a["iterations"] - b["iterations"]) <= 1 for a, b in zip(w1["report"], w0["report"]))
+
+    # batched plan of two microstructures
+    lam2, mu2 = random_material(shape, 24, "fp32")
+    res = {}
+    for ct in (1, 0):
+        h = plan(ct, n_batch=2)
+        h.set_material(lam=np.stack([lam, lam2]), mu=np.stack([mu, mu2]))
+        o = h.solve(np.concatenate([Eb, Eb]), tol=1e-6, max_iter=3000)
+        W = o["energy"]
+        res[ct] = [feh.feh_effective_stiffness(3, Eb, W[6 * b:6 * b + 6, 6 * b:6 * b + 6]) for b in range(2)]
+        h.close()
+    for b in range(2):
+        assert rel(res[1][b], res[0][b]) < 1e-5, b
+    assert rel(res[1][0], o1["C_eff"]) < 1e-5
+
+    # uneven batch of two grids, each with a compile-time last axis
+    shapes = [(8, 6, 128), (6, 4, 256)]
+    maps = []
+    for i, shp in enumerate(shapes):
+        E = np.exp(np.random.default_rng(40 + i).standard_normal(shp))
+        maps.append((E, 0.3))
+    ub = feh.UnevenBatch(maps, precision="fp32")
+    assert all(feh.feh_plan_cg_residual_spectral(hz.plan) for hz, _ in ub.plans)
+    out = ub.solve(Eb, tol=1e-6, max_iter=3000, use_graph=True)
+    ub.close()
+    for (E, nu), o in zip(maps, out):
+        h = plan(0, shp=E.shape)
+        h.set_material(E=E, nu=nu)
+        ref = h.solve(Eb, tol=1e-6, max_iter=3000)
+        h.close()
+        assert rel(o["C_eff"], ref["C_eff"]) < 1e-5, (E.shape, rel(o["C_eff"], ref["C_eff"]))
