@@ -126,8 +126,8 @@ int feh_plan_create_batch(feh_plan **plan, int dim, const int64_t n[], const dou
 int feh_plan_destroy(feh_plan *plan);
 
 /* Bytes of device workspace the plan needs (nodal vectors u, r, p, q for
- * every load case, the half spectrum, the material, tables, partial sums and
- * CG scalars). */
+ * every load case, r sized to hold a half spectrum, the half spectrum, the
+ * material, tables, partial sums and CG scalars). */
 int feh_plan_workspace_bytes(const feh_plan *plan, size_t *bytes);
 
 /* Hand the plan a device buffer of at least feh_plan_workspace_bytes bytes,
@@ -486,8 +486,9 @@ int feh_fft_inverse(feh_plan *plan, const void *X_dev, void *x_dev);
 
 /* Measurement: enable (1) or disable (0) HIP-event timing of every kernel
  * launch inside the CG iterations of feh_solve on the plan's stream, and
- * reset the counters.  Kinds: 0 stencil (p update, q = K p, p.q), 1 alpha,
- * 2 last-axis r2c with r -= alpha q, 3 middle-axis forward (3D), 4 first
+ * reset the counters.  Kinds: 0 stencil (q = K p, p.q), 1 alpha, 2 last-axis
+ * r2c with r -= alpha q (or, see feh_plan_cg_residual_spectral, the r2c of q
+ * with the spectral residual update), 3 middle-axis forward (3D), 4 first
  * axis forward + (B^*B)^-1 + inverse with r.z, 5 middle-axis inverse (3D),
  * 6 last-axis c2r, 7 beta / stop test. */
 int feh_profile_enable(feh_plan *plan, int enable);
