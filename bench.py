@@ -167,6 +167,8 @@ def uneven_batch_measure(log):
          "graph_launches": res["graph"][2],
          "DOF_CG_iterations_per_s_graph": dof_it / res["graph"][0],
          "DOF_CG_iterations_per_s_eager": dof_it / res["eager"][0],
+         "DOF_CG_iterations_per_s": dof_it / min(res["graph"][0], res["eager"][0]),
+         "fastest_mode": "graph" if res["graph"][0] <= res["eager"][0] else "eager",
          "max_cg_iterations": max(max(r["iterations"] for r in o["report"]) for o in res["graph"][1]),
          "C_eff_graph_vs_one_plan_per_map": worst}
     log("uneven batch", u)
