@@ -266,14 +266,13 @@ int feh_plan_cg_residual_spectral(const feh_plan *plan);
 
 /* Uneven batches: plans of different grids (each possibly a batched plan),
  * each on a created HIP stream (plans may share one), solved together.
- * Plans on different streams run concurrently: eagerly each plan's kernels
- * go to its own stream, and a captured graph forks one branch per stream
- * from the first plan's stream and joins them at its end.  After each plan's
- * set-up, the CG iterations of all plans run in chunks of 4, 8, then 16
- * iterations per plan; with use_graph != 0 each chunk is one hipGraphLaunch
- * of a graph captured once per (chunk, tol, max_iter) and replayed, so a
- * batch of many small grids costs one launch per chunk instead of one per
- * kernel.  Every load case stops on its own (converged load cases return
+ * Plans on different streams run concurrently: each plan's kernels go to
+ * its own stream, eagerly or as graphs.  After each plan's set-up, the CG
+ * iterations of all plans run in chunks of 4, 8, then 16 iterations per
+ * plan; with use_graph != 0 each chunk is one hipGraphLaunch per stream, of
+ * a graph of that stream's plans captured once per (chunk, tol, max_iter)
+ * and replayed, so a batch of many small grids costs one launch per stream
+ * and chunk instead of one per kernel.  Every load case stops on its own (converged load cases return
  * at once from every kernel).  The batch keeps pointers to the plans (the
  * caller keeps them, their workspaces and materials alive and unchanged
  * while the batch exists; otherwise destroy and re-create the batch).

@@ -811,66 +811,52 @@ int feh_solve(feh_plan *plan, const double *Ebar_host, double tol, int max_iter,
 }
 
 // ---------------------------------------------------------------------------
-// batches of plans: one HIP graph per chunk of CG iterations of every plan
+// batches of plans: per stream, one HIP graph per chunk of CG iterations of
+// the plans on that stream
 // ---------------------------------------------------------------------------
 
 struct feh_batch {
     std::vector<feh_plan *> plans;
-    hipStream_t stream = nullptr;        // the first plan's stream: graph capture and launch
-    std::vector<hipStream_t> others;     // the other plans' distinct streams
-    hipEvent_t fork = nullptr;           // capture fork (recorded on stream)
-    std::vector<hipEvent_t> joins;       // capture joins, one per other stream
-    // instantiated graphs, keyed by (chunk length, tol, max_iter): the CG
-    // kernels read their state from device memory, so a graph replays for as
-    // long as the plans, their workspaces and the stopping rule are unchanged
+    std::vector<hipStream_t> streams;    // the plans' distinct streams, first plan's first
+    // instantiated graphs, keyed by (stream, chunk length, tol, max_iter): the
+    // CG kernels read their state from device memory, so a graph replays for
+    // as long as the plans, their workspaces and the stopping rule are unchanged
     struct Entry {
+        int si;
         int chunk;
         double tol;
         int max_iter;
         hipGraphExec_t exec;
     };
     std::vector<Entry> graphs;
-    int launches = 0;  // graph launches of the last solve (for tests)
+    int launches = 0;  // chunks run by graph launches in the last solve (for tests)
 };
 
 static void batch_clear(feh_batch &b) {
     for (auto &e : b.graphs) (void)hipGraphExecDestroy(e.exec);
     b.graphs.clear();
-    for (hipEvent_t e : b.joins) (void)hipEventDestroy(e);
-    b.joins.clear();
-    if (b.fork) (void)hipEventDestroy(b.fork);
-    b.fork = nullptr;
 }
 
-static int batch_graph(feh_batch &b, int chunk, double tol, int max_iter, hipGraphExec_t &exec) {
+// The graph of `chunk` CG iterations of the plans on stream si, captured on
+// that stream (each stream's chain is a graph of its own, so the streams'
+// graphs run concurrently as their eager launches do).
+static int batch_graph(feh_batch &b, int si, int chunk, double tol, int max_iter, hipGraphExec_t &exec) {
     for (auto &e : b.graphs)
-        if (e.chunk == chunk && e.tol == tol && e.max_iter == max_iter) {
+        if (e.si == si && e.chunk == chunk && e.tol == tol && e.max_iter == max_iter) {
             exec = e.exec;
             return FEH_OK;
         }
-    CK(hip_check(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal), "begin capture"));
-    // plans on other streams join the capture through the fork event and
-    // rejoin the capturing stream at the end: the graph holds one branch per
-    // stream, and the branches run concurrently
+    hipStream_t s = b.streams[si];
+    CK(hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture"));
     int rc = FEH_OK;
-    if (!b.others.empty()) {
-        rc = hip_check(hipEventRecord(b.fork, b.stream), "capture fork");
-        for (size_t k = 0; k < b.others.size() && rc == FEH_OK; ++k)
-            rc = hip_check(hipStreamWaitEvent(b.others[k], b.fork, 0), "capture fork");
-    }
     for (int i = 0; i < chunk && rc == FEH_OK; ++i)
         for (feh_plan *p : b.plans) {
+            if (p->stream != s) continue;
             rc = cg_iteration(*p, p->ptr<LcState>(p->off_state), tol, max_iter);
             if (rc != FEH_OK) break;
         }
-    for (size_t k = 0; k < b.others.size(); ++k) {
-        // always rejoin, also after an error, so that the capture can end
-        const int r1 = hip_check(hipEventRecord(b.joins[k], b.others[k]), "capture join");
-        const int r2 = hip_check(hipStreamWaitEvent(b.stream, b.joins[k], 0), "capture join");
-        if (rc == FEH_OK) rc = r1 ? r1 : r2;
-    }
     hipGraph_t g = nullptr;
-    const hipError_t ec = hipStreamEndCapture(b.stream, &g);
+    const hipError_t ec = hipStreamEndCapture(s, &g);  // always end the capture, also after an error
     if (rc != FEH_OK) {
         if (g) (void)hipGraphDestroy(g);
         return rc;
@@ -879,7 +865,7 @@ static int batch_graph(feh_batch &b, int chunk, double tol, int max_iter, hipGra
     const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     CK(hip_check(ei, "instantiate graph"));
-    b.graphs.push_back({chunk, tol, max_iter, exec});
+    b.graphs.push_back({si, chunk, tol, max_iter, exec});
     return FEH_OK;
 }
 
@@ -896,22 +882,9 @@ int feh_batch_create(feh_batch **out, feh_plan *const *plans, int n_plans) {
         }
         auto b = new feh_batch();
         b->plans.assign(plans, plans + n_plans);
-        b->stream = plans[0]->stream;
-        for (int i = 1; i < n_plans; ++i)
-            if (plans[i]->stream != b->stream &&
-                std::find(b->others.begin(), b->others.end(), plans[i]->stream) == b->others.end())
-                b->others.push_back(plans[i]->stream);
-        if (!b->others.empty()) {
-            int rc = hip_check(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming), "batch events");
-            b->joins.assign(b->others.size(), nullptr);
-            for (size_t k = 0; k < b->others.size() && rc == FEH_OK; ++k)
-                rc = hip_check(hipEventCreateWithFlags(&b->joins[k], hipEventDisableTiming), "batch events");
-            if (rc != FEH_OK) {
-                batch_clear(*b);
-                delete b;
-                return rc;
-            }
-        }
+        for (int i = 0; i < n_plans; ++i)
+            if (std::find(b->streams.begin(), b->streams.end(), plans[i]->stream) == b->streams.end())
+                b->streams.push_back(plans[i]->stream);
         *out = b;
         return FEH_OK;
     } catch (const std::bad_alloc &) {
@@ -947,9 +920,11 @@ int feh_batch_solve(feh_batch *b, const double *const *Ebar_host, double tol, in
             if (!any) break;
             const int c = chunk < max_iter - done ? chunk : max_iter - done;
             if (use_graph) {
-                hipGraphExec_t exec = nullptr;
-                CK(batch_graph(*b, c, tol, max_iter, exec));
-                CK(hip_check(hipGraphLaunch(exec, b->stream), "graph launch"));
+                for (int si = 0; si < (int)b->streams.size(); ++si) {
+                    hipGraphExec_t exec = nullptr;
+                    CK(batch_graph(*b, si, c, tol, max_iter, exec));
+                    CK(hip_check(hipGraphLaunch(exec, b->streams[si]), "graph launch"));
+                }
             } else {
                 for (int it = 0; it < c; ++it)
                     for (feh_plan *p : b->plans) CK(cg_iteration(*p, p->ptr<LcState>(p->off_state), tol, max_iter));
