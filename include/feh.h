@@ -256,11 +256,12 @@ int feh_plan_set_tuning(feh_plan *plan, const int *values, int n_values);
 
 /* Whether the plan's CG, with its current schedule, keeps the residual as its
  * last-axis half spectrum (1) or as a real field (0); negative on a null
- * plan.  3D FP32 plans whose last-axis passes take the compile-time
- * transform keep it as a half spectrum: the forward last-axis pass then
- * transforms q and updates the spectral residual in place (the transform is
- * linear), and the forward middle pass reads it into the spectrum, which
- * saves about one nodal vector of HBM traffic per iteration.  Both forms give
+ * plan.  FP32 plans whose last-axis passes take the compile-time transform
+ * keep it as a half spectrum: the forward last-axis pass then transforms q
+ * and updates the spectral residual in place (the transform is linear), and
+ * the next forward pass (middle axis in 3D, first axis in 2D) reads it into
+ * the spectrum, which saves about one nodal vector of HBM traffic per
+ * iteration.  Both forms give
  * the same iterates up to rounding.  A host-side query for byte accounting. */
 int feh_plan_cg_residual_spectral(const feh_plan *plan);
 

@@ -283,8 +283,12 @@ static int precondition(const feh_plan &p, const void *r, void *z, double *parti
         FftArgs fm = fa;
         fm.spec_in = rhat;
         CK(launch_middle(p, fm, false));
+        CK(launch_first_fused(p, fa));
+    } else {
+        FftArgs ff = fa;
+        ff.spec_in = rhat;
+        CK(launch_first_fused(p, ff));
     }
-    CK(launch_first_fused(p, fa));
     if (p.dim == 3) CK(launch_middle(p, fa, true));
     return launch_inverse_last(p, fa);
 }
@@ -357,9 +361,10 @@ static int cg_iteration(const feh_plan &p, LcState *st, double tol, int max_iter
     fa.state = st;
     fa.out_scale = 1.0 / (double)p.N;
     fa.unit_volume = true;
-    // residual kept as a last-axis half spectrum r^ (3D): the forward last
-    // pass transforms q and updates r^ -= alpha q^ in place (the FFT is
-    // linear), and the forward middle pass reads r^ into the spectrum
+    // residual kept as a last-axis half spectrum r^: the forward last pass
+    // transforms q and updates r^ -= alpha q^ in place (the FFT is linear),
+    // and the next forward pass (middle in 3D, first axis in 2D) reads r^
+    // into the spectrum
     const bool rs = cg_residual_spectral(p);
     {
         ProfScope ps(p, 2);
@@ -380,7 +385,9 @@ static int cg_iteration(const feh_plan &p, LcState *st, double tol, int max_iter
     }
     {
         ProfScope ps(p, 4);
-        CK(launch_first_fused(p, fa));
+        FftArgs ff = fa;
+        if (rs && p.dim == 2) ff.spec_in = p.ws + p.off_r;  // 2D: the first-axis pass reads r^
+        CK(launch_first_fused(p, ff));
     }
     {
         ProfScope ps(p, 7);

@@ -231,7 +231,7 @@ struct FftArgs {
     const void *q = nullptr;     // fused axpy: r -= alpha q (nullable)
     void *r_out = nullptr;       // updated r (fused axpy)
     void *spec = nullptr;        // half spectrum [L][n0][..][nh][D]
-    const void *spec_in = nullptr;  // forward middle pass: read here, write spec (null: in place)
+    const void *spec_in = nullptr;  // forward middle (3D) / first-axis (2D) pass: read here, write spec (null: in place)
     bool rspec = false;          // forward last pass: spec (the residual's last-axis half spectrum) -= alpha q^
     void *z = nullptr;           // real output
     void *p_upd = nullptr;       // CG update fused into the last inverse pass (nullable):
@@ -252,7 +252,7 @@ int launch_first(const feh_plan &p, const FftArgs &a, bool inverse);  // c2c axi
 int launch_first_plain(const feh_plan &p, const FftArgs &a, bool inverse);  // c2c axis 0, any a.comps
 int launch_inverse_last(const feh_plan &p, const FftArgs &a);   // c2r along the last axis
 bool last_ct_ok(const feh_plan &p, int D);      // the last-axis passes take the compile-time transform
-// the CG keeps its residual as a last-axis half spectrum (3D, compile-time last-axis passes)
+// the CG keeps its residual as a last-axis half spectrum (FP32, compile-time last-axis passes)
 bool cg_residual_spectral(const feh_plan &p);
 
 // scalar / vector kernels (kern_cg.hip)

@@ -1494,8 +1494,10 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu((PE
         // out of the loop into registers
         int tx = threadIdx.x;
         asm volatile("" : "+v"(tx));
-        Cx<T> *base = a.spec + ((long long)lc * n0 * inner + in0) * D;
+        const long long boff = ((long long)lc * n0 * inner + in0) * D;
+        Cx<T> *base = a.spec + boff;
         {
+            const Cx<T> *src = (a.spec_in ? a.spec_in : a.spec) + boff;
             Cx<T> v[PPT];
             #pragma unroll
             for (int k = 0; k < PPT; ++k) {
@@ -1503,7 +1505,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu((PE
                 const int e = e0 < cnt ? e0 : 0;
                 const int j = (int)a.nbd.div((uint32_t)e);
                 const int bc = e - j * nb;
-                v[k] = base[(long long)j * inner * D + (bc < lim ? bc : lim - 1)];
+                v[k] = src[(long long)j * inner * D + (bc < lim ? bc : lim - 1)];
             }
             #pragma unroll
             for (int k = 0; k < PPT; ++k) {
@@ -1617,6 +1619,7 @@ __global__ __launch_bounds__(kFftThreads) void k_first_ct(FK<T> a) {
     const int lim = min(PB, (int)(inner - in0));
     const unsigned rowD = inner * D;      // complex values between consecutive m0
     Cx<T> *base = a.spec + ((long long)lc * N * inner + in0) * D;
+    const Cx<T> *src = (a.spec_in ? a.spec_in : a.spec) + ((long long)lc * N * inner + in0) * D;
     for (int i = threadIdx.x; i < N; i += NT) twl[i] = a.tw[i];
     const int lane = threadIdx.x & (PB - 1), g = threadIdx.x >> LPB;
     // staging slot (i, j): row m0 = g + RS i, value r = lane + PB j of the row,
@@ -1630,7 +1633,7 @@ __global__ __launch_bounds__(kFftThreads) void k_first_ct(FK<T> a) {
             for (int j = 0; j < D; ++j) {
                 const int r = lane + PB * j;
                 const int rc = r < lim * D ? r : lim * D - 1;
-                v[i][j] = base[__umul24((unsigned)(g + RS * i), rowD) + (unsigned)rc];
+                v[i][j] = src[__umul24((unsigned)(g + RS * i), rowD) + (unsigned)rc];
             }
         }
         #pragma unroll
@@ -1795,7 +1798,7 @@ bool last_ct_ok(const feh_plan &p, int D) {
            (double)D * (double)p.N * 4.0 < 4294967296.0;
 }
 
-bool cg_residual_spectral(const feh_plan &p) { return p.dim == 3 && last_ct_ok(p, 3); }
+bool cg_residual_spectral(const feh_plan &p) { return last_ct_ok(p, p.dim); }
 
 namespace {
 

@@ -65,11 +65,12 @@ def test_prime_sizes_factorise(n, passes):
 
 def test_cg_residual_form_follows_the_schedule():
     """The CG keeps its residual as a last-axis half spectrum exactly when the
-    last-axis passes take the compile-time transform in a 3D FP32 plan."""
+    last-axis passes of an FP32 plan take the compile-time transform."""
     cases = [((64, 32, 256), feh.FEH_FP32, True), ((16, 8, 128), feh.FEH_FP32, True),
              ((8, 8, 512), feh.FEH_FP32, True), ((64, 64, 64), feh.FEH_FP32, False),
-             ((16, 8, 256), feh.FEH_FP64, False), ((64, 256), feh.FEH_FP32, False),
-             ((16, 8, 250), feh.FEH_FP32, False)]
+             ((16, 8, 256), feh.FEH_FP64, False), ((64, 256), feh.FEH_FP32, True),
+             ((30, 512), feh.FEH_FP32, True), ((64, 64), feh.FEH_FP32, False),
+             ((64, 250), feh.FEH_FP32, False), ((16, 8, 250), feh.FEH_FP32, False)]
     for n, prec, want in cases:
         p = feh.feh_plan_create(len(n), n, None, 2, prec)
         assert feh.feh_plan_cg_residual_spectral(p) is want, (n, prec)

@@ -73,10 +73,11 @@ def test_fft_with_compile_time_passes_matches_dft(shape, prec):
 
 
 def test_spectral_residual_warm_start_batches():
-    """The CG with its residual kept as a last-axis half spectrum (3D FP32,
+    """The CG with its residual kept as a last-axis half spectrum (FP32,
     compile-time last-axis passes) against the real-field residual on the same
     plans: a warm start from a perturbed solution, a batched plan of two
-    microstructures, and an uneven batch of two grids (graph replay)."""
+    microstructures, and an uneven batch of two grids (graph replay); 2D warm
+    start and uneven batch as well."""
     import paper_2105_03297_amd as feh
     say("spectral residual: warm start, batched plan, uneven batch")
     shape = (10, 12, 128)
@@ -135,6 +136,48 @@ def test_spectral_residual_warm_start_batches():
     ub.close()
     for (E, nu), o in zip(maps, out):
         h = plan(0, shp=E.shape)
+        h.set_material(E=E, nu=nu)
+        ref = h.solve(Eb, tol=1e-6, max_iter=3000)
+        h.close()
+        assert rel(o["C_eff"], ref["C_eff"]) < 1e-5, (E.shape, rel(o["C_eff"], ref["C_eff"]))
+
+
+
+def test_spectral_residual_2d():
+    """2D plans with a 128- or 256-point last axis keep the residual as its
+    last-axis half spectrum (the first-axis pass reads it): warm start and
+    an uneven batch against the real-field residual."""
+    import paper_2105_03297_amd as feh
+    say("spectral residual 2D")
+    Eb = ms.unit_loads(2)
+    shape = (40, 128)
+    lam, mu = random_material(shape, 29, "fp32")
+    res = {}
+    for ct in (1, 0):
+        h = feh.Homogenizer(shape, n_load=3, precision="fp32")
+        t = feh.feh_plan_tuning(h.plan)
+        t["compile_time_transforms"] = ct
+        feh.feh_plan_set_tuning(h.plan, t)
+        assert feh.feh_plan_cg_residual_spectral(h.plan) == bool(ct)
+        h.set_material(lam=lam, mu=mu)
+        o = h.solve(Eb, tol=1e-6, max_iter=3000, return_u=True)
+        u = o["u"].double().cpu().numpy()
+        w = h.solve(Eb, tol=1e-6, max_iter=3000, u0=u + 1e-3 * np.abs(u).max())
+        h.close()
+        res[ct] = (o, w)
+    assert rel(res[1][0]["C_eff"], res[0][0]["C_eff"]) < 1e-5
+    assert all(abs(a["iterations"] - b["iterations"]) <= 1 for a, b in zip(res[1][0]["report"], res[0][0]["report"]))
+    assert res[1][1]["status"] == 0 and rel(res[1][1]["C_eff"], res[0][0]["C_eff"]) < 1e-5
+    maps = [(np.exp(np.random.default_rng(50 + i).standard_normal(s)), 0.3) for i, s in enumerate([(64, 256), (30, 128)])]
+    ub = feh.UnevenBatch(maps, precision="fp32")
+    assert all(feh.feh_plan_cg_residual_spectral(hz.plan) for hz, _ in ub.plans)
+    out = ub.solve(Eb, tol=1e-6, max_iter=3000, use_graph=True)
+    ub.close()
+    for (E, nu), o in zip(maps, out):
+        h = feh.Homogenizer(E.shape, n_load=3, precision="fp32")
+        t = feh.feh_plan_tuning(h.plan)
+        t["compile_time_transforms"] = 0
+        feh.feh_plan_set_tuning(h.plan, t)
         h.set_material(E=E, nu=nu)
         ref = h.solve(Eb, tol=1e-6, max_iter=3000)
         h.close()
