@@ -830,18 +830,6 @@ constexpr int ct_last_stride() {
     return (NB + 1) * (NL / 2) * 8 + NL * 8 <= 160 * 1024 / 3 ? NB + 1 : NB;
 }
 
-// Element at a 32-bit byte offset from a base pointer: with the base uniform
-// the load or store takes the scalar-base form (no 64-bit address arithmetic
-// per access); the launchers check that the offsets fit.
-template <typename P>
-__device__ __forceinline__ P *at_byte(P *base, unsigned off) {
-    return reinterpret_cast<P *>(reinterpret_cast<char *>(base) + off);
-}
-template <typename P>
-__device__ __forceinline__ const P *at_byte(const P *base, unsigned off) {
-    return reinterpret_cast<const P *>(reinterpret_cast<const char *>(base) + off);
-}
-
 // Byte offset of packed pair j of row sl (of the block) and component c in
 // the load case's real SoA field [D][N].
 template <typename T, int NL, int D>

@@ -285,8 +285,8 @@ __global__ __launch_bounds__((Tile<DIM, VYT>::NT)) void k_stencil(SK<T> a) {
 
     // ---- per-thread node slots, fixed for the whole march.  Slot 0 is the
     // thread's own node; later slots cover the last row and column.
-    int e_lds[NSE];        // extended node index, -1 if unused
-    long long e_off[NSE];  // in-plane global offset
+    int e_lds[NSE];        // extended node index (an unused slot repeats slot 0)
+    unsigned e_boff[NSE];  // in-plane byte offset (the launcher checks that a plane fits 31 bits)
     #pragma unroll
     for (int s = 0; s < NSE; ++s) {
         int ey = -1, ez = -1;
@@ -311,13 +311,21 @@ __global__ __launch_bounds__((Tile<DIM, VYT>::NT)) void k_stencil(SK<T> a) {
         }
         if (ey >= 0) {
             e_lds[s] = ey * EZ + ez;
-            e_off[s] = (long long)wrap(y0 + ey, a.n1) * a.n2 + wrap(z0 + ez, a.n2);
+            e_boff[s] = (unsigned)(wrap(y0 + ey, a.n1) * a.n2 + wrap(z0 + ez, a.n2)) * (unsigned)sizeof(T);
         } else {
-            e_lds[s] = -1;  // not staged; its loads re-read the own node
-            e_off[s] = e_off[0];
+            // unused: its loads re-read the own node and its LDS store
+            // repeats the own node's, same value to the same place
+            e_lds[s] = e_lds[0];
+            e_boff[s] = e_boff[0];
         }
     }
     const long long v_off = (long long)wrap(y0 + ty, a.n1) * a.n2 + wrap(z0 + tz, a.n2);
+    const unsigned v_boff = (unsigned)v_off * (unsigned)sizeof(T);
+    // node loads and stores go through raw buffers over one plane of one
+    // component; a lane that updates no node stores past the buffer's end,
+    // which the hardware drops, so no branch splits the node phase
+    const unsigned st_boff = owner ? e_boff[0] : 0x80000000u;
+    const long long plane_bytes = plane * (long long)sizeof(T);
 
     // ---- prefetch registers: node plane P and the material of one voxel
     // plane.  Every load is unconditional (unused slots and planes past the
@@ -325,16 +333,15 @@ __global__ __launch_bounds__((Tile<DIM, VYT>::NT)) void k_stencil(SK<T> a) {
     T rz[NSE][NC];
     T mlam = T(0), mmu = T(0);
     auto fetch_nodes = [&](int P) __attribute__((always_inline)) {
-        const long long base = (long long)wrap(P, a.n0) * plane;
+        const long long base = lcoff + (long long)wrap(P, a.n0) * plane;
         #pragma unroll
         for (int s = 0; s < NSE; ++s) {
             #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                const long long gi = lcoff + c * N + base + e_off[s];
                 if constexpr (MODE == ST_APPLY || MODE == ST_CG) {
-                    rz[s][c] = a.in0[gi];
+                    rz[s][c] = buffer_ld<T>(raw_buffer(a.in0 + base + c * N, plane_bytes), e_boff[s]);
                 } else if constexpr (MODE == ST_RESID) {
-                    rz[s][c] = a.in0 ? a.in0[gi] : T(0);
+                    rz[s][c] = a.in0 ? buffer_ld<T>(raw_buffer(a.in0 + base + c * N, plane_bytes), e_boff[s]) : T(0);
                 }
             }
         }
@@ -345,19 +352,17 @@ __global__ __launch_bounds__((Tile<DIM, VYT>::NT)) void k_stencil(SK<T> a) {
     auto commit_nodes = [&]() __attribute__((always_inline)) {
         #pragma unroll
         for (int s = 0; s < NSE; ++s) {
-            if (e_lds[s] >= 0) {
             #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 Pl[c][e_lds[s]] = rz[s][c];
                 if (s == 0) own[c] = rz[s][c];
             }
-            }
         }
     };
     auto fetch_material = [&](int V) __attribute__((always_inline)) {
-        const long long base = (long long)wrap(V, a.n0) * plane;
-        mlam = a.lam[moff + base + v_off];  // unused (but allocated) for the identity material
-        mmu = a.mu[moff + base + v_off];
+        const long long base = moff + (long long)wrap(V, a.n0) * plane;
+        mlam = buffer_ld<T>(raw_buffer(a.lam + base, plane_bytes), v_boff);  // unused (but allocated) for the identity material
+        mmu = buffer_ld<T>(raw_buffer(a.mu + base, plane_bytes), v_boff);
     };
 
     // in-plane corners of the thread's voxel: k = cy + 2 cz (3D), k = cz (2D);
@@ -397,7 +402,10 @@ __global__ __launch_bounds__((Tile<DIM, VYT>::NT)) void k_stencil(SK<T> a) {
     const int vo = (ty >= HY && tz >= 1) ? tid : HY * VZ + 1;
     auto vix = [&](int dy, int dz) { return vo - dy * VZ - dz; };
 
-    for (int X = x0 - 1; X < x1; ++X) {
+    // one step of the march: the voxels of plane X, then the nodes of plane X
+    // (the first step, plane x0 - 1, only primes the carried terms)
+    auto step = [&](const int X, auto first) __attribute__((always_inline)) {
+        constexpr bool FIRST = decltype(first)::value;
         // ---- stage plane X+1, prefetch plane X+2 and the material of voxel plane X+1
         if constexpr (MODE != ST_DIV) commit_nodes();
         const T clam = mlam, cmu = mmu;
@@ -410,7 +418,7 @@ __global__ __launch_bounds__((Tile<DIM, VYT>::NT)) void k_stencil(SK<T> a) {
         #pragma unroll
         for (int i = 0; i < NC; ++i) {
             q[i] = cq[i];
-            nq[i] = T(0);
+            nq[i] = T(-0.0);  // x + (-0) = x: the first term folds into a move
         }
         T oy[12];    // 3D: the own voxel's axis-1 edge fluxes, kept for the node phase
         {
@@ -556,23 +564,36 @@ __global__ __launch_bounds__((Tile<DIM, VYT>::NT)) void k_stencil(SK<T> a) {
                     nq[i] += Es[(1 * 2 + 1) * 2 + i][vlo] - Es[(1 * 2 + 1) * 2 + i][vhi];
                 }
             }
-            if (X >= x0 && owner) {
-                const long long idx = (long long)X * plane + e_off[0];
+            if constexpr (!FIRST) {
                 #pragma unroll
                 for (int i = 0; i < NC; ++i) {
-                    if constexpr (MODE == ST_RESID) {
-                        a.out0[lcoff + i * N + idx] = -q[i];
-                    } else {
-                        a.out0[lcoff + i * N + idx] = q[i];
-                    }
+                    buffer_st<T>(raw_buffer(a.out0 + lcoff + i * N + (long long)X * plane, plane_bytes), st_boff,
+                                 MODE == ST_RESID ? -q[i] : q[i]);
+                    // p.q of every lane (finite values); the lanes that own no
+                    // node drop their sum at the end
                     if constexpr (MODE == ST_CG) acc += double(pown[i]) * double(q[i]);
                 }
             }
             #pragma unroll
-            for (int i = 0; i < NC; ++i) cq[i] = nq[i];
+            for (int i = 0; i < NC; ++i) {
+                // formed here, next to the lane shifts that feed it, rather
+                // than sunk past the march's exit test into the next step
+                asm volatile("" : "+v"(nq[i]));
+                cq[i] = nq[i];
+            }
         }
+    };
+    // two steps per trip, so that the values carried from one step to the
+    // next alternate between two register sets instead of being copied
+    step(x0 - 1, std::true_type{});
+    for (int X = x0;; X += 2) {
+        step(X, std::false_type{});
+        if (X + 1 >= x1) break;
+        step(X + 1, std::false_type{});
+        if (X + 2 >= x1) break;
     }
     if constexpr (MODE == ST_CG) {
+        if (!owner) acc = 0.0;
         const double s = block_sum<NT>(acc, red);
         if (tid == 0) a.partial[(long long)lc * a.part_stride + blk_in_lc] = s;
     }
@@ -616,6 +637,10 @@ int launch_t(const feh_plan &p, int mode, const StencilArgs &sa) {
         a.ih[2] = T(1);
         a.vol = T(sa.unit_volume ? 0.5 : p.h[0] * p.h[1] / 2.0);
     }
+    // in-plane byte offsets are 32-bit and the store buffers span one plane
+    // (at most 4096^2 values: 128 MiB in FP64)
+    if ((long long)a.n1 * a.n2 * (long long)sizeof(T) >= (1LL << 31))
+        return set_error(FEH_EINVAL, "stencil: one plane of a field must stay below 2 GiB");
     a.N = p.N;
     a.xc = xchunk(a.n0, DIM);
     a.nchunk = (a.n0 + a.xc - 1) / a.xc;
