@@ -155,6 +155,7 @@ struct feh_plan {
     // block size (0: not built); rebuilt by the first-axis launcher on change
     mutable const char *minv_ws = nullptr;
     mutable int minv_pb = 0;
+    mutable int minv_q = -1;            // slot interleave of the table (0: plain order)
 
     // optional per-kernel event timing of the CG loop
     static constexpr int kProfKinds = 8;

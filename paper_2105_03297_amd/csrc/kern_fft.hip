@@ -395,7 +395,19 @@ struct FK {
     float near0;              // FP32 plans: sum_a |aa_a|^2 below which M^-1 is formed in FP64
     float hmax_f, post_f;     // FP32 plans: h_max and h_max^2 / chalf (scale-free FP32 inverse)
     T *minv;                  // (B^*B)^-1 table [block][component][slot] (first-axis pass)
+    int minv_q;               // 0: slots in order; Q: interleaved for Q-wide loads (see minv_pos)
 };
+
+// Position of wavevector slot e in a block's table row.  With q > 0 the
+// slots of each run of 64 q are interleaved so that lane l's q-wide vector
+// load holds slots l, l + 64, .., l + 64 (q - 1) of the run: a wavefront then
+// takes 64 consecutive slots per vector element (consecutive LDS words in the
+// first-axis pass) while each lane still loads 16 contiguous bytes.
+__host__ __device__ inline int minv_pos(int e, int q) {
+    if (q == 0) return e;
+    const int run = 64 * q;
+    return (e / run) * run + (e % 64) * q + (e % run) / 64;
+}
 
 // ---------------------------------------------------------------------------
 // Transforms with the shape fixed at compile time: power-of-two length N in
@@ -521,11 +533,12 @@ __device__ __forceinline__ void ct_pass(Cx<T> *buf, const Cx<T> *tw) {
     __syncthreads();
 }
 
-template <typename T, int N, int NB, int DS, int S, bool INV, int TWS, int NBS>
+// Passes S .. E - 1 (E = all of them by default).
+template <typename T, int N, int NB, int DS, int S, bool INV, int TWS, int NBS, int E = ct_npass(N)>
 __device__ __forceinline__ void ct_passes(Cx<T> *buf, const Cx<T> *tw) {
-    if constexpr (S < ct_npass(N)) {
+    if constexpr (S < E) {
         ct_pass<T, N, NB, DS, S, INV, TWS, NBS>(buf, tw);
-        ct_passes<T, N, NB, DS, S + 1, INV, TWS, NBS>(buf, tw);
+        ct_passes<T, N, NB, DS, S + 1, INV, TWS, NBS, E>(buf, tw);
     }
 }
 
@@ -1399,12 +1412,13 @@ __global__ __launch_bounds__(kFftThreads) void k_first_table(FK<T> a) {
         Cx<T> mo[3];
         bool half;
         slot_inverse<T, DIM>(a, e, PB, in0, lim, pin, md, mo, half);
+        const int pos = minv_pos(e, a.minv_q);
         #pragma unroll
-        for (int c = 0; c < D; ++c) tb[c * cntk + e] = md[c];
+        for (int c = 0; c < D; ++c) tb[c * cntk + pos] = md[c];
         #pragma unroll
         for (int c = 0; c < (DIM == 3 ? 3 : 1); ++c) {
-            tb[(D + 2 * c) * cntk + e] = mo[c].x;
-            tb[(D + 2 * c + 1) * cntk + e] = mo[c].y;
+            tb[(D + 2 * c) * cntk + pos] = mo[c].x;
+            tb[(D + 2 * c + 1) * cntk + pos] = mo[c].y;
         }
     }
 }
@@ -1582,20 +1596,35 @@ constexpr int ct_first_pencils() { return (sizeof(T) == 4 ? 2048 : 1024) / N; }
 // First axis with the compile-time transform, the CG's fused pass only
 // (forward, z = M^-1 r with the inverse table and the Parseval partial,
 // inverse): one workgroup per (pencil block, load case), load cases fastest,
-// as k_first with PERLC and TAB.  LDS holds component c of the block at
-// [c][m0][pencil] (D sub-problems of PB batches); the global spectrum keeps
-// the D components of a wavevector together, so the staging maps the row's
-// PB D contiguous values (pencil-major) onto the components.
+// as k_first with PERLC and TAB.  LDS row m0 holds the block's PB D values of
+// that row in the global order (pencil-major, the D components of a
+// wavevector together): the transforms run over PB D batches of one
+// sub-problem, and the staging, the M^-1 step and the store take consecutive
+// LDS words across the lanes of a wavefront (no bank conflicts).
 template <typename T, int N, int DIM>
 __global__ __launch_bounds__(kFftThreads) void k_first_ct(FK<T> a) {
     constexpr int NT = kFftThreads, D = DIM;
     constexpr int PB = ct_first_pencils<T, N>();
     constexpr int LPB = ct_log2(PB);
+    constexpr int NB = PB * D;            // values per LDS row
     constexpr int RS = NT / PB;           // rows per staging sweep
     constexpr int NC = kMinvComps<DIM>;
     constexpr int CNTK = PB * N;          // wavevector slots of the block
     static_assert(NT % PB == 0 && N % RS == 0, "staging covers whole rows");
-    __shared__ Cx<T> buf[D * N * PB];
+    constexpr int NR = N / RS;            // rows per thread: g + RS i
+    // The forward transform's first pass (no twiddles) has its butterfly q
+    // on rows q + (N / R) c and writes rows q + (N / R) d: with R = NR these
+    // are the thread's own staging rows for q = g, so the pass runs on the
+    // loaded values and the staging store writes its outputs.
+    constexpr bool FUSE_FIRST = ct_radix_at(N, 0) == NR;
+    // The inverse transform's last pass (M = 1) has butterfly p on rows
+    // R p + c and writes rows p + (N / R) d: the butterflies p = g + RS k,
+    // k < KB, produce exactly the thread's rows, so the pass ends in the
+    // registers the global store takes.
+    constexpr int SL = ct_npass(N) - 1, RL = ct_radix_at(N, SL);
+    constexpr int KB = N / (RL * RS);
+    constexpr bool FUSE_LAST = SL >= 1 && KB >= 1 && KB * RL == NR && ct_lstar(N, SL) * RL == N;
+    __shared__ Cx<T> buf[N * NB];
     __shared__ Cx<T> twl[N];
     __shared__ double red[NT / 64];
     const int t = xcd_remap(blockIdx.x, a.total);
@@ -1605,53 +1634,58 @@ __global__ __launch_bounds__(kFftThreads) void k_first_ct(FK<T> a) {
     const unsigned inner = (unsigned)a.inner_total;
     const unsigned in0 = (unsigned)blk * PB;
     const int lim = min(PB, (int)(inner - in0));
+    const int limD = lim * D;             // valid values per row
     const unsigned rowD = inner * D;      // complex values between consecutive m0
     Cx<T> *base = a.spec + ((long long)lc * N * inner + in0) * D;
     const Cx<T> *src = (a.spec_in ? a.spec_in : a.spec) + ((long long)lc * N * inner + in0) * D;
     for (int i = threadIdx.x; i < N; i += NT) twl[i] = a.tw[i];
+    // staging slot (i, j): row m0 = g + RS i, value r = lane + PB j of the row
     const int lane = threadIdx.x & (PB - 1), g = threadIdx.x >> LPB;
-    // staging slot (i, j): row m0 = g + RS i, value r = lane + PB j of the row,
-    // pencil r / D, component r % D
-    auto pencil_of = [](int r) { return D == 3 ? (r * 43) >> 7 : r >> 1; };  // r < 3 * 32
     {
-        Cx<T> v[N / RS][D];
+        Cx<T> v[NR][D];
         #pragma unroll
-        for (int i = 0; i < N / RS; ++i) {
+        for (int i = 0; i < NR; ++i) {
             #pragma unroll
             for (int j = 0; j < D; ++j) {
                 const int r = lane + PB * j;
-                const int rc = r < lim * D ? r : lim * D - 1;
+                const int rc = r < limD ? r : limD - 1;
                 v[i][j] = src[__umul24((unsigned)(g + RS * i), rowD) + (unsigned)rc];
             }
         }
         #pragma unroll
-        for (int i = 0; i < N / RS; ++i) {
+        for (int j = 0; j < D; ++j) {
+            const int r = lane + PB * j;
+            Cx<T> x[NR];
             #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                const int r = lane + PB * j;
-                const int b = pencil_of(r), c = r - D * b;
-                buf[(c * N + g + RS * i) * PB + b] = b < lim ? v[i][j] : Cx<T>{T(0), T(0)};
-            }
+            for (int i = 0; i < NR; ++i) x[i] = r < limD ? v[i][j] : Cx<T>{T(0), T(0)};
+            // radices 2, 4 and 8 take no twiddles from the table
+            if constexpr (FUSE_FIRST) Dft<T, NR>::run(x, false, twl, 1, N);
+            #pragma unroll
+            for (int i = 0; i < NR; ++i) buf[(g + RS * i) * NB + r] = x[i];
         }
     }
     __syncthreads();
-    ct_fft<T, N, PB, D, false>(buf, twl);
+    ct_passes<T, N, NB, 1, FUSE_FIRST ? 1 : 0, false, 1, NB>(buf, twl);
     double acc = 0.0;
     {
-        // Q consecutive wavevector slots per thread and round, so that each
-        // table component arrives in one 16-byte load per round
-        constexpr int Q = 16 / (int)sizeof(T) < PB ? 16 / (int)sizeof(T) : PB;
+        // each table component arrives in one 16-byte load of Q slots per
+        // round; the table interleaves the slots (minv_pos) so that vector
+        // element qq of the lanes of a wavefront covers 64 consecutive slots
+        constexpr int Q = 16 / (int)sizeof(T);
+        constexpr int RUN = 64 * Q;
+        static_assert(CNTK % (NT * Q) == 0, "whole rounds of slots");
         typedef T TV __attribute__((ext_vector_type(Q)));
         const T *tb0 = a.minv + (long long)blk * NC * CNTK;
+        const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
         #pragma unroll
         for (int k = 0; k < CNTK / (NT * Q); ++k) {
-            const int e0 = (threadIdx.x + k * NT) * Q;
+            const int run0 = (wv + k * (NT / 64)) * RUN;
             TV tv[NC];
             #pragma unroll
-            for (int c = 0; c < NC; ++c) tv[c] = *reinterpret_cast<const TV *>(tb0 + c * CNTK + e0);
+            for (int c = 0; c < NC; ++c) tv[c] = *reinterpret_cast<const TV *>(tb0 + c * CNTK + run0 + l * Q);
             #pragma unroll
             for (int qq = 0; qq < Q; ++qq) {
-                const int e = e0 + qq;
+                const int e = run0 + qq * 64 + l;
                 const int m0 = e >> LPB, b = e & (PB - 1);
                 if (b < lim) {
                     T md[D];
@@ -1663,36 +1697,49 @@ __global__ __launch_bounds__(kFftThreads) void k_first_ct(FK<T> a) {
                     const unsigned inn = in0 + b;
                     const int kh = DIM == 3 ? (int)(inn - a.d_nh.div(inn) * (unsigned)a.nh) : (int)inn;
                     const bool half = kh == 0 || (a.last_even && kh == a.nh - 1);
+                    Cx<T> *pt = buf + m0 * NB + b * D;
                     Cx<T> r[D], z[D];
                     #pragma unroll
-                    for (int c = 0; c < D; ++c) r[c] = buf[(c * N + m0) * PB + b];
+                    for (int c = 0; c < D; ++c) r[c] = pt[c];
                     const double dot = apply_minv<T, DIM>(md, mo, r, z);
                     #pragma unroll
-                    for (int c = 0; c < D; ++c) buf[(c * N + m0) * PB + b] = z[c];
+                    for (int c = 0; c < D; ++c) pt[c] = z[c];
                     acc += half ? dot : 2.0 * dot;
                 }
             }
         }
     }
     __syncthreads();
-    ct_fft<T, N, PB, D, true>(buf, twl);
+    ct_passes<T, N, NB, 1, 0, true, 1, NB, FUSE_LAST ? SL : SL + 1>(buf, twl);
     {
-        Cx<T> v[N / RS][D];
+        Cx<T> v[NR][D];
         #pragma unroll
-        for (int i = 0; i < N / RS; ++i) {
-            #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                const int r = lane + PB * j;
-                const int b = pencil_of(r), c = r - D * b;
-                v[i][j] = buf[(c * N + g + RS * i) * PB + b];
+        for (int j = 0; j < D; ++j) {
+            const int r = lane + PB * j;
+            if constexpr (FUSE_LAST) {
+                #pragma unroll
+                for (int k = 0; k < KB; ++k) {
+                    const int pp = g + RS * k;
+                    Cx<T> x[RL];
+                    #pragma unroll
+                    for (int cc = 0; cc < RL; ++cc) x[cc] = buf[(RL * pp + cc) * NB + r];
+                    #pragma unroll
+                    for (int cc = 1; cc < RL; ++cc) x[cc] = cmul(x[cc], twid(twl, 1, cc * pp, true));
+                    Dft<T, RL>::run(x, true, twl, 1, N);
+                    #pragma unroll
+                    for (int d = 0; d < RL; ++d) v[k + KB * d][j] = x[d];
+                }
+            } else {
+                #pragma unroll
+                for (int i = 0; i < NR; ++i) v[i][j] = buf[(g + RS * i) * NB + r];
             }
         }
         #pragma unroll
-        for (int i = 0; i < N / RS; ++i) {
+        for (int i = 0; i < NR; ++i) {
             #pragma unroll
             for (int j = 0; j < D; ++j) {
                 const int r = lane + PB * j;
-                if (r < lim * D) base[__umul24((unsigned)(g + RS * i), rowD) + (unsigned)r] = v[i][j];
+                if (r < limD) base[__umul24((unsigned)(g + RS * i), rowD) + (unsigned)r] = v[i][j];
             }
         }
     }
@@ -1996,12 +2043,15 @@ int first_t(const feh_plan &p, const FftArgs &fa, int mode) {
     const bool tab = mode == 0 && perlc && fa.unit_volume;
     if (tab) {
         a.minv = p.ptr<T>(p.off_minv);
-        if (p.minv_ws != p.ws || p.minv_pb != PB) {
+        // the compile-time pass reads the table with lane-interleaved slots
+        a.minv_q = ctpb > 0 ? 16 / (int)sizeof(T) : 0;
+        if (p.minv_ws != p.ws || p.minv_pb != PB || p.minv_q != a.minv_q) {
             hipLaunchKernelGGL((k_first_table<T, DIM>), dim3(a.nblk), b, 0, p.stream, a);
             const int rc = hip_check(hipGetLastError(), "inverse table launch");
             if (rc != FEH_OK) return rc;
             p.minv_ws = p.ws;
             p.minv_pb = PB;
+            p.minv_q = a.minv_q;
         }
     }
     if (ctpb > 0) {
