@@ -673,12 +673,14 @@ __global__ __launch_bounds__(kThreads) void k_post_march(PK<T> a, MarchGeom geo)
 template <typename T, int DIM>
 __device__ __forceinline__ void plane_corners(const PK<T> &a, int l, uint32_t xo, const uint32_t (&ob)[4],
                                               T (&C)[DIM == 3 ? 4 : 2][DIM]) {
+    // one raw buffer over the plane per component: a uniform base and the
+    // 32-bit lane offsets, no 64-bit address arithmetic per load
+    const long long plane_bytes = (long long)a.n1 * a.n2 * (long long)sizeof(T);
     #pragma unroll
     for (int i = 0; i < DIM; ++i) {
-        const T *ui = a.u + ((long long)l * DIM + i) * a.N + xo;
         #pragma unroll
         for (int k = 0; k < (DIM == 3 ? 4 : 2); ++k)
-            C[k][i] = a.u ? *reinterpret_cast<const T *>(reinterpret_cast<const char *>(ui) + ob[k]) : T(0);
+            C[k][i] = a.u ? buffer_ld<T>(raw_buffer(a.u + ((long long)l * DIM + i) * a.N + xo, plane_bytes), ob[k]) : T(0);
     }
 }
 
@@ -721,7 +723,7 @@ __global__ __launch_bounds__(kThreads) void k_sens_march(PK<T> a, MarchGeom geo,
     const int q0 = gofs[b], q1 = gofs[b + 1];
     ColumnCorners<DIM> cc;
     cc.init(a.n1, a.n2, DIM == 3 ? y : 0, z);
-    uint32_t ob[4];  // in-plane byte offsets (n1 n2 sizeof(T) < 2^32: checked by the launcher)
+    uint32_t ob[4];  // in-plane byte offsets (n1 n2 sizeof(T) < 2^31: checked by the launcher)
     #pragma unroll
     for (int k = 0; k < 4; ++k) ob[k] = cc.o[k] * (uint32_t)sizeof(T);
     double gl[kMarchChunk], gm[kMarchChunk];
@@ -838,7 +840,7 @@ PK<T> post_args(const feh_plan &p) {
 static bool march_ok(const feh_plan &p) {
     const double plane_bytes = (p.dim == 3 ? (double)p.n[1] * (double)p.n[2] : (double)p.n[1]) *
                                (p.prec == FEH_FP64 ? 8.0 : 4.0);
-    return p.G <= kMarchG && plane_bytes < 4294967296.0;
+    return p.G <= kMarchG && plane_bytes < 2147483648.0;  // raw buffers over one plane
 }
 
 int post_num_parts(const feh_plan &p) {
