@@ -26,9 +26,13 @@
 // workgroup stages one node plane of the tile (one extra row and column of
 // nodes) in LDS, each thread evaluates its voxel (edge fluxes into LDS), and
 // each updated node combines the fluxes of its in-plane voxels; the terms
-// whose voxels lie in the previous plane are carried in registers.  The fused
-// CG variant accumulates p.q in FP64 for the step length (the update of p
-// and u is fused into the last inverse FFT pass).
+// whose voxels lie in the previous plane are carried in registers (two
+// planes per loop trip, so that they alternate between two register sets).
+// Global loads and stores go through raw buffers over one plane of one
+// component; the lanes that update no node store past the buffer's end,
+// which the hardware drops, so the node phase has no branch.  The fused CG
+// variant accumulates p.q in FP64 for the step length (the update of p and u
+// is fused into the last inverse FFT pass).
 #include "device_common.hpp"
 
 namespace feh {
