@@ -78,6 +78,41 @@ def test_operator_matches_assembled_stiffness(shape, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_operator_on_the_largest_planes(prec):
+    """q = K p on the largest planes a 3D plan takes (4096 x 4096 in FP32,
+    4096 x 2048 in FP64, where the last-axis transform of 3 components
+    reaches the LDS tile; 64 MiB per component plane, both axes ragged against
+    the 7 x 31-node tiles), at 96 sampled nodes (the plane's last row and
+    column, its far corner, tile borders and random nodes) against the
+    oracle's element sums at those nodes."""
+    import paper_2105_03297_amd as feh
+    from oracle import fe
+    say("operator, largest planes", prec)
+    shape = (3, 4096, 4096) if prec == "fp32" else (3, 4096, 2048)
+    dt = np.float64 if prec == "fp64" else np.float32
+    rng = np.random.default_rng(11)
+    E = rng.uniform(1.0, 10.0, shape)
+    lam, mu = fe.lame(E, 0.3)
+    lam = lam.astype(dt).astype(np.float64)
+    mu = mu.astype(dt).astype(np.float64)
+    h = feh.Homogenizer(shape, n_load=1, precision=prec)
+    h.set_material(lam=lam, mu=mu)
+    N = int(np.prod(shape))
+    p = rng.standard_normal((N, 3)).astype(dt)
+    q = h.apply_operator(p.reshape(1, N, 3)).cpu().numpy()[0].astype(np.float64)
+    h.close()
+    n1, n2 = shape[1], shape[2]
+    picks = [(x, y, z) for x in range(3) for (y, z) in [(n1 - 1, n2 - 1), (0, 0), (n1 - 1, 0), (0, n2 - 1),
+                                                       (7, 31), (6, 30), (n1 - 1, n2 - 4), (n1 - 2, n2 - 1)]]
+    picks += [tuple(int(v) for v in c) for c in zip(rng.integers(0, 3, 72), rng.integers(0, n1, 72), rng.integers(0, n2, 72))]
+    nodes = np.array([np.ravel_multi_index(c, shape) for c in picks])
+    ref = fe.apply_K_at_nodes(lam, mu, p.astype(np.float64), nodes)
+    err = np.abs(q[nodes] - ref).max() / np.abs(ref).max()
+    print(prec, "largest planes: max error at %d nodes relative to max |K p| %.3e" % (len(nodes), err))
+    assert err < (1e-12 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("shape", [(8, 8), (6, 5), (16, 300), (4, 6, 8), (5, 3, 7), (20, 9, 70)])
 def test_preconditioner_matches_direct_solve(shape, prec):
     """z = M^+ r with M the FE stiffness of lambda = 0, mu = 1/2 (B^T B)."""
