@@ -1600,7 +1600,7 @@ constexpr int ct_first_pencils() { return (sizeof(T) == 4 ? 2048 : 1024) / N; }
 // that row in the global order (pencil-major, the D components of a
 // wavevector together): the transforms run over PB D batches of one
 // sub-problem, and the staging, the M^-1 step and the store take consecutive
-// LDS words across the lanes of a wavefront (no bank conflicts).
+// LDS words across the lanes of a wavefront.
 template <typename T, int N, int DIM>
 __global__ __launch_bounds__(kFftThreads) void k_first_ct(FK<T> a) {
     constexpr int NT = kFftThreads, D = DIM;
