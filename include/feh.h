@@ -274,7 +274,12 @@ int feh_plan_cg_residual_spectral(const feh_plan *plan);
  * a graph of that stream's plans captured once per (chunk, tol, max_iter)
  * and replayed, so a batch of many small grids costs one launch per stream
  * and chunk instead of one per kernel.  Every load case stops on its own (converged load cases return
- * at once from every kernel).  The batch keeps pointers to the plans (the
+ * at once from every kernel).  The host reads the stop flags one chunk
+ * behind (it queues the next chunk before it looks at the flags after the
+ * previous one), so the streams do not idle during the check, and after the
+ * last load case stops one more chunk of immediately returning launches
+ * runs.  feh_batch_create allocates pinned host memory for the flags and
+ * one event per stream.  The batch keeps pointers to the plans (the
  * caller keeps them, their workspaces and materials alive and unchanged
  * while the batch exists; otherwise destroy and re-create the batch).
  * FEH_EINVAL for null or repeated plans or plans on the null stream. */

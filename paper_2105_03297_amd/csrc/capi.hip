@@ -837,11 +837,24 @@ struct feh_batch {
     };
     std::vector<Entry> graphs;
     int launches = 0;  // chunks run by graph launches in the last solve (for tests)
+    // the plans' CG states copied back after each chunk (pinned, so the copy
+    // is asynchronous), with one event per stream marking its copies
+    LcState *hstate = nullptr;
+    std::vector<size_t> hstate_at;       // first state of each plan in hstate
+    std::vector<hipEvent_t> copied;
 };
 
 static void batch_clear(feh_batch &b) {
     for (auto &e : b.graphs) (void)hipGraphExecDestroy(e.exec);
     b.graphs.clear();
+}
+
+static void batch_release(feh_batch &b) {
+    batch_clear(b);
+    for (hipEvent_t e : b.copied) (void)hipEventDestroy(e);
+    b.copied.clear();
+    if (b.hstate) (void)hipHostFree(b.hstate);
+    b.hstate = nullptr;
 }
 
 // The graph of `chunk` CG iterations of the plans on stream si, captured on
@@ -892,6 +905,22 @@ int feh_batch_create(feh_batch **out, feh_plan *const *plans, int n_plans) {
         for (int i = 0; i < n_plans; ++i)
             if (std::find(b->streams.begin(), b->streams.end(), plans[i]->stream) == b->streams.end())
                 b->streams.push_back(plans[i]->stream);
+        size_t nst = 0;
+        for (int i = 0; i < n_plans; ++i) {
+            b->hstate_at.push_back(nst);
+            nst += (size_t)plans[i]->L;
+        }
+        int rc = hip_check(hipHostMalloc(reinterpret_cast<void **>(&b->hstate), nst * sizeof(LcState)), "pinned CG states");
+        for (size_t si = 0; si < b->streams.size() && rc == FEH_OK; ++si) {
+            hipEvent_t e = nullptr;
+            rc = hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+            if (rc == FEH_OK) b->copied.push_back(e);
+        }
+        if (rc != FEH_OK) {
+            batch_release(*b);
+            delete b;
+            return rc;
+        }
         *out = b;
         return FEH_OK;
     } catch (const std::bad_alloc &) {
@@ -901,7 +930,7 @@ int feh_batch_create(feh_batch **out, feh_plan *const *plans, int n_plans) {
 
 int feh_batch_destroy(feh_batch *b) {
     if (!b) return FEH_OK;
-    batch_clear(*b);
+    batch_release(*b);
     delete b;
     return FEH_OK;
 }
@@ -918,14 +947,9 @@ int feh_batch_solve(feh_batch *b, const double *const *Ebar_host, double tol, in
             if (b->plans[i]->prof_on) return set_error(FEH_EINVAL, "profiling is not available in a batch");
         }
         for (int i = 0; i < n; ++i) CK(solve_begin(*b->plans[i], Ebar_host[i], tol, max_iter, nullptr));
-        std::vector<std::vector<LcState>> hs(n);
         int done = 0, chunk = 4;
         b->launches = 0;
-        while (done < max_iter) {
-            bool any = false;
-            CK(any_active(b->plans.data(), n, hs, any));
-            if (!any) break;
-            const int c = chunk < max_iter - done ? chunk : max_iter - done;
+        auto launch_chunk = [&](int c) -> int {
             if (use_graph) {
                 for (int si = 0; si < (int)b->streams.size(); ++si) {
                     hipGraphExec_t exec = nullptr;
@@ -939,6 +963,43 @@ int feh_batch_solve(feh_batch *b, const double *const *Ebar_host, double tol, in
             ++b->launches;
             done += c;
             if (chunk < 16) chunk *= 2;
+            return FEH_OK;
+        };
+        // states after the chunks launched so far, copied on each stream
+        auto copy_states = [&]() -> int {
+            for (int i = 0; i < n; ++i) {
+                feh_plan &p = *b->plans[i];
+                CK(hip_check(hipMemcpyAsync(b->hstate + b->hstate_at[i], p.ptr<LcState>(p.off_state), p.L * sizeof(LcState),
+                                            hipMemcpyDeviceToHost, p.stream),
+                             "read CG state"));
+            }
+            for (size_t si = 0; si < b->streams.size(); ++si)
+                CK(hip_check(hipEventRecord(b->copied[si], b->streams[si]), "record"));
+            return FEH_OK;
+        };
+        auto states_active = [&](bool &any) -> int {
+            for (size_t si = 0; si < b->streams.size(); ++si) CK(hip_check(hipEventSynchronize(b->copied[si]), "CG"));
+            any = false;
+            for (int i = 0; i < n; ++i)
+                for (int l = 0; l < b->plans[i]->L; ++l) any = any || b->hstate[b->hstate_at[i] + l].active;
+            return FEH_OK;
+        };
+        // Stop checks one chunk behind: the next chunk is queued before the
+        // host looks at the states after the previous one, so the streams do
+        // not idle while it does; once every load case has stopped, the
+        // chunk queued meanwhile runs kernels that return at once.
+        bool any = false;
+        CK(copy_states());
+        CK(states_active(any));
+        if (any && done < max_iter) {
+            CK(launch_chunk(chunk < max_iter - done ? chunk : max_iter - done));
+            CK(copy_states());
+            while (done < max_iter) {
+                CK(launch_chunk(chunk < max_iter - done ? chunk : max_iter - done));
+                CK(states_active(any));
+                if (!any) break;
+                CK(copy_states());
+            }
         }
         int rc = FEH_OK;
         for (int i = 0; i < n; ++i) {
