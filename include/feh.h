@@ -269,8 +269,7 @@ int feh_plan_cg_residual_spectral(const feh_plan *plan);
  * each on a created HIP stream (plans may share one), solved together.
  * Plans on different streams run concurrently: each plan's kernels go to
  * its own stream, eagerly or as graphs.  After each plan's set-up, the CG
- * iterations of all plans run in chunks of 4, 8, then 16 iterations per
- * plan; with use_graph != 0 each chunk is one hipGraphLaunch per stream, of
+ * iterations of all plans run in chunks of 4, then 8 iterations per plan; with use_graph != 0 each chunk is one hipGraphLaunch per stream, of
  * a graph of that stream's plans captured once per (chunk, tol, max_iter)
  * and replayed, so a batch of many small grids costs one launch per stream
  * and chunk instead of one per kernel.  Every load case stops on its own (converged load cases return

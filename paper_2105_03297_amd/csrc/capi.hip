@@ -962,7 +962,7 @@ int feh_batch_solve(feh_batch *b, const double *const *Ebar_host, double tol, in
             }
             ++b->launches;
             done += c;
-            if (chunk < 16) chunk *= 2;
+            if (chunk < 8) chunk *= 2;  // the checks cost no idle time here, so short chunks
             return FEH_OK;
         };
         // states after the chunks launched so far, copied on each stream
