@@ -222,3 +222,36 @@ def test_uneven_batch_streams_do_not_change_results():
     for key, val in res.items():
         for (c, it), (cr, itr) in zip(val, ref):
             assert np.array_equal(c, cr) and it == itr, key
+
+
+@pytest.mark.parametrize("max_iter", [1, 5, 13])
+def test_uneven_batch_iteration_cap(c5, max_iter):
+    """A cap below convergence for most load cases (chunks of 4 then 8
+    iterations, stop checks one chunk behind): every load case stops at
+    exactly max_iter with FEH_ENOCONV unless it converged first (laminates
+    and homogeneous maps converge in a few iterations), with graph replay and
+    eagerly, and a map's capped result (iteration counts, energies) equals
+    the same map solved alone with the same cap."""
+    import paper_2105_03297_amd as feh
+    from oracle import fe
+    say("uneven batch iteration cap", max_iter)
+    maps, lm, ub, out = c5
+    res = {}
+    for graph in (True, False):
+        got = ub.solve(ms.unit_loads(2), tol=1e-12, max_iter=max_iter, use_graph=graph)
+        assert got[0]["status"] == feh.FEH_ENOCONV
+        for o in got:
+            for r in o["report"]:
+                assert r["iterations"] <= max_iter
+                assert (r["status"] == feh.FEH_ENOCONV) == (r["iterations"] == max_iter and r["rel_residual"] > 1e-12)
+        res[graph] = got
+    for a, b in zip(res[True], res[False]):
+        assert np.array_equal(a["energy"], b["energy"])
+    for i in (0, len(lm) - 1):
+        lam, mu = lm[i]
+        h = feh.Homogenizer(lam.shape, n_load=3, precision="fp32")
+        h.set_material(lam=lam, mu=mu)
+        ref = h.solve(ms.unit_loads(2), tol=1e-12, max_iter=max_iter)
+        h.close()
+        assert [r["iterations"] for r in ref["report"]] == [r["iterations"] for r in res[True][i]["report"]]
+        assert rel(res[True][i]["energy"], ref["energy"]) < 1e-6, (i, rel(res[True][i]["energy"], ref["energy"]))
