@@ -850,6 +850,8 @@ static void batch_clear(feh_batch &b) {
 }
 
 static void batch_release(feh_batch &b) {
+    // a solve that ended on an error may have left state copies queued
+    for (hipStream_t s : b.streams) (void)hipStreamSynchronize(s);
     batch_clear(b);
     for (hipEvent_t e : b.copied) (void)hipEventDestroy(e);
     b.copied.clear();
