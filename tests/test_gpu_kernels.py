@@ -78,6 +78,41 @@ def test_operator_matches_assembled_stiffness(shape, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(5, 9, 70), (70, 9, 40), (65, 17, 33), (3, 40, 5)])
+def test_operator_with_16_row_tiles_matches_assembled_stiffness(shape, prec):
+    """The 3D stencil's taller tile (16 x 32 voxels, 512 threads, updating
+    15 x 31 nodes; a tuning option) against the oracle's assembled stiffness,
+    as the default tile above (ragged tiles, several x-chunks)."""
+    import paper_2105_03297_amd as feh
+    from oracle import fe
+    say("operator, 16-row tiles", shape, prec)
+    L = 2
+    lam, mu = random_material(shape, 8, prec)
+    hvox = (1.0, 1.3, 0.8)
+    h = feh.Homogenizer(shape, n_load=L, precision=prec, h=hvox)
+    t = feh.feh_plan_tuning(h.plan)
+    t["stencil_rows"] = 16
+    feh.feh_plan_set_tuning(h.plan, t)
+    assert feh.feh_plan_tuning(h.plan)["stencil_rows"] == 16
+    h.set_material(lam=lam, mu=mu)
+    rng = np.random.default_rng(3)
+    N = int(np.prod(shape))
+    dt = np.float64 if prec == "fp64" else np.float32
+    p = rng.standard_normal((L, N, 3)).astype(dt).astype(np.float64)
+    q = h.apply_operator(p).cpu().numpy().astype(np.float64)
+    h.close()
+    K = fe.assemble(lam, mu, hvox)
+    Kabs = abs(K)
+    for l in range(L):
+        ref = (K @ p[l].ravel()).reshape(N, 3)
+        if prec == "fp64":
+            assert rel(q[l], ref) < 1e-13
+        else:
+            bound = (Kabs @ np.abs(p[l]).ravel()).reshape(N, 3)
+            assert np.all(np.abs(q[l] - ref) <= 2e-6 * bound + 1e-30)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_operator_on_the_largest_planes(prec):
     """q = K p on the largest planes a 3D plan takes (4096 x 4096 in FP32,
     4096 x 2048 in FP64, where the last-axis transform of 3 components
